@@ -1,0 +1,332 @@
+"""FP64 CPU oracle for VDAMP (Algorithm 1) with SURE-tuned complex soft thresholding,
+and for the FISTA comparator.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or execute
+this module: it is used by ``tests/``, by ``__graft_entry__.smoke()`` and by the
+``cpu_baseline`` leg of ``bench.py``.  It shares no code with the HIP library.
+
+It is written to be checked by eye against the paper: plain NumPy in complex128, the
+steps in the order of Algorithm 1, library primitives only for the FFT and the sort.
+
+Conventions (readings of the paper where it is silent; each is pinned by a test):
+* F is the unitary 2D DFT in natural order (numpy ``norm="ortho"``); exact consistency
+  of the output step (Section 2, final line of Algorithm 1) needs F^H F = I.
+* Psi is the s-level periodic orthonormal 2D Haar transform, Mallat layout.  One level
+  acts on the top-left block: along x, a = (x[2i] + x[2i+1]) / sqrt2 goes left and
+  d = (x[2i] - x[2i+1]) / sqrt2 goes right; then the same along y (top / bottom).
+  Band order b = 0 is LL_s, then for l = s .. 1 the triple (LH_l, HL_l, HH_l), where
+  LH = low along y / high along x (top-right block), HL = high along y / low along x
+  (bottom-left), HH = bottom-right.  Scale 1 is the finest (Section 3).
+* The denoiser is complex soft thresholding eta(r; theta) = r max(0, 1 - theta/|r|),
+  with one threshold per subband (eq. 7).  The threshold minimises the complex,
+  colored SURE over the candidate set theta in {|r_i|} of the band (Section 3).
+* g' of line 7 is the Wirtinger derivative (half the R^2 divergence), averaged within
+  each subband, so alpha has 1+3s entries.
+* Line 10's w is the last denoised estimate w_hat_{K-1}; with K = 0 the output is the
+  zero-filled F^H y.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SQRT2 = np.sqrt(2.0)
+
+
+# ----------------------------------------------------------------------------------
+# Linear operators (Section 1: Phi = M_Omega F; Section 2: orthogonal wavelet Psi)
+
+def fft2u(x):
+    """Unitary 2D DFT, natural order."""
+    return np.fft.fft2(x, norm="ortho")
+
+
+def ifft2u(X):
+    """Inverse unitary 2D DFT (F^H)."""
+    return np.fft.ifft2(X, norm="ortho")
+
+
+def haar_analysis(x, s):
+    """w = Psi x: s-level periodic orthonormal 2D Haar, Mallat layout."""
+    w = np.array(x, dtype=np.complex128, copy=True)
+    h, wd = w.shape
+    for _ in range(s):
+        blk = w[:h, :wd]
+        t = np.concatenate([(blk[:, 0::2] + blk[:, 1::2]) / SQRT2,
+                            (blk[:, 0::2] - blk[:, 1::2]) / SQRT2], axis=1)
+        w[:h, :wd] = np.concatenate([(t[0::2, :] + t[1::2, :]) / SQRT2,
+                                     (t[0::2, :] - t[1::2, :]) / SQRT2], axis=0)
+        h //= 2
+        wd //= 2
+    return w
+
+
+def haar_synthesis(w, s):
+    """x = Psi^H w, the inverse of haar_analysis."""
+    x = np.array(w, dtype=np.complex128, copy=True)
+    ny, nx = x.shape
+    for l in range(s, 0, -1):
+        h, wd = ny >> l, nx >> l
+        blk = x[:2 * h, :2 * wd]
+        t = np.empty_like(blk)
+        lo, hi = blk[:h, :], blk[h:, :]
+        t[0::2, :] = (lo + hi) / SQRT2
+        t[1::2, :] = (lo - hi) / SQRT2
+        out = np.empty_like(blk)
+        lo, hi = t[:, :wd], t[:, wd:]
+        out[:, 0::2] = (lo + hi) / SQRT2
+        out[:, 1::2] = (lo - hi) / SQRT2
+        x[:2 * h, :2 * wd] = out
+    return x
+
+
+def bands(ny, nx, s):
+    """Subband blocks in band order: LL_s, then (LH_l, HL_l, HH_l) for l = s..1.
+    Returns a list of (row slice, column slice, level, kind)."""
+    out = [(slice(0, ny >> s), slice(0, nx >> s), s, "LL")]
+    for l in range(s, 0, -1):
+        h, w = ny >> l, nx >> l
+        out.append((slice(0, h), slice(w, 2 * w), l, "LH"))
+        out.append((slice(h, 2 * h), slice(0, w), l, "HL"))
+        out.append((slice(h, 2 * h), slice(w, 2 * w), l, "HH"))
+    return out
+
+
+def check_shape(ny, nx, s):
+    if s < 1 or ny % (1 << s) or nx % (1 << s):
+        raise ValueError(f"image {ny}x{nx} is not divisible by 2^{s}")
+
+
+# ----------------------------------------------------------------------------------
+# Line 1: S = |Phi Psi^H|^2.  For Haar it is separable per band, S_b(ky,kx) =
+# Y_b(ky) X_b(kx), with 1D factors the squared DFT magnitudes of the 1D scaling
+# function (length 2^m, height 2^(-m/2)) and wavelet (+- 2^(-l/2) on two halves).
+
+def _dirichlet(k, M, n):
+    """D_M(k) = sum_{t<M} exp(-2 pi i k t / n) in magnitude: sin(pi k M/n)/sin(pi k/n)."""
+    k = np.asarray(k, dtype=np.float64)
+    num = np.sin(np.pi * k * M / n)
+    den = np.sin(np.pi * k / n)
+    out = np.empty_like(k)
+    z = np.isclose(np.mod(k, n), 0.0)
+    out[~z] = num[~z] / den[~z]
+    out[z] = M
+    return out
+
+
+def haar_scaling_power(n, m):
+    """|DFT of the level-m scaling function|^2 over k = 0..n-1 (unitary DFT)."""
+    k = np.arange(n)
+    return _dirichlet(k, 2 ** m, n) ** 2 / (n * 2.0 ** m)
+
+
+def haar_wavelet_power(n, l):
+    """|DFT of the level-l wavelet|^2 over k = 0..n-1 (unitary DFT)."""
+    k = np.arange(n)
+    h = 2 ** (l - 1)
+    return 4.0 * _dirichlet(k, h, n) ** 2 * np.sin(np.pi * k * h / n) ** 2 / (n * 2.0 ** l)
+
+
+def tau_weights(ny, nx, s):
+    """S_b(ky, kx) for every band b, as a list of float64 [ny][nx] arrays."""
+    out = []
+    for (_, _, l, kind) in bands(ny, nx, s):
+        Ly, Lx = haar_scaling_power(ny, l), haar_scaling_power(nx, l)
+        Hy, Hx = haar_wavelet_power(ny, l), haar_wavelet_power(nx, l)
+        fy, fx = {"LL": (Ly, Lx), "LH": (Ly, Hx), "HL": (Hy, Lx), "HH": (Hy, Hx)}[kind]
+        out.append(np.outer(fy, fx))
+    return out
+
+
+# ----------------------------------------------------------------------------------
+# Line 6: complex soft thresholding, and its SURE-optimal threshold (Section 3).
+
+def soft(r, theta):
+    """eta(r; theta) = r * max(0, 1 - theta/|r|); zero when |r| <= theta."""
+    a = np.abs(r)
+    out = np.zeros_like(r)
+    keep = a > theta
+    out[keep] = r[keep] * (1.0 - theta / a[keep])
+    return out
+
+
+def sure_value(a, theta, tau):
+    """Complex colored SURE of soft thresholding one band at threshold theta, summed
+    over the band: Stein's estimate with n ~ CN(0, tau) (2 real dimensions per
+    coefficient), written directly from its definition, O(N_b)."""
+    a = np.asarray(a, dtype=np.float64)
+    below = a <= theta
+    above = ~below
+    return (np.sum(a[below] ** 2 - tau)
+            + np.sum(theta ** 2 + tau - tau * theta / a[above]))
+
+
+def sure_threshold(a, tau):
+    """SURE-minimising threshold for one band.
+
+    a: magnitudes |r_i| of the band (float64), tau: effective noise variance of the band.
+    Candidates theta = a_(m) (m = number of magnitudes <= theta), theta > 0, taking only
+    the last index of a run of equal values; ties of the SURE value go to the smallest
+    theta.  With sorted a, A_m = sum_{i<=m} a_(i)^2 and R_m = sum_{i>m} 1/a_(i):
+        SURE(m) = A_m - m tau + (N_b - m)(theta^2 + tau) - tau theta R_m.
+    alpha (line 7) = mean over the band of the Wirtinger derivative of eta, which is
+    1 - theta/(2|r|) above the threshold and 0 below:
+        alpha = ((N_b - m) - (theta/2) R_m) / N_b.
+    Returns (theta, alpha, m, sure_min).  All-zero band: theta = 0, alpha = 0.
+    """
+    a = np.sort(np.asarray(a, dtype=np.float64).ravel())
+    n = a.size
+    if n == 0:
+        raise ValueError("empty band")
+    if a[-1] == 0.0:
+        return 0.0, 0.0, n, float(n * (0.0 - tau))
+    A = np.cumsum(a ** 2)                                  # A[m-1] = A_m
+    inv = np.zeros(n)
+    pos = a > 0
+    inv[pos] = 1.0 / a[pos]
+    Rsuf = np.concatenate([np.cumsum(inv[::-1])[::-1][1:], [0.0]])  # Rsuf[m-1] = R_m
+    m = np.arange(1, n + 1, dtype=np.float64)
+    sure = A - m * tau + (n - m) * (a ** 2 + tau) - tau * a * Rsuf
+    last_of_run = np.concatenate([a[:-1] < a[1:], [True]])
+    valid = last_of_run & (a > 0)
+    sure_v = np.where(valid, sure, np.inf)
+    i = int(np.argmin(sure_v))                             # first minimum = smallest theta
+    theta = float(a[i])
+    mm = i + 1
+    alpha = float(((n - mm) - 0.5 * theta * Rsuf[i]) / n)
+    return theta, alpha, mm, float(sure_v[i])
+
+
+def sure_threshold_brute(a, tau):
+    """O(N_b^2) reference for sure_threshold: evaluate sure_value at every candidate."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    cands = np.unique(a[a > 0])
+    if cands.size == 0:
+        return 0.0, float(a.size * (0.0 - tau))
+    vals = np.array([sure_value(a, t, tau) for t in cands])
+    i = int(np.argmin(vals))
+    return float(cands[i]), float(vals[i])
+
+
+def wirtinger_mean_soft(r, theta):
+    """alpha for one band straight from its definition: the mean over the band of
+    1 - theta/(2|r_i|) for |r_i| > theta, 0 otherwise."""
+    a = np.abs(r)
+    keep = a > theta
+    return float(np.sum(1.0 - theta / (2.0 * a[keep])) / a.size)
+
+
+# ----------------------------------------------------------------------------------
+# Algorithm 1
+
+def tau_estimate(z, mask, p, sigma2, S):
+    """Line 5: tau_b = sum_{j in Omega} S_b(j) p_j^-1 [(p_j^-1 - 1)|z_j|^2 + sigma^2]."""
+    w = np.zeros(z.shape)
+    om = mask.astype(bool)
+    w[om] = 1.0 / p[om]
+    c = w * ((w - 1.0) * np.abs(z) ** 2 + sigma2)
+    return np.array([np.sum(Sb * c) for Sb in S])
+
+
+def vdamp_step(rt, y, mask, p, sigma2, s, S):
+    """Lines 3-5 for one iteration: from r_tilde_k to (r_k, tau_k)."""
+    om = mask.astype(bool)
+    x_t = haar_synthesis(rt, s)
+    z = np.where(om, y - fft2u(x_t), 0.0)                  # line 3 (zero off Omega)
+    v = np.zeros_like(z)
+    v[om] = z[om] / p[om]                                  # P^-1 z, zero-filled
+    r = rt + haar_analysis(ifft2u(v), s)                   # line 4
+    tau = tau_estimate(z, mask, p, sigma2, S)              # line 5
+    return r, tau
+
+
+def denoise(r, tau, s, theta_override=None):
+    """Lines 6-8: per band SURE threshold, eta, alpha, and the corrected r_tilde_{k+1}.
+    theta_override (optional, per band) replaces the SURE search; alpha then follows
+    from its definition at that threshold."""
+    ny, nx = r.shape
+    w_hat = np.zeros_like(r)
+    rt_next = np.zeros_like(r)
+    thetas, alphas = [], []
+    for b, (rs, cs, _, _) in enumerate(bands(ny, nx, s)):
+        rb = r[rs, cs]
+        if theta_override is None:
+            th, al, _, _ = sure_threshold(np.abs(rb), tau[b])
+        else:
+            th = float(theta_override[b])
+            al = wirtinger_mean_soft(rb, th)
+        wb = soft(rb, th)
+        w_hat[rs, cs] = wb
+        rt_next[rs, cs] = (wb - al * rb) / (1.0 - al)      # line 8
+        thetas.append(th)
+        alphas.append(al)
+    return w_hat, rt_next, np.array(thetas), np.array(alphas)
+
+
+def output_step(w_hat, y, mask, s):
+    """Line 10: x_hat = Psi^H w + Phi^H (y - Phi Psi^H w)."""
+    x = haar_synthesis(w_hat, s)
+    om = mask.astype(bool)
+    resid = np.where(om, y - fft2u(x), 0.0)
+    return x + ifft2u(resid)
+
+
+def vdamp(y, mask, p, sigma2, s, iters, record=False):
+    """Algorithm 1 in FP64.  y: zero-filled measurements (natural order), mask: 0/1,
+    p: sampling probabilities (used on Omega), sigma2: E|eps_j|^2, s: Haar levels.
+    Returns dict with x_hat and, per iteration, tau, theta, alpha (and r if record)."""
+    y = np.asarray(y, dtype=np.complex128)
+    p = np.asarray(p, dtype=np.float64)
+    ny, nx = y.shape
+    check_shape(ny, nx, s)
+    S = tau_weights(ny, nx, s)
+    rt = np.zeros((ny, nx), dtype=np.complex128)           # line 1: r_tilde_0 = 0
+    w_hat = np.zeros_like(rt)
+    taus, thetas, alphas, rs = [], [], [], []
+    for _ in range(iters):
+        r, tau = vdamp_step(rt, y, mask, p, sigma2, s, S)
+        w_hat, rt, th, al = denoise(r, tau, s)
+        taus.append(tau)
+        thetas.append(th)
+        alphas.append(al)
+        if record:
+            rs.append(r)
+    x_hat = output_step(w_hat, y, mask, s)
+    out = dict(x_hat=x_hat, tau=np.array(taus), theta=np.array(thetas),
+               alpha=np.array(alphas))
+    if record:
+        out["r"] = rs
+    return out
+
+
+# ----------------------------------------------------------------------------------
+# FISTA comparator (Section 1, eq. 2 with f = lambda ||Psi x||_1; Section 3 setup):
+# synthesis form over w = Psi x (equal to the analysis form since Psi is orthogonal),
+# step 1 because ||M F Psi^H|| <= 1, zero initialisation, every band thresholded.
+
+def fista(y, mask, lam, s, iters):
+    y = np.asarray(y, dtype=np.complex128)
+    om = mask.astype(bool)
+    ny, nx = y.shape
+    check_shape(ny, nx, s)
+    v = np.zeros((ny, nx), dtype=np.complex128)
+    w_prev = np.zeros_like(v)
+    t = 1.0
+    objective = []
+    for _ in range(iters):
+        resid = np.where(om, y - fft2u(haar_synthesis(v, s)), 0.0)
+        w = soft(v + haar_analysis(ifft2u(resid), s), lam)
+        t_next = 0.5 * (1.0 + np.sqrt(1.0 + 4.0 * t * t))
+        v = w + ((t - 1.0) / t_next) * (w - w_prev)
+        w_prev, t = w, t_next
+        objective.append(fista_objective(w, y, mask, lam, s))
+    return dict(x_hat=haar_synthesis(w_prev, s), w=w_prev, objective=np.array(objective))
+
+
+def fista_objective(w, y, mask, lam, s):
+    om = mask.astype(bool)
+    resid = np.where(om, y - fft2u(haar_synthesis(w, s)), 0.0)
+    return float(0.5 * np.sum(np.abs(resid) ** 2) + lam * np.sum(np.abs(w)))
+
+
+def nmse_db(x_hat, x0):
+    return float(10.0 * np.log10(np.sum(np.abs(x_hat - x0) ** 2) / np.sum(np.abs(x0) ** 2)))
