@@ -239,10 +239,11 @@ def vdamp_step(rt, y, mask, p, sigma2, s, S):
     return r, tau
 
 
-def denoise(r, tau, s, theta_override=None):
+def denoise(r, tau, s, theta_override=None, alpha_override=None):
     """Lines 6-8: per band SURE threshold, eta, alpha, and the corrected r_tilde_{k+1}.
     theta_override (optional, per band) replaces the SURE search; alpha then follows
-    from its definition at that threshold."""
+    from its definition at that threshold unless alpha_override gives it too (a test
+    that replays another implementation's decisions supplies both)."""
     ny, nx = r.shape
     w_hat = np.zeros_like(r)
     rt_next = np.zeros_like(r)
@@ -253,7 +254,8 @@ def denoise(r, tau, s, theta_override=None):
             th, al, _, _ = sure_threshold(np.abs(rb), tau[b])
         else:
             th = float(theta_override[b])
-            al = wirtinger_mean_soft(rb, th)
+            al = (wirtinger_mean_soft(rb, th) if alpha_override is None
+                  else float(alpha_override[b]))
         wb = soft(rb, th)
         w_hat[rs, cs] = wb
         rt_next[rs, cs] = (wb - al * rb) / (1.0 - al)      # line 8

@@ -1,0 +1,611 @@
+// Host side of libvdamp: argument checks, the plan (line 1's tau weights, FFT twiddles
+// and radix plans, work lists), workspace layout, the pass schedule of Algorithm 1 and
+// of FISTA, optional hipGraph capture and per-pass event timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "vdamp.h"
+#include "vdamp_internal.h"
+
+namespace vdamp {
+hipError_t launch_rows_synth(const KArgs& a, int do_fft, size_t lds, hipStream_t st);
+hipError_t launch_cols(const KArgs& a, size_t lds, hipStream_t st);
+hipError_t launch_rows_anal(const KArgs& a, size_t lds, hipStream_t st);
+hipError_t launch_sure(const KArgs& a, size_t lds, hipStream_t st);
+hipError_t launch_prep(const uint8_t* mask, const float* p, const float2* y, float* wgt,
+                       long long n, int check, int* bad, hipStream_t st);
+hipError_t launch_zero(float2* x, long long n, hipStream_t st);
+hipError_t set_lds_limits(size_t rows, size_t cols, size_t sure);
+}  // namespace vdamp
+
+using namespace vdamp;
+
+namespace {
+
+thread_local std::string g_err;
+
+vdamp_status fail(vdamp_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(VDAMP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Radix plan: radix-4 stages first, then 5, 3, 4 and 2 for the remaining factor.
+bool radix_plan(int n, std::vector<int>& rad) {
+  rad.clear();
+  int m = n;
+  while (m % 4 == 0 && m > 4) { rad.push_back(4); m /= 4; }
+  for (int r : {5, 3, 4, 2})
+    while (m % r == 0) { rad.push_back(r); m /= r; }
+  return m == 1 && (int)rad.size() <= kMaxRadices;
+}
+
+// |unitary DFT of a 1D Haar basis function of length n|^2 at every k, by direct summation
+// over its support: the scaling function of level m is 2^(-m/2) on 2^m samples; the
+// wavelet of level l is +2^(-l/2) on 2^(l-1) samples then -2^(-l/2) on 2^(l-1) samples.
+void haar_power(int n, int level, bool wavelet, std::vector<double>& out) {
+  out.assign(n, 0.0);
+  const int len = 1 << level;
+  const double h = std::pow(2.0, -0.5 * level);
+  for (int k = 0; k < n; ++k) {
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < len; ++t) {
+      const double sgn = (wavelet && t >= len / 2) ? -1.0 : 1.0;
+      const double ang = -2.0 * M_PI * double((long long)k * t % n) / double(n);
+      re += sgn * h * std::cos(ang);
+      im += sgn * h * std::sin(ang);
+    }
+    out[k] = (re * re + im * im) / double(n);
+  }
+}
+
+struct GraphKey {
+  int kind = -1;
+  const void *ws = nullptr, *y = nullptr, *mask = nullptr, *p = nullptr, *sig = nullptr,
+             *lam = nullptr, *x = nullptr, *trace = nullptr;
+  int iters = -1;
+  hipStream_t stream = nullptr;
+  bool operator==(const GraphKey& o) const {
+    return kind == o.kind && ws == o.ws && y == o.y && mask == o.mask && p == o.p &&
+           sig == o.sig && lam == o.lam && x == o.x && trace == o.trace && iters == o.iters &&
+           stream == o.stream;
+  }
+};
+
+}  // namespace
+
+struct vdamp_plan_t {
+  int B = 0, levels = 0, nbands = 0;
+  uint32_t flags = 0;
+  std::vector<int> ny, nx;
+  std::vector<long long> off;
+  long long ntot = 0;
+  int ncolstrips = 0;
+  // device constants
+  SliceDev* d_slices = nullptr;
+  FftPlanDev* d_ffts = nullptr;
+  float2* d_tw = nullptr;
+  float* d_tables = nullptr;
+  int2* d_work_rows = nullptr;
+  int2* d_work_cols = nullptr;
+  int2* d_work_sure = nullptr;
+  int nrows = 0, ncols = 0, nsure = 0;
+  size_t lds_rows = 0, lds_cols = 0, lds_sure = 0;
+  // workspace layout (byte offsets)
+  size_t o_wgt = 0, o_r = 0, o_X = 0, o_r2 = 0, o_theta = 0, o_thr2 = 0, o_alpha = 0, o_tau = 0,
+         o_taup = 0, o_bad = 0, ws_bytes = 0;
+  // last solve
+  const void* state_ws = nullptr;
+  bool has_state = false;
+  // graph cache
+  GraphKey gkey;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  // timing
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_used;  // (pass, index of start event in ev_pool)
+  size_t ev_next = 0;
+};
+
+namespace {
+
+void free_plan(vdamp_plan_t* P) {
+  if (!P) return;
+  if (P->gexec) hipGraphExecDestroy(P->gexec);
+  if (P->graph) hipGraphDestroy(P->graph);
+  for (auto e : P->ev_pool) hipEventDestroy(e);
+  hipFree(P->d_slices);
+  hipFree(P->d_ffts);
+  hipFree(P->d_tw);
+  hipFree(P->d_tables);
+  hipFree(P->d_work_rows);
+  hipFree(P->d_work_cols);
+  hipFree(P->d_work_sure);
+  delete P;
+}
+
+struct Ws {
+  float* wgt;
+  float2 *r, *X, *r2;
+  float *theta, *thr2, *alpha, *tau, *taup;
+  int* bad;
+};
+
+Ws layout(const vdamp_plan_t* P, void* ws) {
+  char* b = static_cast<char*>(ws);
+  Ws w;
+  w.wgt = reinterpret_cast<float*>(b + P->o_wgt);
+  w.r = reinterpret_cast<float2*>(b + P->o_r);
+  w.X = reinterpret_cast<float2*>(b + P->o_X);
+  w.r2 = reinterpret_cast<float2*>(b + P->o_r2);
+  w.theta = reinterpret_cast<float*>(b + P->o_theta);
+  w.thr2 = reinterpret_cast<float*>(b + P->o_thr2);
+  w.alpha = reinterpret_cast<float*>(b + P->o_alpha);
+  w.tau = reinterpret_cast<float*>(b + P->o_tau);
+  w.taup = reinterpret_cast<float*>(b + P->o_taup);
+  w.bad = reinterpret_cast<int*>(b + P->o_bad);
+  return w;
+}
+
+// Launch helper that records timing events around each kernel when asked.
+struct Launcher {
+  vdamp_plan_t* P;
+  hipStream_t st;
+  bool timing;
+  hipError_t begin(int pass) {
+    if (!timing) return hipSuccess;
+    if (P->ev_next + 2 > P->ev_pool.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        P->ev_pool.push_back(e);
+      }
+    }
+    P->ev_used.emplace_back(pass, (int)P->ev_next);
+    hipError_t err = hipEventRecord(P->ev_pool[P->ev_next], st);
+    P->ev_next += 2;
+    return err;
+  }
+  hipError_t end() {
+    if (!timing) return hipSuccess;
+    return hipEventRecord(P->ev_pool[P->ev_used.back().second + 1], st);
+  }
+};
+
+#define LAUNCH(L, pass, call)                                                           \
+  do {                                                                                  \
+    HIP_TRY((L).begin(pass));                                                           \
+    HIP_TRY(call);                                                                      \
+    HIP_TRY((L).end());                                                                 \
+  } while (0)
+
+KArgs base_args(const vdamp_plan_t* P, const Ws& w) {
+  KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.slices = P->d_slices;
+  a.ffts = P->d_ffts;
+  a.twiddles = P->d_tw;
+  a.tables = P->d_tables;
+  a.levels = P->levels;
+  a.nbands = P->nbands;
+  a.batch = P->B;
+  a.wgt = w.wgt;
+  a.r = w.r;
+  a.r2 = w.r2;
+  a.X = w.X;
+  a.theta = w.theta;
+  a.thr2 = w.thr2;
+  a.alpha = w.alpha;
+  a.tau = w.tau;
+  a.tau_part = w.taup;
+  return a;
+}
+
+vdamp_status check_common(vdamp_plan_h plan, void* ws, size_t wsb, const void* y,
+                          const void* mask, int iters, const void* x_hat) {
+  if (!plan) return fail(VDAMP_ERR_ARG, "plan is null");
+  if (!ws) return fail(VDAMP_ERR_WORKSPACE, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(VDAMP_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (wsb < plan->ws_bytes)
+    return fail(VDAMP_ERR_WORKSPACE, "workspace has " + std::to_string(wsb) + " bytes, needs " +
+                                         std::to_string(plan->ws_bytes));
+  if (!y || !mask || !x_hat) return fail(VDAMP_ERR_ARG, "y, mask and x_hat must be non-null");
+  if (iters < 0) return fail(VDAMP_ERR_ARG, "iters must be >= 0");
+  return VDAMP_OK;
+}
+
+vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const float2* y,
+                           const uint8_t* mask, const float* p, const float* sigma2, int iters,
+                           float2* x_hat, float* trace, bool timing) {
+  const Ws w = layout(P, ws);
+  Launcher L{P, st, timing};
+  const int check = (P->flags & VDAMP_FLAG_CHECK_FINITE) ? 1 : 0;
+  LAUNCH(L, VDAMP_PASS_PREP, launch_prep(mask, p, y, w.wgt, P->ntot, check, w.bad, st));
+  KArgs a = base_args(P, w);
+  a.y = y;
+  a.sigma2 = sigma2;
+  a.out = x_hat;
+  a.trace = trace;
+  for (int k = 0; k < iters; ++k) {
+    a.iter = k;
+    if (k > 0) {
+      a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_RTILDE;
+      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, 1, P->lds_rows, st));
+    }
+    a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = k ? CM_VDAMP : CM_VDAMP_FIRST;
+    LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->lds_cols, st));
+    a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = k ? RA_VDAMP : RA_VDAMP_FIRST;
+    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->lds_rows, st));
+    a.work = P->d_work_sure; a.nwork = P->nsure;
+    LAUNCH(L, VDAMP_PASS_SURE, launch_sure(a, P->lds_sure, st));
+  }
+  // line 10: x_hat = F^H [ (1 - m) F Psi^H w + m y ]
+  if (iters > 0) {
+    a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_WHAT;
+    LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, 1, P->lds_rows, st));
+  }
+  a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = iters > 0 ? CM_OUTPUT : CM_ZEROFILL;
+  LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->lds_cols, st));
+  a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RA_IMAGE;
+  LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->lds_rows, st));
+  return VDAMP_OK;
+}
+
+vdamp_status enqueue_fista(vdamp_plan_t* P, hipStream_t st, void* ws, const float2* y,
+                           const uint8_t* mask, const float* lambda, int iters, float2* x_hat,
+                           bool timing) {
+  const Ws w = layout(P, ws);
+  Launcher L{P, st, timing};
+  // weights: m (p taken as 1)
+  LAUNCH(L, VDAMP_PASS_PREP, launch_prep(mask, nullptr, y, w.wgt, P->ntot, 0, w.bad, st));
+  KArgs a = base_args(P, w);
+  a.y = y;
+  a.lambda = lambda;
+  a.out = x_hat;
+  double t = 1.0;
+  for (int k = 0; k < iters; ++k) {
+    const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+    a.beta = (float)((t - 1.0) / tn);
+    t = tn;
+    if (k > 0) {
+      a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_PLAIN;
+      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, 1, P->lds_rows, st));
+    }
+    a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = k ? CM_FISTA : CM_FISTA_FIRST;
+    LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->lds_cols, st));
+    a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = k ? RA_FISTA : RA_FISTA_FIRST;
+    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->lds_rows, st));
+  }
+  // x_hat = Psi^H w_K (w_K lives in r2); K = 0 gives zeros (a fill kernel, so that a
+  // captured graph holds no memset node)
+  if (iters == 0) {
+    HIP_TRY(launch_zero(x_hat, P->ntot, st));
+    return VDAMP_OK;
+  }
+  a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_PLAIN;
+  a.r = w.r2;
+  LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, 0, P->lds_rows, st));
+  return VDAMP_OK;
+}
+
+template <class F>
+vdamp_status run_maybe_graph(vdamp_plan_t* P, hipStream_t st, const GraphKey& key, F&& enqueue) {
+  const bool timing = (P->flags & VDAMP_FLAG_TIMING) != 0;
+  if (timing || !(P->flags & VDAMP_FLAG_USE_GRAPH)) return enqueue(timing);
+  if (!(P->gexec && P->gkey == key)) {
+    if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+    if (P->graph) { hipGraphDestroy(P->graph); P->graph = nullptr; }
+    P->gkey = GraphKey();
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    vdamp_status s = enqueue(false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (s != VDAMP_OK) {
+      if (g) hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return fail(VDAMP_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    P->graph = g;
+    HIP_TRY(hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0));
+    P->gkey = key;
+  }
+  HIP_TRY(hipGraphLaunch(P->gexec, st));
+  return VDAMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vdamp_status_string(vdamp_status s) {
+  switch (s) {
+    case VDAMP_OK: return "ok";
+    case VDAMP_ERR_ARG: return "invalid argument";
+    case VDAMP_ERR_SHAPE: return "invalid shape";
+    case VDAMP_ERR_UNSUPPORTED: return "unsupported";
+    case VDAMP_ERR_WORKSPACE: return "bad workspace";
+    case VDAMP_ERR_HIP: return "HIP error";
+    case VDAMP_ERR_NONFINITE: return "invalid data";
+    case VDAMP_ERR_STATE: return "no state";
+  }
+  return "unknown status";
+}
+
+const char* vdamp_last_error(void) { return g_err.c_str(); }
+
+vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, const int32_t* nx,
+                        int32_t levels, int32_t wavelet, uint32_t flags, size_t* workspace_bytes) {
+  g_err.clear();
+  if (!plan || !ny || !nx || !workspace_bytes) return fail(VDAMP_ERR_ARG, "null pointer argument");
+  *plan = nullptr;
+  if (batch < 1) return fail(VDAMP_ERR_ARG, "batch must be >= 1");
+  if (wavelet != VDAMP_WAVELET_HAAR) return fail(VDAMP_ERR_UNSUPPORTED, "only the Haar wavelet is implemented");
+  if (levels < 1 || levels > 4) return fail(VDAMP_ERR_UNSUPPORTED, "levels must be in 1..4");
+  const uint32_t known = VDAMP_FLAG_USE_GRAPH | VDAMP_FLAG_CHECK_FINITE | VDAMP_FLAG_TIMING;
+  if (flags & ~known) return fail(VDAMP_ERR_ARG, "unknown flag bits");
+  const int H = 1 << levels;
+  std::vector<int> rad;
+  for (int b = 0; b < batch; ++b) {
+    for (int n : {ny[b], nx[b]}) {
+      if (n < H || n % H || n > kMaxN)
+        return fail(VDAMP_ERR_SHAPE, "slice " + std::to_string(b) + ": size " + std::to_string(n) +
+                                         " must be a multiple of 2^levels in [2^levels, 512]");
+      if (!radix_plan(n, rad))
+        return fail(VDAMP_ERR_UNSUPPORTED, "size " + std::to_string(n) + " is not 2^a 3^b 5^c");
+    }
+    if (nx[b] % kColW)
+      return fail(VDAMP_ERR_UNSUPPORTED, "nx must be a multiple of 16 (column strip width)");
+    if (H * nx[b] > kMaxElems || ny[b] * kColW > kMaxElems)
+      return fail(VDAMP_ERR_UNSUPPORTED, "strip does not fit the LDS tile");
+    const long long finest = (long long)(ny[b] >> 1) * (nx[b] >> 1);
+    if (finest > kMaxSortKeys)
+      return fail(VDAMP_ERR_UNSUPPORTED, "finest subband larger than the LDS threshold search");
+  }
+
+  vdamp_plan_t* P = new vdamp_plan_t();
+  P->B = batch;
+  P->levels = levels;
+  P->nbands = 1 + 3 * levels;
+  P->flags = flags;
+  P->ny.assign(ny, ny + batch);
+  P->nx.assign(nx, nx + batch);
+  P->off.resize(batch);
+
+  // FFT plans and twiddles, one per distinct length
+  std::map<int, int> fft_index;
+  std::vector<FftPlanDev> ffts;
+  std::vector<float2> tw;
+  auto get_fft = [&](int n) {
+    auto it = fft_index.find(n);
+    if (it != fft_index.end()) return it->second;
+    FftPlanDev f;
+    std::memset(&f, 0, sizeof(f));
+    std::vector<int> rr;
+    radix_plan(n, rr);
+    f.n = n;
+    f.nst = (int)rr.size();
+    for (size_t i = 0; i < rr.size(); ++i) f.rad[i] = rr[i];
+    f.tw_off = (int)tw.size();
+    for (int k = 0; k < n; ++k) {
+      const double ang = -2.0 * M_PI * double(k) / double(n);
+      tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
+    }
+    ffts.push_back(f);
+    fft_index[n] = (int)ffts.size() - 1;
+    return (int)ffts.size() - 1;
+  };
+  // tau-weight tables (line 1), one set per distinct length: L_1..L_s then H_1..H_s
+  std::map<int, int> tab_index;
+  std::vector<float> tables;
+  auto get_tab = [&](int n) {
+    auto it = tab_index.find(n);
+    if (it != tab_index.end()) return it->second;
+    const int o = (int)tables.size();
+    std::vector<double> pw;
+    for (int wv = 0; wv < 2; ++wv)
+      for (int l = 1; l <= levels; ++l) {
+        haar_power(n, l, wv == 1, pw);
+        for (int k = 0; k < n; ++k) tables.push_back((float)pw[k]);
+      }
+    tab_index[n] = o;
+    return o;
+  };
+
+  std::vector<SliceDev> sl(batch);
+  long long off = 0;
+  int colstrip = 0;
+  for (int b = 0; b < batch; ++b) {
+    SliceDev& S = sl[b];
+    std::memset(&S, 0, sizeof(S));
+    S.off = off;
+    S.ny = ny[b];
+    S.nx = nx[b];
+    S.fft_y = get_fft(ny[b]);
+    S.fft_x = get_fft(nx[b]);
+    S.ytab_off = get_tab(ny[b]);
+    S.xtab_off = get_tab(nx[b]);
+    S.colstrip0 = colstrip;
+    P->off[b] = off;
+    off += (long long)ny[b] * nx[b];
+    colstrip += nx[b] / kColW;
+  }
+  P->ntot = off;
+  P->ncolstrips = colstrip;
+
+  // work lists, heaviest items first
+  std::vector<std::pair<long long, int2>> wr, wc, wsu;
+  int maxnx = 0, maxny = 0, maxpad = 1;
+  for (int b = 0; b < batch; ++b) {
+    maxnx = std::max(maxnx, nx[b]);
+    maxny = std::max(maxny, ny[b]);
+    for (int i = 0; i < ny[b] / H; ++i) wr.push_back({(long long)nx[b], make_int2(b, i)});
+    for (int i = 0; i < nx[b] / kColW; ++i) wc.push_back({(long long)ny[b], make_int2(b, i)});
+    for (int band = 0; band < P->nbands; ++band) {
+      int l = band == 0 ? levels : levels - (band - 1) / 3;
+      long long nbsz = (long long)(ny[b] >> l) * (nx[b] >> l);
+      int pad = 1;
+      while (pad < nbsz) pad <<= 1;
+      maxpad = std::max(maxpad, pad);
+      wsu.push_back({(long long)pad, make_int2(b, band)});
+    }
+  }
+  auto sort_items = [](std::vector<std::pair<long long, int2>>& v) {
+    std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    std::vector<int2> out;
+    for (auto& e : v) out.push_back(e.second);
+    return out;
+  };
+  std::vector<int2> vr = sort_items(wr), vc = sort_items(wc), vs = sort_items(wsu);
+  P->nrows = (int)vr.size();
+  P->ncols = (int)vc.size();
+  P->nsure = (int)vs.size();
+  P->lds_rows = sizeof(float2) * (size_t)H * maxnx;
+  P->lds_cols = sizeof(float2) * (size_t)maxny * kColW;
+  P->lds_sure = sizeof(float) * (size_t)maxpad;
+
+  // workspace layout
+  size_t o = 0;
+  const size_t N = (size_t)P->ntot;
+  P->o_wgt = o; o = align256(o + 4 * N);
+  P->o_r = o; o = align256(o + 8 * N);
+  P->o_X = o; o = align256(o + 8 * N);
+  P->o_r2 = o; o = align256(o + 8 * N);
+  P->o_theta = o; o = align256(o + 4 * (size_t)batch * kMaxBands);
+  P->o_thr2 = o; o = align256(o + 4 * (size_t)batch * kMaxBands);
+  P->o_alpha = o; o = align256(o + 4 * (size_t)batch * kMaxBands);
+  P->o_tau = o; o = align256(o + 4 * (size_t)batch * kMaxBands);
+  P->o_taup = o; o = align256(o + 4 * (size_t)colstrip * kMaxBands);
+  P->o_bad = o; o = align256(o + 4);
+  P->ws_bytes = o;
+
+  auto upload = [&](auto*& dst, const auto& vec) -> hipError_t {
+    using T = typename std::decay_t<decltype(vec)>::value_type;
+    hipError_t e = hipMalloc((void**)&dst, sizeof(T) * std::max<size_t>(vec.size(), 1));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(dst, vec.data(), sizeof(T) * vec.size(), hipMemcpyHostToDevice);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(P->d_slices, sl);
+  if (e == hipSuccess) e = upload(P->d_ffts, ffts);
+  if (e == hipSuccess) e = upload(P->d_tw, tw);
+  if (e == hipSuccess) e = upload(P->d_tables, tables);
+  if (e == hipSuccess) e = upload(P->d_work_rows, vr);
+  if (e == hipSuccess) e = upload(P->d_work_cols, vc);
+  if (e == hipSuccess) e = upload(P->d_work_sure, vs);
+  if (e == hipSuccess) e = set_lds_limits(P->lds_rows, P->lds_cols, P->lds_sure);
+  if (e != hipSuccess) {
+    free_plan(P);
+    return fail(VDAMP_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));
+  }
+  *plan = P;
+  *workspace_bytes = P->ws_bytes;
+  return VDAMP_OK;
+}
+
+vdamp_status vdamp_plan_destroy(vdamp_plan_h plan) {
+  g_err.clear();
+  if (!plan) return fail(VDAMP_ERR_ARG, "plan is null");
+  free_plan(plan);
+  return VDAMP_OK;
+}
+
+vdamp_status vdamp_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
+                         size_t workspace_bytes, const float* y, const uint8_t* mask,
+                         const float* p, const float* sigma2, int32_t iters, float* x_hat,
+                         float* trace) {
+  g_err.clear();
+  vdamp_status s = check_common(plan, workspace, workspace_bytes, y, mask, iters, x_hat);
+  if (s != VDAMP_OK) return s;
+  if (!p || !sigma2) return fail(VDAMP_ERR_ARG, "p and sigma2 must be non-null");
+  GraphKey key;
+  key.kind = 0; key.ws = workspace; key.y = y; key.mask = mask; key.p = p; key.sig = sigma2;
+  key.x = x_hat; key.trace = trace; key.iters = iters; key.stream = stream;
+  s = run_maybe_graph(plan, stream, key, [&](bool timing) {
+    return enqueue_vdamp(plan, stream, workspace, reinterpret_cast<const float2*>(y), mask, p,
+                         sigma2, iters, reinterpret_cast<float2*>(x_hat), trace, timing);
+  });
+  if (s != VDAMP_OK) return s;
+  if (plan->flags & VDAMP_FLAG_CHECK_FINITE) {
+    int bad = 0;
+    const Ws w = layout(plan, workspace);
+    HIP_TRY(hipMemcpyAsync(&bad, w.bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (bad) return fail(VDAMP_ERR_NONFINITE, "p outside (0, 1] on the mask or non-finite y");
+  }
+  plan->state_ws = workspace;
+  plan->has_state = iters > 0;
+  return VDAMP_OK;
+}
+
+vdamp_status fista_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
+                         size_t workspace_bytes, const float* y, const uint8_t* mask,
+                         const float* lambda, int32_t iters, float* x_hat) {
+  g_err.clear();
+  vdamp_status s = check_common(plan, workspace, workspace_bytes, y, mask, iters, x_hat);
+  if (s != VDAMP_OK) return s;
+  if (!lambda) return fail(VDAMP_ERR_ARG, "lambda must be non-null");
+  GraphKey key;
+  key.kind = 1; key.ws = workspace; key.y = y; key.mask = mask; key.lam = lambda;
+  key.x = x_hat; key.iters = iters; key.stream = stream;
+  s = run_maybe_graph(plan, stream, key, [&](bool timing) {
+    return enqueue_fista(plan, stream, workspace, reinterpret_cast<const float2*>(y), mask,
+                         lambda, iters, reinterpret_cast<float2*>(x_hat), timing);
+  });
+  if (s != VDAMP_OK) return s;
+  plan->has_state = false;
+  return VDAMP_OK;
+}
+
+vdamp_status vdamp_state_export(vdamp_plan_h plan, hipStream_t stream, const void* workspace,
+                                float* r, float* theta, float* alpha, float* tau) {
+  g_err.clear();
+  if (!plan || !workspace) return fail(VDAMP_ERR_ARG, "plan and workspace must be non-null");
+  if (!plan->has_state || plan->state_ws != workspace)
+    return fail(VDAMP_ERR_STATE, "no vdamp_solve with iters >= 1 on this workspace");
+  const Ws w = layout(plan, const_cast<void*>(workspace));
+  if (r)
+    HIP_TRY(hipMemcpyAsync(r, w.r, sizeof(float2) * (size_t)plan->ntot, hipMemcpyDeviceToDevice, stream));
+  const int nb = plan->nbands;
+  float* outs[3] = {theta, alpha, tau};
+  float* srcs[3] = {w.theta, w.alpha, w.tau};
+  for (int i = 0; i < 3; ++i) {
+    if (!outs[i]) continue;
+    HIP_TRY(hipMemcpy2DAsync(outs[i], sizeof(float) * nb, srcs[i], sizeof(float) * kMaxBands,
+                             sizeof(float) * nb, plan->B, hipMemcpyDeviceToDevice, stream));
+  }
+  return VDAMP_OK;
+}
+
+vdamp_status vdamp_pass_times(vdamp_plan_h plan, double* ms, int64_t* launches, int32_t npass) {
+  g_err.clear();
+  if (!plan || !ms || !launches || npass < 0) return fail(VDAMP_ERR_ARG, "null pointer or npass < 0");
+  for (int i = 0; i < npass; ++i) { ms[i] = 0.0; launches[i] = 0; }
+  for (auto& u : plan->ev_used) {
+    hipEvent_t a = plan->ev_pool[u.second], b = plan->ev_pool[u.second + 1];
+    HIP_TRY(hipEventSynchronize(b));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, a, b));
+    if (u.first < npass) { ms[u.first] += t; launches[u.first] += 1; }
+  }
+  plan->ev_used.clear();
+  plan->ev_next = 0;
+  return VDAMP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal structures shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vdamp {
+
+constexpr int kThreads = 256;      // threads per workgroup for every pass
+constexpr int kEpt = 32;           // max complex elements per thread held by an LDS pass
+constexpr int kMaxElems = kThreads * kEpt;  // complex elements an LDS tile may hold
+constexpr int kMaxBands = 16;      // per-slice band slots (1 + 3 s, s <= 4 uses 13)
+constexpr int kColW = 16;          // columns per column strip (16 complex = 128 B per row)
+constexpr int kMaxRadices = 8;
+constexpr int kMaxN = 512;         // largest ny / nx
+constexpr int kMaxSortKeys = 32768;// largest padded band for the LDS threshold search
+
+struct FftPlanDev {
+  int n;                 // transform length
+  int nst;               // number of Stockham stages
+  int rad[kMaxRadices];  // radix of each stage (2, 3, 4 or 5)
+  int tw_off;            // offset of exp(-2 pi i k / n), k < n, in the twiddle pool
+};
+
+struct SliceDev {
+  long long off;         // pixel offset in packed arrays
+  int ny, nx;
+  int fft_y, fft_x;      // FFT plan index for column (length ny) / row (length nx)
+  int ytab_off;          // 2 s tables of ny floats: L_1..L_s, H_1..H_s (y axis)
+  int xtab_off;          // 2 s tables of nx floats (x axis)
+  int colstrip0;         // index of this slice's first column strip in tau_part
+  int pad;
+};
+
+// Modes of the row-synthesis pass (Psi^H on row strips, then row FFT).
+enum RowSynthMode : int {
+  RS_RTILDE = 0,   // line 8: r_tilde = (eta(r; theta) - alpha r) / (1 - alpha)
+  RS_WHAT = 1,     // eta(r; theta) (line 6, used by line 10)
+  RS_PLAIN = 2     // r as is (FISTA momentum iterate)
+};
+
+// Modes of the column k-space pass.
+enum ColMode : int {
+  CM_VDAMP = 0,        // z = y - X on Omega, v = z / p, tau partials
+  CM_VDAMP_FIRST = 1,  // same with X = 0 (r_tilde_0 = 0)
+  CM_OUTPUT = 2,       // (1 - m) X + m y (line 10)
+  CM_ZEROFILL = 3,     // y (iters = 0)
+  CM_FISTA = 4,        // m (y - X)
+  CM_FISTA_FIRST = 5   // m y
+};
+
+// Modes of the row-analysis pass (row IFFT, then Psi on row strips).
+enum RowAnalMode : int {
+  RA_VDAMP = 0,        // r_k = r_tilde_k + coefficients (r_tilde from r_{k-1})
+  RA_VDAMP_FIRST = 1,  // r_0 = coefficients
+  RA_IMAGE = 2,        // no wavelet: write the image rows (line 10 output)
+  RA_FISTA = 3,        // w = eta(v + g; lambda); v' = w + beta (w - w_prev)
+  RA_FISTA_FIRST = 4
+};
+
+struct KArgs {
+  const SliceDev* slices;
+  const FftPlanDev* ffts;
+  const float2* twiddles;
+  const float* tables;       // tau weight tables
+  const int2* work;          // work items of this launch
+  int nwork;
+  int levels;
+  int nbands;
+  int batch;
+  // data
+  const float2* y;
+  const float* wgt;          // m / p (0 off Omega)
+  const float* sigma2;       // [B]
+  const float* lambda;       // [B] (FISTA)
+  float2* r;                 // wavelet iterate (VDAMP r_k; FISTA v_k)
+  float2* r2;                // FISTA w_{k-1}
+  float2* X;                 // image / k-space scratch
+  float2* out;               // x_hat for image-writing modes
+  float* theta;              // [B][kMaxBands] threshold theta_b
+  float* thr2;               // [B][kMaxBands] its key: the FP32 squared magnitude
+  float* alpha;
+  float* tau;
+  float* tau_part;           // [total column strips][kMaxBands]
+  float* trace;              // nullable [iters][B][nb][3]
+  int iter;
+  float beta;                // FISTA momentum factor for this iteration
+  int mode;
+};
+
+}  // namespace vdamp

@@ -1,0 +1,174 @@
+"""Python binding of libvdamp (ctypes).  Argument marshalling only: every step of the
+solve runs in the library's HIP kernels; torch supplies device memory and streams.
+
+The names follow the C ABI in ``include/vdamp.h``: ``vdamp_plan``, ``vdamp_solve``,
+``fista_solve``, ``vdamp_state_export``, ``vdamp_pass_times``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvdamp.so")
+
+VDAMP_OK = 0
+VDAMP_WAVELET_HAAR = 0
+VDAMP_FLAG_CHECK_FINITE = 1 << 2
+VDAMP_FLAG_USE_GRAPH = 1 << 3
+VDAMP_FLAG_TIMING = 1 << 5
+PASS_NAMES = ("prep", "rows_synth", "cols", "rows_anal", "sure")
+STATUS_NAMES = {0: "VDAMP_OK", 1: "VDAMP_ERR_ARG", 2: "VDAMP_ERR_SHAPE", 3: "VDAMP_ERR_UNSUPPORTED",
+                4: "VDAMP_ERR_WORKSPACE", 5: "VDAMP_ERR_HIP", 6: "VDAMP_ERR_NONFINITE",
+                7: "VDAMP_ERR_STATE"}
+
+EXPORTED = ("vdamp_plan", "vdamp_plan_destroy", "vdamp_solve", "fista_solve",
+            "vdamp_state_export", "vdamp_pass_times", "vdamp_status_string", "vdamp_last_error")
+
+
+class VdampError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {detail}")
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load the in-tree libvdamp.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
+    lib.vdamp_plan.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                               i32, i32, u32, ctypes.POINTER(sz)]
+    lib.vdamp_plan.restype = ctypes.c_int
+    lib.vdamp_plan_destroy.argtypes = [vp]
+    lib.vdamp_plan_destroy.restype = ctypes.c_int
+    lib.vdamp_solve.argtypes = [vp, vp, vp, sz, vp, vp, vp, vp, i32, vp, vp]
+    lib.vdamp_solve.restype = ctypes.c_int
+    lib.fista_solve.argtypes = [vp, vp, vp, sz, vp, vp, vp, i32, vp]
+    lib.fista_solve.restype = ctypes.c_int
+    lib.vdamp_state_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.vdamp_state_export.restype = ctypes.c_int
+    lib.vdamp_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64), i32]
+    lib.vdamp_pass_times.restype = ctypes.c_int
+    lib.vdamp_status_string.argtypes = [ctypes.c_int]
+    lib.vdamp_status_string.restype = ctypes.c_char_p
+    lib.vdamp_last_error.argtypes = []
+    lib.vdamp_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != VDAMP_OK:
+        raise VdampError(status, load_library().vdamp_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Plan:
+    """A batch of slices (ragged sizes allowed) planned once; see ``vdamp_plan``."""
+
+    def __init__(self, ny: Sequence[int], nx: Sequence[int], levels: int, flags: int = 0):
+        lib = load_library()
+        self.ny = [int(v) for v in ny]
+        self.nx = [int(v) for v in nx]
+        if len(self.ny) != len(self.nx):
+            raise ValueError("ny and nx must have the same length")
+        self.batch = len(self.ny)
+        self.levels = int(levels)
+        self.nbands = 1 + 3 * self.levels
+        self.flags = int(flags)
+        self.offsets = np.concatenate([[0], np.cumsum([a * b for a, b in zip(self.ny, self.nx)])])
+        self.ntot = int(self.offsets[-1])
+        a_ny = (ctypes.c_int32 * self.batch)(*self.ny)
+        a_nx = (ctypes.c_int32 * self.batch)(*self.nx)
+        h = ctypes.c_void_p()
+        wsb = ctypes.c_size_t()
+        _check(lib.vdamp_plan(ctypes.byref(h), self.batch, a_ny, a_nx, self.levels,
+                              VDAMP_WAVELET_HAAR, self.flags, ctypes.byref(wsb)))
+        self._h = h
+        self.workspace_bytes = int(wsb.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().vdamp_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, device="cuda"):
+        import torch
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+
+    def vdamp_solve(self, ws, y, mask, p, sigma2, iters, x_hat, trace=None, stream=None):
+        _check(load_library().vdamp_solve(self._h, _stream_handle(stream), _ptr(ws), ws.numel(),
+                                          _ptr(y), _ptr(mask), _ptr(p), _ptr(sigma2), int(iters),
+                                          _ptr(x_hat), _ptr(trace)))
+
+    def fista_solve(self, ws, y, mask, lam, iters, x_hat, stream=None):
+        _check(load_library().fista_solve(self._h, _stream_handle(stream), _ptr(ws), ws.numel(),
+                                          _ptr(y), _ptr(mask), _ptr(lam), int(iters), _ptr(x_hat)))
+
+    def vdamp_state_export(self, ws, r=None, theta=None, alpha=None, tau=None, stream=None):
+        _check(load_library().vdamp_state_export(self._h, _stream_handle(stream), _ptr(ws),
+                                                 _ptr(r), _ptr(theta), _ptr(alpha), _ptr(tau)))
+
+    def vdamp_pass_times(self):
+        n = len(PASS_NAMES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(load_library().vdamp_pass_times(self._h, ms, cnt, n))
+        return {PASS_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+    # ---- marshalling helpers (host numpy <-> packed device tensors)
+    def pack(self, arrays, dtype):
+        """Concatenate per-slice 2D numpy arrays in plan order into one flat array."""
+        out = np.concatenate([np.asarray(a).reshape(-1) for a in arrays]).astype(dtype)
+        if out.size != self.ntot:
+            raise ValueError("arrays do not match the plan's slice sizes")
+        return out
+
+    def unpack(self, flat):
+        """Split a flat per-pixel array into per-slice 2D arrays."""
+        flat = np.asarray(flat)
+        return [flat[self.offsets[b]:self.offsets[b + 1]].reshape(self.ny[b], self.nx[b])
+                for b in range(self.batch)]
+
+
+def to_device(plan: Plan, slices, device="cuda"):
+    """Pack a list of synth.Slice objects into the device tensors vdamp_solve reads."""
+    import torch
+    y = torch.from_numpy(plan.pack([s.y for s in slices], np.complex64)).to(device)
+    mask = torch.from_numpy(plan.pack([s.mask for s in slices], np.uint8)).to(device)
+    p = torch.from_numpy(plan.pack([s.p for s in slices], np.float32)).to(device)
+    sigma2 = torch.tensor([s.sigma2 for s in slices], dtype=torch.float32, device=device)
+    return y, mask, p, sigma2

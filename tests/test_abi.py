@@ -1,0 +1,85 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function that
+include/vdamp.h declares, and rejects bad arguments on the host before any launch."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1911_01234_amd import vdamp as V
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "vdamp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_header_function():
+    lib = V.load_library()
+    names = header_functions()
+    assert "vdamp_solve" in names and "fista_solve" in names and "vdamp_plan" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(V.EXPORTED)
+
+
+def test_status_strings():
+    lib = V.load_library()
+    for code in range(8):
+        assert lib.vdamp_status_string(code)
+    assert lib.vdamp_status_string(99) == b"unknown status"
+
+
+def _plan_status(batch, ny, nx, levels, wavelet=0, flags=0, null=None):
+    lib = V.load_library()
+    h = ctypes.c_void_p()
+    wsb = ctypes.c_size_t()
+    a_ny = (ctypes.c_int32 * max(batch, 1))(*ny) if ny is not None else None
+    a_nx = (ctypes.c_int32 * max(batch, 1))(*nx) if nx is not None else None
+    st = lib.vdamp_plan(None if null == "plan" else ctypes.byref(h), batch, a_ny, a_nx, levels,
+                        wavelet, flags, None if null == "ws" else ctypes.byref(wsb))
+    return st, lib.vdamp_last_error().decode()
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, [64], [64], 3), 1),                 # empty batch
+    ((1, [64], [64], 0), 3),                 # levels < 1
+    ((1, [64], [64], 5), 3),                 # levels beyond this build
+    ((1, [60], [64], 3), 2),                 # not divisible by 2^s
+    ((1, [64], [1024], 3), 2),               # too large
+    ((1, [64], [56], 3), 3),                 # 7 is not a supported radix
+    ((2, [64, 64], [64, 4], 3), 2),          # second slice smaller than 2^s
+    ((1, [64], [64], 3, 1), 3),              # unknown wavelet
+    ((1, [64], [64], 3, 0, 1 << 30), 1),     # unknown flag
+])
+def test_plan_rejects_bad_arguments(args, code):
+    st, msg = _plan_status(*args)
+    assert st == code, msg
+    assert msg
+
+
+def test_plan_null_pointers():
+    assert _plan_status(1, [64], [64], 3, null="plan")[0] == 1
+    assert _plan_status(1, [64], [64], 3, null="ws")[0] == 1
+    assert _plan_status(1, None, [64], 3)[0] == 1
+
+
+def test_solve_rejects_null_plan_and_workspace():
+    lib = V.load_library()
+    st = lib.vdamp_solve(None, None, None, 0, None, None, None, None, 1, None, None)
+    assert st == 1
+    st = lib.fista_solve(None, None, None, 0, None, None, None, 1, None)
+    assert st == 1
+    st = lib.vdamp_state_export(None, None, None, None, None, None, None)
+    assert st == 1
+    assert lib.vdamp_plan_destroy(None) == 1
+
+
+def test_python_binding_refuses_missing_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(V, "_lib", None)
+    monkeypatch.setattr(V, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(ImportError):
+        V.load_library()

@@ -1,0 +1,236 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded
+inputs.  Tolerances: relative L2 <= 1e-5 per iterate (FP32 arithmetic against FP64),
+final NMSE within 0.05 dB, tau to 1e-5 relative, SURE thresholds equal or accepted by
+the near-tie rule (gpu_helpers.theta_accepted).  The measured errors are printed."""
+import numpy as np
+import pytest
+
+from oracle import vdamp_ref as o
+from paper_1911_01234_amd import synth
+
+from gpu_helpers import alpha_at_key, key32, rel_l2, run_fista, run_vdamp, snap_theta, theta_accepted, theta_key
+
+pytestmark = pytest.mark.gpu
+
+TOL_ITER = 1e-5
+TOL_TAU = 1e-5
+TOL_NMSE_DB = 0.05
+
+
+def _bands(sl, s):
+    return o.bands(sl.y.shape[0], sl.y.shape[1], s)
+
+
+def one_step_check(sl, s, k):
+    """Feed the oracle the GPU state after k iterations (r_{k-1}, tau_{k-1}); one oracle
+    step must reproduce the GPU's theta_{k-1}, alpha_{k-1}, r_k and tau_k."""
+    g0 = run_vdamp([sl], s, k, want_state=True)
+    g1 = run_vdamp([sl], s, k + 1, want_state=True)
+    r_prev = g0["r"][0].astype(np.complex128)
+    tau_prev = g0["tau"][0].astype(np.float64)
+    ny, nx = sl.y.shape
+    bl = _bands(sl, s)
+    th_use, al_use = [], []
+    flips = 0
+    for b, (rs, cs, _, _) in enumerate(bl):
+        th_gpu = float(g0["theta"][0][b])
+        assert theta_accepted(r_prev, tau_prev[b], rs, cs, th_gpu), (k, b, th_gpu)
+        a = np.sqrt(key32(r_prev[rs, cs]).astype(np.float64))
+        kth = theta_key(r_prev[rs, cs], th_gpu)
+        flips += np.sqrt(kth) != o.sure_threshold(a, tau_prev[b])[0]
+        # alpha at the GPU's threshold with the kernel's membership |r|^2 <= theta^2
+        al_def = alpha_at_key(r_prev[rs, cs], kth)
+        assert abs(g0["alpha"][0][b] - al_def) <= 1e-5, (k, b)
+        th_use.append(np.sqrt(kth))
+        al_use.append(al_def)
+    # step with the GPU's (accepted) thresholds and their alpha
+    _, rt, _, _ = o.denoise(r_prev, tau_prev, s, theta_override=th_use, alpha_override=al_use)
+    S = o.tau_weights(ny, nx, s)
+    r_k, tau_k = o.vdamp_step(rt, sl.y, sl.mask, sl.p, sl.sigma2, s, S)
+    e_r = rel_l2(g1["r"][0], r_k)
+    e_tau = np.max(np.abs(g1["tau"][0] - tau_k) / np.abs(tau_k))
+    print(f"one-step k={k}: rel L2 r = {e_r:.2e}, max rel tau = {e_tau:.2e}, "
+          f"near-tie threshold flips {flips}")
+    assert e_r <= TOL_ITER
+    assert e_tau <= TOL_TAU
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 15, 29])
+def test_one_step_64(k):
+    sl = synth.workload_single64()[0][0]
+    one_step_check(sl, 3, k)
+
+
+@pytest.mark.parametrize("R,k", [(4.0, 1), (4.0, 10), (6.0, 3), (8.0, 1), (8.0, 25), (8.0, 49)])
+def test_one_step_256(R, k):
+    sl = synth.workload_single256(R)[0][0]
+    one_step_check(sl, 4, k)
+
+
+def test_first_iteration_r0():
+    """k = 0: r_0 = Psi F^H P^-1 y and tau_0 from line 5 with r_tilde_0 = 0."""
+    sl = synth.workload_single256(6.0)[0][0]
+    g = run_vdamp([sl], 4, 1, want_state=True)
+    S = o.tau_weights(256, 256, 4)
+    r0, tau0 = o.vdamp_step(np.zeros_like(sl.y), sl.y, sl.mask, sl.p, sl.sigma2, 4, S)
+    e = rel_l2(g["r"][0], r0)
+    print(f"r_0 rel L2 {e:.2e}; tau_0 max rel {np.max(np.abs(g['tau'][0] - tau0) / tau0):.2e}")
+    assert e <= TOL_ITER
+    assert np.max(np.abs(g["tau"][0] - tau0) / tau0) <= TOL_TAU
+
+
+def free_running(sl, s, K):
+    """Per iterate: the GPU's thresholds must be SURE-optimal (up to near ties) for the
+    GPU's own r_k and tau_k; until the first iteration where the GPU picks a different
+    candidate than the oracle (a near-tie flip, after which the two trajectories are
+    different valid runs), r_k must match to 1e-5 relative L2, alpha to 1e-5 and tau to
+    1e-4 (tau is quadratic in the residual z = y - Phi Psi^H r_tilde, a difference of
+    nearly equal terms, so it amplifies iterate differences).  The final NMSE must match
+    to 0.05 dB in any case."""
+    ref = o.vdamp(sl.y, sl.mask, sl.p, sl.sigma2, s, K, record=True)
+    g = run_vdamp([sl], s, K)
+    tr = g["trace"][:, 0]
+    errs = []
+    first_flip = None
+    for k in range(K):
+        gk = run_vdamp([sl], s, k + 1, want_state=True)
+        rg = gk["r"][0].astype(np.complex128)
+        e = rel_l2(rg, ref["r"][k])
+        errs.append(e)
+        for b, (rs, cs, _, _) in enumerate(_bands(sl, s)):
+            assert theta_accepted(rg, float(gk["tau"][0][b]), rs, cs, tr[k, b, 1]), (k, b)
+            if first_flip is None and snap_theta(ref["r"][k][rs, cs], tr[k, b, 1]) != ref["theta"][k][b]:
+                first_flip = (k, b)
+        if first_flip is None or first_flip[0] > k:
+            assert e <= TOL_ITER, (k, e)
+            assert np.max(np.abs(tr[k, :, 0] - ref["tau"][k]) / ref["tau"][k]) <= 1e-4, k
+            assert np.max(np.abs(tr[k, :, 2] - ref["alpha"][k])) <= 1e-5, k
+    n_gpu = o.nmse_db(g["x_hat"][0], sl.x0)
+    n_ref = o.nmse_db(ref["x_hat"], sl.x0)
+    ex = rel_l2(g["x_hat"][0], ref["x_hat"])
+    upto = K if first_flip is None else first_flip[0] + 1
+    print(f"free-running K={K}: max rel L2 r_k before any flip = {max(errs[:upto]):.2e}; "
+          f"first near-tie flip {first_flip}; x_hat rel L2 = {ex:.2e}; "
+          f"NMSE gpu {n_gpu:.3f} dB, oracle {n_ref:.3f} dB")
+    assert abs(n_gpu - n_ref) <= TOL_NMSE_DB
+    if first_flip is None:
+        assert ex <= TOL_ITER
+
+
+def test_free_running_64():
+    sl, s, K = synth.workload_single64()
+    free_running(sl[0], s, K)
+
+
+@pytest.mark.parametrize("R", [4.0, 6.0, 8.0])
+def test_free_running_256(R):
+    sl, s, K = synth.workload_single256(R)
+    free_running(sl[0], s, K)
+
+
+def test_zero_iterations_is_zero_filled():
+    sl = synth.workload_single64()[0][0]
+    g = run_vdamp([sl], 3, 0)
+    e = rel_l2(g["x_hat"][0], o.ifft2u(sl.y))
+    print(f"K=0 rel L2 {e:.2e}")
+    assert e <= 1e-6
+
+
+def test_ragged_batch_matches_single_slices_bitwise():
+    """Slices of different sizes in one plan give exactly the single-slice results."""
+    sizes = [(64, 64), (128, 128), (96, 160), (192, 192), (320, 320), (256, 256), (64, 192)]
+    sls = [synth.make_slice(7, i, ny, nx, 16, 4.0 + 2 * (i % 3), 6.0, 16, 35.0)
+           for i, (ny, nx) in enumerate(sizes)]
+    K = 6
+    gb = run_vdamp(sls, 4, K)
+    for i, sl in enumerate(sls):
+        gs = run_vdamp([sl], 4, K)
+        assert np.array_equal(gb["x_hat"][i], gs["x_hat"][0]), sizes[i]
+        assert np.array_equal(gb["trace"][:, i], gs["trace"][:, 0]), sizes[i]
+        ref = o.vdamp(sl.y, sl.mask, sl.p, sl.sigma2, 4, K)
+        print(f"{sizes[i]}: x_hat rel L2 vs oracle {rel_l2(gs['x_hat'][0], ref['x_hat']):.2e}")
+        assert abs(o.nmse_db(gs["x_hat"][0], sl.x0) - o.nmse_db(ref["x_hat"], sl.x0)) <= TOL_NMSE_DB
+
+
+def test_graph_replay_matches_eager_bitwise():
+    import torch
+    from paper_1911_01234_amd import vdamp as V
+    sls = [synth.make_slice(8, i, 128, 128, 16, 6.0, 6.0, 16, 40.0) for i in range(3)]
+    eager = run_vdamp(sls, 4, 8)
+    stream = torch.cuda.Stream()
+    plan = V.Plan([128] * 3, [128] * 3, 4, V.VDAMP_FLAG_USE_GRAPH)
+    ws = plan.workspace()
+    y, mask, p, sigma2 = V.to_device(plan, sls)
+    x = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+    for rep in range(3):
+        x.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            plan.vdamp_solve(ws, y, mask, p, sigma2, 8, x, None, stream=stream)
+        stream.synchronize()
+        got = plan.unpack(x.cpu().numpy())
+        for i in range(3):
+            assert np.array_equal(got[i], eager["x_hat"][i]), rep
+
+
+def test_deterministic():
+    sl = synth.workload_single256(8.0)[0][0]
+    a = run_vdamp([sl], 4, 10)
+    b = run_vdamp([sl], 4, 10)
+    assert np.array_equal(a["x_hat"][0], b["x_hat"][0])
+    assert np.array_equal(a["trace"], b["trace"])
+
+
+def test_check_finite_flags_bad_probability_and_nan():
+    import torch
+    from paper_1911_01234_amd import vdamp as V
+    sl = synth.workload_single64()[0][0]
+    plan = V.Plan([64], [64], 3, V.VDAMP_FLAG_CHECK_FINITE)
+    ws = plan.workspace()
+    y, mask, p, sigma2 = V.to_device(plan, [sl])
+    x = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+    plan.vdamp_solve(ws, y, mask, p, sigma2, 2, x)
+    j = int(np.flatnonzero(sl.mask.ravel())[5])
+    p_bad = p.clone()
+    p_bad[j] = 0.0
+    with pytest.raises(V.VdampError) as ei:
+        plan.vdamp_solve(ws, y, mask, p_bad, sigma2, 2, x)
+    assert ei.value.status == 6
+    y_bad = y.clone()
+    y_bad[j] = complex(float("nan"), 0.0)
+    with pytest.raises(V.VdampError):
+        plan.vdamp_solve(ws, y_bad, mask, p, sigma2, 2, x)
+
+
+def test_workspace_too_small_is_rejected():
+    import torch
+    from paper_1911_01234_amd import vdamp as V
+    sl = synth.workload_single64()[0][0]
+    plan = V.Plan([64], [64], 3)
+    ws = torch.empty(plan.workspace_bytes - 256, dtype=torch.uint8, device="cuda")
+    y, mask, p, sigma2 = V.to_device(plan, [sl])
+    x = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+    with pytest.raises(V.VdampError) as ei:
+        plan.vdamp_solve(ws, y, mask, p, sigma2, 2, x)
+    assert ei.value.status == 4
+
+
+@pytest.mark.parametrize("K", [1, 3, 20])
+def test_fista_matches_oracle(K):
+    sls = [synth.workload_single256(R)[0][0] for R in (4.0, 8.0)]
+    lams = []
+    for sl in sls:
+        lam_max = np.abs(o.haar_analysis(o.ifft2u(sl.y), 4)).max()
+        lams.append(float(np.float32(lam_max * 10 ** (-14 / 4))))
+    got = run_fista(sls, 4, lams, K)
+    for sl, lam, g in zip(sls, lams, got):
+        ref = o.fista(sl.y, sl.mask, lam, 4, K)
+        e = rel_l2(g, ref["x_hat"])
+        print(f"FISTA K={K}: rel L2 {e:.2e}")
+        assert e <= TOL_ITER
+
+
+def test_fista_zero_iterations():
+    sl = synth.workload_single64()[0][0]
+    got = run_fista([sl], 3, [0.01], 0)
+    assert np.all(got[0] == 0)
