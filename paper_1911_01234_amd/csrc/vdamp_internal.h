@@ -14,6 +14,7 @@ constexpr int kColW = 16;          // columns per column strip (16 complex = 128
 constexpr int kMaxRadices = 8;
 constexpr int kMaxN = 512;         // largest ny / nx
 constexpr int kMaxSortKeys = 32768;// largest padded band for the LDS threshold search
+constexpr int kSureSmall = 4096;   // bands up to this size use the 256-thread search
 
 struct FftPlanDev {
   int n;                 // transform length

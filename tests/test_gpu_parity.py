@@ -86,7 +86,12 @@ def free_running(sl, s, K):
     different valid runs), r_k must match to 1e-5 relative L2, alpha to 1e-5 and tau to
     1e-4 (tau is quadratic in the residual z = y - Phi Psi^H r_tilde, a difference of
     nearly equal terms, so it amplifies iterate differences).  The final NMSE must match
-    to 0.05 dB in any case."""
+    to 0.05 dB when no flip occurred.  After a flip the two runs are different valid
+    trajectories of an iteration whose final NMSE is itself sensitive to perturbations
+    far below FP32 rounding (a 3e-7 relative change of y moves the FP64 oracle's final
+    NMSE by up to 0.3 dB on the 64x64 case): the GPU's final NMSE must then lie within
+    max(0.05 dB, 4 sigma) of the mean of an ensemble of 16 oracle runs on inputs
+    perturbed at that scale."""
     ref = o.vdamp(sl.y, sl.mask, sl.p, sl.sigma2, s, K, record=True)
     g = run_vdamp([sl], s, K)
     tr = g["trace"][:, 0]
@@ -112,9 +117,23 @@ def free_running(sl, s, K):
     print(f"free-running K={K}: max rel L2 r_k before any flip = {max(errs[:upto]):.2e}; "
           f"first near-tie flip {first_flip}; x_hat rel L2 = {ex:.2e}; "
           f"NMSE gpu {n_gpu:.3f} dB, oracle {n_ref:.3f} dB")
-    assert abs(n_gpu - n_ref) <= TOL_NMSE_DB
     if first_flip is None:
+        assert abs(n_gpu - n_ref) <= TOL_NMSE_DB
         assert ex <= TOL_ITER
+    elif abs(n_gpu - n_ref) > TOL_NMSE_DB:
+        mean, sd = oracle_nmse_envelope(sl, s, K, n_ref)
+        print(f"  oracle envelope under 3e-7 input perturbation: mean {mean:.3f} dB, sd {sd:.3f} dB")
+        assert abs(n_gpu - mean) <= max(TOL_NMSE_DB, 4 * sd)
+
+
+def oracle_nmse_envelope(sl, s, K, n_ref, runs=16, eps=3e-7):
+    rng = np.random.default_rng(2024)
+    vals = [n_ref]
+    for _ in range(runs):
+        pert = (rng.standard_normal(sl.y.shape) + 1j * rng.standard_normal(sl.y.shape)) / np.sqrt(2)
+        yp = sl.y * (1 + eps * pert)
+        vals.append(o.nmse_db(o.vdamp(yp, sl.mask, sl.p, sl.sigma2, s, K)["x_hat"], sl.x0))
+    return float(np.mean(vals)), float(np.std(vals))
 
 
 def test_free_running_64():
@@ -234,3 +253,35 @@ def test_fista_zero_iterations():
     sl = synth.workload_single64()[0][0]
     got = run_fista([sl], 3, [0.01], 0)
     assert np.all(got[0] == 0)
+
+
+def test_one_step_320_big_bands():
+    """320x320: finest bands of 25600 keys (the 1024-thread search)."""
+    sl = synth.make_slice(9, 0, 320, 320, 16, 6.0, 6.0, 16, 35.0)
+    one_step_check(sl, 4, 3)
+
+
+def test_all_zero_measurements():
+    """y = 0: every band is all zeros (one bucket holds every key, so the search takes
+    its full-sort path); theta = alpha = 0 and x_hat = 0."""
+    sl = synth.workload_single64()[0][0]
+    sl.y = np.zeros_like(sl.y)
+    g = run_vdamp([sl], 3, 4)
+    assert np.all(g["x_hat"][0] == 0)
+    assert np.all(g["trace"][:, 0, :, 1] == 0) and np.all(g["trace"][:, 0, :, 2] == 0)
+
+
+def test_noise_free_full_sampling_tau_zero():
+    """p = 1 everywhere and sigma = 0: tau = 0 in every band (bucketing degenerates to a
+    single bucket and the full-sort path runs); the output equals the oracle's F^H y."""
+    sl = synth.workload_single64()[0][0]
+    sl.mask = np.ones_like(sl.mask)
+    sl.p = np.ones_like(sl.p)
+    sl.sigma2 = 0.0
+    sl.y = o.fft2u(sl.x0)
+    g = run_vdamp([sl], 3, 3)
+    assert np.all(g["trace"][:, 0, :, 0] == 0)
+    ref = o.vdamp(sl.y, sl.mask, sl.p, 0.0, 3, 3)
+    e = rel_l2(g["x_hat"][0], ref["x_hat"])
+    print(f"tau = 0 case: x_hat rel L2 {e:.2e}")
+    assert e <= TOL_ITER
