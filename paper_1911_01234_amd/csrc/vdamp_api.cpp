@@ -15,14 +15,15 @@
 #include "vdamp_internal.h"
 
 namespace vdamp {
-hipError_t launch_rows_synth(const KArgs& a, int do_fft, size_t lds, hipStream_t st);
-hipError_t launch_cols(const KArgs& a, size_t lds, hipStream_t st);
-hipError_t launch_rows_anal(const KArgs& a, size_t lds, hipStream_t st);
+hipError_t launch_rows_synth(const KArgs& a, int ept, int do_fft, size_t lds, hipStream_t st);
+hipError_t launch_cols(const KArgs& a, int ept, size_t lds, hipStream_t st);
+hipError_t launch_rows_anal(const KArgs& a, int ept, size_t lds, hipStream_t st);
 hipError_t launch_sure(const KArgs& a, bool big, size_t lds, hipStream_t st);
 hipError_t launch_prep(const uint8_t* mask, const float* p, const float2* y, float* wgt,
                        long long n, int check, int* bad, hipStream_t st);
 hipError_t launch_zero(float2* x, long long n, hipStream_t st);
-hipError_t set_lds_limits(size_t rows, size_t cols, size_t sure_big, size_t sure_small);
+hipError_t set_lds_limits_passes(size_t rows, size_t cols);
+hipError_t set_lds_limits_sure(size_t big, size_t small);
 }  // namespace vdamp
 
 using namespace vdamp;
@@ -105,6 +106,7 @@ struct vdamp_plan_t {
   int2* d_work_cols = nullptr;
   int2* d_work_sure = nullptr;      // big bands first, then small ones
   int nrows = 0, ncols = 0, nsure_big = 0, nsure_small = 0;
+  int ept = 16;                     // complex elements per thread of the LDS passes
   size_t lds_rows = 0, lds_cols = 0, lds_sure_big = 0, lds_sure_small = 0;
   // workspace layout (byte offsets)
   size_t o_wgt = 0, o_r = 0, o_X = 0, o_r2 = 0, o_theta = 0, o_thr2 = 0, o_alpha = 0, o_tau = 0,
@@ -246,12 +248,12 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
     a.iter = k;
     if (k > 0) {
       a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_RTILDE;
-      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, 1, P->lds_rows, st));
+      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
     }
     a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = k ? CM_VDAMP : CM_VDAMP_FIRST;
-    LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->lds_cols, st));
+    LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->ept, P->lds_cols, st));
     a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = k ? RA_VDAMP : RA_VDAMP_FIRST;
-    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->lds_rows, st));
+    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
     if (P->nsure_big) {
       a.work = P->d_work_sure; a.nwork = P->nsure_big;
       LAUNCH(L, VDAMP_PASS_SURE, launch_sure(a, true, P->lds_sure_big, st));
@@ -264,12 +266,12 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
   // line 10: x_hat = F^H [ (1 - m) F Psi^H w + m y ]
   if (iters > 0) {
     a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_WHAT;
-    LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, 1, P->lds_rows, st));
+    LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
   }
   a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = iters > 0 ? CM_OUTPUT : CM_ZEROFILL;
-  LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->lds_cols, st));
+  LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->ept, P->lds_cols, st));
   a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RA_IMAGE;
-  LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->lds_rows, st));
+  LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
   return VDAMP_OK;
 }
 
@@ -291,12 +293,12 @@ vdamp_status enqueue_fista(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
     t = tn;
     if (k > 0) {
       a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_PLAIN;
-      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, 1, P->lds_rows, st));
+      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
     }
     a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = k ? CM_FISTA : CM_FISTA_FIRST;
-    LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->lds_cols, st));
+    LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->ept, P->lds_cols, st));
     a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = k ? RA_FISTA : RA_FISTA_FIRST;
-    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->lds_rows, st));
+    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
   }
   // x_hat = Psi^H w_K (w_K lives in r2); K = 0 gives zeros (a fill kernel, so that a
   // captured graph holds no memset node)
@@ -306,7 +308,7 @@ vdamp_status enqueue_fista(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
   }
   a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_PLAIN;
   a.r = w.r2;
-  LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, 0, P->lds_rows, st));
+  LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 0, P->lds_rows, st));
   return VDAMP_OK;
 }
 
@@ -491,6 +493,7 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   P->ncols = (int)vc.size();
   P->lds_rows = sizeof(float2) * (size_t)H * maxnx;
   P->lds_cols = sizeof(float2) * (size_t)maxny * kColW;
+  P->ept = (H * maxnx <= 16 * kThreads && maxny * kColW <= 16 * kThreads) ? 16 : 32;
   // bucket offsets, then the sorted keys with one pad word per 16 keys
   P->lds_sure_big = sizeof(int) * (4096 + 1) + sizeof(float) * (size_t)(maxpad_big + maxpad_big / 16 + 1);
   P->lds_sure_small = sizeof(int) * (1024 + 1) + sizeof(float) * (size_t)(maxpad_small + maxpad_small / 16 + 1);
@@ -524,7 +527,8 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   if (e == hipSuccess) e = upload(P->d_work_rows, vr);
   if (e == hipSuccess) e = upload(P->d_work_cols, vc);
   if (e == hipSuccess) e = upload(P->d_work_sure, vs);
-  if (e == hipSuccess) e = set_lds_limits(P->lds_rows, P->lds_cols, P->lds_sure_big, P->lds_sure_small);
+  if (e == hipSuccess) e = set_lds_limits_passes(P->lds_rows, P->lds_cols);
+  if (e == hipSuccess) e = set_lds_limits_sure(P->lds_sure_big, P->lds_sure_small);
   if (e != hipSuccess) {
     free_plan(P);
     return fail(VDAMP_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));

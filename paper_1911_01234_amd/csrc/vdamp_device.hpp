@@ -1,0 +1,297 @@
+// Device building blocks shared by the gfx950 kernels: complex helpers, small DFTs,
+// the in-LDS mixed-radix Stockham FFT, the strip-local Haar transforms, the Mallat
+// mapping of a strip, and complex soft thresholding.
+#pragma once
+
+#include "vdamp_internal.h"
+
+namespace vdamp {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 lo2(float4 v) { return make_float2(v.x, v.y); }
+__device__ __forceinline__ float2 hi2(float4 v) { return make_float2(v.z, v.w); }
+__device__ __forceinline__ float4 pack4(float2 a, float2 b) { return make_float4(a.x, a.y, b.x, b.y); }
+// multiply by -i (forward sign) or +i (inverse sign)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// ------------------------------------------------------------------ small DFTs
+template <int R, bool INV> struct Dft;
+
+template <bool INV> struct Dft<2, INV> {
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <bool INV> struct Dft<4, INV> {
+  static __device__ __forceinline__ void run(float2* v) {
+    float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    float2 t2 = cadd(v[1], v[3]), t3 = mul_mi<INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+template <bool INV> struct Dft<3, INV> {
+  static __device__ __forceinline__ void run(float2* v) {
+    const float c = -0.5f, s3 = 0.86602540378443864676f;
+    float2 sum = cadd(v[1], v[2]);
+    float2 dif = cscale(mul_mi<INV>(csub(v[1], v[2])), s3);
+    float2 base = make_float2(v[0].x + c * sum.x, v[0].y + c * sum.y);
+    v[0] = cadd(v[0], sum);
+    v[1] = cadd(base, dif);
+    v[2] = csub(base, dif);
+  }
+};
+
+template <bool INV> struct Dft<5, INV> {
+  static __device__ __forceinline__ void run(float2* v) {
+    const float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
+    const float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
+    const float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
+    const float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
+    float2 b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
+    float2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+    float2 a0 = v[0];
+    float2 e1 = make_float2(a0.x + c1 * b1.x + c2 * b2.x, a0.y + c1 * b1.y + c2 * b2.y);
+    float2 e2 = make_float2(a0.x + c2 * b1.x + c1 * b2.x, a0.y + c2 * b1.y + c1 * b2.y);
+    float2 f1 = mul_mi<INV>(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
+    float2 f2 = mul_mi<INV>(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+    v[0] = make_float2(a0.x + b1.x + b2.x, a0.y + b1.y + b2.y);
+    v[1] = cadd(e1, f1);
+    v[4] = csub(e1, f1);
+    v[2] = cadd(e2, f2);
+    v[3] = csub(e2, f2);
+  }
+};
+
+// ------------------------------------------------------------------ LDS Stockham FFT
+// Lines of length n live in LDS at buf[line * ls + i * es]; tw holds exp(-2 pi i k/n),
+// k < n (in LDS).  One stage gathers R inputs per butterfly into registers, waits for
+// the workgroup, applies twiddles and the radix-R DFT and scatters to the Stockham
+// output positions (in place: every read of the stage precedes every write).  COLS
+// selects the thread mapping: consecutive threads take consecutive lines (the columns
+// of a column strip) or consecutive butterflies of one line (rows), so LDS accesses
+// stay unit-stride.  EPT bounds the elements per thread (n * nlines <= 256 * EPT).
+template <int R, bool INV, bool COLS, int EPT>
+__device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int n, int Ns, int nlines,
+                                          int ls, int es, const float2* __restrict__ tw) {
+  constexpr int MAXB = (EPT + R - 1) / R;
+  const int nb = n / R;
+  const int total = nb * nlines;
+  float2 v[MAXB][R];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int t = threadIdx.x + q * kThreads;
+    if (t < total) {
+      int line, j;
+      if (COLS) { line = t % nlines; j = t / nlines; }
+      else { line = t / nb; j = t - line * nb; }
+      const float2* src = buf + line * ls;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[(j + r * nb) * es];
+    }
+  }
+  __syncthreads();
+  const int twstride = n / (Ns * R);
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int t = threadIdx.x + q * kThreads;
+    if (t < total) {
+      int line, j;
+      if (COLS) { line = t % nlines; j = t / nlines; }
+      else { line = t / nb; j = t - line * nb; }
+      const int k = j % Ns;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = tw[r * k * twstride];
+        if (INV) w.y = -w.y;
+        v[q][r] = cmul(v[q][r], w);
+      }
+      Dft<R, INV>::run(v[q]);
+      const int idx = (j / Ns) * Ns * R + k;
+      float2* dst = buf + line * ls;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[(idx + r * Ns) * es] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <bool INV, bool COLS, int EPT>
+__device__ void fft_lines(float2* buf, const FftPlanDev& P, int nlines, int ls, int es,
+                          const float2* __restrict__ tw) {
+  int Ns = 1;
+  for (int st = 0; st < P.nst; ++st) {
+    const int R = P.rad[st];
+    switch (R) {
+      case 4: fft_stage<4, INV, COLS, EPT>(buf, P.n, Ns, nlines, ls, es, tw); break;
+      case 2: fft_stage<2, INV, COLS, EPT>(buf, P.n, Ns, nlines, ls, es, tw); break;
+      case 3: fft_stage<3, INV, COLS, EPT>(buf, P.n, Ns, nlines, ls, es, tw); break;
+      default: fft_stage<5, INV, COLS, EPT>(buf, P.n, Ns, nlines, ls, es, tw); break;
+    }
+    Ns *= R;
+  }
+}
+
+// Copy a plan's twiddle table into LDS (issued alongside the tile loads).
+__device__ __forceinline__ void load_twiddles(float2* tw_s, const FftPlanDev& P,
+                                              const float2* __restrict__ pool) {
+  for (int i = threadIdx.x; i < P.n; i += kThreads) tw_s[i] = pool[P.tw_off + i];
+}
+
+// ------------------------------------------------------------------ Haar on a strip
+// The strip holds H = 2^s image rows x nx columns.  Its coefficients form the Mallat
+// layout of an H x nx image with s levels ("mini-Mallat"); one 2x2 orthonormal Haar
+// butterfly per coefficient quadruple (LL, LH, HL, HH):
+//   x00 = (a + b + c + d)/2, x01 = (a - b + c - d)/2,
+//   x10 = (a + b - c - d)/2, x11 = (a - b - c + d)/2,
+// with a = LL, b = LH (low y, high x), c = HL (high y, low x), d = HH.
+template <int EPT>
+__device__ void haar_strip_synth(float2* buf, int H, int nx, int s) {
+  constexpr int MAXQ = EPT / 4;
+  for (int l = s; l >= 1; --l) {
+    const int hp = H >> l, w = nx >> l;
+    const int nblk = hp * w;
+    float2 o[MAXQ][4];
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+      const int t = threadIdx.x + q * kThreads;
+      if (t < nblk) {
+        const int i = t / w, j = t - (t / w) * w;
+        const float2 a = buf[i * nx + j], b = buf[i * nx + w + j];
+        const float2 c = buf[(hp + i) * nx + j], d = buf[(hp + i) * nx + w + j];
+        const float2 apc = cadd(a, c), amc = csub(a, c), bpd = cadd(b, d), bmd = csub(b, d);
+        o[q][0] = cscale(cadd(apc, bpd), 0.5f);
+        o[q][1] = cscale(csub(apc, bpd), 0.5f);
+        o[q][2] = cscale(cadd(amc, bmd), 0.5f);
+        o[q][3] = cscale(csub(amc, bmd), 0.5f);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+      const int t = threadIdx.x + q * kThreads;
+      if (t < nblk) {
+        const int i = t / w, j = t - (t / w) * w;
+        float4* row0 = reinterpret_cast<float4*>(buf + (2 * i) * nx + 2 * j);
+        float4* row1 = reinterpret_cast<float4*>(buf + (2 * i + 1) * nx + 2 * j);
+        *row0 = pack4(o[q][0], o[q][1]);
+        *row1 = pack4(o[q][2], o[q][3]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int EPT>
+__device__ void haar_strip_anal(float2* buf, int H, int nx, int s) {
+  constexpr int MAXQ = EPT / 4;
+  for (int l = 1; l <= s; ++l) {
+    const int hp = H >> l, w = nx >> l;
+    const int nblk = hp * w;
+    float2 o[MAXQ][4];
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+      const int t = threadIdx.x + q * kThreads;
+      if (t < nblk) {
+        const int i = t / w, j = t - (t / w) * w;
+        const float4 r0 = *reinterpret_cast<const float4*>(buf + (2 * i) * nx + 2 * j);
+        const float4 r1 = *reinterpret_cast<const float4*>(buf + (2 * i + 1) * nx + 2 * j);
+        const float2 x00 = lo2(r0), x01 = hi2(r0), x10 = lo2(r1), x11 = hi2(r1);
+        const float2 s0 = cadd(x00, x01), d0 = csub(x00, x01), s1 = cadd(x10, x11), d1 = csub(x10, x11);
+        o[q][0] = cscale(cadd(s0, s1), 0.5f);  // LL
+        o[q][1] = cscale(cadd(d0, d1), 0.5f);  // LH: low along y, high along x
+        o[q][2] = cscale(csub(s0, s1), 0.5f);  // HL: high along y, low along x
+        o[q][3] = cscale(csub(d0, d1), 0.5f);  // HH
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXQ; ++q) {
+      const int t = threadIdx.x + q * kThreads;
+      if (t < nblk) {
+        const int i = t / w, j = t - (t / w) * w;
+        buf[i * nx + j] = o[q][0];
+        buf[i * nx + w + j] = o[q][1];
+        buf[(hp + i) * nx + j] = o[q][2];
+        buf[(hp + i) * nx + w + j] = o[q][3];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Position (lr, lc) of a strip's mini-Mallat image -> global Mallat row and band.
+// The column is the same in both layouts.  Band boundaries along x sit at multiples
+// of nx >> s (even), so an even-aligned pair (lc, lc + 1) shares row and band.
+__device__ __forceinline__ int strip_to_global(int lr, int lc, int strip, int s, int ny, int nx,
+                                               int& band) {
+  const int H = 1 << s;
+#pragma unroll 1
+  for (int l = 1; l <= s; ++l) {
+    const bool hy = lr >= (H >> l);
+    const bool hx = lc >= (nx >> l);
+    if (hy || hx) {
+      const int hp = H >> l;
+      band = 1 + 3 * (s - l) + (hy ? (hx ? 2 : 1) : 0);
+      return (hy ? (ny >> l) : 0) + strip * hp + (lr - (hy ? hp : 0));
+    }
+  }
+  band = 0;
+  return strip;
+}
+
+// |r|^2 with each multiply and the add rounded to nearest (no contraction): the key on
+// which the threshold search sorts and decides, and on which thresholding tests
+// membership, so both see bit-identical values (as does any host computing
+// x*x + y*y in IEEE FP32).
+__device__ __forceinline__ float key_rn(float2 v) {
+  return __fadd_rn(__fmul_rn(v.x, v.x), __fmul_rn(v.y, v.y));
+}
+
+// eta(r; theta) = r max(0, 1 - theta/|r|); zero when |r|^2 <= theta^2 (th2 is the
+// threshold's own key, so the element that defines theta is zeroed).
+__device__ __forceinline__ float2 soft_c(float2 v, float th, float th2) {
+  const float key = key_rn(v);
+  if (!(key > th2)) return make_float2(0.f, 0.f);
+  const float g = 1.0f - th / sqrtf(key);
+  return make_float2(v.x * g, v.y * g);
+}
+
+// line 8: r_tilde = (eta(r) - alpha r) / (1 - alpha)
+__device__ __forceinline__ float2 rtilde_c(float2 v, float th, float th2, float al) {
+  const float2 w = soft_c(v, th, th2);
+  const float inv = 1.0f / (1.0f - al);
+  return make_float2((w.x - al * v.x) * inv, (w.y - al * v.y) * inv);
+}
+
+// Band geometry in the global Mallat layout.
+__device__ __forceinline__ void band_geom(int b, int s, int ny, int nx, int& r0, int& c0,
+                                          int& bh, int& bw) {
+  if (b == 0) { r0 = 0; c0 = 0; bh = ny >> s; bw = nx >> s; return; }
+  const int l = s - (b - 1) / 3, kind = (b - 1) % 3;
+  bh = ny >> l; bw = nx >> l;
+  r0 = (kind == 0) ? 0 : bh;
+  c0 = (kind == 1) ? 0 : bw;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace vdamp

@@ -1,0 +1,362 @@
+// gfx950 kernels of the three transform passes of one iteration (Algorithm 1):
+//   rows_synth  (row strip of 2^s image rows): line 8 applied to r_{k-1}, Psi^H on the
+//               strip (Haar never couples strips of 2^s rows), then the row FFTs.
+//   cols        (column strip of 16 columns): column FFT, k-space residual of line 3,
+//               density compensation P^-1 of line 4, the tau partial sums of line 5
+//               (S is separable per band for Haar), column IFFT.
+//   rows_anal   (row strip): row IFFTs, Psi on the strip, add r_tilde_k (line 4).
+// One workgroup of 256 threads per work item; every tile is staged in LDS and moved
+// with 16-byte accesses (two complex values), all of a thread's loads issued before
+// the first use.  EPT (8 B elements per thread) is 16 when every tile of the plan
+// holds at most 4096 complex values, else 32.
+#include "vdamp_device.hpp"
+
+namespace vdamp {
+
+// ------------------------------------------------------------------ rows_synth
+// do_fft = 0 writes the image rows Psi^H r (the FISTA output).
+template <int EPT>
+__global__ void __launch_bounds__(kThreads) k_rows_synth(KArgs a, int do_fft) {
+  extern __shared__ float4 lds4[];
+  float2* lds = reinterpret_cast<float2*>(lds4);
+  __shared__ float2 tw_s[kMaxN];
+  __shared__ float th_s[kMaxBands], t2_s[kMaxBands], al_s[kMaxBands];
+  const int2 item = a.work[blockIdx.x];
+  const SliceDev S = a.slices[item.x];
+  const int strip = item.y, s = a.levels, H = 1 << s, nx = S.nx, ny = S.ny;
+  const int tid = threadIdx.x, mode = a.mode;
+  if (tid < kMaxBands) {
+    th_s[tid] = a.theta[item.x * kMaxBands + tid];
+    t2_s[tid] = a.thr2[item.x * kMaxBands + tid];
+    al_s[tid] = a.alpha[item.x * kMaxBands + tid];
+  }
+  const FftPlanDev& P = a.ffts[S.fft_x];
+  if (do_fft) load_twiddles(tw_s, P, a.twiddles);
+  constexpr int U = EPT / 2;
+  const int half = nx >> 1, npairs = H * half;
+  const float2* r = a.r + S.off;
+  float4 v[U];
+  int bnd[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    bnd[u] = 0;
+    if (p < npairs) {
+      const int lr = p / half, lc = 2 * (p - lr * half);
+      int b;
+      const int gr = strip_to_global(lr, lc, strip, s, ny, nx, b);
+      bnd[u] = b;
+      v[u] = *reinterpret_cast<const float4*>(r + (long long)gr * nx + lc);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    if (p < npairs) {
+      const int b = bnd[u];
+      float2 x0 = lo2(v[u]), x1 = hi2(v[u]);
+      if (mode == RS_RTILDE) {
+        x0 = rtilde_c(x0, th_s[b], t2_s[b], al_s[b]);
+        x1 = rtilde_c(x1, th_s[b], t2_s[b], al_s[b]);
+      } else if (mode == RS_WHAT) {
+        x0 = soft_c(x0, th_s[b], t2_s[b]);
+        x1 = soft_c(x1, th_s[b], t2_s[b]);
+      }
+      lds4[p] = pack4(x0, x1);  // LDS index lr * nx + lc = 2 p
+    }
+  }
+  __syncthreads();
+  haar_strip_synth<EPT>(lds, H, nx, s);
+  if (do_fft) fft_lines<false, false, EPT>(lds, P, H, nx, 1, tw_s);
+  float4* dst = reinterpret_cast<float4*>((do_fft ? a.X : a.out) + S.off + (long long)strip * H * nx);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    if (p < npairs) dst[p] = lds4[p];
+  }
+}
+
+// ------------------------------------------------------------------ cols
+template <int EPT>
+__global__ void __launch_bounds__(kThreads) k_cols(KArgs a) {
+  extern __shared__ float4 lds4[];
+  float2* lds = reinterpret_cast<float2*>(lds4);
+  __shared__ float2 tw_s[kMaxN];
+  __shared__ float ytab_s[8 * kMaxN];
+  __shared__ float red[kThreads / 64][kMaxBands];
+  const int2 item = a.work[blockIdx.x];
+  const int sl = item.x;
+  const SliceDev S = a.slices[sl];
+  const int ny = S.ny, nx = S.nx, c0 = item.y * kColW, s = a.levels;
+  const int tid = threadIdx.x, mode = a.mode;
+  const bool first = (mode == CM_VDAMP_FIRST || mode == CM_ZEROFILL || mode == CM_FISTA_FIRST);
+  const bool vd = (mode == CM_VDAMP || mode == CM_VDAMP_FIRST);
+  const FftPlanDev& P = a.ffts[S.fft_y];
+  load_twiddles(tw_s, P, a.twiddles);
+  const int ntab = 2 * s;
+  if (vd)
+    for (int i = tid; i < ntab * ny; i += kThreads) ytab_s[i] = a.tables[S.ytab_off + i];
+  constexpr int U = EPT / 2;
+  constexpr int PPR = kColW / 2;  // column pairs per row
+  const int npairs = ny * PPR;
+  const long long base = S.off + c0;
+  if (!first) {
+    float4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tid + u * kThreads;
+      v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (p < npairs) {
+        const int row = p / PPR, cp = p % PPR;
+        v[u] = *reinterpret_cast<const float4*>(a.X + base + (long long)row * nx + 2 * cp);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tid + u * kThreads;
+      if (p < npairs) lds4[p] = v[u];  // LDS index row * 16 + 2 cp = 2 p
+    }
+  }
+  // measurements and weights of this thread's pairs (its column pair is fixed)
+  const int cp = tid % PPR;
+  float4 yv[U];
+  float2 wv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    yv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    wv[u] = make_float2(0.f, 0.f);
+    if (p < npairs) {
+      const long long g = base + (long long)(p / PPR) * nx + 2 * cp;
+      yv[u] = *reinterpret_cast<const float4*>(a.y + g);
+      wv[u] = *reinterpret_cast<const float2*>(a.wgt + g);
+    }
+  }
+  __syncthreads();
+  if (!first) fft_lines<false, true, EPT>(lds, P, kColW, 1, kColW, tw_s);
+  const float isq = rsqrtf((float)ny * (float)nx);  // unitary scaling, once per direction
+  const float sig2 = a.sigma2 ? a.sigma2[sl] : 0.f;
+  float Q0[8], Q1[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) { Q0[t] = 0.f; Q1[t] = 0.f; }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    if (p < npairs) {
+      const int row = p / PPR;
+      const float4 xr = first ? make_float4(0.f, 0.f, 0.f, 0.f) : lds4[p];
+      float2 out[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float2 X = cscale(h ? hi2(xr) : lo2(xr), isq);
+        const float2 yy = h ? hi2(yv[u]) : lo2(yv[u]);
+        const float w = h ? wv[u].y : wv[u].x;
+        float2 o;
+        if (vd) {
+          o = make_float2(0.f, 0.f);
+          if (w > 0.f) {
+            const float2 z = csub(yy, X);
+            o = cscale(z, w);
+            const float cc = w * ((w - 1.0f) * (z.x * z.x + z.y * z.y) + sig2);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+              if (t < ntab) {
+                if (h) Q1[t] = fmaf(ytab_s[t * ny + row], cc, Q1[t]);
+                else Q0[t] = fmaf(ytab_s[t * ny + row], cc, Q0[t]);
+              }
+          }
+        } else if (mode == CM_OUTPUT) {
+          o = (w > 0.f) ? yy : X;
+        } else if (mode == CM_ZEROFILL) {
+          o = yy;
+        } else {  // FISTA: m (y - X)
+          o = (w > 0.f) ? csub(yy, X) : make_float2(0.f, 0.f);
+        }
+        out[h] = cscale(o, isq);
+      }
+      lds4[p] = pack4(out[0], out[1]);
+    }
+  }
+  if (vd) {
+    // tau_b partial = sum over this strip's columns of Xtab_b(kx) sum_ky Ytab_b(ky) c
+    const float* xtab = a.tables + S.xtab_off;
+    const int kx = c0 + 2 * cp;
+    const int lane = tid & 63, wid = tid >> 6;
+    for (int b = 0; b < a.nbands; ++b) {
+      int ty, tx;
+      if (b == 0) { ty = s - 1; tx = s - 1; }
+      else {
+        const int l = s - (b - 1) / 3, kind = (b - 1) % 3;
+        const int L = l - 1, Hh = s + l - 1;
+        ty = (kind == 0) ? L : Hh;
+        tx = (kind == 1) ? L : Hh;
+      }
+      float q0 = 0.f, q1 = 0.f;
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (t == ty) { q0 = Q0[t]; q1 = Q1[t]; }
+      const float part = wave_sum(q0 * xtab[tx * nx + kx] + q1 * xtab[tx * nx + kx + 1]);
+      if (lane == 0) red[wid][b] = part;
+    }
+  }
+  __syncthreads();
+  if (vd && tid < a.nbands) {
+    float acc = 0.f;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) acc += red[w][tid];
+    a.tau_part[(S.colstrip0 + item.y) * kMaxBands + tid] = acc;
+  }
+  fft_lines<true, true, EPT>(lds, P, kColW, 1, kColW, tw_s);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    if (p < npairs)
+      *reinterpret_cast<float4*>(a.X + base + (long long)(p / PPR) * nx + 2 * (p % PPR)) = lds4[p];
+  }
+}
+
+// ------------------------------------------------------------------ rows_anal
+template <int EPT>
+__global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
+  extern __shared__ float4 lds4[];
+  float2* lds = reinterpret_cast<float2*>(lds4);
+  __shared__ float2 tw_s[kMaxN];
+  __shared__ float th_s[kMaxBands], t2_s[kMaxBands], al_s[kMaxBands];
+  const int2 item = a.work[blockIdx.x];
+  const SliceDev S = a.slices[item.x];
+  const int strip = item.y, s = a.levels, H = 1 << s, nx = S.nx, ny = S.ny;
+  const int tid = threadIdx.x, mode = a.mode;
+  constexpr int U = EPT / 2;
+  const int half = nx >> 1, npairs = H * half;
+  const float4* src = reinterpret_cast<const float4*>(a.X + S.off + (long long)strip * H * nx);
+  float4 v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (p < npairs) v[u] = src[p];
+  }
+  if (tid < kMaxBands) {
+    th_s[tid] = a.theta[item.x * kMaxBands + tid];
+    t2_s[tid] = a.thr2[item.x * kMaxBands + tid];
+    al_s[tid] = a.alpha[item.x * kMaxBands + tid];
+  }
+  const FftPlanDev& P = a.ffts[S.fft_x];
+  load_twiddles(tw_s, P, a.twiddles);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    if (p < npairs) lds4[p] = v[u];
+  }
+  __syncthreads();
+  fft_lines<true, false, EPT>(lds, P, H, nx, 1, tw_s);
+  if (mode == RA_IMAGE) {
+    float4* dst = reinterpret_cast<float4*>(a.out + S.off + (long long)strip * H * nx);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tid + u * kThreads;
+      if (p < npairs) dst[p] = lds4[p];
+    }
+    return;
+  }
+  haar_strip_anal<EPT>(lds, H, nx, s);
+  float2* r = a.r + S.off;
+  float2* r2 = a.r2 ? a.r2 + S.off : nullptr;
+  const float lam = a.lambda ? a.lambda[item.x] : 0.f;
+  const float lam2 = __fmul_rn(lam, lam);
+  const bool need_r = (mode == RA_VDAMP || mode == RA_FISTA);
+  long long gi[U];
+  int bnd[U];
+  float4 ro[U], rw[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    bnd[u] = 0;
+    gi[u] = 0;
+    ro[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    rw[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (p < npairs) {
+      const int lr = p / half, lc = 2 * (p - lr * half);
+      int b;
+      const int gr = strip_to_global(lr, lc, strip, s, ny, nx, b);
+      bnd[u] = b;
+      gi[u] = (long long)gr * nx + lc;
+      if (need_r) ro[u] = *reinterpret_cast<const float4*>(r + gi[u]);
+      if (mode == RA_FISTA) rw[u] = *reinterpret_cast<const float4*>(r2 + gi[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    if (p < npairs) {
+      const int b = bnd[u];
+      const float4 gv = lds4[p];
+      float2 o[2], w2[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float2 g = h ? hi2(gv) : lo2(gv);
+        switch (mode) {
+          case RA_VDAMP_FIRST: o[h] = g; break;
+          case RA_VDAMP: {
+            const float2 x = h ? hi2(ro[u]) : lo2(ro[u]);
+            o[h] = cadd(rtilde_c(x, th_s[b], t2_s[b], al_s[b]), g);
+          } break;
+          case RA_FISTA_FIRST: {
+            w2[h] = soft_c(g, lam, lam2);
+            o[h] = w2[h];
+          } break;
+          default: {  // RA_FISTA: w = eta(v + g); v' = w + beta (w - w_prev)
+            const float2 x = h ? hi2(ro[u]) : lo2(ro[u]);
+            const float2 wp = h ? hi2(rw[u]) : lo2(rw[u]);
+            w2[h] = soft_c(cadd(x, g), lam, lam2);
+            o[h] = make_float2(w2[h].x + a.beta * (w2[h].x - wp.x), w2[h].y + a.beta * (w2[h].y - wp.y));
+          } break;
+        }
+      }
+      *reinterpret_cast<float4*>(r + gi[u]) = pack4(o[0], o[1]);
+      if (mode == RA_FISTA || mode == RA_FISTA_FIRST)
+        *reinterpret_cast<float4*>(r2 + gi[u]) = pack4(w2[0], w2[1]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_rows_synth(const KArgs& a, int ept, int do_fft, size_t lds, hipStream_t st) {
+  if (ept == 16)
+    hipLaunchKernelGGL(k_rows_synth<16>, dim3(a.nwork), dim3(kThreads), lds, st, a, do_fft);
+  else
+    hipLaunchKernelGGL(k_rows_synth<32>, dim3(a.nwork), dim3(kThreads), lds, st, a, do_fft);
+  return hipGetLastError();
+}
+hipError_t launch_cols(const KArgs& a, int ept, size_t lds, hipStream_t st) {
+  if (ept == 16)
+    hipLaunchKernelGGL(k_cols<16>, dim3(a.nwork), dim3(kThreads), lds, st, a);
+  else
+    hipLaunchKernelGGL(k_cols<32>, dim3(a.nwork), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+hipError_t launch_rows_anal(const KArgs& a, int ept, size_t lds, hipStream_t st) {
+  if (ept == 16)
+    hipLaunchKernelGGL(k_rows_anal<16>, dim3(a.nwork), dim3(kThreads), lds, st, a);
+  else
+    hipLaunchKernelGGL(k_rows_anal<32>, dim3(a.nwork), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t set_lds_limits_passes(size_t rows, size_t cols) {
+  const void* rk[] = {(const void*)k_rows_synth<16>, (const void*)k_rows_synth<32>,
+                      (const void*)k_rows_anal<16>, (const void*)k_rows_anal<32>};
+  for (const void* f : rk) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rows);
+    if (e != hipSuccess) return e;
+  }
+  const void* ck[] = {(const void*)k_cols<16>, (const void*)k_cols<32>};
+  for (const void* f : ck) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cols);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace vdamp

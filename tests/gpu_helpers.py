@@ -86,26 +86,50 @@ def snap_theta(r_band, theta_gpu):
     return float(a[i])
 
 
-def theta_key(r_band, theta_gpu):
-    """The key (FP32 squared magnitude) of the element the GPU's theta stands for."""
-    k = np.unique(key32(r_band).astype(np.float64).ravel())
+def theta_keys(r_band, theta_gpu):
+    """Keys (FP32 squared magnitudes) the GPU's theta may stand for.  The kernel decides
+    on keys and reports theta = sqrt(key) in FP32, which its sqrt can leave one ulp off
+    the correctly rounded value, so the candidates are the keys whose FP32 square root
+    is within one ulp of theta (two keys one ulp apart can both qualify); the nearest
+    key if none does."""
+    k = np.unique(key32(r_band).ravel())
     if float(theta_gpu) == 0.0:
-        return 0.0
-    return float(k[int(np.argmin(np.abs(np.sqrt(k) - float(theta_gpu))))])
+        return [0.0]
+    t = np.float32(theta_gpu)
+    lo = np.nextafter(t, np.float32(0))
+    hi = np.nextafter(t, np.float32(np.inf))
+    sq = np.sqrt(k)
+    hit = k[(sq >= lo) & (sq <= hi)]
+    if hit.size:
+        return [float(v) for v in hit]
+    k64 = k.astype(np.float64)
+    return [float(k64[int(np.argmin(np.abs(np.sqrt(k64) - float(theta_gpu))))])]
 
 
-def theta_accepted(r, tau_b, rs, cs, theta_gpu):
+def theta_key(r_band, theta_gpu):
+    return theta_keys(r_band, theta_gpu)[0]
+
+
+def theta_accepted(r, tau_b, rs, cs, theta_gpu, alpha_gpu=None, return_key=False):
     """The SURE argmin is an index decided in floating point, so the oracle takes it on
     the kernel's FP32 keys of the same r (magnitudes sqrt(key32) in FP64): the GPU's
     threshold is accepted when it is the oracle's choice or, for a near tie, when its
-    FP64 SURE value is within 1e-6 (|SURE_min| + N_b tau) of the oracle's minimum."""
-    a = np.sqrt(key32(np.asarray(r)[rs, cs]).astype(np.float64)).ravel()
+    FP64 SURE value is within 1e-6 (|SURE_min| + N_b tau) of the oracle's minimum.
+    Among keys theta may stand for, the one whose alpha (line 7) matches the GPU's
+    alpha is the GPU's choice."""
+    band = np.asarray(r)[rs, cs]
+    a = np.sqrt(key32(band).astype(np.float64)).ravel()
     th_ref, _, _, s_ref = o.sure_threshold(a, float(tau_b))
-    th = float(np.sqrt(theta_key(np.asarray(r)[rs, cs], theta_gpu)))
-    if th == th_ref:
-        return True
-    s_gpu = o.sure_value(a, th, float(tau_b))
-    return s_gpu <= s_ref + 1e-6 * (abs(s_ref) + a.size * tau_b)
+    cands = theta_keys(band, theta_gpu)
+    if alpha_gpu is not None and len(cands) > 1:
+        cands.sort(key=lambda kth: abs(alpha_at_key(band, kth) - float(alpha_gpu)))
+    ok_key = None
+    for kth in cands:
+        th = float(np.sqrt(kth))
+        if th == th_ref or o.sure_value(a, th, float(tau_b)) <= s_ref + 1e-6 * (abs(s_ref) + a.size * tau_b):
+            ok_key = kth
+            break
+    return (ok_key is not None, ok_key) if return_key else ok_key is not None
 
 
 def alpha_at_key(r_band, kth):

@@ -34,9 +34,10 @@ def one_step_check(sl, s, k):
     flips = 0
     for b, (rs, cs, _, _) in enumerate(bl):
         th_gpu = float(g0["theta"][0][b])
-        assert theta_accepted(r_prev, tau_prev[b], rs, cs, th_gpu), (k, b, th_gpu)
+        ok, kth = theta_accepted(r_prev, tau_prev[b], rs, cs, th_gpu, alpha_gpu=g0["alpha"][0][b],
+                                 return_key=True)
+        assert ok, (k, b, th_gpu)
         a = np.sqrt(key32(r_prev[rs, cs]).astype(np.float64))
-        kth = theta_key(r_prev[rs, cs], th_gpu)
         flips += np.sqrt(kth) != o.sure_threshold(a, tau_prev[b])[0]
         # alpha at the GPU's threshold with the kernel's membership |r|^2 <= theta^2
         al_def = alpha_at_key(r_prev[rs, cs], kth)
@@ -103,7 +104,8 @@ def free_running(sl, s, K):
         e = rel_l2(rg, ref["r"][k])
         errs.append(e)
         for b, (rs, cs, _, _) in enumerate(_bands(sl, s)):
-            assert theta_accepted(rg, float(gk["tau"][0][b]), rs, cs, tr[k, b, 1]), (k, b)
+            assert theta_accepted(rg, float(gk["tau"][0][b]), rs, cs, tr[k, b, 1],
+                                  alpha_gpu=tr[k, b, 2]), (k, b)
             if first_flip is None and snap_theta(ref["r"][k][rs, cs], tr[k, b, 1]) != ref["theta"][k][b]:
                 first_flip = (k, b)
         if first_flip is None or first_flip[0] > k:
