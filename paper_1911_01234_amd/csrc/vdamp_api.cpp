@@ -18,12 +18,11 @@ namespace vdamp {
 hipError_t launch_rows_synth(const KArgs& a, int ept, int do_fft, size_t lds, hipStream_t st);
 hipError_t launch_cols(const KArgs& a, int ept, size_t lds, hipStream_t st);
 hipError_t launch_rows_anal(const KArgs& a, int ept, size_t lds, hipStream_t st);
-hipError_t launch_sure(const KArgs& a, bool big, size_t lds, hipStream_t st);
+hipError_t launch_sure(const KArgs& a, int cls, hipStream_t st);
 hipError_t launch_prep(const uint8_t* mask, const float* p, const float2* y, float* wgt,
                        long long n, int check, int* bad, hipStream_t st);
 hipError_t launch_zero(float2* x, long long n, hipStream_t st);
 hipError_t set_lds_limits_passes(size_t rows, size_t cols);
-hipError_t set_lds_limits_sure(size_t big, size_t small);
 }  // namespace vdamp
 
 using namespace vdamp;
@@ -104,10 +103,10 @@ struct vdamp_plan_t {
   float* d_tables = nullptr;
   int2* d_work_rows = nullptr;
   int2* d_work_cols = nullptr;
-  int2* d_work_sure = nullptr;      // big bands first, then small ones
-  int nrows = 0, ncols = 0, nsure_big = 0, nsure_small = 0;
+  int2* d_work_sure = nullptr;      // bands by size class: > 16384, > 4096, the rest
+  int nrows = 0, ncols = 0, nsure_cls[3] = {0, 0, 0};
   int ept = 16;                     // complex elements per thread of the LDS passes
-  size_t lds_rows = 0, lds_cols = 0, lds_sure_big = 0, lds_sure_small = 0;
+  size_t lds_rows = 0, lds_cols = 0;
   // workspace layout (byte offsets)
   size_t o_wgt = 0, o_r = 0, o_X = 0, o_r2 = 0, o_theta = 0, o_thr2 = 0, o_alpha = 0, o_tau = 0,
          o_taup = 0, o_bad = 0, ws_bytes = 0;
@@ -254,13 +253,11 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
     LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->ept, P->lds_cols, st));
     a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = k ? RA_VDAMP : RA_VDAMP_FIRST;
     LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
-    if (P->nsure_big) {
-      a.work = P->d_work_sure; a.nwork = P->nsure_big;
-      LAUNCH(L, VDAMP_PASS_SURE, launch_sure(a, true, P->lds_sure_big, st));
-    }
-    if (P->nsure_small) {
-      a.work = P->d_work_sure + P->nsure_big; a.nwork = P->nsure_small;
-      LAUNCH(L, VDAMP_PASS_SURE, launch_sure(a, false, P->lds_sure_small, st));
+    for (int c = 2, first = 0; c >= 0; --c) {
+      if (!P->nsure_cls[c]) continue;
+      a.work = P->d_work_sure + first; a.nwork = P->nsure_cls[c];
+      LAUNCH(L, VDAMP_PASS_SURE, launch_sure(a, c, st));
+      first += P->nsure_cls[c];
     }
   }
   // line 10: x_hat = F^H [ (1 - m) F Psi^H w + m y ]
@@ -382,8 +379,9 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     if (H * nx[b] > kMaxElems || ny[b] * kColW > kMaxElems)
       return fail(VDAMP_ERR_UNSUPPORTED, "strip does not fit the LDS tile");
     const long long finest = (long long)(ny[b] >> 1) * (nx[b] >> 1);
-    if (finest > kMaxSortKeys)
-      return fail(VDAMP_ERR_UNSUPPORTED, "finest subband larger than the LDS threshold search");
+    if (finest > kSureMaxKeys)
+      return fail(VDAMP_ERR_UNSUPPORTED, "finest subband larger than the LDS threshold search (" +
+                                             std::to_string(kSureMaxKeys) + " coefficients)");
   }
 
   vdamp_plan_t* P = new vdamp_plan_t();
@@ -457,8 +455,8 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   P->ncolstrips = colstrip;
 
   // work lists, heaviest items first
-  std::vector<std::pair<long long, int2>> wr, wc, wsb, wss;
-  int maxnx = 0, maxny = 0, maxpad_big = 1, maxpad_small = 1;
+  std::vector<std::pair<long long, int2>> wr, wc, wsh, wsb, wss;
+  int maxnx = 0, maxny = 0;
   for (int b = 0; b < batch; ++b) {
     maxnx = std::max(maxnx, nx[b]);
     maxny = std::max(maxny, ny[b]);
@@ -467,15 +465,10 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     for (int band = 0; band < P->nbands; ++band) {
       int l = band == 0 ? levels : levels - (band - 1) / 3;
       long long nbsz = (long long)(ny[b] >> l) * (nx[b] >> l);
-      int pad = 1;
-      while (pad < nbsz) pad <<= 1;
-      if (nbsz > kSureSmall) {
-        maxpad_big = std::max(maxpad_big, pad);
-        wsb.push_back({(long long)pad, make_int2(b, band)});
-      } else {
-        maxpad_small = std::max(maxpad_small, pad);
-        wss.push_back({(long long)pad, make_int2(b, band)});
-      }
+      if (nbsz > kSureSmall)
+        (nbsz > 4 * kSureSmall ? wsh : wsb).push_back({nbsz, make_int2(b, band)});
+      else
+        wss.push_back({nbsz, make_int2(b, band)});
     }
   }
   auto sort_items = [](std::vector<std::pair<long long, int2>>& v) {
@@ -484,19 +477,18 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     for (auto& e : v) out.push_back(e.second);
     return out;
   };
-  std::vector<int2> vr = sort_items(wr), vc = sort_items(wc), vs = sort_items(wsb);
-  std::vector<int2> vss = sort_items(wss);
-  P->nsure_big = (int)vs.size();
-  P->nsure_small = (int)vss.size();
+  std::vector<int2> vr = sort_items(wr), vc = sort_items(wc), vs = sort_items(wsh);
+  std::vector<int2> vsb = sort_items(wsb), vss = sort_items(wss);
+  P->nsure_cls[2] = (int)vs.size();
+  P->nsure_cls[1] = (int)vsb.size();
+  P->nsure_cls[0] = (int)vss.size();
+  vs.insert(vs.end(), vsb.begin(), vsb.end());
   vs.insert(vs.end(), vss.begin(), vss.end());
   P->nrows = (int)vr.size();
   P->ncols = (int)vc.size();
   P->lds_rows = sizeof(float2) * (size_t)H * maxnx;
   P->lds_cols = sizeof(float2) * (size_t)maxny * kColW;
   P->ept = (H * maxnx <= 16 * kThreads && maxny * kColW <= 16 * kThreads) ? 16 : 32;
-  // bucket offsets, then the sorted keys with one pad word per 16 keys
-  P->lds_sure_big = sizeof(int) * (4096 + 1) + sizeof(float) * (size_t)(maxpad_big + maxpad_big / 16 + 1);
-  P->lds_sure_small = sizeof(int) * (1024 + 1) + sizeof(float) * (size_t)(maxpad_small + maxpad_small / 16 + 1);
 
   // workspace layout
   size_t o = 0;
@@ -528,7 +520,6 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   if (e == hipSuccess) e = upload(P->d_work_cols, vc);
   if (e == hipSuccess) e = upload(P->d_work_sure, vs);
   if (e == hipSuccess) e = set_lds_limits_passes(P->lds_rows, P->lds_cols);
-  if (e == hipSuccess) e = set_lds_limits_sure(P->lds_sure_big, P->lds_sure_small);
   if (e != hipSuccess) {
     free_plan(P);
     return fail(VDAMP_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));

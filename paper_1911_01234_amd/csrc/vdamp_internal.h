@@ -13,8 +13,8 @@ constexpr int kMaxBands = 16;      // per-slice band slots (1 + 3 s, s <= 4 uses
 constexpr int kColW = 16;          // columns per column strip (16 complex = 128 B per row)
 constexpr int kMaxRadices = 8;
 constexpr int kMaxN = 512;         // largest ny / nx
-constexpr int kMaxSortKeys = 32768;// largest padded band for the LDS threshold search
 constexpr int kSureSmall = 4096;   // bands up to this size use the 256-thread search
+constexpr int kSureMaxKeys = 27648;// largest subband the LDS threshold search holds
 
 struct FftPlanDev {
   int n;                 // transform length

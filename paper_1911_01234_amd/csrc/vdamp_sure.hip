@@ -33,29 +33,26 @@ __device__ __forceinline__ int wave_incl_prefix_int(int v, int lane) {
 // Bucket of a key for the counting sort, from the FP32 bit pattern of v = key/tau.
 // Monotone in key: multiplying by a positive constant with round-to-nearest is
 // monotone, and so is the bit pattern of a non-negative float.  The buckets are
-// piecewise logarithmic: fine (MB mantissa bits) over v in [2^-4, 2^3), where the
-// noise-only keys concentrate (key/tau of a CN(0, tau) coefficient is Exp(1)), and
-// coarse (LB bits) over [2^-16, 2^-4) and [2^3, 2^23); keys outside fall into the first
-// or last bucket.  NB = 12 * 2^LB + 7 * 2^MB + 20 * 2^LB.  (tau = 0 sends every key to
-// the last bucket: the search then takes its full-sort path.)
+// piecewise logarithmic: fine (2^MB per binade) over v in [2^-6, 2^3), where the
+// noise-only keys concentrate (key/tau of a CN(0, tau) coefficient is Exp(1)), coarse
+// (2^LB per binade) over [2^-16, 2^-6) and [2^3, 2^23); keys outside fall into the first
+// or the last used bucket.  (tau = 0 sends every key to the last bucket: the search
+// then takes its full-sort path.)
 template <int NB> struct SureBuckets;
-template <> struct SureBuckets<4096> { static constexpr int LB = 4, MB = 9; };
-template <> struct SureBuckets<1024> { static constexpr int LB = 2, MB = 7; };
+template <> struct SureBuckets<10240> { static constexpr int LB = 5, MB = 10; };
+template <> struct SureBuckets<2560> { static constexpr int LB = 3, MB = 8; };
 
 template <int NB>
 __device__ __forceinline__ int sure_bucket(float key, float inv_tau) {
   constexpr int LB = SureBuckets<NB>::LB, MB = SureBuckets<NB>::MB;
-  constexpr unsigned E_LO = 111u << 23, E_MID = 123u << 23, E_HI = 130u << 23;
-  constexpr int N_LO = 12 << LB, N_MID = 7 << MB;
-  static_assert(N_LO + N_MID + (20 << LB) == NB, "bucket layout");
+  constexpr unsigned E_LO = 111u << 23, E_MID = 121u << 23, E_HI = 130u << 23;
+  constexpr int N_LO = 10 << LB, N_MID = 9 << MB, N_HI = 20 << LB;
+  static_assert(N_LO + N_MID + N_HI <= NB, "bucket layout");
   const unsigned e = __float_as_uint(key * inv_tau);
-  if (e < E_MID) {
-    const int v = (e < E_LO) ? 0 : (int)((e - E_LO) >> (23 - LB));
-    return v;
-  }
+  if (e < E_MID) return (e < E_LO) ? 0 : (int)((e - E_LO) >> (23 - LB));
   if (e < E_HI) return N_LO + (int)((e - E_MID) >> (23 - MB));
   const unsigned v = (e - E_HI) >> (23 - LB);
-  return N_LO + N_MID + (int)min(v, (unsigned)((20 << LB) - 1));
+  return N_LO + N_MID + (int)min(v, (unsigned)(N_HI - 1));
 }
 
 // LDS index of sorted position i: one pad word per 16 keys, so that threads walking
@@ -78,19 +75,24 @@ __device__ __forceinline__ int skx(int i) { return i + (i >> 4); }
 //      (the last index of a run of equal keys, a > 0).
 //   4. Workgroup argmin, ties to the smaller index; theta = a_m, theta^2 = key_m and
 //      alpha = ((N_b - m) - theta R_m / 2) / N_b (line 7).
-constexpr int kSureBucketLimit = 128;
+constexpr int kSureBucketLimit = 64;
 
-template <int NT, int KPT, int NB>
+// LDS words of a size class: the bucket table, then the sorted keys with one pad word
+// per 16 keys.
+constexpr int sure_smem_words(int NB, int MAXK) { return NB + 1 + MAXK + MAXK / 16 + 1; }
+
+template <int NT, int KPT, int NB, int MAXK>
 __global__ void __launch_bounds__(NT) k_sure(KArgs a) {
-  extern __shared__ int sure_smem[];
+  static_assert(NT * KPT >= MAXK, "keys per thread");
+  __shared__ __align__(16) int sure_smem[sure_smem_words(NB, MAXK)];
   constexpr int NW = NT / 64;
   constexpr int BPT = NB / NT;
   __shared__ double wsA[NW], wsR[NW], bv[NW], bR[NW];
   __shared__ int bi[NW], wsC[NW], wsM[NW];
   __shared__ float tau_sh;
   __shared__ int maxc_sh;
-  int* off = sure_smem;                                      // [NB + 1]
-  float* sk = reinterpret_cast<float*>(sure_smem + NB + 1);  // [skx(npad)]
+  int* off = sure_smem;                                       // [NB + 1]
+  float* const sk = reinterpret_cast<float*>(sure_smem + NB + 1);  // [skx(Nb)] sorted keys
   const int2 item = a.work[blockIdx.x];
   const int sl = item.x, b = item.y, s = a.levels;
   const SliceDev S = a.slices[sl];
@@ -163,16 +165,16 @@ __global__ void __launch_bounds__(NT) k_sure(KArgs a) {
     maxc_sh = m;
   }
   __syncthreads();
-  // scatter into bucket slots
-#pragma unroll
-  for (int j = 0; j < KPT; ++j) {
-    const int i = tid + j * NT;
-    if (i < Nb) sk[skx(off[sure_bucket<NB>(kk[j], inv_tau)] + pos[j])] = kk[j];
-  }
-  __syncthreads();
   if (maxc_sh <= kSureBucketLimit) {
-    // final position = bucket offset + rank within the bucket (ties by slot)
-    int fin[KPT];
+    // scatter into bucket slots
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      const int i = tid + j * NT;
+      if (i < Nb) sk[skx(off[sure_bucket<NB>(kk[j], inv_tau)] + pos[j])] = kk[j];
+    }
+    __syncthreads();
+    // final position = bucket offset + rank within the bucket (ties by slot); it
+    // replaces the slot in pos[]
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const int i = tid + j * NT;
@@ -186,28 +188,46 @@ __global__ void __launch_bounds__(NT) k_sure(KArgs a) {
           const float u = sk[skx(x)];
           rank += (u < v) || (u == v && x < me);
         }
-        fin[j] = lo + rank;
+        pos[j] = lo + rank;
       }
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const int i = tid + j * NT;
-      if (i < Nb) sk[skx(fin[j])] = kk[j];
+      if (i < Nb) sk[skx(pos[j])] = kk[j];
     }
-    for (int i = Nb + tid; i < npad; i += NT) sk[skx(i)] = __builtin_huge_valf();
     __syncthreads();
   } else {
-    for (int i = Nb + tid; i < npad; i += NT) sk[skx(i)] = __builtin_huge_valf();
+    // Full sort: a bitonic network whose compare-exchanges all put the smaller key
+    // first (each merge starts by comparing mirrored positions), so +inf padding up to
+    // the next power of two never moves and needs no storage: only pairs with both
+    // indices < Nb are compared.
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      const int i = tid + j * NT;
+      if (i < Nb) sk[skx(i)] = kk[j];
+    }
     __syncthreads();
     for (int k = 2; k <= npad; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < (npad >> 1); i += NT) {
+        const int half = k >> 1;
+        const int blk = i / half, ofs = i - blk * half;
+        const int lo = blk * k + ofs, hi = blk * k + k - 1 - ofs;
+        if (hi < Nb) {
+          const float x = sk[skx(lo)], y = sk[skx(hi)];
+          if (x > y) { sk[skx(lo)] = y; sk[skx(hi)] = x; }
+        }
+      }
+      __syncthreads();
+      for (int j = k >> 2; j > 0; j >>= 1) {
         for (int i = tid; i < (npad >> 1); i += NT) {
           const int lo = 2 * j * (i / j) + (i & (j - 1));
           const int hi = lo + j;
-          const bool asc = (lo & k) == 0;
-          const float x = sk[skx(lo)], y = sk[skx(hi)];
-          if ((x > y) == asc) { sk[skx(lo)] = y; sk[skx(hi)] = x; }
+          if (hi < Nb) {
+            const float x = sk[skx(lo)], y = sk[skx(hi)];
+            if (x > y) { sk[skx(lo)] = y; sk[skx(hi)] = x; }
+          }
         }
         __syncthreads();
       }
@@ -215,7 +235,7 @@ __global__ void __launch_bounds__(NT) k_sure(KArgs a) {
   }
   const double tau = (double)tau_sh;
   const float kmax = sk[skx(Nb - 1)];
-  const int E = (npad + NT - 1) / NT;
+  const int E = (Nb + NT - 1) / NT;
   const int i0 = tid * E;
   const int i1 = min(i0 + E, Nb);
   double cA = 0.0, cR = 0.0;
@@ -290,23 +310,18 @@ __global__ void __launch_bounds__(NT) k_sure(KArgs a) {
   }
 }
 
-// Bands with more than kSureSmall keys go to the 1024-thread variant (up to 32768 keys,
-// 4096 buckets); the rest to the 256-thread one (up to 4096 keys, 1024 buckets).
-hipError_t launch_sure(const KArgs& a, bool big, size_t lds, hipStream_t st) {
-  if (big)
-    hipLaunchKernelGGL((k_sure<1024, 32, 4096>), dim3(a.nwork), dim3(1024), lds, st, a);
+// Size classes: up to 4096 keys (256 threads, 2560 buckets), up to 16384 keys
+// (1024 threads, 16 keys each) and up to kSureMaxKeys keys (1024 threads, 32 keys each),
+// the last two with 10240 buckets.  All LDS is static: the largest class uses about
+// 158 KB of the 160 KB a gfx950 workgroup may hold.
+hipError_t launch_sure(const KArgs& a, int cls, hipStream_t st) {
+  if (cls == 2)
+    hipLaunchKernelGGL((k_sure<1024, 32, 10240, kSureMaxKeys>), dim3(a.nwork), dim3(1024), 0, st, a);
+  else if (cls == 1)
+    hipLaunchKernelGGL((k_sure<1024, 16, 10240, 4 * kSureSmall>), dim3(a.nwork), dim3(1024), 0, st, a);
   else
-    hipLaunchKernelGGL((k_sure<256, 16, 1024>), dim3(a.nwork), dim3(256), lds, st, a);
+    hipLaunchKernelGGL((k_sure<256, 16, 2560, kSureSmall>), dim3(a.nwork), dim3(256), 0, st, a);
   return hipGetLastError();
-}
-
-hipError_t set_lds_limits_sure(size_t big, size_t small) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_sure<1024, 32, 4096>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)big);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_sure<256, 16, 1024>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)small);
-  return e;
 }
 
 }  // namespace vdamp
