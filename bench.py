@@ -10,7 +10,9 @@ Prints ONE JSON line.  `value` is slice-iterations per second over the timed ste
 `roofline` reports the dominant kernel class (largest share of kernel time, from HIP
 events recorded around every launch on the solve's stream inside the timed region):
 algorithmic bytes it must move per launch / its average launch time, against the
-MI355X HBM peak.  `cpu_baseline` is the FP64 oracle timed on the host on a bounded
+MI355X HBM peak; `traffic` is the HBM bytes per launch that rocprofv3's FETCH_SIZE and
+WRITE_SIZE counters measured for that kernel (scaled by a copy of known size), taken
+from profiles/ while the kernel's sources are unchanged, else null.  `cpu_baseline` is the FP64 oracle timed on the host on a bounded
 sample of the same workload.
 """
 from __future__ import annotations
@@ -59,15 +61,38 @@ def make_batch(B):
     return slices, s, K
 
 
-def nmse_db_batch(x_hat, x0, plan):
+def nmse_db_batch(x_hat, x0, seg, batch):
+    """Per-slice NMSE (dB) of a packed batch; seg holds each pixel's slice index."""
     import torch
-    d = (x_hat - x0).abs().pow(2)
-    n = x0.abs().pow(2)
-    out = []
-    for b in range(plan.batch):
-        a, e = int(plan.offsets[b]), int(plan.offsets[b + 1])
-        out.append(10.0 * torch.log10(d[a:e].sum() / n[a:e].sum()).item())
-    return np.array(out)
+    d = torch.zeros(batch, dtype=torch.float64, device=x0.device)
+    n = torch.zeros_like(d)
+    d.index_add_(0, seg, (x_hat - x0).abs().pow(2).double())
+    n.index_add_(0, seg, x0.abs().pow(2).double())
+    return (10.0 * torch.log10(d / n)).cpu().numpy()
+
+
+KERNEL_SOURCES = {"cols": ["paper_1911_01234_amd/csrc/vdamp_passes.hip",
+                           "paper_1911_01234_amd/csrc/vdamp_device.hpp",
+                           "paper_1911_01234_amd/csrc/vdamp_internal.h"]}
+
+
+def measured_traffic(kernel_class):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the kernel sources as they are now (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_k_{kernel_class}_b256_256x256.md")
+    if kernel_class not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("TRAFFIC_RECORD "):
+            rec = json.loads(line[len("TRAFFIC_RECORD "):])
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel_class]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest()[:16] == rec["source_sha"] else None
 
 
 def cpu_baseline(slices, s, iters, budget_s):
@@ -95,6 +120,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="time hipGraph replays instead of eager launches")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device three times (a kernel of known traffic "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: slices are independent, so a multi-GPU run "
@@ -106,6 +134,14 @@ def main():
     from paper_1911_01234_amd import vdamp as V
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t_gen = time.perf_counter()
     slices, s, K = make_batch(args.batch)
     t_gen = time.perf_counter() - t_gen
@@ -124,6 +160,7 @@ def main():
     y, mask, p, sigma2 = V.to_device(plan, slices)
     x_hat = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
     x0 = torch.from_numpy(plan.pack([sl.x0 for sl in slices], np.complex64)).cuda()
+    seg = torch.from_numpy(np.repeat(np.arange(B), [a * b for a, b in zip(ny, nx)])).cuda()
 
     def step(iters=K):
         with torch.cuda.stream(stream):
@@ -156,8 +193,9 @@ def main():
         bytes_total = alg[dom][0] * args.steps
         avg_launch_s = tot_ms / 1e3 / launches
         achieved = bytes_total / launches / avg_launch_s / 1e9
+        traffic = measured_traffic(dom)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": dom, "avg_launch_us": round(1e6 * avg_launch_s, 2),
                     "alg_bytes_per_launch": int(bytes_total / launches)}
         allb = sum(v[0] for v in alg.values()) * args.steps
@@ -168,12 +206,12 @@ def main():
     # the 50-iteration value (monitored runs), timed unmonitored
     step(K)
     stream.synchronize()
-    target = float(nmse_db_batch(x_hat, x0, plan).mean()) + 0.1
+    target = float(nmse_db_batch(x_hat, x0, seg, B).mean()) + 0.1
     k_hit = K
     for k in range(1, K + 1):
         step(k)
         stream.synchronize()
-        if float(nmse_db_batch(x_hat, x0, plan).mean()) <= target:
+        if float(nmse_db_batch(x_hat, x0, seg, B).mean()) <= target:
             k_hit = k
             break
     reps = 3
