@@ -77,7 +77,8 @@ enum {
   VDAMP_PASS_COLS = 2,      /* column FFT, k-space residual, tau partials, col IFFT  */
   VDAMP_PASS_ROWS_ANAL = 3, /* row IFFT, Psi on row strips, + r_tilde (line 4)       */
   VDAMP_PASS_SURE = 4,      /* tau reduction, SURE threshold search, alpha           */
-  VDAMP_PASS_COUNT = 5
+  VDAMP_PASS_DENOISER = 5,  /* learned denoiser: transforms, CNN + JVP, judge         */
+  VDAMP_PASS_COUNT = 6
 };
 
 /*
@@ -150,6 +151,109 @@ vdamp_status vdamp_state_export(vdamp_plan_h plan, hipStream_t stream, const voi
  *   ms, launches    host arrays of npass entries
  */
 vdamp_status vdamp_pass_times(vdamp_plan_h plan, double* ms, int64_t* launches, int32_t npass);
+
+/* ------------------------------------------------------------------------------------
+ * Learned denoiser.  Algorithm 1 accepts any denoiser g(r; tau) together with its mean
+ * derivative (line 7); the conclusion proposes denoisers trained for wavelet
+ * coefficients under the known colored Gaussian noise of VDAMP.  This one is a CNN in
+ * the image domain, g(r) = Psi f(Psi^H r; tau), with
+ *   u = (Re x, Im x) / s0,  t_b = log(max(tau_b / s0^2, 1e-12)),
+ *   a1 = relu(conv(u; W1) + b1 + Wt t),  a_l = relu(conv(a_{l-1}; W_l) + b_l), l = 2..5,
+ *   o = conv(a5; W6) + b6,  f(x) = s0 (u - o),
+ * six circular 3x3 convolutions (2 -> 48 -> 48 -> 48 -> 48 -> 48 -> 2 channels).  BF16
+ * weights and activations, FP32 accumulation (MFMA).  Parameters are FP32 masters,
+ * flat, in the order W1[48][2][3][3], b1[48], Wt[48][nb], W2[48][48][3][3], b2[48], ...,
+ * W5, b5, W6[2][48][3][3], b6[2].  Every slice's ny and nx must be multiples of 16.
+ * A denoiser object is not shared by concurrently running streams.
+ * ---------------------------------------------------------------------------------- */
+typedef struct vdamp_cnn_t* vdamp_cnn_h;
+
+/* How vdamp_solve_learned picks the denoiser of each subband. */
+enum {
+  VDAMP_JUDGE_SURE = 0, /* learned where its SURE is below soft thresholding's minimum */
+  VDAMP_JUDGE_NONE = 1  /* learned in every subband (subject to the bound on alpha)   */
+};
+
+enum {
+  VDAMP_CNN_WS_FORWARD = 0, /* vdamp_cnn_forward (with or without the JVP) */
+  VDAMP_CNN_WS_TRAIN = 1,   /* vdamp_cnn_train_step */
+  VDAMP_CNN_WS_SOLVE = 2    /* vdamp_solve_learned */
+};
+
+/* Create a denoiser for nbands = 1 + 3 levels noise levels; parameters start at zero. */
+vdamp_status vdamp_cnn_create(vdamp_cnn_h* cnn, int32_t nbands);
+vdamp_status vdamp_cnn_destroy(vdamp_cnn_h cnn);
+/* Number of FP32 parameters. */
+vdamp_status vdamp_cnn_param_count(vdamp_cnn_h cnn, int64_t* count);
+/* Copy count parameters from device memory (layout above) and reset the Adam state. */
+vdamp_status vdamp_cnn_set_params(vdamp_cnn_h cnn, hipStream_t stream, const float* params);
+/* Copy the parameters (and, if grad is non-null, the last training step's gradient) to
+ * device memory. */
+vdamp_status vdamp_cnn_get_params(vdamp_cnn_h cnn, hipStream_t stream, float* params, float* grad);
+/* Workspace bytes for one of the VDAMP_CNN_WS_* uses on this plan's batch. */
+vdamp_status vdamp_cnn_workspace(vdamp_cnn_h cnn, vdamp_plan_h plan, int32_t kind, size_t* bytes);
+
+/*
+ * vdamp_cnn_forward -- x_out = f(x; tau) for every slice of the plan and, if tangent is
+ * non-null, jvp_out = J_f(x) tangent (the Jacobian-vector product the divergence
+ * estimate of line 7 needs).
+ *   x, tangent       complex64[sum N] images (device)
+ *   tau              float32[B][16] noise levels per band (first nbands used)
+ *   s0               float32[B] input scales (> 0)
+ *   x_out, jvp_out   complex64[sum N] out
+ */
+vdamp_status vdamp_cnn_forward(vdamp_cnn_h cnn, vdamp_plan_h plan, hipStream_t stream,
+                               void* workspace, size_t workspace_bytes, const float* x,
+                               const float* tau, const float* s0, float* x_out,
+                               const float* tangent, float* jvp_out);
+
+/*
+ * vdamp_cnn_train_step -- one Adam step (beta = 0.9, 0.999, eps = 1e-8, learning rate
+ * lr) on the loss (1/B) sum_slices ||f(x; tau) - x0||^2 / (s0^2 N), with the gradient
+ * by backpropagation; loss (device float32[1]) receives the loss before the step.
+ */
+vdamp_status vdamp_cnn_train_step(vdamp_cnn_h cnn, vdamp_plan_h plan, hipStream_t stream,
+                                  void* workspace, size_t workspace_bytes, const float* x,
+                                  const float* tau, const float* s0, const float* x0, float lr,
+                                  float* loss);
+
+/*
+ * vdamp_solve_learned -- Algorithm 1 with the learned denoiser judged against SURE soft
+ * thresholding per subband: each iteration computes soft thresholding's SURE minimum
+ * (lines 6-7 as in vdamp_solve), then w_cnn = Psi f(Psi^H r; tau) and its mean
+ * derivative alpha from one complex Rademacher probe b (Psi J_f Psi^H b, drawn from
+ * seed by SplitMix64 as a counter-based generator), and uses w_cnn with that alpha in
+ * lines 8 and 10 in the subbands where its SURE, ||w_cnn - r||^2 + (2 alpha - 1) N_b tau,
+ * is below soft thresholding's (judge = VDAMP_JUDGE_SURE; with VDAMP_JUDGE_NONE in
+ * every subband) and alpha <= 1 - 1/N_b.  s0 per slice is sqrt(mean over pixels of
+ * (m / p) |y|^2) (1 if that is zero).  Arguments as in vdamp_solve plus the denoiser,
+ * its VDAMP_CNN_WS_SOLVE workspace, the judge and the seed; trace holds soft
+ * thresholding's (tau, theta, alpha).
+ */
+vdamp_status vdamp_solve_learned(vdamp_plan_h plan, vdamp_cnn_h cnn, hipStream_t stream,
+                                 void* workspace, size_t workspace_bytes, void* cnn_workspace,
+                                 size_t cnn_workspace_bytes, const float* y, const uint8_t* mask,
+                                 const float* p, const float* sigma2, int32_t iters,
+                                 int32_t judge, uint64_t seed, float* x_hat, float* trace);
+
+/*
+ * vdamp_learned_export -- after vdamp_solve_learned, the last iteration's judge: per
+ * band the choice (int32[B][nb], 1 = learned denoiser), the learned denoiser's SURE, its
+ * alpha estimate and soft thresholding's SURE minimum (float32[B][nb] each), and the
+ * input scales s0 (float32[B]); any output may be null.  vdamp_state_export gives r, theta and tau of that iteration and
+ * the alpha that line 8 used (the learned one where chosen).
+ */
+vdamp_status vdamp_learned_export(vdamp_cnn_h cnn, vdamp_plan_h plan, hipStream_t stream,
+                                  const void* cnn_workspace, int32_t* sel, float* s0,
+                                  float* sure_cnn, float* alpha_cnn, float* sure_soft);
+
+/*
+ * vdamp_wavelet -- Psi (inverse = 0) or Psi^H (inverse = 1) of every slice: s-level
+ * periodic orthonormal Haar, Mallat layout.  in and out are complex64[sum N] and must
+ * not overlap.
+ */
+vdamp_status vdamp_wavelet(vdamp_plan_h plan, hipStream_t stream, int32_t inverse,
+                           const float* in, float* out);
 
 /* Static description of a status code. */
 const char* vdamp_status_string(vdamp_status s);

@@ -7,7 +7,7 @@ TEST INFRASTRUCTURE ONLY: used by tests/ (and nothing in the product path).
 
 Network (image domain, circular padding to match the periodic model):
   u  = (Re x, Im x) / s0                                   2 channels
-  t  = log(tau_b / s0^2), b = 0..nb-1                      per-slice noise levels
+  t  = log(max(tau_b / s0^2, 1e-12)), b = 0..nb-1         per-slice noise levels
   a1 = relu(conv(u; W1) + b1 + Wt t)                       48 channels
   a_l = relu(conv(a_{l-1}; W_l) + b_l), l = 2..5           48 channels
   o  = conv(a5; W6) + b6                                   2 channels
@@ -88,7 +88,7 @@ def forward(p, x, tau, s0, bf16=False, keep=False):
     """x: complex image [H][W]; tau: [nb]; returns x_out (complex) and, with keep, the
     cached layer inputs/activations."""
     u = np.stack([x.real, x.imag]) / s0
-    t = np.log(np.asarray(tau, dtype=np.float64) / s0 ** 2)
+    t = np.log(np.maximum(np.asarray(tau, dtype=np.float64) / s0 ** 2, 1e-12))
     acts = [_maybe(u, bf16)]
     h = acts[0]
     for l in range(1, LAYERS + 1):

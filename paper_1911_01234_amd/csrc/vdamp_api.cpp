@@ -12,38 +12,13 @@
 #include <vector>
 
 #include "vdamp.h"
-#include "vdamp_internal.h"
+#include "vdamp_host.h"
 
-namespace vdamp {
-hipError_t launch_rows_synth(const KArgs& a, int ept, int do_fft, size_t lds, hipStream_t st);
-hipError_t launch_cols(const KArgs& a, int ept, size_t lds, hipStream_t st);
-hipError_t launch_rows_anal(const KArgs& a, int ept, size_t lds, hipStream_t st);
-hipError_t launch_sure(const KArgs& a, int cls, hipStream_t st);
-hipError_t launch_prep(const uint8_t* mask, const float* p, const float2* y, float* wgt,
-                       long long n, int check, int* bad, hipStream_t st);
-hipError_t launch_zero(float2* x, long long n, hipStream_t st);
-hipError_t set_lds_limits_passes(size_t rows, size_t cols);
-}  // namespace vdamp
 
 using namespace vdamp;
 
 namespace {
 
-thread_local std::string g_err;
-
-vdamp_status fail(vdamp_status st, const std::string& msg) {
-  g_err = msg;
-  return st;
-}
-
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(VDAMP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
-  } while (0)
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Radix plan: radix-4 stages first, then 5, 3, 4 and 2 for the remaining factor.
 bool radix_plan(int n, std::vector<int>& rad) {
@@ -74,54 +49,9 @@ void haar_power(int n, int level, bool wavelet, std::vector<double>& out) {
   }
 }
 
-struct GraphKey {
-  int kind = -1;
-  const void *ws = nullptr, *y = nullptr, *mask = nullptr, *p = nullptr, *sig = nullptr,
-             *lam = nullptr, *x = nullptr, *trace = nullptr;
-  int iters = -1;
-  hipStream_t stream = nullptr;
-  bool operator==(const GraphKey& o) const {
-    return kind == o.kind && ws == o.ws && y == o.y && mask == o.mask && p == o.p &&
-           sig == o.sig && lam == o.lam && x == o.x && trace == o.trace && iters == o.iters &&
-           stream == o.stream;
-  }
-};
 
 }  // namespace
 
-struct vdamp_plan_t {
-  int B = 0, levels = 0, nbands = 0;
-  uint32_t flags = 0;
-  std::vector<int> ny, nx;
-  std::vector<long long> off;
-  long long ntot = 0;
-  int ncolstrips = 0;
-  // device constants
-  SliceDev* d_slices = nullptr;
-  FftPlanDev* d_ffts = nullptr;
-  float2* d_tw = nullptr;
-  float* d_tables = nullptr;
-  int2* d_work_rows = nullptr;
-  int2* d_work_cols = nullptr;
-  int2* d_work_sure = nullptr;      // bands by size class: > 16384, > 4096, the rest
-  int nrows = 0, ncols = 0, nsure_cls[3] = {0, 0, 0};
-  int ept = 16;                     // complex elements per thread of the LDS passes
-  size_t lds_rows = 0, lds_cols = 0;
-  // workspace layout (byte offsets)
-  size_t o_wgt = 0, o_r = 0, o_X = 0, o_r2 = 0, o_theta = 0, o_thr2 = 0, o_alpha = 0, o_tau = 0,
-         o_taup = 0, o_bad = 0, ws_bytes = 0;
-  // last solve
-  const void* state_ws = nullptr;
-  bool has_state = false;
-  // graph cache
-  GraphKey gkey;
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  // timing
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<int, int>> ev_used;  // (pass, index of start event in ev_pool)
-  size_t ev_next = 0;
-};
 
 namespace {
 
@@ -137,15 +67,21 @@ void free_plan(vdamp_plan_t* P) {
   hipFree(P->d_work_rows);
   hipFree(P->d_work_cols);
   hipFree(P->d_work_sure);
+  hipFree(P->d_tiles);
+  hipFree(P->d_tile_off);
   delete P;
 }
 
-struct Ws {
-  float* wgt;
-  float2 *r, *X, *r2;
-  float *theta, *thr2, *alpha, *tau, *taup;
-  int* bad;
-};
+
+}  // namespace
+
+namespace vdamp {
+thread_local std::string g_err;
+
+vdamp_status fail(vdamp_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
 
 Ws layout(const vdamp_plan_t* P, void* ws) {
   char* b = static_cast<char*>(ws);
@@ -162,61 +98,9 @@ Ws layout(const vdamp_plan_t* P, void* ws) {
   w.bad = reinterpret_cast<int*>(b + P->o_bad);
   return w;
 }
+}  // namespace vdamp
 
-// Launch helper that records timing events around each kernel when asked.
-struct Launcher {
-  vdamp_plan_t* P;
-  hipStream_t st;
-  bool timing;
-  hipError_t begin(int pass) {
-    if (!timing) return hipSuccess;
-    if (P->ev_next + 2 > P->ev_pool.size()) {
-      for (int i = 0; i < 64; ++i) {
-        hipEvent_t e;
-        hipError_t err = hipEventCreate(&e);
-        if (err != hipSuccess) return err;
-        P->ev_pool.push_back(e);
-      }
-    }
-    P->ev_used.emplace_back(pass, (int)P->ev_next);
-    hipError_t err = hipEventRecord(P->ev_pool[P->ev_next], st);
-    P->ev_next += 2;
-    return err;
-  }
-  hipError_t end() {
-    if (!timing) return hipSuccess;
-    return hipEventRecord(P->ev_pool[P->ev_used.back().second + 1], st);
-  }
-};
-
-#define LAUNCH(L, pass, call)                                                           \
-  do {                                                                                  \
-    HIP_TRY((L).begin(pass));                                                           \
-    HIP_TRY(call);                                                                      \
-    HIP_TRY((L).end());                                                                 \
-  } while (0)
-
-KArgs base_args(const vdamp_plan_t* P, const Ws& w) {
-  KArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.slices = P->d_slices;
-  a.ffts = P->d_ffts;
-  a.twiddles = P->d_tw;
-  a.tables = P->d_tables;
-  a.levels = P->levels;
-  a.nbands = P->nbands;
-  a.batch = P->B;
-  a.wgt = w.wgt;
-  a.r = w.r;
-  a.r2 = w.r2;
-  a.X = w.X;
-  a.theta = w.theta;
-  a.thr2 = w.thr2;
-  a.alpha = w.alpha;
-  a.tau = w.tau;
-  a.tau_part = w.taup;
-  return a;
-}
+namespace {
 
 vdamp_status check_common(vdamp_plan_h plan, void* ws, size_t wsb, const void* y,
                           const void* mask, int iters, const void* x_hat) {
@@ -309,31 +193,6 @@ vdamp_status enqueue_fista(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
   return VDAMP_OK;
 }
 
-template <class F>
-vdamp_status run_maybe_graph(vdamp_plan_t* P, hipStream_t st, const GraphKey& key, F&& enqueue) {
-  const bool timing = (P->flags & VDAMP_FLAG_TIMING) != 0;
-  if (timing || !(P->flags & VDAMP_FLAG_USE_GRAPH)) return enqueue(timing);
-  if (!(P->gexec && P->gkey == key)) {
-    if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
-    if (P->graph) { hipGraphDestroy(P->graph); P->graph = nullptr; }
-    P->gkey = GraphKey();
-    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    vdamp_status s = enqueue(false);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(st, &g);
-    if (s != VDAMP_OK) {
-      if (g) hipGraphDestroy(g);
-      return s;
-    }
-    if (e != hipSuccess) return fail(VDAMP_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    P->graph = g;
-    HIP_TRY(hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0));
-    P->gkey = key;
-  }
-  HIP_TRY(hipGraphLaunch(P->gexec, st));
-  return VDAMP_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -376,6 +235,9 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     }
     if (nx[b] % kColW)
       return fail(VDAMP_ERR_UNSUPPORTED, "nx must be a multiple of 16 (column strip width)");
+    if ((nx[b] >> levels) % 2)
+      return fail(VDAMP_ERR_UNSUPPORTED,
+                  "nx / 2^levels must be even (both coefficients of an 8-byte pair lie in one subband)");
     if (H * nx[b] > kMaxElems || ny[b] * kColW > kMaxElems)
       return fail(VDAMP_ERR_UNSUPPORTED, "strip does not fit the LDS tile");
     const long long finest = (long long)(ny[b] >> 1) * (nx[b] >> 1);
@@ -435,7 +297,7 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
 
   std::vector<SliceDev> sl(batch);
   long long off = 0;
-  int colstrip = 0;
+  int colstrip = 0, rowstrip = 0;
   for (int b = 0; b < batch; ++b) {
     SliceDev& S = sl[b];
     std::memset(&S, 0, sizeof(S));
@@ -447,12 +309,28 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     S.ytab_off = get_tab(ny[b]);
     S.xtab_off = get_tab(nx[b]);
     S.colstrip0 = colstrip;
+    S.rowstrip0 = rowstrip;
     P->off[b] = off;
     off += (long long)ny[b] * nx[b];
     colstrip += nx[b] / kColW;
+    rowstrip += ny[b] / H;
   }
   P->ntot = off;
   P->ncolstrips = colstrip;
+  P->nrowstrips = rowstrip;
+
+  // 16x16 pixel tiles of the learned denoiser, slice-major (only when every size allows)
+  std::vector<int2> tiles;
+  P->tiles_ok = true;
+  for (int b = 0; b < batch; ++b) P->tiles_ok = P->tiles_ok && ny[b] % 16 == 0 && nx[b] % 16 == 0;
+  P->tile_off.assign(1, 0);
+  if (P->tiles_ok)
+    for (int b = 0; b < batch; ++b) {
+      const int nt = (ny[b] / 16) * (nx[b] / 16);
+      for (int t = 0; t < nt; ++t) tiles.push_back(make_int2(b, t));
+      P->tile_off.push_back((int)tiles.size());
+    }
+  P->ntiles = (int)tiles.size();
 
   // work lists, heaviest items first
   std::vector<std::pair<long long, int2>> wr, wc, wsh, wsb, wss;
@@ -519,7 +397,9 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   if (e == hipSuccess) e = upload(P->d_work_rows, vr);
   if (e == hipSuccess) e = upload(P->d_work_cols, vc);
   if (e == hipSuccess) e = upload(P->d_work_sure, vs);
-  if (e == hipSuccess) e = set_lds_limits_passes(P->lds_rows, P->lds_cols);
+  if (e == hipSuccess) e = upload(P->d_tiles, tiles);
+  if (e == hipSuccess) e = upload(P->d_tile_off, P->tile_off);
+  if (e == hipSuccess) e = set_lds_limits_passes(sizeof(float2) * kMaxElems, sizeof(float2) * kMaxElems);
   if (e != hipSuccess) {
     free_plan(P);
     return fail(VDAMP_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));

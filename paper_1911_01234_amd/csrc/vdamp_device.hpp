@@ -278,6 +278,32 @@ __device__ __forceinline__ float2 rtilde_c(float2 v, float th, float th2, float 
   return make_float2((w.x - al * v.x) * inv, (w.y - al * v.y) * inv);
 }
 
+// line 8 for a general denoiser output w: (w - alpha r) / (1 - alpha)
+__device__ __forceinline__ float2 rtilde_w(float2 w, float2 v, float al) {
+  const float inv = 1.0f / (1.0f - al);
+  return make_float2((w.x - al * v.x) * inv, (w.y - al * v.y) * inv);
+}
+
+// Probe of the Monte-Carlo divergence: a complex Rademacher value (+-1 +- i)/sqrt(2)
+// per wavelet coefficient, drawn by SplitMix64 (Steele, Lea and Flood, 2014) used as a
+// counter-based generator: the value at counter c of the stream with seed k is
+// mix(k + (c + 1) * 0x9E3779B97F4A7C15), with c = iteration << 48 | slice << 32 | index
+// (index = row * nx + column of the coefficient in its slice).  Bit 0 gives the sign of
+// the real part, bit 1 that of the imaginary part (set = negative).
+__device__ __forceinline__ unsigned long long splitmix64_mix(unsigned long long z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ float2 probe_c(unsigned long long seed, int iter, int slice,
+                                          long long index) {
+  const unsigned long long c = ((unsigned long long)iter << 48) |
+                               ((unsigned long long)slice << 32) | (unsigned long long)index;
+  const unsigned long long z = splitmix64_mix(seed + (c + 1ull) * 0x9E3779B97F4A7C15ull);
+  const float h = 0.70710678118654752f;
+  return make_float2((z & 1ull) ? -h : h, (z & 2ull) ? -h : h);
+}
+
 // Band geometry in the global Mallat layout.
 __device__ __forceinline__ void band_geom(int b, int s, int ny, int nx, int& r0, int& c0,
                                           int& bh, int& bw) {

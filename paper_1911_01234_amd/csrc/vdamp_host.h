@@ -1,0 +1,193 @@
+// Host-side internals shared by the library's translation units: the plan, the
+// workspace layout, error reporting.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "vdamp.h"
+#include "vdamp_internal.h"
+
+namespace vdamp {
+
+struct GraphKey {
+  int kind = -1;
+  const void *ws = nullptr, *y = nullptr, *mask = nullptr, *p = nullptr, *sig = nullptr,
+             *lam = nullptr, *x = nullptr, *trace = nullptr;
+  const void* aux = nullptr;   // learned solve: the denoiser and its workspace
+  const void* aux_ws = nullptr;
+  unsigned long long seed = 0;
+  int iters = -1;
+  hipStream_t stream = nullptr;
+  bool operator==(const GraphKey& o) const {
+    return kind == o.kind && ws == o.ws && y == o.y && mask == o.mask && p == o.p &&
+           sig == o.sig && lam == o.lam && x == o.x && trace == o.trace && aux == o.aux &&
+           aux_ws == o.aux_ws && seed == o.seed && iters == o.iters && stream == o.stream;
+  }
+};
+
+struct Ws {
+  float* wgt;
+  float2 *r, *X, *r2;
+  float *theta, *thr2, *alpha, *tau, *taup;
+  int* bad;
+};
+
+extern thread_local std::string g_err;  // detail of the last failure on this thread
+vdamp_status fail(vdamp_status st, const std::string& msg);
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return ::vdamp::fail(VDAMP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace vdamp
+
+struct vdamp_plan_t {
+  using GraphKey = vdamp::GraphKey;
+  int B = 0, levels = 0, nbands = 0;
+  uint32_t flags = 0;
+  std::vector<int> ny, nx;
+  std::vector<long long> off;
+  long long ntot = 0;
+  int ncolstrips = 0;
+  // device constants
+  vdamp::SliceDev* d_slices = nullptr;
+  vdamp::FftPlanDev* d_ffts = nullptr;
+  float2* d_tw = nullptr;
+  float* d_tables = nullptr;
+  int2* d_work_rows = nullptr;
+  int2* d_work_cols = nullptr;
+  int2* d_work_sure = nullptr;      // bands by size class: > 16384, > 4096, the rest
+  int nrows = 0, ncols = 0, nsure_cls[3] = {0, 0, 0};
+  int nrowstrips = 0;
+  // learned denoiser: 16x16 tiles (slice, tile index), slice-major; tile_off[b] = first
+  // tile of slice b
+  bool tiles_ok = false;
+  int ntiles = 0;
+  std::vector<int> tile_off;
+  int2* d_tiles = nullptr;
+  int* d_tile_off = nullptr;
+  int ept = 16;                     // complex elements per thread of the LDS passes
+  size_t lds_rows = 0, lds_cols = 0;
+  // workspace layout (byte offsets)
+  size_t o_wgt = 0, o_r = 0, o_X = 0, o_r2 = 0, o_theta = 0, o_thr2 = 0, o_alpha = 0, o_tau = 0,
+         o_taup = 0, o_bad = 0, ws_bytes = 0;
+  // last solve
+  const void* state_ws = nullptr;
+  bool has_state = false;
+  // graph cache
+  GraphKey gkey;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  // timing
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_used;  // (pass, index of start event in ev_pool)
+  size_t ev_next = 0;
+};
+
+namespace vdamp {
+Ws layout(const vdamp_plan_t* P, void* ws);
+hipError_t launch_rows_synth(const KArgs& a, int ept, int do_fft, size_t lds, hipStream_t st);
+hipError_t launch_cols(const KArgs& a, int ept, size_t lds, hipStream_t st);
+hipError_t launch_rows_anal(const KArgs& a, int ept, size_t lds, hipStream_t st);
+hipError_t launch_sure(const KArgs& a, int cls, hipStream_t st);
+hipError_t launch_prep(const uint8_t* mask, const float* p, const float2* y, float* wgt,
+                       long long n, int check, int* bad, hipStream_t st);
+hipError_t launch_zero(float2* x, long long n, hipStream_t st);
+hipError_t set_lds_limits_passes(size_t rows, size_t cols);
+hipError_t launch_wave_anal(const KArgs& a, int ept, int jmode, size_t lds, hipStream_t st);
+hipError_t launch_scale(const SliceDev* slices, int batch, const float2* y, const float* wgt,
+                        float* s0, hipStream_t st);
+hipError_t launch_judge(const KArgs& a, int nrowstrips, int always, int* sel, float* jout,
+                        hipStream_t st);
+
+// Launch helper that records timing events around each kernel when asked.
+struct Launcher {
+  vdamp_plan_t* P;
+  hipStream_t st;
+  bool timing;
+  hipError_t begin(int pass) {
+    if (!timing) return hipSuccess;
+    if (P->ev_next + 2 > P->ev_pool.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        P->ev_pool.push_back(e);
+      }
+    }
+    P->ev_used.emplace_back(pass, (int)P->ev_next);
+    hipError_t err = hipEventRecord(P->ev_pool[P->ev_next], st);
+    P->ev_next += 2;
+    return err;
+  }
+  hipError_t end() {
+    if (!timing) return hipSuccess;
+    return hipEventRecord(P->ev_pool[P->ev_used.back().second + 1], st);
+  }
+};
+
+#define LAUNCH(L, pass, call)                                                           \
+  do {                                                                                  \
+    HIP_TRY((L).begin(pass));                                                           \
+    HIP_TRY(call);                                                                      \
+    HIP_TRY((L).end());                                                                 \
+  } while (0)
+
+inline KArgs base_args(const vdamp_plan_t* P, const Ws& w) {
+  KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.slices = P->d_slices;
+  a.ffts = P->d_ffts;
+  a.twiddles = P->d_tw;
+  a.tables = P->d_tables;
+  a.levels = P->levels;
+  a.nbands = P->nbands;
+  a.batch = P->B;
+  a.wgt = w.wgt;
+  a.r = w.r;
+  a.r2 = w.r2;
+  a.X = w.X;
+  a.theta = w.theta;
+  a.thr2 = w.thr2;
+  a.alpha = w.alpha;
+  a.tau = w.tau;
+  a.tau_part = w.taup;
+  return a;
+}
+
+
+template <class F>
+inline vdamp_status run_maybe_graph(vdamp_plan_t* P, hipStream_t st, const GraphKey& key, F&& enqueue) {
+  const bool timing = (P->flags & VDAMP_FLAG_TIMING) != 0;
+  if (timing || !(P->flags & VDAMP_FLAG_USE_GRAPH)) return enqueue(timing);
+  if (!(P->gexec && P->gkey == key)) {
+    if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+    if (P->graph) { hipGraphDestroy(P->graph); P->graph = nullptr; }
+    P->gkey = GraphKey();
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    vdamp_status s = enqueue(false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (s != VDAMP_OK) {
+      if (g) hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return fail(VDAMP_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    P->graph = g;
+    HIP_TRY(hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0));
+    P->gkey = key;
+  }
+  HIP_TRY(hipGraphLaunch(P->gexec, st));
+  return VDAMP_OK;
+}
+
+}  // namespace vdamp

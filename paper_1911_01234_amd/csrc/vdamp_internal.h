@@ -30,14 +30,17 @@ struct SliceDev {
   int ytab_off;          // 2 s tables of ny floats: L_1..L_s, H_1..H_s (y axis)
   int xtab_off;          // 2 s tables of nx floats (x axis)
   int colstrip0;         // index of this slice's first column strip in tau_part
-  int pad;
+  int rowstrip0;         // index of this slice's first row strip (learned-denoiser partials)
 };
 
 // Modes of the row-synthesis pass (Psi^H on row strips, then row FFT).
 enum RowSynthMode : int {
   RS_RTILDE = 0,   // line 8: r_tilde = (eta(r; theta) - alpha r) / (1 - alpha)
   RS_WHAT = 1,     // eta(r; theta) (line 6, used by line 10)
-  RS_PLAIN = 2     // r as is (FISTA momentum iterate)
+  RS_PLAIN = 2,    // r as is (FISTA momentum iterate; learned denoiser input)
+  RS_RTILDE_L = 3, // line 8 with the learned denoiser where the judge chose it (sel = 1)
+  RS_WHAT_L = 4,   // line 6 output with the learned denoiser where chosen
+  RS_PROBE = 5     // the Rademacher probe b of the divergence estimate (no input read)
 };
 
 // Modes of the column k-space pass.
@@ -56,7 +59,8 @@ enum RowAnalMode : int {
   RA_VDAMP_FIRST = 1,  // r_0 = coefficients
   RA_IMAGE = 2,        // no wavelet: write the image rows (line 10 output)
   RA_FISTA = 3,        // w = eta(v + g; lambda); v' = w + beta (w - w_prev)
-  RA_FISTA_FIRST = 4
+  RA_FISTA_FIRST = 4,
+  RA_LEARNED = 5       // as RA_VDAMP with r_tilde from the judged denoiser (RS_RTILDE_L)
 };
 
 struct KArgs {
@@ -84,6 +88,10 @@ struct KArgs {
   float* tau;
   float* tau_part;           // [total column strips][kMaxBands]
   float* trace;              // nullable [iters][B][nb][3]
+  float* smin;               // nullable [B][kMaxBands]: minimum SURE of soft thresholding
+  const int* sel;            // [B][kMaxBands]: 1 where the learned denoiser is used
+  float* jpart;              // [2][total row strips][kMaxBands] learned-denoiser partial sums
+  unsigned long long seed;   // probe generator seed
   int iter;
   float beta;                // FISTA momentum factor for this iteration
   int mode;

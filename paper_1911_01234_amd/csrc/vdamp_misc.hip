@@ -58,4 +58,74 @@ hipError_t launch_zero(float2* x, long long n, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Per-slice input scale of the learned denoiser: s0^2 = (1/N) sum_j w_j |y_j|^2 with
+// w = m / p (an unbiased estimate of the mean |x0|^2 plus noise, since E[m/p] = 1);
+// s0 = 1 when that sum is not positive.  One block per slice, fixed-order reduction.
+__global__ void __launch_bounds__(kThreads) k_scale(const SliceDev* __restrict__ slices,
+                                                    const float2* __restrict__ y,
+                                                    const float* __restrict__ wgt,
+                                                    float* __restrict__ s0) {
+  __shared__ double red[kThreads];
+  const SliceDev S = slices[blockIdx.x];
+  const long long n = (long long)S.ny * S.nx;
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < n; i += kThreads) {
+    const float2 v = y[S.off + i];
+    acc += (double)wgt[S.off + i] * ((double)v.x * v.x + (double)v.y * v.y);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double m = red[0] / (double)n;
+    s0[blockIdx.x] = (m > 0.0 && m < 1e300) ? (float)sqrt(m) : 1.0f;
+  }
+}
+
+// Judge of the learned denoiser against soft thresholding, per slice and subband: from
+// the strip partial sums D = sum |w_cnn - r|^2 and J = sum Re(conj(b) (J_g b)), the
+// divergence estimate alpha = J / N_b (mean Wirtinger derivative) and the denoiser's
+// SURE = D + (2 alpha - 1) N_b tau; the learned output is used (sel = 1, alpha replaced)
+// when its SURE is below soft thresholding's minimum and alpha <= 1 - 1/N_b (the range
+// soft thresholding's alpha has, which keeps line 8's division bounded).  always != 0:
+// no SURE comparison, only the bound on alpha.
+__global__ void k_judge(KArgs a, int nrowstrips, int always, int* __restrict__ sel,
+                        float* __restrict__ jout) {
+  const int sl = blockIdx.x, b = threadIdx.x;
+  if (sl >= a.batch || b >= a.nbands) return;
+  const SliceDev S = a.slices[sl];
+  const int s = a.levels, nstr = S.ny >> s;
+  double D = 0.0, J = 0.0;
+  for (int i = 0; i < nstr; ++i) {
+    D += (double)a.jpart[((long long)S.rowstrip0 + i) * kMaxBands + b];
+    J += (double)a.jpart[((long long)nrowstrips + S.rowstrip0 + i) * kMaxBands + b];
+  }
+  const int l = (b == 0) ? s : s - (b - 1) / 3;
+  const double Nb = (double)(S.ny >> l) * (double)(S.nx >> l);
+  const double tau = (double)a.tau[sl * kMaxBands + b];
+  const double al = J / Nb;
+  const double sure = D + (2.0 * al - 1.0) * Nb * tau;
+  const bool use = (always || sure < (double)a.smin[sl * kMaxBands + b]) && (al <= 1.0 - 1.0 / Nb);
+  sel[sl * kMaxBands + b] = use ? 1 : 0;
+  jout[sl * kMaxBands + b] = (float)sure;                             // the denoiser's SURE
+  jout[(a.batch + sl) * kMaxBands + b] = (float)al;                   // its alpha
+  jout[(2 * a.batch + sl) * kMaxBands + b] = a.smin[sl * kMaxBands + b];  // soft's SURE
+  if (use) a.alpha[sl * kMaxBands + b] = (float)al;
+}
+
+hipError_t launch_scale(const SliceDev* slices, int batch, const float2* y, const float* wgt,
+                        float* s0, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale, dim3(batch), dim3(kThreads), 0, st, slices, y, wgt, s0);
+  return hipGetLastError();
+}
+
+hipError_t launch_judge(const KArgs& a, int nrowstrips, int always, int* sel, float* jout,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_judge, dim3(a.batch), dim3(64), 0, st, a, nrowstrips, always, sel, jout);
+  return hipGetLastError();
+}
+
 }  // namespace vdamp

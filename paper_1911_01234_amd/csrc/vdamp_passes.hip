@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_synth(KArgs a, int do_fft) {
   const SliceDev S = a.slices[item.x];
   const int strip = item.y, s = a.levels, H = 1 << s, nx = S.nx, ny = S.ny;
   const int tid = threadIdx.x, mode = a.mode;
-  if (tid < kMaxBands) {
+  if (tid < kMaxBands && a.theta) {  // null for the plain transform Psi^H
     th_s[tid] = a.theta[item.x * kMaxBands + tid];
     t2_s[tid] = a.thr2[item.x * kMaxBands + tid];
     al_s[tid] = a.alpha[item.x * kMaxBands + tid];
@@ -35,20 +35,30 @@ __global__ void __launch_bounds__(kThreads) k_rows_synth(KArgs a, int do_fft) {
   constexpr int U = EPT / 2;
   const int half = nx >> 1, npairs = H * half;
   const float2* r = a.r + S.off;
-  float4 v[U];
+  const bool learned = (mode == RS_RTILDE_L || mode == RS_WHAT_L);
+  const float2* wc = learned ? a.r2 + S.off : nullptr;
+  float4 v[U], c4[U];
   int bnd[U];
+  long long gi[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int p = tid + u * kThreads;
     bnd[u] = 0;
+    gi[u] = 0;
+    v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    c4[u] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (p < npairs) {
       const int lr = p / half, lc = 2 * (p - lr * half);
       int b;
       const int gr = strip_to_global(lr, lc, strip, s, ny, nx, b);
       bnd[u] = b;
-      v[u] = *reinterpret_cast<const float4*>(r + (long long)gr * nx + lc);
+      gi[u] = (long long)gr * nx + lc;
+      if (mode != RS_PROBE) v[u] = *reinterpret_cast<const float4*>(r + gi[u]);
+      if (learned) c4[u] = *reinterpret_cast<const float4*>(wc + gi[u]);
     }
   }
+  __shared__ int sel_s[kMaxBands];
+  if (learned && tid < kMaxBands) sel_s[tid] = a.sel[item.x * kMaxBands + tid];
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -62,6 +72,20 @@ __global__ void __launch_bounds__(kThreads) k_rows_synth(KArgs a, int do_fft) {
       } else if (mode == RS_WHAT) {
         x0 = soft_c(x0, th_s[b], t2_s[b]);
         x1 = soft_c(x1, th_s[b], t2_s[b]);
+      } else if (mode == RS_RTILDE_L) {
+        if (sel_s[b]) {
+          x0 = rtilde_w(lo2(c4[u]), x0, al_s[b]);
+          x1 = rtilde_w(hi2(c4[u]), x1, al_s[b]);
+        } else {
+          x0 = rtilde_c(x0, th_s[b], t2_s[b], al_s[b]);
+          x1 = rtilde_c(x1, th_s[b], t2_s[b], al_s[b]);
+        }
+      } else if (mode == RS_WHAT_L) {
+        x0 = sel_s[b] ? lo2(c4[u]) : soft_c(x0, th_s[b], t2_s[b]);
+        x1 = sel_s[b] ? hi2(c4[u]) : soft_c(x1, th_s[b], t2_s[b]);
+      } else if (mode == RS_PROBE) {
+        x0 = probe_c(a.seed, a.iter, item.x, gi[u]);
+        x1 = probe_c(a.seed, a.iter, item.x, gi[u] + 1);
       }
       lds4[p] = pack4(x0, x1);  // LDS index lr * nx + lc = 2 p
     }
@@ -223,6 +247,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
   float2* lds = reinterpret_cast<float2*>(lds4);
   __shared__ float2 tw_s[kMaxN];
   __shared__ float th_s[kMaxBands], t2_s[kMaxBands], al_s[kMaxBands];
+  __shared__ int sel_s[kMaxBands];
   const int2 item = a.work[blockIdx.x];
   const SliceDev S = a.slices[item.x];
   const int strip = item.y, s = a.levels, H = 1 << s, nx = S.nx, ny = S.ny;
@@ -241,6 +266,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
     th_s[tid] = a.theta[item.x * kMaxBands + tid];
     t2_s[tid] = a.thr2[item.x * kMaxBands + tid];
     al_s[tid] = a.alpha[item.x * kMaxBands + tid];
+    if (mode == RA_LEARNED) sel_s[tid] = a.sel[item.x * kMaxBands + tid];
   }
   const FftPlanDev& P = a.ffts[S.fft_x];
   load_twiddles(tw_s, P, a.twiddles);
@@ -265,7 +291,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
   float2* r2 = a.r2 ? a.r2 + S.off : nullptr;
   const float lam = a.lambda ? a.lambda[item.x] : 0.f;
   const float lam2 = __fmul_rn(lam, lam);
-  const bool need_r = (mode == RA_VDAMP || mode == RA_FISTA);
+  const bool need_r = (mode == RA_VDAMP || mode == RA_FISTA || mode == RA_LEARNED);
   long long gi[U];
   int bnd[U];
   float4 ro[U], rw[U];
@@ -283,7 +309,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
       bnd[u] = b;
       gi[u] = (long long)gr * nx + lc;
       if (need_r) ro[u] = *reinterpret_cast<const float4*>(r + gi[u]);
-      if (mode == RA_FISTA) rw[u] = *reinterpret_cast<const float4*>(r2 + gi[u]);
+      if (mode == RA_FISTA || mode == RA_LEARNED) rw[u] = *reinterpret_cast<const float4*>(r2 + gi[u]);
     }
   }
 #pragma unroll
@@ -302,6 +328,11 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
             const float2 x = h ? hi2(ro[u]) : lo2(ro[u]);
             o[h] = cadd(rtilde_c(x, th_s[b], t2_s[b], al_s[b]), g);
           } break;
+          case RA_LEARNED: {
+            const float2 x = h ? hi2(ro[u]) : lo2(ro[u]);
+            const float2 wv = h ? hi2(rw[u]) : lo2(rw[u]);
+            o[h] = cadd(sel_s[b] ? rtilde_w(wv, x, al_s[b]) : rtilde_c(x, th_s[b], t2_s[b], al_s[b]), g);
+          } break;
           case RA_FISTA_FIRST: {
             w2[h] = soft_c(g, lam, lam2);
             o[h] = w2[h];
@@ -318,6 +349,98 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
       if (mode == RA_FISTA || mode == RA_FISTA_FIRST)
         *reinterpret_cast<float4*>(r2 + gi[u]) = pack4(w2[0], w2[1]);
     }
+  }
+}
+
+
+// ------------------------------------------------------------------ wave_anal
+// Learned-denoiser support (row strip): Psi of an image strip (no transform), then per
+// subband partial sums over the strip.  jmode 0: the image is the denoiser output; write
+// its coefficients w to r2 and sum |w - r|^2.  jmode 1: the image is the denoiser's
+// Jacobian applied to Psi^H b; sum Re(conj(b) w) with the probe b regenerated.  Partial
+// sums go to jpart[jmode][row strip][band], reduced in a fixed order.  jmode 2: only
+// write the coefficients to r2 (the plain transform Psi).
+template <int EPT>
+__global__ void __launch_bounds__(kThreads) k_wave_anal(KArgs a, int jmode) {
+  extern __shared__ float4 lds4[];
+  float2* lds = reinterpret_cast<float2*>(lds4);
+  __shared__ float red[kThreads / 64][kMaxBands];
+  const int2 item = a.work[blockIdx.x];
+  const SliceDev S = a.slices[item.x];
+  const int strip = item.y, s = a.levels, H = 1 << s, nx = S.nx, ny = S.ny;
+  const int tid = threadIdx.x;
+  constexpr int U = EPT / 2;
+  const int half = nx >> 1, npairs = H * half;
+  const float4* src = reinterpret_cast<const float4*>(a.X + S.off + (long long)strip * H * nx);
+  float4 v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (p < npairs) v[u] = src[p];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    if (p < npairs) lds4[p] = v[u];
+  }
+  __syncthreads();
+  haar_strip_anal<EPT>(lds, H, nx, s);
+  float2* r = a.r + S.off;
+  float2* wc = a.r2 + S.off;
+  long long gi[U];
+  int bnd[U];
+  float4 ro[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    bnd[u] = -1;
+    gi[u] = 0;
+    ro[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (p < npairs) {
+      const int lr = p / half, lc = 2 * (p - lr * half);
+      int b;
+      const int gr = strip_to_global(lr, lc, strip, s, ny, nx, b);
+      bnd[u] = b;
+      gi[u] = (long long)gr * nx + lc;
+      if (jmode == 0) ro[u] = *reinterpret_cast<const float4*>(r + gi[u]);
+    }
+  }
+  float cv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int p = tid + u * kThreads;
+    cv[u] = 0.f;
+    if (p < npairs) {
+      const float4 w = lds4[p];
+      if (jmode == 2) {
+        *reinterpret_cast<float4*>(wc + gi[u]) = w;
+      } else if (jmode == 0) {
+        *reinterpret_cast<float4*>(wc + gi[u]) = w;
+        const float d0 = w.x - ro[u].x, d1 = w.y - ro[u].y, d2 = w.z - ro[u].z, d3 = w.w - ro[u].w;
+        cv[u] = (d0 * d0 + d1 * d1) + (d2 * d2 + d3 * d3);
+      } else {
+        const float2 b0 = probe_c(a.seed, a.iter, item.x, gi[u]);
+        const float2 b1 = probe_c(a.seed, a.iter, item.x, gi[u] + 1);
+        cv[u] = (b0.x * w.x + b0.y * w.y) + (b1.x * w.z + b1.y * w.w);
+      }
+    }
+  }
+  if (jmode == 2) return;
+  const int lane = tid & 63, wid = tid >> 6;
+  for (int b = 0; b < a.nbands; ++b) {
+    float t = 0.f;
+#pragma unroll
+    for (int u = 0; u < U; ++u) t += (bnd[u] == b) ? cv[u] : 0.f;
+    t = wave_sum(t);
+    if (lane == 0) red[wid][b] = t;
+  }
+  __syncthreads();
+  if (tid < a.nbands) {
+    float t = 0.f;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) t += red[w][tid];
+    a.jpart[((long long)jmode * a.nwork + S.rowstrip0 + strip) * kMaxBands + tid] = t;
   }
 }
 
@@ -344,9 +467,18 @@ hipError_t launch_rows_anal(const KArgs& a, int ept, size_t lds, hipStream_t st)
   return hipGetLastError();
 }
 
+hipError_t launch_wave_anal(const KArgs& a, int ept, int jmode, size_t lds, hipStream_t st) {
+  if (ept == 16)
+    hipLaunchKernelGGL(k_wave_anal<16>, dim3(a.nwork), dim3(kThreads), lds, st, a, jmode);
+  else
+    hipLaunchKernelGGL(k_wave_anal<32>, dim3(a.nwork), dim3(kThreads), lds, st, a, jmode);
+  return hipGetLastError();
+}
+
 hipError_t set_lds_limits_passes(size_t rows, size_t cols) {
   const void* rk[] = {(const void*)k_rows_synth<16>, (const void*)k_rows_synth<32>,
-                      (const void*)k_rows_anal<16>, (const void*)k_rows_anal<32>};
+                      (const void*)k_rows_anal<16>, (const void*)k_rows_anal<32>,
+                      (const void*)k_wave_anal<16>, (const void*)k_wave_anal<32>};
   for (const void* f : rk) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rows);
     if (e != hipSuccess) return e;

@@ -297,6 +297,8 @@ __global__ void __launch_bounds__(NT) k_sure(KArgs a) {
       const double m = (double)(fi + 1);
       al = (float)(((Nbd - m) - 0.5 * (double)th * fR) / Nbd);
     }
+    if (a.smin)  // all-zero band: eta = 0 gives SURE = -N_b tau
+      a.smin[sl * kMaxBands + b] = (!(kmax > 0.f) || fi == 0x7fffffff) ? (float)(-Nbd * tau) : (float)fb;
     a.theta[sl * kMaxBands + b] = th;
     a.thr2[sl * kMaxBands + b] = th2;
     a.alpha[sl * kMaxBands + b] = al;

@@ -2,7 +2,8 @@
 solve runs in the library's HIP kernels; torch supplies device memory and streams.
 
 The names follow the C ABI in ``include/vdamp.h``: ``vdamp_plan``, ``vdamp_solve``,
-``fista_solve``, ``vdamp_state_export``, ``vdamp_pass_times``.
+``fista_solve``, ``vdamp_state_export``, ``vdamp_pass_times``, ``vdamp_wavelet``, the
+learned denoiser ``vdamp_cnn_*`` and ``vdamp_solve_learned``.
 """
 from __future__ import annotations
 
@@ -20,13 +21,23 @@ VDAMP_WAVELET_HAAR = 0
 VDAMP_FLAG_CHECK_FINITE = 1 << 2
 VDAMP_FLAG_USE_GRAPH = 1 << 3
 VDAMP_FLAG_TIMING = 1 << 5
-PASS_NAMES = ("prep", "rows_synth", "cols", "rows_anal", "sure")
+PASS_NAMES = ("prep", "rows_synth", "cols", "rows_anal", "sure", "denoiser")
+VDAMP_CNN_WS_FORWARD = 0
+VDAMP_CNN_WS_TRAIN = 1
+VDAMP_CNN_WS_SOLVE = 2
+VDAMP_JUDGE_SURE = 0
+VDAMP_JUDGE_NONE = 1
+# flat parameter order of the learned denoiser
+CNN_PARAM_ORDER = ("W1", "b1", "Wt", "W2", "b2", "W3", "b3", "W4", "b4", "W5", "b5", "W6", "b6")
 STATUS_NAMES = {0: "VDAMP_OK", 1: "VDAMP_ERR_ARG", 2: "VDAMP_ERR_SHAPE", 3: "VDAMP_ERR_UNSUPPORTED",
                 4: "VDAMP_ERR_WORKSPACE", 5: "VDAMP_ERR_HIP", 6: "VDAMP_ERR_NONFINITE",
                 7: "VDAMP_ERR_STATE"}
 
 EXPORTED = ("vdamp_plan", "vdamp_plan_destroy", "vdamp_solve", "fista_solve",
-            "vdamp_state_export", "vdamp_pass_times", "vdamp_status_string", "vdamp_last_error")
+            "vdamp_state_export", "vdamp_pass_times", "vdamp_status_string", "vdamp_last_error",
+            "vdamp_cnn_create", "vdamp_cnn_destroy", "vdamp_cnn_param_count", "vdamp_cnn_set_params",
+            "vdamp_cnn_get_params", "vdamp_cnn_workspace", "vdamp_cnn_forward", "vdamp_cnn_train_step",
+            "vdamp_solve_learned", "vdamp_learned_export", "vdamp_wavelet")
 
 
 class VdampError(RuntimeError):
@@ -65,6 +76,24 @@ def load_library() -> ctypes.CDLL:
     lib.vdamp_status_string.restype = ctypes.c_char_p
     lib.vdamp_last_error.argtypes = []
     lib.vdamp_last_error.restype = ctypes.c_char_p
+    u64 = ctypes.c_uint64
+    sigs = {
+        "vdamp_cnn_create": [ctypes.POINTER(vp), i32],
+        "vdamp_cnn_destroy": [vp],
+        "vdamp_cnn_param_count": [vp, ctypes.POINTER(ctypes.c_int64)],
+        "vdamp_cnn_set_params": [vp, vp, vp],
+        "vdamp_cnn_get_params": [vp, vp, vp, vp],
+        "vdamp_cnn_workspace": [vp, vp, i32, ctypes.POINTER(sz)],
+        "vdamp_cnn_forward": [vp, vp, vp, vp, sz, vp, vp, vp, vp, vp, vp],
+        "vdamp_cnn_train_step": [vp, vp, vp, vp, sz, vp, vp, vp, vp, ctypes.c_float, vp],
+        "vdamp_solve_learned": [vp, vp, vp, vp, sz, vp, sz, vp, vp, vp, vp, i32, i32, u64, vp, vp],
+        "vdamp_learned_export": [vp, vp, vp, vp, vp, vp, vp, vp, vp],
+        "vdamp_wavelet": [vp, vp, i32, vp, vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -149,6 +178,17 @@ class Plan:
         _check(load_library().vdamp_pass_times(self._h, ms, cnt, n))
         return {PASS_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
 
+    def vdamp_wavelet(self, x, out, inverse, stream=None):
+        _check(load_library().vdamp_wavelet(self._h, _stream_handle(stream), int(bool(inverse)),
+                                            _ptr(x), _ptr(out)))
+
+    def vdamp_solve_learned(self, cnn, ws, cnn_ws, y, mask, p, sigma2, iters, seed, x_hat,
+                            trace=None, judge=0, stream=None):
+        _check(load_library().vdamp_solve_learned(
+            self._h, cnn._h, _stream_handle(stream), _ptr(ws), ws.numel(), _ptr(cnn_ws),
+            cnn_ws.numel(), _ptr(y), _ptr(mask), _ptr(p), _ptr(sigma2), int(iters), int(judge),
+            ctypes.c_uint64(int(seed)), _ptr(x_hat), _ptr(trace)))
+
     # ---- marshalling helpers (host numpy <-> packed device tensors)
     def pack(self, arrays, dtype):
         """Concatenate per-slice 2D numpy arrays in plan order into one flat array."""
@@ -172,3 +212,81 @@ def to_device(plan: Plan, slices, device="cuda"):
     p = torch.from_numpy(plan.pack([s.p for s in slices], np.float32)).to(device)
     sigma2 = torch.tensor([s.sigma2 for s in slices], dtype=torch.float32, device=device)
     return y, mask, p, sigma2
+
+
+class Cnn:
+    """The learned denoiser (``vdamp_cnn_*``): FP32 master parameters, BF16 kernels."""
+
+    def __init__(self, nbands: int):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.vdamp_cnn_create(ctypes.byref(h), int(nbands)))
+        self._h = h
+        self.nbands = int(nbands)
+        n = ctypes.c_int64()
+        _check(lib.vdamp_cnn_param_count(self._h, ctypes.byref(n)))
+        self.param_count = int(n.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().vdamp_cnn_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat, stream=None):
+        _check(load_library().vdamp_cnn_set_params(self._h, _stream_handle(stream), _ptr(flat)))
+
+    def get_params(self, params=None, grad=None, stream=None):
+        _check(load_library().vdamp_cnn_get_params(self._h, _stream_handle(stream), _ptr(params),
+                                                   _ptr(grad)))
+
+    def workspace(self, plan: Plan, kind: int, device="cuda"):
+        import torch
+        b = ctypes.c_size_t()
+        _check(load_library().vdamp_cnn_workspace(self._h, plan._h, int(kind), ctypes.byref(b)))
+        return torch.empty(int(b.value), dtype=torch.uint8, device=device)
+
+    def forward(self, plan: Plan, ws, x, tau, s0, x_out, tangent=None, jvp_out=None, stream=None):
+        _check(load_library().vdamp_cnn_forward(self._h, plan._h, _stream_handle(stream), _ptr(ws),
+                                                ws.numel(), _ptr(x), _ptr(tau), _ptr(s0), _ptr(x_out),
+                                                _ptr(tangent), _ptr(jvp_out)))
+
+    def train_step(self, plan: Plan, ws, x, tau, s0, x0, lr, loss, stream=None):
+        _check(load_library().vdamp_cnn_train_step(self._h, plan._h, _stream_handle(stream), _ptr(ws),
+                                                   ws.numel(), _ptr(x), _ptr(tau), _ptr(s0), _ptr(x0),
+                                                   ctypes.c_float(float(lr)), _ptr(loss)))
+
+    def learned_export(self, plan: Plan, cnn_ws, sel=None, s0=None, sure_cnn=None, alpha_cnn=None,
+                       sure_soft=None, stream=None):
+        _check(load_library().vdamp_learned_export(self._h, plan._h, _stream_handle(stream), _ptr(cnn_ws),
+                                                   _ptr(sel), _ptr(s0), _ptr(sure_cnn), _ptr(alpha_cnn),
+                                                   _ptr(sure_soft)))
+
+
+def cnn_flatten(params) -> np.ndarray:
+    """Flatten a dict of denoiser parameters (W1..W6, b1..b6, Wt) in the library's order."""
+    return np.concatenate([np.asarray(params[k], dtype=np.float64).reshape(-1) for k in CNN_PARAM_ORDER])
+
+
+def cnn_unflatten(flat, nbands: int, channels: int = 48):
+    """Inverse of cnn_flatten."""
+    flat = np.asarray(flat)
+    shapes = {"W1": (channels, 2, 3, 3), "b1": (channels,), "Wt": (channels, nbands)}
+    for l in range(2, 6):
+        shapes[f"W{l}"] = (channels, channels, 3, 3)
+        shapes[f"b{l}"] = (channels,)
+    shapes["W6"] = (2, channels, 3, 3)
+    shapes["b6"] = (2,)
+    out, o = {}, 0
+    for k in CNN_PARAM_ORDER:
+        n = int(np.prod(shapes[k]))
+        out[k] = flat[o:o + n].reshape(shapes[k])
+        o += n
+    if o != flat.size:
+        raise ValueError("flat parameter vector has the wrong length")
+    return out
