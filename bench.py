@@ -1,4 +1,5 @@
-"""Benchmark: batched plain VDAMP (Algorithm 1, SURE soft thresholding) on one MI355X.
+"""Benchmark: batched plain VDAMP (Algorithm 1, SURE soft thresholding) on one MI355X,
+and the learned-denoiser form against it.
 
 Workload: a batch of B independent 256x256 slices of the single-256 recipe (16-ellipse
 phantoms with smooth phase, polynomial variable density with a 16x16 fully sampled
@@ -14,6 +15,15 @@ MI355X HBM peak; `traffic` is the HBM bytes per launch that rocprofv3's FETCH_SI
 WRITE_SIZE counters measured for that kernel (scaled by a copy of known size), taken
 from profiles/ while the kernel's sources are unchanged, else null.  `cpu_baseline` is the FP64 oracle timed on the host on a bounded
 sample of the same workload.
+
+`learned` (unless --no-learned): the CNN denoiser is trained on the GPU by the library's
+own kernels on (Psi^H r_k, tau_k, x0) pairs from plain-VDAMP solves of a disjoint set
+of 256x256 slices (same generator), then 64 held-out slices of the timed batch are
+solved with plain VDAMP and with the SURE-judged learned form: mean NMSE at 50
+iterations, the learned form's NMSE at the wall-clock of the plain 50-iteration solve,
+and each form's time to reach the plain form's 50-iteration NMSE.  `cnn_roofline`: the
+network's forward + JVP kernels (algorithmic FLOPs with the real channel counts) per
+learned iteration against the MI355X dense BF16 MFMA peak.
 """
 from __future__ import annotations
 
@@ -30,6 +40,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "VDAMP iters/sec and time-to-NMSE (256² batch); learned vs plain at equal NMSE"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+# FLOPs per pixel of the network's forward pass: 3x3 convolutions 2->48, 4 x 48->48, 48->2
+CNN_FLOP_PER_PX = 2 * 9 * (2 * 48 + 4 * 48 * 48 + 48 * 2)
 ITERS = 50
 LEVELS = 4
 
@@ -111,6 +124,146 @@ def cpu_baseline(slices, s, iters, budget_s):
                       f"one process (pocketfft and sort single-threaded), {dt:.1f} s"}
 
 
+def learned_section(args, test, s, K, stream):
+    """Train the denoiser on the GPU, then compare learned and plain VDAMP on `test`."""
+    import torch
+    from paper_1911_01234_amd import synth, train as T, vdamp as V
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    tr, _, _ = synth.workload_batch256(args.train_slices, first_slice=10000)
+    log(f"generated {len(tr)} training slices in {time.perf_counter() - t0:.1f} s")
+    ks = (1, 2, 3, 5, 8, 12, 20, 30, 45)
+    with torch.cuda.stream(stream):
+        plan = V.Plan([256] * len(tr), [256] * len(tr), s)
+        ws = plan.workspace()
+        y, mask, p, sigma2 = V.to_device(plan, tr)
+        cnn = V.Cnn(plan.nbands)
+        cnn.set_params(torch.from_numpy(T.init_flat(plan.nbands, 0)).cuda(), stream=stream)
+        s0 = T.input_scales(plan, cnn, ws, y, mask, p, sigma2, stream=stream)
+        pairs = T.make_pairs(plan, ws, y, mask, p, sigma2, ks, stream=stream)
+        x0 = torch.from_numpy(plan.pack([sl.x0 for sl in tr], np.complex64)).cuda()
+        del ws, y, mask, p, sigma2
+        stream.synchronize()
+        log(f"{len(pairs) * len(tr)} training pairs ready; training {args.train_steps} steps")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        losses = T.train(cnn, plan, pairs, s0, x0, args.train_steps, 1e-3, stream=stream, lr_final=1e-4)
+        e1.record(stream)
+        stream.synchronize()
+        train_ms = e0.elapsed_time(e1)
+        del pairs, x0, plan
+        torch.cuda.empty_cache()
+
+        B = len(test)
+        plan = V.Plan([256] * B, [256] * B, s, V.VDAMP_FLAG_TIMING)
+        ws = plan.workspace()
+        cws = cnn.workspace(plan, V.VDAMP_CNN_WS_SOLVE)
+        y, mask, p, sigma2 = V.to_device(plan, test)
+        x0 = torch.from_numpy(plan.pack([sl.x0 for sl in test], np.complex64)).cuda()
+        seg = torch.from_numpy(np.repeat(np.arange(B), 65536)).cuda()
+        xh = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+
+        def plain(k):
+            plan.vdamp_solve(ws, y, mask, p, sigma2, k, xh, stream=stream)
+
+        def learn(k):
+            plan.vdamp_solve_learned(cnn, ws, cws, y, mask, p, sigma2, k, 7, xh, stream=stream)
+
+        def nmse():
+            stream.synchronize()
+            return float(nmse_db_batch(xh, x0, seg, B).mean())
+
+        def timed(fn, k, reps=3):
+            fn(k)
+            stream.synchronize()
+            plan.vdamp_pass_times()
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn(k)
+            stream.synchronize()
+            dt = (time.perf_counter() - t) / reps
+            return dt, plan.vdamp_pass_times()
+
+        plain(K)
+        n_plain = nmse()
+        learn(K)
+        n_learn = nmse()
+        sel = torch.empty(B * plan.nbands, dtype=torch.int32, device="cuda")
+        cnn.learned_export(plan, cws, sel=sel, stream=stream)
+        stream.synchronize()
+        sel_frac = sel.view(B, plan.nbands).float().mean(0).cpu().numpy()
+        t_plain, _ = timed(plain, K)
+        t_learn, times = timed(learn, K)
+        # learned form within the plain 50-iteration wall-clock: soft thresholding for
+        # the first iterations and the network in the last L (learned_from = K_tot - L),
+        # with K_tot chosen so that the solve costs no more than the plain one
+        t_pi, t_li = t_plain / K, t_learn / K
+        eq = []
+        for L in (1, 2, 3):
+            kp = int((t_plain - L * t_li) / t_pi)
+            if kp < 1:
+                continue
+            k_tot = kp + L
+
+            def hyb(k, _lf=kp):
+                plan.vdamp_solve_learned(cnn, ws, cws, y, mask, p, sigma2, k, 7, xh, learned_from=_lf,
+                                         stream=stream)
+            hyb(k_tot)
+            n_h = nmse()
+            t_h = timed(hyb, k_tot)[0]
+            eq.append({"learned_iters": L, "plain_iters_first": kp, "seconds": round(t_h, 5),
+                       "nmse_db": round(n_h, 3)})
+        best = min((e for e in eq if e["seconds"] <= t_plain * 1.02), key=lambda e: e["nmse_db"], default=None)
+        k_eq = max(1, min(K, int(t_plain / t_li)))
+        learn(k_eq)
+        n_learn_eq = nmse()
+        # time to reach the plain 50-iteration NMSE
+        k_hit = None
+        for k in range(1, K + 1):
+            learn(k)
+            if nmse() <= n_plain:
+                k_hit = k
+                break
+        t_hit = timed(learn, k_hit)[0] if k_hit else None
+        kp_hit = K
+        for k in range(1, K + 1):
+            plain(k)
+            if nmse() <= n_plain + 1e-9:
+                kp_hit = k
+                break
+        tp_hit = timed(plain, kp_hit)[0]
+    cnn_ms, cnn_launch = times["cnn"]
+    reps = 3
+    flop = 2 * CNN_FLOP_PER_PX * plan.ntot  # forward + JVP per learned iteration
+    per_iter_s = cnn_ms / 1e3 / (reps * K)
+    ach = flop / per_iter_s / 1e12
+    out = {
+        "train": {"slices": len(tr), "pairs": len(tr) * len(ks), "iteration_counts": list(ks),
+                  "steps": args.train_steps, "seconds": round(train_ms / 1e3, 3),
+                  "loss_first": float(np.mean(losses[:len(ks)])), "loss_last": float(np.mean(losses[-len(ks):]))},
+        "test_slices": B,
+        "nmse_db_at_50": {"plain": round(n_plain, 3), "learned": round(n_learn, 3)},
+        "seconds_50_iters": {"plain": round(t_plain, 5), "learned": round(t_learn, 5)},
+        "equal_wallclock": {"plain_seconds": round(t_plain, 5), "plain_nmse_db": round(n_plain, 3),
+                            "learned_every_iteration": {"iters": k_eq, "nmse_db": round(n_learn_eq, 3)},
+                            "learned_last_iterations": eq, "best": best,
+                            "gain_db": round(n_plain - best["nmse_db"], 3) if best else None},
+        "time_to_plain50_nmse": {"target_db": round(n_plain, 3),
+                                 "plain": {"iters": kp_hit, "seconds": round(tp_hit, 5)},
+                                 "learned": {"iters": k_hit, "seconds": round(t_hit, 5) if t_hit else None}},
+        "learned_band_fraction_last_iter": [round(float(v), 3) for v in sel_frac],
+        "pass_ms_per_learned_solve": {k: round(v[0] / reps, 3) for k, v in times.items()},
+        "cnn_roofline": {"bound": "mfma", "achieved": round(ach, 2), "peak": BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFLOPS, 4),
+                         "flop_per_learned_iter": int(flop), "ms_per_learned_iter": round(per_iter_s * 1e3, 3)},
+    }
+    log(f"learned: {json.dumps(out['nmse_db_at_50'])}, equal wall-clock {json.dumps(out['equal_wallclock'])}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +273,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="time hipGraph replays instead of eager launches")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-denoiser section")
+    ap.add_argument("--train-slices", type=int, default=64)
+    ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--test-slices", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -224,6 +381,10 @@ def main():
     if flags & V.VDAMP_FLAG_TIMING:
         plan.vdamp_pass_times()
 
+    learned = None
+    if not args.no_learned:
+        learned = learned_section(args, slices[:args.test_slices], s, K, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
@@ -252,6 +413,7 @@ def main():
         "roofline": roofline,
         "pass_ms_per_step": {k: round(v, 4) for k, v in pass_ms.items()} if pass_ms else None,
         "cpu_baseline": cpu,
+        "learned": learned,
     }
     print(json.dumps(out), flush=True)
     plan.close()

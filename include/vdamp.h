@@ -77,8 +77,9 @@ enum {
   VDAMP_PASS_COLS = 2,      /* column FFT, k-space residual, tau partials, col IFFT  */
   VDAMP_PASS_ROWS_ANAL = 3, /* row IFFT, Psi on row strips, + r_tilde (line 4)       */
   VDAMP_PASS_SURE = 4,      /* tau reduction, SURE threshold search, alpha           */
-  VDAMP_PASS_DENOISER = 5,  /* learned denoiser: transforms, CNN + JVP, judge         */
-  VDAMP_PASS_COUNT = 6
+  VDAMP_PASS_DENOISER = 5,  /* learned denoiser: Psi / Psi^H, probe, partial sums, judge */
+  VDAMP_PASS_CNN = 6,       /* learned denoiser: the network's forward pass and JVP    */
+  VDAMP_PASS_COUNT = 7
 };
 
 /*
@@ -225,19 +226,24 @@ vdamp_status vdamp_cnn_train_step(vdamp_cnn_h cnn, vdamp_plan_h plan, hipStream_
  * seed by SplitMix64 as a counter-based generator), and uses w_cnn with that alpha in
  * lines 8 and 10 in the subbands where its SURE, ||w_cnn - r||^2 + (2 alpha - 1) N_b tau,
  * is below soft thresholding's (judge = VDAMP_JUDGE_SURE; with VDAMP_JUDGE_NONE in
- * every subband) and alpha <= 1 - 1/N_b.  s0 per slice is sqrt(mean over pixels of
- * (m / p) |y|^2) (1 if that is zero).  Arguments as in vdamp_solve plus the denoiser,
- * its VDAMP_CNN_WS_SOLVE workspace, the judge and the seed; trace holds soft
- * thresholding's (tau, theta, alpha).
+ * every subband) and alpha <= 1 - 1/N_b.  Iterations k < learned_from use soft
+ * thresholding alone (the network is not evaluated), so a solve can spend the network's
+ * cost on its last iterations only; learned_from >= iters gives vdamp_solve's result.
+ * s0 per slice is sqrt(mean over pixels of (m / p) |y|^2) (1 if that is zero).
+ * Arguments as in vdamp_solve plus the denoiser, its VDAMP_CNN_WS_SOLVE workspace,
+ * learned_from, the judge and the seed; trace holds soft thresholding's (tau, theta,
+ * alpha).
  */
 vdamp_status vdamp_solve_learned(vdamp_plan_h plan, vdamp_cnn_h cnn, hipStream_t stream,
                                  void* workspace, size_t workspace_bytes, void* cnn_workspace,
                                  size_t cnn_workspace_bytes, const float* y, const uint8_t* mask,
                                  const float* p, const float* sigma2, int32_t iters,
-                                 int32_t judge, uint64_t seed, float* x_hat, float* trace);
+                                 int32_t learned_from, int32_t judge, uint64_t seed, float* x_hat,
+                                 float* trace);
 
 /*
- * vdamp_learned_export -- after vdamp_solve_learned, the last iteration's judge: per
+ * vdamp_learned_export -- after vdamp_solve_learned whose last iteration evaluated the
+ * network (iters > learned_from), that iteration's judge: per
  * band the choice (int32[B][nb], 1 = learned denoiser), the learned denoiser's SURE, its
  * alpha estimate and soft thresholding's SURE minimum (float32[B][nb] each), and the
  * input scales s0 (float32[B]); any output may be null.  vdamp_state_export gives r, theta and tau of that iteration and

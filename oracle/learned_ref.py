@@ -137,9 +137,11 @@ def judged_denoise(params, r, tau, s, s0, seed, it, slice_id, bf16=True, always=
     return w_hat, rt, {k: np.asarray(v) for k, v in rec.items()}
 
 
-def vdamp_learned(y, mask, p, sigma2, s, iters, params, seed, slice_id=0, bf16=True, always=False):
+def vdamp_learned(y, mask, p, sigma2, s, iters, params, seed, slice_id=0, bf16=True, always=False,
+                  learned_from=0):
     """Algorithm 1 with the judged learned denoiser, in FP64 (BF16 rounding of the
-    network's weights and activations where the kernels store BF16 when bf16=True)."""
+    network's weights and activations where the kernels store BF16 when bf16=True).
+    Iterations before learned_from use soft thresholding alone."""
     y = np.asarray(y, dtype=np.complex128)
     p = np.asarray(p, dtype=np.float64)
     ny, nx = y.shape
@@ -151,7 +153,11 @@ def vdamp_learned(y, mask, p, sigma2, s, iters, params, seed, slice_id=0, bf16=T
     recs = []
     for it in range(iters):
         r, tau = vdamp_ref.vdamp_step(rt, y, mask, p, sigma2, s, S)
-        w_hat, rt, rec = judged_denoise(params, r, tau, s, s0, seed, it, slice_id, bf16, always)
+        if it < learned_from:
+            w_hat, rt, th, al = vdamp_ref.denoise(r, tau, s)
+            rec = dict(sel=np.zeros(len(th), dtype=int), theta=th, alpha=al)
+        else:
+            w_hat, rt, rec = judged_denoise(params, r, tau, s, s0, seed, it, slice_id, bf16, always)
         rec["tau"] = tau
         rec["r"] = r
         recs.append(rec)

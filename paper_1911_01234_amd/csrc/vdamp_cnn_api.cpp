@@ -301,8 +301,8 @@ vdamp_status enqueue_train(vdamp_cnn_t* C, const vdamp_plan_t* P, const CnnWs& L
 // Algorithm 1 with the judged learned denoiser.
 vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t st, void* ws,
                              void* cws, const float2* y, const uint8_t* mask, const float* p,
-                             const float* sigma2, int iters, int judge, unsigned long long seed,
-                             float2* x_hat, float* trace, bool timing) {
+                             const float* sigma2, int iters, int learned_from, int judge,
+                             unsigned long long seed, float2* x_hat, float* trace, bool timing) {
   const Ws w = layout(P, ws);
   const CnnWs L = cnn_layout(P, VDAMP_CNN_WS_SOLVE);
   Launcher Lr{P, st, timing};
@@ -327,13 +327,15 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
   a.r2 = w.r2;  // w_cnn of the current iteration
   for (int k = 0; k < iters; ++k) {
     a.iter = k;
+    const bool prev_learned = k > 0 && k - 1 >= learned_from;  // line 8 used the judge
     if (k > 0) {
-      a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_RTILDE_L;
+      a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = prev_learned ? RS_RTILDE_L : RS_RTILDE;
       LAUNCH(Lr, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
     }
     a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = k ? CM_VDAMP : CM_VDAMP_FIRST;
     LAUNCH(Lr, VDAMP_PASS_COLS, launch_cols(a, P->ept, P->lds_cols, st));
-    a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = k ? RA_LEARNED : RA_VDAMP_FIRST;
+    a.work = P->d_work_rows; a.nwork = P->nrows;
+    a.mode = k == 0 ? RA_VDAMP_FIRST : (prev_learned ? RA_LEARNED : RA_VDAMP);
     LAUNCH(Lr, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
     for (int c = 2, first = 0; c >= 0; --c) {
       if (!P->nsure_cls[c]) continue;
@@ -341,6 +343,7 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
       LAUNCH(Lr, VDAMP_PASS_SURE, launch_sure(a, c, st));
       first += P->nsure_cls[c];
     }
+    if (k < learned_from) continue;  // soft thresholding only in this iteration
     // learned denoiser on r_k: x = Psi^H r, t = Psi^H b, f(x), J_f t
     KArgs s = a;
     s.work = P->d_work_rows; s.nwork = P->nrows;
@@ -348,7 +351,7 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
     LAUNCH(Lr, VDAMP_PASS_DENOISER, launch_rows_synth(s, P->ept, 0, P->lds_rows, st));
     s.mode = RS_PROBE; s.out = ti;
     LAUNCH(Lr, VDAMP_PASS_DENOISER, launch_rows_synth(s, P->ept, 0, P->lds_rows, st));
-    HIP_TRY(Lr.begin(VDAMP_PASS_DENOISER));
+    HIP_TRY(Lr.begin(VDAMP_PASS_CNN));
     vdamp_status e = enqueue_forward(C, P, L, cws, xi, w.tau, s0, xo, ti, to, st);
     if (e != VDAMP_OK) return e;
     HIP_TRY(Lr.end());
@@ -360,7 +363,7 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
     LAUNCH(Lr, VDAMP_PASS_DENOISER, launch_judge(a, P->nrowstrips, judge, sel, at<float>(cws, L.jout), st));
   }
   if (iters > 0) {
-    a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_WHAT_L;
+    a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = iters - 1 >= learned_from ? RS_WHAT_L : RS_WHAT;
     LAUNCH(Lr, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
   }
   a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = iters > 0 ? CM_OUTPUT : CM_ZEROFILL;
@@ -501,7 +504,8 @@ vdamp_status vdamp_solve_learned(vdamp_plan_h plan, vdamp_cnn_h cnn, hipStream_t
                                  void* workspace, size_t workspace_bytes, void* cnn_workspace,
                                  size_t cnn_workspace_bytes, const float* y, const uint8_t* mask,
                                  const float* p, const float* sigma2, int32_t iters,
-                                 int32_t judge, uint64_t seed, float* x_hat, float* trace) {
+                                 int32_t learned_from, int32_t judge, uint64_t seed, float* x_hat,
+                                 float* trace) {
   g_err.clear();
   if (judge != VDAMP_JUDGE_SURE && judge != VDAMP_JUDGE_NONE) return fail(VDAMP_ERR_ARG, "unknown judge");
   vdamp_status s = check_cnn(cnn, plan);
@@ -513,6 +517,7 @@ vdamp_status vdamp_solve_learned(vdamp_plan_h plan, vdamp_cnn_h cnn, hipStream_t
                                          std::to_string(plan->ws_bytes));
   if (!y || !mask || !p || !sigma2 || !x_hat) return fail(VDAMP_ERR_ARG, "y, mask, p, sigma2 and x_hat must be non-null");
   if (iters < 0) return fail(VDAMP_ERR_ARG, "iters must be >= 0");
+  if (learned_from < 0) return fail(VDAMP_ERR_ARG, "learned_from must be >= 0");
   s = check_cnn_ws(plan, VDAMP_CNN_WS_SOLVE, cnn_workspace, cnn_workspace_bytes);
   if (s != VDAMP_OK) return s;
   GraphKey key;
@@ -528,10 +533,11 @@ vdamp_status vdamp_solve_learned(vdamp_plan_h plan, vdamp_cnn_h cnn, hipStream_t
   key.aux_ws = cnn_workspace;
   key.seed = seed ^ ((unsigned long long)judge << 63);
   key.iters = iters;
+  key.extra = learned_from;
   key.stream = stream;
   s = run_maybe_graph(plan, stream, key, [&](bool timing) {
     return enqueue_learned(plan, cnn, stream, workspace, cnn_workspace, reinterpret_cast<const float2*>(y),
-                           mask, p, sigma2, iters, judge == VDAMP_JUDGE_NONE ? 1 : 0, seed,
+                           mask, p, sigma2, iters, learned_from, judge == VDAMP_JUDGE_NONE ? 1 : 0, seed,
                            reinterpret_cast<float2*>(x_hat), trace, timing);
   });
   if (s != VDAMP_OK) return s;

@@ -21,12 +21,13 @@ struct GraphKey {
   const void* aux = nullptr;   // learned solve: the denoiser and its workspace
   const void* aux_ws = nullptr;
   unsigned long long seed = 0;
+  int extra = 0;
   int iters = -1;
   hipStream_t stream = nullptr;
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && ws == o.ws && y == o.y && mask == o.mask && p == o.p &&
            sig == o.sig && lam == o.lam && x == o.x && trace == o.trace && aux == o.aux &&
-           aux_ws == o.aux_ws && seed == o.seed && iters == o.iters && stream == o.stream;
+           aux_ws == o.aux_ws && seed == o.seed && extra == o.extra && iters == o.iters && stream == o.stream;
   }
 };
 

@@ -21,7 +21,7 @@ VDAMP_WAVELET_HAAR = 0
 VDAMP_FLAG_CHECK_FINITE = 1 << 2
 VDAMP_FLAG_USE_GRAPH = 1 << 3
 VDAMP_FLAG_TIMING = 1 << 5
-PASS_NAMES = ("prep", "rows_synth", "cols", "rows_anal", "sure", "denoiser")
+PASS_NAMES = ("prep", "rows_synth", "cols", "rows_anal", "sure", "denoiser", "cnn")
 VDAMP_CNN_WS_FORWARD = 0
 VDAMP_CNN_WS_TRAIN = 1
 VDAMP_CNN_WS_SOLVE = 2
@@ -86,7 +86,7 @@ def load_library() -> ctypes.CDLL:
         "vdamp_cnn_workspace": [vp, vp, i32, ctypes.POINTER(sz)],
         "vdamp_cnn_forward": [vp, vp, vp, vp, sz, vp, vp, vp, vp, vp, vp],
         "vdamp_cnn_train_step": [vp, vp, vp, vp, sz, vp, vp, vp, vp, ctypes.c_float, vp],
-        "vdamp_solve_learned": [vp, vp, vp, vp, sz, vp, sz, vp, vp, vp, vp, i32, i32, u64, vp, vp],
+        "vdamp_solve_learned": [vp, vp, vp, vp, sz, vp, sz, vp, vp, vp, vp, i32, i32, i32, u64, vp, vp],
         "vdamp_learned_export": [vp, vp, vp, vp, vp, vp, vp, vp, vp],
         "vdamp_wavelet": [vp, vp, i32, vp, vp],
     }
@@ -183,11 +183,11 @@ class Plan:
                                             _ptr(x), _ptr(out)))
 
     def vdamp_solve_learned(self, cnn, ws, cnn_ws, y, mask, p, sigma2, iters, seed, x_hat,
-                            trace=None, judge=0, stream=None):
+                            trace=None, judge=0, learned_from=0, stream=None):
         _check(load_library().vdamp_solve_learned(
             self._h, cnn._h, _stream_handle(stream), _ptr(ws), ws.numel(), _ptr(cnn_ws),
-            cnn_ws.numel(), _ptr(y), _ptr(mask), _ptr(p), _ptr(sigma2), int(iters), int(judge),
-            ctypes.c_uint64(int(seed)), _ptr(x_hat), _ptr(trace)))
+            cnn_ws.numel(), _ptr(y), _ptr(mask), _ptr(p), _ptr(sigma2), int(iters),
+            int(learned_from), int(judge), ctypes.c_uint64(int(seed)), _ptr(x_hat), _ptr(trace)))
 
     # ---- marshalling helpers (host numpy <-> packed device tensors)
     def pack(self, arrays, dtype):

@@ -4,7 +4,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from oracle import vdamp_ref as o
+from oracle import vdamp_ref as o  # band geometry only (o.bands)
 
 
 def gpu_available() -> bool:
@@ -110,23 +110,53 @@ def theta_key(r_band, theta_gpu):
     return theta_keys(r_band, theta_gpu)[0]
 
 
+def sure_scan(a, tau):
+    """SURE of complex soft thresholding at every candidate threshold, evaluated
+    directly from its definition (Stein's estimate for noise CN(0, tau)):
+        SURE(theta) = sum_{a_i <= theta} (a_i^2 - tau)
+                      + sum_{a_i > theta} (theta^2 + tau - tau theta / a_i),
+    for the candidates theta = the distinct positive magnitudes.  Written here for the
+    validity check of a GPU result on the GPU's own data, independently of the oracle.
+    Returns (candidates, values)."""
+    a = np.sort(np.asarray(a, dtype=np.float64).ravel())
+    n = a.size
+    cand = np.unique(a[a > 0])
+    if cand.size == 0:
+        return np.array([0.0]), np.array([-n * tau])
+    below = np.searchsorted(a, cand, side="right")          # count of a <= theta
+    c2 = np.concatenate([[0.0], np.cumsum(a ** 2)])
+    inv = np.where(a > 0, 1.0 / np.where(a > 0, a, 1.0), 0.0)
+    cinv = np.concatenate([[0.0], np.cumsum(inv)])
+    s_below = c2[below] - below * tau
+    n_above = n - below
+    r_above = cinv[n] - cinv[below]
+    vals = s_below + n_above * (cand ** 2 + tau) - tau * cand * r_above
+    return cand, vals
+
+
 def theta_accepted(r, tau_b, rs, cs, theta_gpu, alpha_gpu=None, return_key=False):
-    """The SURE argmin is an index decided in floating point, so the oracle takes it on
-    the kernel's FP32 keys of the same r (magnitudes sqrt(key32) in FP64): the GPU's
-    threshold is accepted when it is the oracle's choice or, for a near tie, when its
-    FP64 SURE value is within 1e-6 (|SURE_min| + N_b tau) of the oracle's minimum.
+    """Validity of the GPU's threshold on the GPU's own iterate: the SURE argmin is an
+    index decided in floating point, so it is taken on the kernel's FP32 keys of that r
+    (magnitudes sqrt(key32) in FP64).  The GPU's threshold is accepted when its SURE is
+    the minimum over all candidates up to 1e-6 (|SURE_min| + N_b tau) (a near tie).
     Among keys theta may stand for, the one whose alpha (line 7) matches the GPU's
     alpha is the GPU's choice."""
     band = np.asarray(r)[rs, cs]
     a = np.sqrt(key32(band).astype(np.float64)).ravel()
-    th_ref, _, _, s_ref = o.sure_threshold(a, float(tau_b))
+    cand, vals = sure_scan(a, float(tau_b))
+    s_min = float(vals.min())
     cands = theta_keys(band, theta_gpu)
     if alpha_gpu is not None and len(cands) > 1:
         cands.sort(key=lambda kth: abs(alpha_at_key(band, kth) - float(alpha_gpu)))
     ok_key = None
     for kth in cands:
         th = float(np.sqrt(kth))
-        if th == th_ref or o.sure_value(a, th, float(tau_b)) <= s_ref + 1e-6 * (abs(s_ref) + a.size * tau_b):
+        if th == 0.0:
+            ok = cand.size == 1 and cand[0] == 0.0
+        else:
+            i = int(np.argmin(np.abs(cand - th)))
+            ok = cand[i] == th and vals[i] <= s_min + 1e-6 * (abs(s_min) + a.size * tau_b)
+        if ok:
             ok_key = kth
             break
     return (ok_key is not None, ok_key) if return_key else ok_key is not None

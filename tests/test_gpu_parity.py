@@ -1,14 +1,19 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded
-inputs.  Tolerances: relative L2 <= 1e-5 per iterate (FP32 arithmetic against FP64),
-final NMSE within 0.05 dB, tau to 1e-5 relative, SURE thresholds equal or accepted by
-the near-tie rule (gpu_helpers.theta_accepted).  The measured errors are printed."""
+inputs.  Every oracle run starts from the seeded synthetic inputs; no GPU result is fed
+to the oracle.  Tolerances: relative L2 <= 1e-5 per iterate (FP32 arithmetic against
+FP64), final NMSE within 0.05 dB, tau to 1e-5 relative (1e-4 along a trajectory).
+Where the two legitimately part (a SURE near tie decided differently in FP32 and FP64,
+after which both are valid trajectories), the GPU's threshold is checked for validity
+on the GPU's own iterate by test code (gpu_helpers.theta_accepted), and the final NMSE
+against the spread of oracle runs on inputs perturbed at FP32 rounding scale.  The
+measured errors are printed."""
 import numpy as np
 import pytest
 
 from oracle import vdamp_ref as o
 from paper_1911_01234_amd import synth
 
-from gpu_helpers import alpha_at_key, key32, rel_l2, run_fista, run_vdamp, snap_theta, theta_accepted, theta_key
+from gpu_helpers import rel_l2, run_fista, run_vdamp, snap_theta, theta_accepted
 
 pytestmark = pytest.mark.gpu
 
@@ -19,53 +24,6 @@ TOL_NMSE_DB = 0.05
 
 def _bands(sl, s):
     return o.bands(sl.y.shape[0], sl.y.shape[1], s)
-
-
-def one_step_check(sl, s, k):
-    """Feed the oracle the GPU state after k iterations (r_{k-1}, tau_{k-1}); one oracle
-    step must reproduce the GPU's theta_{k-1}, alpha_{k-1}, r_k and tau_k."""
-    g0 = run_vdamp([sl], s, k, want_state=True)
-    g1 = run_vdamp([sl], s, k + 1, want_state=True)
-    r_prev = g0["r"][0].astype(np.complex128)
-    tau_prev = g0["tau"][0].astype(np.float64)
-    ny, nx = sl.y.shape
-    bl = _bands(sl, s)
-    th_use, al_use = [], []
-    flips = 0
-    for b, (rs, cs, _, _) in enumerate(bl):
-        th_gpu = float(g0["theta"][0][b])
-        ok, kth = theta_accepted(r_prev, tau_prev[b], rs, cs, th_gpu, alpha_gpu=g0["alpha"][0][b],
-                                 return_key=True)
-        assert ok, (k, b, th_gpu)
-        a = np.sqrt(key32(r_prev[rs, cs]).astype(np.float64))
-        flips += np.sqrt(kth) != o.sure_threshold(a, tau_prev[b])[0]
-        # alpha at the GPU's threshold with the kernel's membership |r|^2 <= theta^2
-        al_def = alpha_at_key(r_prev[rs, cs], kth)
-        assert abs(g0["alpha"][0][b] - al_def) <= 1e-5, (k, b)
-        th_use.append(np.sqrt(kth))
-        al_use.append(al_def)
-    # step with the GPU's (accepted) thresholds and their alpha
-    _, rt, _, _ = o.denoise(r_prev, tau_prev, s, theta_override=th_use, alpha_override=al_use)
-    S = o.tau_weights(ny, nx, s)
-    r_k, tau_k = o.vdamp_step(rt, sl.y, sl.mask, sl.p, sl.sigma2, s, S)
-    e_r = rel_l2(g1["r"][0], r_k)
-    e_tau = np.max(np.abs(g1["tau"][0] - tau_k) / np.abs(tau_k))
-    print(f"one-step k={k}: rel L2 r = {e_r:.2e}, max rel tau = {e_tau:.2e}, "
-          f"near-tie threshold flips {flips}")
-    assert e_r <= TOL_ITER
-    assert e_tau <= TOL_TAU
-
-
-@pytest.mark.parametrize("k", [1, 2, 5, 15, 29])
-def test_one_step_64(k):
-    sl = synth.workload_single64()[0][0]
-    one_step_check(sl, 3, k)
-
-
-@pytest.mark.parametrize("R,k", [(4.0, 1), (4.0, 10), (6.0, 3), (8.0, 1), (8.0, 25), (8.0, 49)])
-def test_one_step_256(R, k):
-    sl = synth.workload_single256(R)[0][0]
-    one_step_check(sl, 4, k)
 
 
 def test_first_iteration_r0():
@@ -257,10 +215,17 @@ def test_fista_zero_iterations():
     assert np.all(got[0] == 0)
 
 
-def test_one_step_320_big_bands():
-    """320x320: finest bands of 25600 keys (the 1024-thread search)."""
+def test_free_running_320_big_bands():
+    """320x320: finest bands of 25600 keys (the 1024-thread search, 32 keys a thread)."""
     sl = synth.make_slice(9, 0, 320, 320, 16, 6.0, 6.0, 16, 35.0)
-    one_step_check(sl, 4, 3)
+    free_running(sl, 4, 12)
+
+
+@pytest.mark.parametrize("n", [128, 192])
+def test_free_running_mixed_sizes(n):
+    """Sizes of the mixed-size batch with non-power-of-two factors (192 = 2^6 3)."""
+    sl = synth.make_slice(3, n, n, n, 16, 6.0, 6.0, 16, 35.0)
+    free_running(sl, 4, 20)
 
 
 def test_all_zero_measurements():
@@ -287,3 +252,54 @@ def test_noise_free_full_sampling_tau_zero():
     e = rel_l2(g["x_hat"][0], ref["x_hat"])
     print(f"tau = 0 case: x_hat rel L2 {e:.2e}")
     assert e <= TOL_ITER
+
+
+def sampled_trace_parity(g, b, sl, s, K, runs=6):
+    """Slice b of a batched solve: its (tau, theta, alpha) trace must match the oracle's
+    trajectory of that slice until the first near-tie flip, and its final NMSE the
+    oracle's (or, after a flip, the envelope of perturbed oracle runs)."""
+    ref = o.vdamp(sl.y, sl.mask, sl.p, sl.sigma2, s, K, record=True)
+    tr = g["trace"][:, b]
+    flip = None
+    for k in range(K):
+        same = all(snap_theta(ref["r"][k][rs, cs], tr[k, bb, 1]) == ref["theta"][k][bb]
+                   for bb, (rs, cs, _, _) in enumerate(_bands(sl, s)))
+        if not same:
+            flip = k
+            break
+        assert np.max(np.abs(tr[k, :, 0] - ref["tau"][k]) / ref["tau"][k]) <= 1e-4, (b, k)
+        assert np.max(np.abs(tr[k, :, 2] - ref["alpha"][k])) <= 1e-5, (b, k)
+    n_gpu = o.nmse_db(g["x_hat"][b], sl.x0)
+    n_ref = o.nmse_db(ref["x_hat"], sl.x0)
+    print(f"  slice {b} ({sl.y.shape[0]}x{sl.y.shape[1]}): first theta difference at iteration "
+          f"{flip}; NMSE gpu {n_gpu:.3f} dB, oracle {n_ref:.3f} dB", flush=True)
+    if flip is None:
+        assert abs(n_gpu - n_ref) <= TOL_NMSE_DB
+    elif abs(n_gpu - n_ref) > TOL_NMSE_DB:
+        mean, sd = oracle_nmse_envelope(sl, s, K, n_ref, runs=runs)
+        print(f"    oracle envelope: mean {mean:.3f} dB, sd {sd:.3f} dB", flush=True)
+        assert abs(n_gpu - mean) <= max(TOL_NMSE_DB, 4 * sd)
+
+
+def test_full_batch_256_sampled():
+    """The benchmark's configuration (256 slices of 256x256, 4 levels, 50 iterations,
+    eager launches with per-kernel timing events): sampled slices against the oracle."""
+    from paper_1911_01234_amd import vdamp as V
+    slices, s, K = synth.workload_batch256(256)
+    g = run_vdamp(slices, s, K, flags=V.VDAMP_FLAG_TIMING)
+    print(f"batch of {len(slices)} solved", flush=True)
+    for b in (0, 101, 255):
+        sampled_trace_parity(g, b, slices[b], s, K)
+
+
+def test_mixed_size_batch_sampled():
+    """The ragged batch of 512 slices (128, 192, 256 and 320 square, R 4-10, 30-40 dB)
+    as one plan: one sampled slice of each size against the oracle."""
+    slices, s, K = synth.workload_mixed()
+    g = run_vdamp(slices, s, K)
+    print(f"mixed batch of {len(slices)} solved", flush=True)
+    seen = {}
+    for b, sl in enumerate(slices):
+        seen.setdefault(sl.y.shape[0], b)
+    for n, b in sorted(seen.items()):
+        sampled_trace_parity(g, b, slices[b], s, K)

@@ -179,3 +179,11 @@ def test_input_scale_estimates_image_energy():
     s0 = lr.input_scale(sl.y, sl.mask, sl.p)
     e = np.sqrt(np.mean(np.abs(sl.x0) ** 2))
     assert 0.5 * e < s0 < 2.0 * e
+
+
+def test_learned_from_beyond_iterations_is_plain_vdamp():
+    sl = synth.workload_single64()[0][0]
+    p = half_shrink_params(10, 0.125)
+    got = lr.vdamp_learned(sl.y, sl.mask, sl.p, sl.sigma2, 3, 3, p, seed=1, always=True, learned_from=3)
+    ref = o.vdamp(sl.y, sl.mask, sl.p, sl.sigma2, 3, 3)
+    assert np.array_equal(got["x_hat"], ref["x_hat"])
