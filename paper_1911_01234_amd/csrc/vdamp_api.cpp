@@ -133,8 +133,8 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
       a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_RTILDE;
       LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
     }
-    a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = k ? CM_VDAMP : CM_VDAMP_FIRST;
-    LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->ept, P->lds_cols, st));
+    a.mode = k ? CM_VDAMP : CM_VDAMP_FIRST;
+    LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
     a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = k ? RA_VDAMP : RA_VDAMP_FIRST;
     LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
     for (int c = 2, first = 0; c >= 0; --c) {
@@ -149,8 +149,8 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
     a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_WHAT;
     LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
   }
-  a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = iters > 0 ? CM_OUTPUT : CM_ZEROFILL;
-  LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->ept, P->lds_cols, st));
+  a.mode = iters > 0 ? CM_OUTPUT : CM_ZEROFILL;
+  LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
   a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RA_IMAGE;
   LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
   return VDAMP_OK;
@@ -176,8 +176,8 @@ vdamp_status enqueue_fista(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
       a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_PLAIN;
       LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
     }
-    a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = k ? CM_FISTA : CM_FISTA_FIRST;
-    LAUNCH(L, VDAMP_PASS_COLS, launch_cols(a, P->ept, P->lds_cols, st));
+    a.mode = k ? CM_FISTA : CM_FISTA_FIRST;
+    LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
     a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = k ? RA_FISTA : RA_FISTA_FIRST;
     LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
   }
@@ -364,6 +364,13 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   vs.insert(vs.end(), vss.begin(), vss.end());
   P->nrows = (int)vr.size();
   P->ncols = (int)vc.size();
+  for (int i = 0; i < P->ncols;) {
+    const int n = ny[vc[i].x];
+    int j = i;
+    while (j < P->ncols && ny[vc[j].x] == n) ++j;
+    P->col_groups.push_back({i, j - i, cols4_supported(n) ? n / 16 : 0});
+    i = j;
+  }
   P->lds_rows = sizeof(float2) * (size_t)H * maxnx;
   P->lds_cols = sizeof(float2) * (size_t)maxny * kColW;
   P->ept = (H * maxnx <= 16 * kThreads && maxny * kColW <= 16 * kThreads) ? 16 : 32;

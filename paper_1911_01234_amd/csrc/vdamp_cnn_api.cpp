@@ -332,8 +332,8 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
       a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = prev_learned ? RS_RTILDE_L : RS_RTILDE;
       LAUNCH(Lr, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
     }
-    a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = k ? CM_VDAMP : CM_VDAMP_FIRST;
-    LAUNCH(Lr, VDAMP_PASS_COLS, launch_cols(a, P->ept, P->lds_cols, st));
+    a.mode = k ? CM_VDAMP : CM_VDAMP_FIRST;
+    LAUNCH(Lr, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
     a.work = P->d_work_rows; a.nwork = P->nrows;
     a.mode = k == 0 ? RA_VDAMP_FIRST : (prev_learned ? RA_LEARNED : RA_VDAMP);
     LAUNCH(Lr, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
@@ -366,8 +366,8 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
     a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = iters - 1 >= learned_from ? RS_WHAT_L : RS_WHAT;
     LAUNCH(Lr, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
   }
-  a.work = P->d_work_cols; a.nwork = P->ncols; a.mode = iters > 0 ? CM_OUTPUT : CM_ZEROFILL;
-  LAUNCH(Lr, VDAMP_PASS_COLS, launch_cols(a, P->ept, P->lds_cols, st));
+  a.mode = iters > 0 ? CM_OUTPUT : CM_ZEROFILL;
+  LAUNCH(Lr, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
   a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RA_IMAGE;
   LAUNCH(Lr, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
   return VDAMP_OK;

@@ -146,6 +146,65 @@ __device__ void fft_lines(float2* buf, const FftPlanDev& P, int nlines, int ls, 
   }
 }
 
+// ------------------------------------------------------------------ register FFT
+// M-point DFT of v[0..M) held in registers (natural order in and out), decimation in
+// time over the radices 4, 2, 3, 5; M = R * M2: the R interleaved sub-sequences
+// v[R m + r] are transformed recursively, then combined by R-point DFTs with twiddles
+// W_M^{r k}.  Twiddles come from the table tw of exp(-2 pi i j / n) (LDS; every lane
+// reads the same entry): W_M^j = tw[j * tstride] with tstride = n / M.
+template <int M>
+struct FirstRadix {
+  static constexpr int value = (M % 4 == 0 && M != 8) ? 4 : (M % 2 == 0 ? 2 : (M % 3 == 0 ? 3 : 5));
+};
+
+template <int M, bool INV>
+struct RegFft {
+  static constexpr int R = FirstRadix<M>::value;
+  static constexpr int M2 = M / R;
+  static __device__ __forceinline__ void run(float2* v, const float2* __restrict__ tw, int tstride) {
+    float2 s[R][M2];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int m = 0; m < M2; ++m) s[r][m] = v[R * m + r];
+#pragma unroll
+    for (int r = 0; r < R; ++r) RegFft<M2, INV>::run(s[r], tw, tstride * R);
+#pragma unroll
+    for (int k = 0; k < M2; ++k) {
+      float2 t[R];
+      t[0] = s[0][k];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        if (k == 0) {
+          t[r] = s[r][k];
+        } else {
+          float2 w = tw[r * k * tstride];
+          if (INV) w.y = -w.y;
+          t[r] = cmul(s[r][k], w);
+        }
+      }
+      Dft<R, INV>::run(t);
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[k + M2 * q] = t[q];
+    }
+  }
+};
+template <bool INV> struct RegFft<1, INV> {
+  static __device__ __forceinline__ void run(float2*, const float2* __restrict__, int) {}
+};
+template <bool INV> struct RegFft<2, INV> {
+  static __device__ __forceinline__ void run(float2* v, const float2* __restrict__, int) { Dft<2, INV>::run(v); }
+};
+template <bool INV> struct RegFft<3, INV> {
+  static __device__ __forceinline__ void run(float2* v, const float2* __restrict__, int) { Dft<3, INV>::run(v); }
+};
+template <bool INV> struct RegFft<4, INV> {
+  static __device__ __forceinline__ void run(float2* v, const float2* __restrict__, int) { Dft<4, INV>::run(v); }
+};
+template <bool INV> struct RegFft<5, INV> {
+  static __device__ __forceinline__ void run(float2* v, const float2* __restrict__, int) { Dft<5, INV>::run(v); }
+};
+
 // Copy a plan's twiddle table into LDS (issued alongside the tile loads).
 __device__ __forceinline__ void load_twiddles(float2* tw_s, const FftPlanDev& P,
                                               const float2* __restrict__ pool) {

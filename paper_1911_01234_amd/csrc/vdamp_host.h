@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstring>
 #include <string>
 #include <utility>
@@ -69,6 +70,9 @@ struct vdamp_plan_t {
   int2* d_work_sure = nullptr;      // bands by size class: > 16384, > 4096, the rest
   int nrows = 0, ncols = 0, nsure_cls[3] = {0, 0, 0};
   int nrowstrips = 0;
+  // column launches: runs of the column work list with one ny each (first, count, M),
+  // M = ny / 16 for the four-step kernel, 0 for the LDS Stockham kernel
+  std::vector<std::array<int, 3>> col_groups;
   // learned denoiser: 16x16 tiles (slice, tile index), slice-major; tile_off[b] = first
   // tile of slice b
   bool tiles_ok = false;
@@ -104,6 +108,8 @@ hipError_t launch_prep(const uint8_t* mask, const float* p, const float2* y, flo
                        long long n, int check, int* bad, hipStream_t st);
 hipError_t launch_zero(float2* x, long long n, hipStream_t st);
 hipError_t set_lds_limits_passes(size_t rows, size_t cols);
+hipError_t launch_cols4(const KArgs& a, int m, hipStream_t st);
+bool cols4_supported(int ny);
 hipError_t launch_wave_anal(const KArgs& a, int ept, int jmode, size_t lds, hipStream_t st);
 hipError_t launch_scale(const SliceDev* slices, int batch, const float2* y, const float* wgt,
                         float* s0, hipStream_t st);
@@ -142,6 +148,17 @@ struct Launcher {
     HIP_TRY(call);                                                                      \
     HIP_TRY((L).end());                                                                 \
   } while (0)
+
+// Every column strip of the plan: one launch per run of equal ny.
+inline hipError_t launch_cols_all(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
+  for (const auto& g : P->col_groups) {
+    a.work = P->d_work_cols + g[0];
+    a.nwork = g[1];
+    hipError_t e = g[2] ? launch_cols4(a, g[2], st) : launch_cols(a, P->ept, P->lds_cols, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 inline KArgs base_args(const vdamp_plan_t* P, const Ws& w) {
   KArgs a;

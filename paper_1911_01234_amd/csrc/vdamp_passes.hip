@@ -240,6 +240,173 @@ __global__ void __launch_bounds__(kThreads) k_cols(KArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ cols, four-step
+// Column strip of 16 columns with ny = 16 M, as two-level FFTs held in registers: the
+// forward transform factors ny = 16 x M (thread (a, c) transforms rows a + 16 b,
+// b < M, of column c, scales by W_ny^{a kb}, one LDS transpose, then 16-point DFTs give
+// k-space rows kb + M ka), the k-space step runs on those registers, and the inverse
+// factors ny = M x 16 so that it starts from exactly the rows each thread holds and
+// ends, after one more transpose, on the rows the forward transform started from.
+// Loads of X, y and m/p are all issued at the start.
+template <int M>
+__global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
+  constexpr int N = 16 * M;
+  constexpr int NI = (N + kThreads - 1) / kThreads;  // 16-point DFT items per thread
+  constexpr int P1 = 256 + 16;                       // LDS pitch of a forward kb block
+  constexpr int P2 = N + ((M % 2) ? 0 : 16);         // LDS pitch of an inverse block
+  constexpr int TB = (M * P1 > 16 * P2) ? M * P1 : 16 * P2;
+  __shared__ float2 tw_s[N];
+  __shared__ float ytab_s[8 * N];
+  __shared__ float2 tb[TB];
+  __shared__ float red[kThreads / 64][kMaxBands];
+  const int2 item = a.work[blockIdx.x];
+  const int sl = item.x;
+  const SliceDev S = a.slices[sl];
+  const int nx = S.nx, c0 = item.y * kColW, s = a.levels;
+  const int tid = threadIdx.x, mode = a.mode;
+  const bool first = (mode == CM_VDAMP_FIRST || mode == CM_ZEROFILL || mode == CM_FISTA_FIRST);
+  const bool vd = (mode == CM_VDAMP || mode == CM_VDAMP_FIRST);
+  const long long base = S.off + c0;
+  const int c = tid & 15, a1 = tid >> 4;
+  // forward input: rows a1 + 16 b of column c
+  float2 xin[M];
+#pragma unroll
+  for (int b = 0; b < M; ++b)
+    xin[b] = first ? make_float2(0.f, 0.f) : a.X[base + (long long)(a1 + 16 * b) * nx + c];
+  // y and m/p at the k-space rows kb + M ka of this thread's items
+  float2 yv[NI][16];
+  float wv[NI][16];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int it = tid + j * kThreads, kb = it >> 4;
+#pragma unroll
+    for (int ka = 0; ka < 16; ++ka) {
+      yv[j][ka] = make_float2(0.f, 0.f);
+      wv[j][ka] = 0.f;
+      if (it < N) {
+        const long long g = base + (long long)(kb + M * ka) * nx + c;
+        yv[j][ka] = a.y[g];
+        wv[j][ka] = a.wgt[g];
+      }
+    }
+  }
+  const FftPlanDev& P = a.ffts[S.fft_y];
+  for (int i = tid; i < N; i += kThreads) tw_s[i] = a.twiddles[P.tw_off + i];
+  const int ntab = 2 * s;
+  if (vd)
+    for (int i = tid; i < ntab * N; i += kThreads) ytab_s[i] = a.tables[S.ytab_off + i];
+  __syncthreads();
+  if (!first) {
+    RegFft<M, false>::run(xin, tw_s, 16);
+#pragma unroll
+    for (int kb = 0; kb < M; ++kb) {
+      float2 v = xin[kb];
+      if (kb) v = cmul(v, tw_s[a1 * kb]);
+      tb[kb * P1 + a1 * 16 + c] = v;
+    }
+  }
+  __syncthreads();
+  const float isq = rsqrtf((float)N * (float)nx);
+  const float sig2 = a.sigma2 ? a.sigma2[sl] : 0.f;
+  float Q[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) Q[t] = 0.f;
+  float2 d[NI][16];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int it = tid + j * kThreads, kb = it >> 4;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) d[j][q] = make_float2(0.f, 0.f);
+    if (it < N) {
+      if (!first) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) d[j][q] = tb[kb * P1 + q * 16 + c];
+        RegFft<16, false>::run(d[j], tw_s, M);
+      }
+#pragma unroll
+      for (int ka = 0; ka < 16; ++ka) {
+        const int row = kb + M * ka;
+        const float2 X = cscale(d[j][ka], isq);
+        const float2 yy = yv[j][ka];
+        const float w = wv[j][ka];
+        float2 o;
+        if (vd) {
+          o = make_float2(0.f, 0.f);
+          if (w > 0.f) {
+            const float2 z = csub(yy, X);
+            o = cscale(z, w);
+            const float cc = w * ((w - 1.0f) * (z.x * z.x + z.y * z.y) + sig2);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+              if (t < ntab) Q[t] = fmaf(ytab_s[t * N + row], cc, Q[t]);
+          }
+        } else if (mode == CM_OUTPUT) {
+          o = (w > 0.f) ? yy : X;
+        } else if (mode == CM_ZEROFILL) {
+          o = yy;
+        } else {  // FISTA: m (y - X)
+          o = (w > 0.f) ? csub(yy, X) : make_float2(0.f, 0.f);
+        }
+        d[j][ka] = cscale(o, isq);
+      }
+    }
+  }
+  if (vd) {
+    // tau_b partial = sum over this strip's columns of Xtab_b(kx) sum_ky Ytab_b(ky) c
+    const float* xtab = a.tables + S.xtab_off;
+    const int kx = c0 + c;
+    const int lane = tid & 63, wid = tid >> 6;
+    for (int b = 0; b < a.nbands; ++b) {
+      int ty, tx;
+      if (b == 0) { ty = s - 1; tx = s - 1; }
+      else {
+        const int l = s - (b - 1) / 3, kind = (b - 1) % 3;
+        const int L = l - 1, Hh = s + l - 1;
+        ty = (kind == 0) ? L : Hh;
+        tx = (kind == 1) ? L : Hh;
+      }
+      float q0 = 0.f;
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (t == ty) q0 = Q[t];
+      const float part = wave_sum(q0 * xtab[tx * nx + kx]);
+      if (lane == 0) red[wid][b] = part;
+    }
+  }
+  __syncthreads();  // tau partials visible; every forward read of tb done
+  if (vd && tid < a.nbands) {
+    float acc = 0.f;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) acc += red[w][tid];
+    a.tau_part[(S.colstrip0 + item.y) * kMaxBands + tid] = acc;
+  }
+  // inverse: 16-point DFTs over ka (rows kb + M ka), twiddle, transpose
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int it = tid + j * kThreads, kb = it >> 4;
+    if (it < N) {
+      RegFft<16, true>::run(d[j], tw_s, M);
+#pragma unroll
+      for (int k2 = 0; k2 < 16; ++k2) {
+        float2 v = d[j][k2];
+        if (k2 && kb) {
+          float2 w = tw_s[kb * k2];
+          w.y = -w.y;
+          v = cmul(v, w);
+        }
+        tb[k2 * P2 + kb * 16 + c] = v;
+      }
+    }
+  }
+  __syncthreads();
+  float2 f[M];
+#pragma unroll
+  for (int kb = 0; kb < M; ++kb) f[kb] = tb[a1 * P2 + kb * 16 + c];
+  RegFft<M, true>::run(f, tw_s, 16);
+#pragma unroll
+  for (int b = 0; b < M; ++b) a.X[base + (long long)(a1 + 16 * b) * nx + c] = f[b];
+}
+
 // ------------------------------------------------------------------ rows_anal
 template <int EPT>
 __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
@@ -459,6 +626,28 @@ hipError_t launch_cols(const KArgs& a, int ept, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL(k_cols<32>, dim3(a.nwork), dim3(kThreads), lds, st, a);
   return hipGetLastError();
 }
+#define COLS4_CASE(MM) \
+  case MM: hipLaunchKernelGGL(k_cols4<MM>, dim3(a.nwork), dim3(kThreads), 0, st, a); break
+
+hipError_t launch_cols4(const KArgs& a, int m, hipStream_t st) {
+  switch (m) {
+    COLS4_CASE(1); COLS4_CASE(2); COLS4_CASE(3); COLS4_CASE(4); COLS4_CASE(5);
+    COLS4_CASE(6); COLS4_CASE(8); COLS4_CASE(10); COLS4_CASE(12); COLS4_CASE(15);
+    COLS4_CASE(16); COLS4_CASE(20); COLS4_CASE(24); COLS4_CASE(30); COLS4_CASE(32);
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+bool cols4_supported(int ny) {
+  if (ny % 16) return false;
+  switch (ny / 16) {
+    case 1: case 2: case 3: case 4: case 5: case 6: case 8: case 10: case 12: case 15:
+    case 16: case 20: case 24: case 30: case 32: return true;
+    default: return false;
+  }
+}
+
 hipError_t launch_rows_anal(const KArgs& a, int ept, size_t lds, hipStream_t st) {
   if (ept == 16)
     hipLaunchKernelGGL(k_rows_anal<16>, dim3(a.nwork), dim3(kThreads), lds, st, a);
