@@ -130,13 +130,13 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
   for (int k = 0; k < iters; ++k) {
     a.iter = k;
     if (k > 0) {
-      a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_RTILDE;
-      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
+      a.mode = RS_RTILDE;
+      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, a, st));
     }
     a.mode = k ? CM_VDAMP : CM_VDAMP_FIRST;
     LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
-    a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = k ? RA_VDAMP : RA_VDAMP_FIRST;
-    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
+    a.mode = k ? RA_VDAMP : RA_VDAMP_FIRST;
+    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
     for (int c = 2, first = 0; c >= 0; --c) {
       if (!P->nsure_cls[c]) continue;
       a.work = P->d_work_sure + first; a.nwork = P->nsure_cls[c];
@@ -146,13 +146,13 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
   }
   // line 10: x_hat = F^H [ (1 - m) F Psi^H w + m y ]
   if (iters > 0) {
-    a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_WHAT;
-    LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
+    a.mode = RS_WHAT;
+    LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, a, st));
   }
   a.mode = iters > 0 ? CM_OUTPUT : CM_ZEROFILL;
   LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
-  a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RA_IMAGE;
-  LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
+  a.mode = RA_IMAGE;
+  LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
   return VDAMP_OK;
 }
 
@@ -173,13 +173,13 @@ vdamp_status enqueue_fista(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
     a.beta = (float)((t - 1.0) / tn);
     t = tn;
     if (k > 0) {
-      a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RS_PLAIN;
-      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
+      a.mode = RS_PLAIN;
+      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, a, st));
     }
     a.mode = k ? CM_FISTA : CM_FISTA_FIRST;
     LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
-    a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = k ? RA_FISTA : RA_FISTA_FIRST;
-    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
+    a.mode = k ? RA_FISTA : RA_FISTA_FIRST;
+    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
   }
   // x_hat = Psi^H w_K (w_K lives in r2); K = 0 gives zeros (a fill kernel, so that a
   // captured graph holds no memset node)
@@ -364,6 +364,13 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   vs.insert(vs.end(), vss.begin(), vss.end());
   P->nrows = (int)vr.size();
   P->ncols = (int)vc.size();
+  for (int i = 0; i < P->nrows;) {
+    const int n = nx[vr[i].x];
+    int j = i;
+    while (j < P->nrows && nx[vr[j].x] == n) ++j;
+    P->row_groups.push_back({i, j - i, cols4_supported(n) ? n / 16 : 0});
+    i = j;
+  }
   for (int i = 0; i < P->ncols;) {
     const int n = ny[vc[i].x];
     int j = i;

@@ -329,14 +329,13 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
     a.iter = k;
     const bool prev_learned = k > 0 && k - 1 >= learned_from;  // line 8 used the judge
     if (k > 0) {
-      a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = prev_learned ? RS_RTILDE_L : RS_RTILDE;
-      LAUNCH(Lr, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
+      a.mode = prev_learned ? RS_RTILDE_L : RS_RTILDE;
+      LAUNCH(Lr, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, a, st));
     }
     a.mode = k ? CM_VDAMP : CM_VDAMP_FIRST;
     LAUNCH(Lr, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
-    a.work = P->d_work_rows; a.nwork = P->nrows;
     a.mode = k == 0 ? RA_VDAMP_FIRST : (prev_learned ? RA_LEARNED : RA_VDAMP);
-    LAUNCH(Lr, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
+    LAUNCH(Lr, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
     for (int c = 2, first = 0; c >= 0; --c) {
       if (!P->nsure_cls[c]) continue;
       a.work = P->d_work_sure + first; a.nwork = P->nsure_cls[c];
@@ -363,13 +362,13 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
     LAUNCH(Lr, VDAMP_PASS_DENOISER, launch_judge(a, P->nrowstrips, judge, sel, at<float>(cws, L.jout), st));
   }
   if (iters > 0) {
-    a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = iters - 1 >= learned_from ? RS_WHAT_L : RS_WHAT;
-    LAUNCH(Lr, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth(a, P->ept, 1, P->lds_rows, st));
+    a.mode = iters - 1 >= learned_from ? RS_WHAT_L : RS_WHAT;
+    LAUNCH(Lr, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, a, st));
   }
   a.mode = iters > 0 ? CM_OUTPUT : CM_ZEROFILL;
   LAUNCH(Lr, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
-  a.work = P->d_work_rows; a.nwork = P->nrows; a.mode = RA_IMAGE;
-  LAUNCH(Lr, VDAMP_PASS_ROWS_ANAL, launch_rows_anal(a, P->ept, P->lds_rows, st));
+  a.mode = RA_IMAGE;
+  LAUNCH(Lr, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
   return VDAMP_OK;
 }
 

@@ -211,6 +211,54 @@ __device__ __forceinline__ void load_twiddles(float2* tw_s, const FftPlanDev& P,
   for (int i = threadIdx.x; i < P.n; i += kThreads) tw_s[i] = pool[P.tw_off + i];
 }
 
+// ------------------------------------------------------------------ four-step row FFTs
+// Row FFTs of a strip of H <= 16 rows of length N = 16 M: thread (a, line) transforms
+// the M samples a + 16 b of its row (b < M), scales by W_N^{a kb}, and an LDS transpose
+// hands the 16 values of each (kb, line) to one thread, whose 16-point DFT gives the
+// outputs kb + M ka.  The transpose buffer (pitch PR, odd, so that the lanes of a step
+// hit distinct banks) aliases the strip buffer; every thread has read its inputs before
+// the first write.
+template <int M>
+struct RowFft4 {
+  static constexpr int N = 16 * M;
+  static constexpr int PR = (M % 2) ? M : M + 1;
+  static constexpr int NI = (16 * M + kThreads - 1) / kThreads;
+  static constexpr int LDS_ELEMS = (16 * N > 256 * PR) ? 16 * N : 256 * PR;
+
+  // step 1 (inputs in v, lanes with line >= H idle) and the transpose
+  template <bool INV>
+  static __device__ __forceinline__ void step1(float2 (&v)[M], int H, const float2* __restrict__ tw,
+                                               float2* buf) {
+    const int a = threadIdx.x & 15, line = threadIdx.x >> 4;
+    if (line < H) {
+      RegFft<M, INV>::run(v, tw, 16);
+#pragma unroll
+      for (int kb = 0; kb < M; ++kb) {
+        float2 x = v[kb];
+        if (kb && a) {
+          float2 w = tw[a * kb];
+          if (INV) w.y = -w.y;
+          x = cmul(x, w);
+        }
+        buf[(line * 16 + a) * PR + kb] = x;
+      }
+    }
+  }
+  // step 2 for item j of this thread: the 16 outputs kb + M ka of row `line`
+  template <bool INV>
+  static __device__ __forceinline__ bool step2(int j, int H, const float2* __restrict__ tw,
+                                               const float2* buf, float2 (&d)[16], int& kb, int& line) {
+    const int it = threadIdx.x + j * kThreads;
+    kb = it % M;
+    line = it / M;
+    if (line >= H) return false;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) d[q] = buf[(line * 16 + q) * PR + kb];
+    RegFft<16, INV>::run(d, tw, M);
+    return true;
+  }
+};
+
 // ------------------------------------------------------------------ Haar on a strip
 // The strip holds H = 2^s image rows x nx columns.  Its coefficients form the Mallat
 // layout of an H x nx image with s levels ("mini-Mallat"); one 2x2 orthonormal Haar

@@ -73,6 +73,9 @@ struct vdamp_plan_t {
   // column launches: runs of the column work list with one ny each (first, count, M),
   // M = ny / 16 for the four-step kernel, 0 for the LDS Stockham kernel
   std::vector<std::array<int, 3>> col_groups;
+  // row launches: runs of the row work list with one nx each (first, count, M), M = nx / 16
+  // for the four-step row kernels, 0 for the LDS Stockham ones
+  std::vector<std::array<int, 3>> row_groups;
   // learned denoiser: 16x16 tiles (slice, tile index), slice-major; tile_off[b] = first
   // tile of slice b
   bool tiles_ok = false;
@@ -109,6 +112,9 @@ hipError_t launch_prep(const uint8_t* mask, const float* p, const float2* y, flo
 hipError_t launch_zero(float2* x, long long n, hipStream_t st);
 hipError_t set_lds_limits_passes(size_t rows, size_t cols);
 hipError_t launch_cols4(const KArgs& a, int m, hipStream_t st);
+hipError_t launch_rows_synth4(const KArgs& a, int m, size_t lds, hipStream_t st);
+hipError_t launch_rows_anal4(const KArgs& a, int m, size_t lds, hipStream_t st);
+size_t rows4_lds_bytes(int m, int H);
 bool cols4_supported(int ny);
 hipError_t launch_wave_anal(const KArgs& a, int ept, int jmode, size_t lds, hipStream_t st);
 hipError_t launch_scale(const SliceDev* slices, int batch, const float2* y, const float* wgt,
@@ -155,6 +161,29 @@ inline hipError_t launch_cols_all(const vdamp_plan_t* P, KArgs a, hipStream_t st
     a.work = P->d_work_cols + g[0];
     a.nwork = g[1];
     hipError_t e = g[2] ? launch_cols4(a, g[2], st) : launch_cols(a, P->ept, P->lds_cols, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Every row strip of the plan through the transform passes: one launch per run of equal
+// nx (line 8 + Psi^H + row FFT, and row IFFT + Psi + line 4).
+inline hipError_t launch_rows_synth_all(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
+  for (const auto& g : P->row_groups) {
+    a.work = P->d_work_rows + g[0];
+    a.nwork = g[1];
+    hipError_t e = g[2] ? launch_rows_synth4(a, g[2], rows4_lds_bytes(g[2], 1 << P->levels), st)
+                        : launch_rows_synth(a, P->ept, 1, P->lds_rows, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+inline hipError_t launch_rows_anal_all(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
+  for (const auto& g : P->row_groups) {
+    a.work = P->d_work_rows + g[0];
+    a.nwork = g[1];
+    hipError_t e = g[2] ? launch_rows_anal4(a, g[2], rows4_lds_bytes(g[2], 1 << P->levels), st)
+                        : launch_rows_anal(a, P->ept, P->lds_rows, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

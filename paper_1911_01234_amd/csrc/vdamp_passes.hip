@@ -9,13 +9,15 @@
 // with 16-byte accesses (two complex values), all of a thread's loads issued before
 // the first use.  EPT (8 B elements per thread) is 16 when every tile of the plan
 // holds at most 4096 complex values, else 32.
+#include <vector>
+
 #include "vdamp_device.hpp"
 
 namespace vdamp {
 
 // ------------------------------------------------------------------ rows_synth
 // do_fft = 0 writes the image rows Psi^H r (the FISTA output).
-template <int EPT>
+template <int EPT, int M>
 __global__ void __launch_bounds__(kThreads) k_rows_synth(KArgs a, int do_fft) {
   extern __shared__ float4 lds4[];
   float2* lds = reinterpret_cast<float2*>(lds4);
@@ -92,7 +94,33 @@ __global__ void __launch_bounds__(kThreads) k_rows_synth(KArgs a, int do_fft) {
   }
   __syncthreads();
   haar_strip_synth<EPT>(lds, H, nx, s);
-  if (do_fft) fft_lines<false, false, EPT>(lds, P, H, nx, 1, tw_s);
+  if constexpr (M > 0) {
+    if (do_fft) {  // four-step row FFT, outputs straight to X
+      using F = RowFft4<M>;
+      float2 v[M];
+      const int a16 = tid & 15, line = tid >> 4;
+      if (line < H) {
+#pragma unroll
+        for (int b = 0; b < M; ++b) v[b] = lds[line * F::N + a16 + 16 * b];
+      }
+      __syncthreads();
+      F::template step1<false>(v, H, tw_s, lds);
+      __syncthreads();
+      float2* X = a.X + S.off + (long long)strip * H * nx;
+#pragma unroll
+      for (int j = 0; j < F::NI; ++j) {
+        float2 d[16];
+        int kb, l2;
+        if (F::template step2<false>(j, H, tw_s, lds, d, kb, l2)) {
+#pragma unroll
+          for (int ka = 0; ka < 16; ++ka) X[l2 * F::N + kb + M * ka] = d[ka];
+        }
+      }
+      return;
+    }
+  } else {
+    if (do_fft) fft_lines<false, false, EPT>(lds, P, H, nx, 1, tw_s);
+  }
   float4* dst = reinterpret_cast<float4*>((do_fft ? a.X : a.out) + S.off + (long long)strip * H * nx);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -408,7 +436,7 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
 }
 
 // ------------------------------------------------------------------ rows_anal
-template <int EPT>
+template <int EPT, int M>
 __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
   extern __shared__ float4 lds4[];
   float2* lds = reinterpret_cast<float2*>(lds4);
@@ -422,12 +450,22 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
   constexpr int U = EPT / 2;
   const int half = nx >> 1, npairs = H * half;
   const float4* src = reinterpret_cast<const float4*>(a.X + S.off + (long long)strip * H * nx);
-  float4 v[U];
+  constexpr int MV = M > 0 ? M : 1;
+  float4 v[M > 0 ? 1 : U];
+  float2 v4[MV];  // four-step inputs: samples a + 16 b of row `line`
+  if constexpr (M > 0) {
+    const int a16 = tid & 15, line = tid >> 4;
+    const float2* xs = a.X + S.off + (long long)strip * H * nx;
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int p = tid + u * kThreads;
-    v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (p < npairs) v[u] = src[p];
+    for (int b = 0; b < MV; ++b)
+      v4[b] = (line < H) ? xs[line * nx + a16 + 16 * b] : make_float2(0.f, 0.f);
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tid + u * kThreads;
+      v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (p < npairs) v[u] = src[p];
+    }
   }
   if (tid < kMaxBands) {
     th_s[tid] = a.theta[item.x * kMaxBands + tid];
@@ -437,13 +475,33 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
   }
   const FftPlanDev& P = a.ffts[S.fft_x];
   load_twiddles(tw_s, P, a.twiddles);
+  if constexpr (M > 0) {
+    using F = RowFft4<M>;
+    __syncthreads();  // twiddles
+    F::template step1<true>(v4, H, tw_s, lds);
+    __syncthreads();
+    float2 d[F::NI][16];
+    int kbs[F::NI], ls[F::NI];
+    bool ok[F::NI];
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int p = tid + u * kThreads;
-    if (p < npairs) lds4[p] = v[u];
+    for (int j = 0; j < F::NI; ++j) ok[j] = F::template step2<true>(j, H, tw_s, lds, d[j], kbs[j], ls[j]);
+    __syncthreads();  // every transpose read done before the strip is rewritten
+#pragma unroll
+    for (int j = 0; j < F::NI; ++j)
+      if (ok[j]) {
+#pragma unroll
+        for (int ka = 0; ka < 16; ++ka) lds[ls[j] * F::N + kbs[j] + M * ka] = d[j][ka];
+      }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = tid + u * kThreads;
+      if (p < npairs) lds4[p] = v[u];
+    }
+    __syncthreads();
+    fft_lines<true, false, EPT>(lds, P, H, nx, 1, tw_s);
   }
-  __syncthreads();
-  fft_lines<true, false, EPT>(lds, P, H, nx, 1, tw_s);
   if (mode == RA_IMAGE) {
     float4* dst = reinterpret_cast<float4*>(a.out + S.off + (long long)strip * H * nx);
 #pragma unroll
@@ -614,9 +672,9 @@ __global__ void __launch_bounds__(kThreads) k_wave_anal(KArgs a, int jmode) {
 // ------------------------------------------------------------------ launchers
 hipError_t launch_rows_synth(const KArgs& a, int ept, int do_fft, size_t lds, hipStream_t st) {
   if (ept == 16)
-    hipLaunchKernelGGL(k_rows_synth<16>, dim3(a.nwork), dim3(kThreads), lds, st, a, do_fft);
+    hipLaunchKernelGGL((k_rows_synth<16, 0>), dim3(a.nwork), dim3(kThreads), lds, st, a, do_fft);
   else
-    hipLaunchKernelGGL(k_rows_synth<32>, dim3(a.nwork), dim3(kThreads), lds, st, a, do_fft);
+    hipLaunchKernelGGL((k_rows_synth<32, 0>), dim3(a.nwork), dim3(kThreads), lds, st, a, do_fft);
   return hipGetLastError();
 }
 hipError_t launch_cols(const KArgs& a, int ept, size_t lds, hipStream_t st) {
@@ -650,9 +708,45 @@ bool cols4_supported(int ny) {
 
 hipError_t launch_rows_anal(const KArgs& a, int ept, size_t lds, hipStream_t st) {
   if (ept == 16)
-    hipLaunchKernelGGL(k_rows_anal<16>, dim3(a.nwork), dim3(kThreads), lds, st, a);
+    hipLaunchKernelGGL((k_rows_anal<16, 0>), dim3(a.nwork), dim3(kThreads), lds, st, a);
   else
-    hipLaunchKernelGGL(k_rows_anal<32>, dim3(a.nwork), dim3(kThreads), lds, st, a);
+    hipLaunchKernelGGL((k_rows_anal<32, 0>), dim3(a.nwork), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+// Four-step row kernels for nx = 16 m; dynamic LDS = the strip or the transpose buffer.
+size_t rows4_lds_bytes(int m, int H) {
+  const int pr = (m % 2) ? m : m + 1;
+  const size_t strip = (size_t)H * 16 * m, tb = (size_t)256 * pr;
+  return sizeof(float2) * (strip > tb ? strip : tb);
+}
+
+#define ROWS4_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(15) X(16) X(20) X(24) X(30) X(32)
+#define EPT_OF(MM) ((MM) <= 16 ? 16 : 32)
+
+hipError_t launch_rows_synth4(const KArgs& a, int m, size_t lds, hipStream_t st) {
+  switch (m) {
+#define RS4(MM)                                                                                \
+  case MM:                                                                                     \
+    hipLaunchKernelGGL((k_rows_synth<EPT_OF(MM), MM>), dim3(a.nwork), dim3(kThreads), lds, st, a, 1); \
+    break;
+    ROWS4_CASES(RS4)
+#undef RS4
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_anal4(const KArgs& a, int m, size_t lds, hipStream_t st) {
+  switch (m) {
+#define RA4(MM)                                                                                \
+  case MM:                                                                                     \
+    hipLaunchKernelGGL((k_rows_anal<EPT_OF(MM), MM>), dim3(a.nwork), dim3(kThreads), lds, st, a); \
+    break;
+    ROWS4_CASES(RA4)
+#undef RA4
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -665,13 +759,25 @@ hipError_t launch_wave_anal(const KArgs& a, int ept, int jmode, size_t lds, hipS
 }
 
 hipError_t set_lds_limits_passes(size_t rows, size_t cols) {
-  const void* rk[] = {(const void*)k_rows_synth<16>, (const void*)k_rows_synth<32>,
-                      (const void*)k_rows_anal<16>, (const void*)k_rows_anal<32>,
-                      (const void*)k_wave_anal<16>, (const void*)k_wave_anal<32>};
+  std::vector<const void*> rk = {(const void*)k_rows_synth<16, 0>, (const void*)k_rows_synth<32, 0>,
+                                 (const void*)k_rows_anal<16, 0>, (const void*)k_rows_anal<32, 0>,
+                                 (const void*)k_wave_anal<16>, (const void*)k_wave_anal<32>};
   for (const void* f : rk) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rows);
     if (e != hipSuccess) return e;
   }
+  const int r4 = (int)rows4_lds_bytes(32, 16);  // the largest four-step row tile
+#define LIM4(MM)                                                                                      \
+  {                                                                                                   \
+    hipError_t e = hipFuncSetAttribute((const void*)k_rows_synth<EPT_OF(MM), MM>,                     \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, r4);               \
+    if (e == hipSuccess)                                                                              \
+      e = hipFuncSetAttribute((const void*)k_rows_anal<EPT_OF(MM), MM>,                               \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, r4);                        \
+    if (e != hipSuccess) return e;                                                                    \
+  }
+  ROWS4_CASES(LIM4)
+#undef LIM4
   const void* ck[] = {(const void*)k_cols<16>, (const void*)k_cols<32>};
   for (const void* f : ck) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cols);
