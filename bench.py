@@ -75,17 +75,25 @@ def make_batch(B):
 
 
 def nmse_db_batch(x_hat, x0, seg, batch):
-    """Per-slice NMSE (dB) of a packed batch; seg holds each pixel's slice index."""
+    """Per-slice NMSE (dB) of a packed batch; seg holds each pixel's slice index (slices
+    of equal size are reduced as rows of a matrix, others by an indexed sum)."""
     import torch
-    d = torch.zeros(batch, dtype=torch.float64, device=x0.device)
-    n = torch.zeros_like(d)
-    d.index_add_(0, seg, (x_hat - x0).abs().pow(2).double())
-    n.index_add_(0, seg, x0.abs().pow(2).double())
-    return (10.0 * torch.log10(d / n)).cpu().numpy()
+    n = x0.numel()
+    if n % batch == 0 and bool((seg.view(batch, -1) == torch.arange(batch, device=seg.device)[:, None]).all()):
+        d = (x_hat - x0).abs().pow(2).double().view(batch, -1).sum(1)
+        s = x0.abs().pow(2).double().view(batch, -1).sum(1)
+    else:
+        d = torch.zeros(batch, dtype=torch.float64, device=x0.device)
+        s = torch.zeros_like(d)
+        d.index_add_(0, seg, (x_hat - x0).abs().pow(2).double())
+        s.index_add_(0, seg, x0.abs().pow(2).double())
+    return (10.0 * torch.log10(d / s)).cpu().numpy()
 
 
-KERNEL_SOURCES = {"cols": ["paper_1911_01234_amd/csrc/vdamp_passes.hip",
-                           "paper_1911_01234_amd/csrc/vdamp_device.hpp",
+_PASS_SRC = ["paper_1911_01234_amd/csrc/vdamp_passes.hip", "paper_1911_01234_amd/csrc/vdamp_device.hpp",
+             "paper_1911_01234_amd/csrc/vdamp_internal.h"]
+KERNEL_SOURCES = {"cols": _PASS_SRC, "rows_synth": _PASS_SRC, "rows_anal": _PASS_SRC,
+                  "sure": ["paper_1911_01234_amd/csrc/vdamp_sure.hip", "paper_1911_01234_amd/csrc/vdamp_device.hpp",
                            "paper_1911_01234_amd/csrc/vdamp_internal.h"]}
 
 
@@ -93,7 +101,7 @@ def measured_traffic(kernel_class):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
     on the kernel sources as they are now (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_k_{kernel_class}_b256_256x256.md")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_class}_b256_256x256.md")
     if kernel_class not in KERNEL_SOURCES or not os.path.exists(path):
         return None
     rec = None

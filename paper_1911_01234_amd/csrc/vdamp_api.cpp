@@ -137,12 +137,7 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
     LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
     a.mode = k ? RA_VDAMP : RA_VDAMP_FIRST;
     LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
-    for (int c = 2, first = 0; c >= 0; --c) {
-      if (!P->nsure_cls[c]) continue;
-      a.work = P->d_work_sure + first; a.nwork = P->nsure_cls[c];
-      LAUNCH(L, VDAMP_PASS_SURE, launch_sure(a, c, st));
-      first += P->nsure_cls[c];
-    }
+    LAUNCH(L, VDAMP_PASS_SURE, launch_sure_all(P, a, st));
   }
   // line 10: x_hat = F^H [ (1 - m) F Psi^H w + m y ]
   if (iters > 0) {
@@ -333,7 +328,7 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   P->ntiles = (int)tiles.size();
 
   // work lists, heaviest items first
-  std::vector<std::pair<long long, int2>> wr, wc, wsh, wsb, wss;
+  std::vector<std::pair<long long, int2>> wr, wc, wsc[kSureClasses];
   int maxnx = 0, maxny = 0;
   for (int b = 0; b < batch; ++b) {
     maxnx = std::max(maxnx, nx[b]);
@@ -343,10 +338,8 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     for (int band = 0; band < P->nbands; ++band) {
       int l = band == 0 ? levels : levels - (band - 1) / 3;
       long long nbsz = (long long)(ny[b] >> l) * (nx[b] >> l);
-      if (nbsz > kSureSmall)
-        (nbsz > 4 * kSureSmall ? wsh : wsb).push_back({nbsz, make_int2(b, band)});
-      else
-        wss.push_back({nbsz, make_int2(b, band)});
+      const int cls = nbsz > 4 * kSureSmall ? 2 : nbsz > kSureSmall ? 1 : 0;
+      wsc[cls].push_back({nbsz, make_int2(b, band)});
     }
   }
   auto sort_items = [](std::vector<std::pair<long long, int2>>& v) {
@@ -355,13 +348,12 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     for (auto& e : v) out.push_back(e.second);
     return out;
   };
-  std::vector<int2> vr = sort_items(wr), vc = sort_items(wc), vs = sort_items(wsh);
-  std::vector<int2> vsb = sort_items(wsb), vss = sort_items(wss);
-  P->nsure_cls[2] = (int)vs.size();
-  P->nsure_cls[1] = (int)vsb.size();
-  P->nsure_cls[0] = (int)vss.size();
-  vs.insert(vs.end(), vsb.begin(), vsb.end());
-  vs.insert(vs.end(), vss.begin(), vss.end());
+  std::vector<int2> vr = sort_items(wr), vc = sort_items(wc), vs;
+  for (int c = kSureClasses - 1; c >= 0; --c) {  // largest class first, as launched
+    std::vector<int2> v = sort_items(wsc[c]);
+    P->nsure_cls[c] = (int)v.size();
+    vs.insert(vs.end(), v.begin(), v.end());
+  }
   P->nrows = (int)vr.size();
   P->ncols = (int)vc.size();
   for (int i = 0; i < P->nrows;) {

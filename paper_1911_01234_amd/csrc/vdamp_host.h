@@ -68,7 +68,7 @@ struct vdamp_plan_t {
   int2* d_work_rows = nullptr;
   int2* d_work_cols = nullptr;
   int2* d_work_sure = nullptr;      // bands by size class: > 16384, > 4096, the rest
-  int nrows = 0, ncols = 0, nsure_cls[3] = {0, 0, 0};
+  int nrows = 0, ncols = 0, nsure_cls[vdamp::kSureClasses] = {};
   int nrowstrips = 0;
   // column launches: runs of the column work list with one ny each (first, count, M),
   // M = ny / 16 for the four-step kernel, 0 for the LDS Stockham kernel
@@ -185,6 +185,19 @@ inline hipError_t launch_rows_anal_all(const vdamp_plan_t* P, KArgs a, hipStream
     hipError_t e = g[2] ? launch_rows_anal4(a, g[2], rows4_lds_bytes(g[2], 1 << P->levels), st)
                         : launch_rows_anal(a, P->ept, P->lds_rows, st);
     if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Every band's threshold search (line 6): one launch per size class, largest first.
+inline hipError_t launch_sure_all(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
+  for (int c = kSureClasses - 1, first = 0; c >= 0; --c) {
+    if (!P->nsure_cls[c]) continue;
+    a.work = P->d_work_sure + first;
+    a.nwork = P->nsure_cls[c];
+    hipError_t e = launch_sure(a, c, st);
+    if (e != hipSuccess) return e;
+    first += P->nsure_cls[c];
   }
   return hipSuccess;
 }

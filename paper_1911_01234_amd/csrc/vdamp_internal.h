@@ -14,6 +14,7 @@ constexpr int kColW = 16;          // columns per column strip (16 complex = 128
 constexpr int kMaxRadices = 8;
 constexpr int kMaxN = 512;         // largest ny / nx
 constexpr int kSureSmall = 4096;   // bands up to this size use the 256-thread search
+constexpr int kSureClasses = 3;
 constexpr int kSureMaxKeys = 27648;// largest subband the LDS threshold search holds
 
 struct FftPlanDev {

@@ -77,22 +77,34 @@ __device__ __forceinline__ int skx(int i) { return i + (i >> 4); }
 //      alpha = ((N_b - m) - theta R_m / 2) / N_b (line 7).
 constexpr int kSureBucketLimit = 64;
 
-// LDS words of a size class: the bucket table, then the sorted keys with one pad word
-// per 16 keys.
-constexpr int sure_smem_words(int NB, int MAXK) { return NB + 1 + MAXK + MAXK / 16 + 1; }
+// LDS words of a size class: the bucket table and the sorted keys with one pad word per
+// 16 keys.  With up to 16 keys a thread the keys overlay the table (each thread keeps
+// its keys' bucket bounds in registers before the table is overwritten), which halves
+// the LDS of the 16384-key class; with 32 keys a thread those registers would spill.
+constexpr bool sure_overlay(int KPT) { return KPT <= 16; }
+// Waves per SIMD the compiler is asked to fit (register budget): 8 for the classes with
+// up to 16 keys a thread (two 1024-thread workgroups per CU; a few registers spill,
+// measured faster than one workgroup), no constraint for the 32-key class.
+constexpr int sure_waves(int NT, int KPT) { return KPT <= 16 ? 8 : 1; }
+constexpr int sure_smem_words(int NB, int MAXK, int KPT) {
+  return sure_overlay(KPT) ? ((NB + 1 > MAXK + MAXK / 16 + 1) ? NB + 1 : MAXK + MAXK / 16 + 1)
+                           : NB + 1 + MAXK + MAXK / 16 + 1;
+}
 
 template <int NT, int KPT, int NB, int MAXK>
-__global__ void __launch_bounds__(NT) k_sure(KArgs a) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sure_waves(NT, KPT))))
+k_sure(KArgs a) {
   static_assert(NT * KPT >= MAXK, "keys per thread");
-  __shared__ __align__(16) int sure_smem[sure_smem_words(NB, MAXK)];
+  constexpr bool OV = sure_overlay(KPT);
+  __shared__ __align__(16) int sure_smem[sure_smem_words(NB, MAXK, KPT)];
   constexpr int NW = NT / 64;
   constexpr int BPT = NB / NT;
   __shared__ double wsA[NW], wsR[NW], bv[NW], bR[NW];
   __shared__ int bi[NW], wsC[NW], wsM[NW];
   __shared__ float tau_sh;
   __shared__ int maxc_sh;
-  int* off = sure_smem;                                       // [NB + 1]
-  float* const sk = reinterpret_cast<float*>(sure_smem + NB + 1);  // [skx(Nb)] sorted keys
+  int* off = sure_smem;                                                 // [NB + 1]
+  float* const sk = reinterpret_cast<float*>(sure_smem + (OV ? 0 : NB + 1));  // sorted keys
   const int2 item = a.work[blockIdx.x];
   const int sl = item.x, b = item.y, s = a.levels;
   const SliceDev S = a.slices[sl];
@@ -166,38 +178,73 @@ __global__ void __launch_bounds__(NT) k_sure(KArgs a) {
   }
   __syncthreads();
   if (maxc_sh <= kSureBucketLimit) {
+    // bucket bounds and slot into registers, packed as offset | count << 15 | slot << 22
+    // (offsets < 2^15, counts and slots <= kSureBucketLimit < 2^7); the table is then
+    // overwritten by the keys
+    static_assert(MAXK < (1 << 15) && kSureBucketLimit < (1 << 7), "packed bucket bounds");
+    int bpk[OV ? KPT : 1];
+    if constexpr (OV) {
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) {
+        const int i = tid + j * NT;
+        bpk[j] = 0;
+        if (i < Nb) {
+          const int bk = sure_bucket<NB>(kk[j], inv_tau);
+          const int lo = off[bk];
+          bpk[j] = lo | ((off[bk + 1] - lo) << 15) | (pos[j] << 22);
+        }
+      }
+      __syncthreads();
+    }
+#define SURE_BOUNDS(j, lo, hi, slot)                 \
+  if constexpr (OV) {                                \
+    lo = bpk[j] & 0x7FFF;                            \
+    hi = lo + ((bpk[j] >> 15) & 0x7F);               \
+    slot = bpk[j] >> 22;                             \
+  } else {                                           \
+    const int bk_ = sure_bucket<NB>(kk[j], inv_tau); \
+    lo = off[bk_];                                   \
+    hi = off[bk_ + 1];                               \
+    slot = pos[j];                                   \
+  }
     // scatter into bucket slots
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const int i = tid + j * NT;
-      if (i < Nb) sk[skx(off[sure_bucket<NB>(kk[j], inv_tau)] + pos[j])] = kk[j];
+      if (i < Nb) {
+        int lo, hi, slot;
+        SURE_BOUNDS(j, lo, hi, slot);
+        (void)hi;
+        sk[skx(lo + slot)] = kk[j];
+      }
     }
     __syncthreads();
-    // final position = bucket offset + rank within the bucket (ties by slot); it
-    // replaces the slot in pos[]
+    // final position = bucket offset + rank within the bucket (ties by slot)
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const int i = tid + j * NT;
       if (i < Nb) {
-        const int bk = sure_bucket<NB>(kk[j], inv_tau);
-        const int lo = off[bk], hi = off[bk + 1];
+        int lo, hi, slot;
+        SURE_BOUNDS(j, lo, hi, slot);
         const float v = kk[j];
-        const int me = lo + pos[j];
+        const int me = lo + slot;
         int rank = 0;
         for (int x = lo; x < hi; ++x) {
           const float u = sk[skx(x)];
           rank += (u < v) || (u == v && x < me);
         }
-        pos[j] = lo + rank;
+        if constexpr (OV) bpk[j] = lo + rank;  // final position
+        else pos[j] = lo + rank;
       }
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const int i = tid + j * NT;
-      if (i < Nb) sk[skx(pos[j])] = kk[j];
+      if (i < Nb) sk[skx(OV ? bpk[j] : pos[j])] = kk[j];
     }
     __syncthreads();
+#undef SURE_BOUNDS
   } else {
     // Full sort: a bitonic network whose compare-exchanges all put the smaller key
     // first (each merge starts by comparing mirrored positions), so +inf padding up to
