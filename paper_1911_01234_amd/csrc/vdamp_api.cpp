@@ -96,6 +96,7 @@ Ws layout(const vdamp_plan_t* P, void* ws) {
   w.tau = reinterpret_cast<float*>(b + P->o_tau);
   w.taup = reinterpret_cast<float*>(b + P->o_taup);
   w.bad = reinterpret_cast<int*>(b + P->o_bad);
+  w.big = P->o_big ? reinterpret_cast<float*>(b + P->o_big) : nullptr;
   return w;
 }
 }  // namespace vdamp
@@ -137,7 +138,7 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
     LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
     a.mode = k ? RA_VDAMP : RA_VDAMP_FIRST;
     LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
-    LAUNCH(L, VDAMP_PASS_SURE, launch_sure_all(P, a, st));
+    LAUNCH(L, VDAMP_PASS_SURE, launch_sure_all(P, a, w.big, st));
   }
   // line 10: x_hat = F^H [ (1 - m) F Psi^H w + m y ]
   if (iters > 0) {
@@ -236,9 +237,9 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     if (H * nx[b] > kMaxElems || ny[b] * kColW > kMaxElems)
       return fail(VDAMP_ERR_UNSUPPORTED, "strip does not fit the LDS tile");
     const long long finest = (long long)(ny[b] >> 1) * (nx[b] >> 1);
-    if (finest > kSureMaxKeys)
-      return fail(VDAMP_ERR_UNSUPPORTED, "finest subband larger than the LDS threshold search (" +
-                                             std::to_string(kSureMaxKeys) + " coefficients)");
+    if (finest > kSureBigMaxKeys)
+      return fail(VDAMP_ERR_UNSUPPORTED, "finest subband larger than the threshold search (" +
+                                             std::to_string(kSureBigMaxKeys) + " coefficients)");
   }
 
   vdamp_plan_t* P = new vdamp_plan_t();
@@ -338,7 +339,7 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     for (int band = 0; band < P->nbands; ++band) {
       int l = band == 0 ? levels : levels - (band - 1) / 3;
       long long nbsz = (long long)(ny[b] >> l) * (nx[b] >> l);
-      const int cls = nbsz > 4 * kSureSmall ? 2 : nbsz > kSureSmall ? 1 : 0;
+      const int cls = nbsz > kSureMaxKeys ? 3 : nbsz > 4 * kSureSmall ? 2 : nbsz > kSureSmall ? 1 : 0;
       wsc[cls].push_back({nbsz, make_int2(b, band)});
     }
   }
@@ -387,6 +388,7 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   P->o_tau = o; o = align256(o + 4 * (size_t)batch * kMaxBands);
   P->o_taup = o; o = align256(o + 4 * (size_t)colstrip * kMaxBands);
   P->o_bad = o; o = align256(o + 4);
+  if (P->nsure_cls[3]) { P->o_big = o; o = align256(o + 4 * (size_t)P->nsure_cls[3] * kSureBigStride); }
   P->ws_bytes = o;
 
   auto upload = [&](auto*& dst, const auto& vec) -> hipError_t {

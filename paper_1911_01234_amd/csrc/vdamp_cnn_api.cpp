@@ -336,7 +336,7 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
     LAUNCH(Lr, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
     a.mode = k == 0 ? RA_VDAMP_FIRST : (prev_learned ? RA_LEARNED : RA_VDAMP);
     LAUNCH(Lr, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
-    LAUNCH(Lr, VDAMP_PASS_SURE, launch_sure_all(P, a, st));
+    LAUNCH(Lr, VDAMP_PASS_SURE, launch_sure_all(P, a, w.big, st));
     if (k < learned_from) continue;  // soft thresholding only in this iteration
     // learned denoiser on r_k: x = Psi^H r, t = Psi^H b, f(x), J_f t
     KArgs s = a;

@@ -37,6 +37,7 @@ struct Ws {
   float2 *r, *X, *r2;
   float *theta, *thr2, *alpha, *tau, *taup;
   int* bad;
+  float* big;  // full-sort scratch of the bands larger than the LDS search (or null)
 };
 
 extern thread_local std::string g_err;  // detail of the last failure on this thread
@@ -67,7 +68,7 @@ struct vdamp_plan_t {
   float* d_tables = nullptr;
   int2* d_work_rows = nullptr;
   int2* d_work_cols = nullptr;
-  int2* d_work_sure = nullptr;      // bands by size class: > 16384, > 4096, the rest
+  int2* d_work_sure = nullptr;      // bands by size class: > 27648, > 16384, > 4096, the rest
   int nrows = 0, ncols = 0, nsure_cls[vdamp::kSureClasses] = {};
   int nrowstrips = 0;
   // column launches: runs of the column work list with one ny each (first, count, M),
@@ -87,7 +88,7 @@ struct vdamp_plan_t {
   size_t lds_rows = 0, lds_cols = 0;
   // workspace layout (byte offsets)
   size_t o_wgt = 0, o_r = 0, o_X = 0, o_r2 = 0, o_theta = 0, o_thr2 = 0, o_alpha = 0, o_tau = 0,
-         o_taup = 0, o_bad = 0, ws_bytes = 0;
+         o_taup = 0, o_bad = 0, o_big = 0, ws_bytes = 0;
   // last solve
   const void* state_ws = nullptr;
   bool has_state = false;
@@ -106,7 +107,7 @@ Ws layout(const vdamp_plan_t* P, void* ws);
 hipError_t launch_rows_synth(const KArgs& a, int ept, int do_fft, size_t lds, hipStream_t st);
 hipError_t launch_cols(const KArgs& a, int ept, size_t lds, hipStream_t st);
 hipError_t launch_rows_anal(const KArgs& a, int ept, size_t lds, hipStream_t st);
-hipError_t launch_sure(const KArgs& a, int cls, hipStream_t st);
+hipError_t launch_sure(const KArgs& a, int cls, float* scratch, hipStream_t st);
 hipError_t launch_prep(const uint8_t* mask, const float* p, const float2* y, float* wgt,
                        long long n, int check, int* bad, hipStream_t st);
 hipError_t launch_zero(float2* x, long long n, hipStream_t st);
@@ -190,12 +191,12 @@ inline hipError_t launch_rows_anal_all(const vdamp_plan_t* P, KArgs a, hipStream
 }
 
 // Every band's threshold search (line 6): one launch per size class, largest first.
-inline hipError_t launch_sure_all(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
+inline hipError_t launch_sure_all(const vdamp_plan_t* P, KArgs a, float* scratch, hipStream_t st) {
   for (int c = kSureClasses - 1, first = 0; c >= 0; --c) {
     if (!P->nsure_cls[c]) continue;
     a.work = P->d_work_sure + first;
     a.nwork = P->nsure_cls[c];
-    hipError_t e = launch_sure(a, c, st);
+    hipError_t e = launch_sure(a, c, scratch, st);
     if (e != hipSuccess) return e;
     first += P->nsure_cls[c];
   }

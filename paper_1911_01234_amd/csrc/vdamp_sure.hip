@@ -41,6 +41,7 @@ __device__ __forceinline__ int wave_incl_prefix_int(int v, int lane) {
 template <int NB> struct SureBuckets;
 template <> struct SureBuckets<10240> { static constexpr int LB = 5, MB = 10; };
 template <> struct SureBuckets<2560> { static constexpr int LB = 3, MB = 8; };
+template <> struct SureBuckets<3072> { static constexpr int LB = 4, MB = 8; };
 
 template <int NB>
 __device__ __forceinline__ int sure_bucket(float key, float inv_tau) {
@@ -359,12 +360,477 @@ k_sure(KArgs a) {
   }
 }
 
+// In-place ascending sort of the keys sk[skx(0 .. Nb)) by a bitonic network whose
+// compare-exchanges all put the smaller key first (each merge starts by comparing
+// mirrored positions), so +inf padding up to npad (the next power of two) never moves
+// and needs no storage: only pairs with both indices < Nb are compared.
+template <int NT>
+__device__ void sure_bitonic(float* sk, int Nb, int npad) {
+  const int tid = threadIdx.x;
+  for (int k = 2; k <= npad; k <<= 1) {
+    for (int i = tid; i < (npad >> 1); i += NT) {
+      const int half = k >> 1;
+      const int blk = i / half, ofs = i - blk * half;
+      const int lo = blk * k + ofs, hi = blk * k + k - 1 - ofs;
+      if (hi < Nb) {
+        const float x = sk[skx(lo)], y = sk[skx(hi)];
+        if (x > y) { sk[skx(lo)] = y; sk[skx(hi)] = x; }
+      }
+    }
+    __syncthreads();
+    for (int j = k >> 2; j > 0; j >>= 1) {
+      for (int i = tid; i < (npad >> 1); i += NT) {
+        const int lo = 2 * j * (i / j) + (i & (j - 1));
+        const int hi = lo + j;
+        if (hi < Nb) {
+          const float x = sk[skx(lo)], y = sk[skx(hi)];
+          if (x > y) { sk[skx(lo)] = y; sk[skx(hi)] = x; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// SURE at every candidate of the sorted keys: each thread walks a contiguous chunk with
+// a = sqrt(key), A_m = sum_{i<=m} a_i^2 and R_m = sum_{i>m} 1/a_i (FP64 accumulation of
+// FP32 terms, chunk offsets from FP64 prefix/suffix scans) and evaluates
+// SURE(m) = A_m - m tau + (N_b - m)(a_m^2 + tau) - tau a_m R_m at the last index of each
+// run of equal keys with a > 0; per thread the best (value, index, R_m, key).
+template <int NT>
+__device__ void sure_walk(const float* sk, int Nb, double tau, double* wsA, double* wsR,
+                          double& best, int& besti, double& bestR, float& bestK) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int E = (Nb + NT - 1) / NT;
+  const int i0 = tid * E;
+  const int i1 = min(i0 + E, Nb);
+  double cA = 0.0, cR = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    const float k2 = sk[skx(i)];
+    cA += (double)k2;
+    if (k2 > 0.f) cR += (double)__frsqrt_rn(k2);
+  }
+  const double pA = wave_incl_prefix(cA, lane);
+  const double sR = wave_incl_suffix(cR, lane);
+  if (lane == 63) wsA[wid] = pA;
+  if (lane == 0) wsR[wid] = sR;
+  __syncthreads();
+  double offA = 0.0, offR = 0.0;
+  for (int w = 0; w < wid; ++w) offA += wsA[w];
+  for (int w = NW - 1; w > wid; --w) offR += wsR[w];
+  double A = offA + pA - cA;          // sum of a^2 over indices < i0
+  double Rrun = offR + sR;            // sum of 1/a over indices >= i0
+  best = __builtin_huge_val();
+  bestR = 0.0;
+  besti = 0x7fffffff;
+  bestK = 0.f;
+  const double Nbd = (double)Nb;
+  float knext = (i0 < i1) ? sk[skx(i0)] : 0.f;
+  for (int i = i0; i < i1; ++i) {
+    const float k2 = knext;
+    knext = (i + 1 < Nb) ? sk[skx(i + 1)] : __builtin_huge_valf();
+    A += (double)k2;
+    if (k2 > 0.f) {
+      Rrun -= (double)__frsqrt_rn(k2);  // now the sum over indices > i
+      if (knext > k2) {                 // last index of a run of equal keys
+        const double x = (double)__fsqrt_rn(k2);
+        const double m = (double)(i + 1);
+        const double sv = A - m * tau + (Nbd - m) * ((double)k2 + tau) - tau * x * Rrun;
+        if (sv < best) { best = sv; besti = i; bestR = Rrun; bestK = k2; }
+      }
+    }
+  }
+}
+
+// Workgroup argmin of the per-thread bests (ties to the smaller index), then theta =
+// sqrt(key), theta^2 = key and alpha = ((N_b - m) - theta R_m / 2) / N_b (line 7) for
+// the band, and the band's outputs.  No candidate (every key zero): eta = 0, alpha = 0.
+template <int NT>
+__device__ void sure_finish(const KArgs& a, int sl, int b, int Nb, float tau_f, double best, int besti,
+                            double bestR, float bestK, double* bv, int* bi, double* bR, float* bK) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double ov = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(besti, o, 64);
+    const double oR = __shfl_xor(bestR, o, 64);
+    const float oK = __shfl_xor(bestK, o, 64);
+    if (ov < best || (ov == best && oi < besti)) { best = ov; besti = oi; bestR = oR; bestK = oK; }
+  }
+  if (lane == 0) { bv[wid] = best; bi[wid] = besti; bR[wid] = bestR; bK[wid] = bestK; }
+  __syncthreads();
+  if (tid == 0) {
+    double fb = bv[0], fR = bR[0];
+    int fi = bi[0];
+    float fK = bK[0];
+    for (int w = 1; w < NW; ++w)
+      if (bv[w] < fb || (bv[w] == fb && bi[w] < fi)) { fb = bv[w]; fi = bi[w]; fR = bR[w]; fK = bK[w]; }
+    const double Nbd = (double)Nb, tau = (double)tau_f;
+    const bool none = fi == 0x7fffffff;
+    float th, th2, al;
+    if (none) {
+      th = 0.f;
+      th2 = 0.f;
+      al = 0.f;
+    } else {
+      th2 = fK;
+      th = __fsqrt_rn(th2);
+      const double m = (double)(fi + 1);
+      al = (float)(((Nbd - m) - 0.5 * (double)th * fR) / Nbd);
+    }
+    if (a.smin)  // every key zero: eta = 0 gives SURE = -N_b tau
+      a.smin[sl * kMaxBands + b] = none ? (float)(-Nbd * tau) : (float)fb;
+    a.theta[sl * kMaxBands + b] = th;
+    a.thr2[sl * kMaxBands + b] = th2;
+    a.alpha[sl * kMaxBands + b] = al;
+    a.tau[sl * kMaxBands + b] = tau_f;
+    if (a.trace) {
+      float* t = a.trace + (((long long)a.iter * a.batch + sl) * a.nbands + b) * 3;
+      t[0] = tau_f;
+      t[1] = th;
+      t[2] = al;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ large bands
+// Bands of more than kSureMaxKeys keys (up to 65536: the finest band of a 512 x 512
+// slice) do not fit LDS, so the argmin is found without sorting the band.  Keys are
+// re-read from r for each pass (the band stays in L2).  Per bucket of the key/tau
+// bucket map: count, smallest positive and largest key (integer atomics on the bit
+// patterns), and the sums of the keys and of their reciprocal square roots in 64-bit
+// fixed point with a power-of-two scale per bucket (integer additions commute, so the
+// sums do not depend on the order the atomics land in).  Bucket prefix/suffix scans
+// (FP64, fixed order) give for every bucket its first index P, the key sum A before it
+// and the 1/a sum R after it.  Then
+//   - the last key of each bucket is a candidate whose SURE is known from the sums;
+//     U = the smallest of these;
+//   - a candidate inside bucket b (t of its c keys at or below it, 1 <= t < c) has
+//     SURE >= A + t kmin - m tau + (N_b - m)(kmin + tau) - tau sqrt(kmax)(R + (c - t)/sqrt(kmin+))
+//     with m = P + t, linear in t, so its smallest value is at t = 1 or t = c - 1;
+//   - only buckets whose bound or end value is within a rounding margin of U can hold
+//     the argmin: their keys are gathered, ranked inside their bucket (one wave per
+//     bucket) and walked exactly, A and R carried in FP64 from the bucket boundaries.
+// A band with too many surviving keys or buckets (tau = 0 puts every key in one bucket)
+// is sorted in full in its global scratch region and walked there instead.
+constexpr int kSureBigBucketLimit = 256;  // keys of one surviving bucket
+constexpr int kSureBigMaxSeg = 256;       // surviving buckets
+constexpr int kSureBigCap = 6144;         // surviving keys
+constexpr int kSureBigNB = 3072;
+
+template <int NT, int NB, int CAP>
+__global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ scratch, int stride) {
+  constexpr int NW = NT / 64, BPT = NB / NT;
+  static_assert(NB % NT == 0, "buckets per thread");
+  __shared__ __align__(16) int smem[8 * NB + CAP];
+  int* cnt = smem;                   // [NB] counts, later fill counters
+  int* kmn = smem + NB;              // [NB] smallest positive key (bits), +inf if none
+  int* kmx = smem + 2 * NB;          // [NB] largest key (bits)
+  int* coff = smem + 3 * NB;         // [NB] offset of a surviving bucket in comp, else -1
+  unsigned long long* sA = reinterpret_cast<unsigned long long*>(smem + 4 * NB);  // [NB]
+  unsigned long long* sRq = sA + NB;                                              // [NB]
+  float* comp = reinterpret_cast<float*>(smem + 8 * NB);  // [CAP] surviving keys
+  __shared__ double wsA[NW], wsR[NW], bv[NW], bR[NW], wsU[NW];
+  __shared__ int bi[NW], wsC[NW], wsS[NW], wsM[NW];
+  __shared__ float bK[NW];
+  __shared__ float tau_sh;
+  __shared__ double ustar_sh, mag_sh;
+  __shared__ int tot_sh, bigc_sh, nseg_sh;
+  __shared__ int seg_off[kSureBigMaxSeg], seg_n[kSureBigMaxSeg], seg_p[kSureBigMaxSeg];
+  __shared__ double seg_a[kSureBigMaxSeg], seg_r[kSureBigMaxSeg];
+  const int2 item = a.work[blockIdx.x];
+  const int sl = item.x, b = item.y, s = a.levels;
+  const SliceDev S = a.slices[sl];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  int r0, c0, bh, bw;
+  band_geom(b, s, S.ny, S.nx, r0, c0, bh, bw);
+  const int Nb = bh * bw;
+  const float2* r = a.r + S.off + (long long)r0 * S.nx + c0;
+  const int lbw = 31 - __clz(bw);
+  const bool pow2 = (bw & (bw - 1)) == 0;
+#define KEY_AT(i) key_rn(r[(long long)(pow2 ? ((i) >> lbw) : (i) / bw) * S.nx + \
+                           ((i) - (pow2 ? ((i) >> lbw) : (i) / bw) * bw)])
+  for (int i = tid; i < NB; i += NT) {
+    cnt[i] = 0;
+    kmn[i] = 0x7f800000;
+    kmx[i] = 0;
+    sA[i] = 0ull;
+    sRq[i] = 0ull;
+  }
+  if (wid == 0) {
+    const int ncs = S.nx / kColW;
+    double acc = 0.0;
+    for (int i = lane; i < ncs; i += 64) acc += (double)a.tau_part[(S.colstrip0 + i) * kMaxBands + b];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) tau_sh = (float)acc;
+  }
+  __syncthreads();
+  const float inv_tau = 1.0f / tau_sh;
+  const double tau = (double)tau_sh;
+  for (int i = tid; i < Nb; i += NT) {
+    const float k = KEY_AT(i);
+    const int bk = sure_bucket<NB>(k, inv_tau);
+    atomicAdd(&cnt[bk], 1);
+    const int bits = (int)__float_as_uint(k);
+    atomicMax(&kmx[bk], bits);
+    if (k > 0.f) atomicMin(&kmn[bk], bits);
+  }
+  __syncthreads();
+  // fixed-point sums: scale 2^(40 - e) with 2^e >= the bucket's largest term
+  for (int i = tid; i < Nb; i += NT) {
+    const float k = KEY_AT(i);
+    if (k > 0.f) {
+      const int bk = sure_bucket<NB>(k, inv_tau);
+      int e;
+      frexp((double)__uint_as_float((unsigned)kmx[bk]), &e);
+      atomicAdd(&sA[bk], (unsigned long long)ldexp((double)k, 40 - e));
+      frexp((double)__frsqrt_rn(__uint_as_float((unsigned)kmn[bk])), &e);
+      atomicAdd(&sRq[bk], (unsigned long long)ldexp((double)__frsqrt_rn(k), 40 - e));
+    }
+  }
+  __syncthreads();
+  // this thread's buckets tid*BPT .. +BPT: counts and sums, then block scans
+  int c[BPT];
+  double dA[BPT], dR[BPT];
+  int csum = 0;
+  double asum = 0.0, rsum = 0.0;
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int bk = tid * BPT + q;
+    c[q] = cnt[bk];
+    dA[q] = 0.0;
+    dR[q] = 0.0;
+    const float kx = __uint_as_float((unsigned)kmx[bk]);
+    if (c[q] && kx > 0.f) {
+      int e;
+      frexp((double)kx, &e);
+      dA[q] = ldexp((double)sA[bk], e - 40);
+      frexp((double)__frsqrt_rn(__uint_as_float((unsigned)kmn[bk])), &e);
+      dR[q] = ldexp((double)sRq[bk], e - 40);
+    }
+    csum += c[q];
+    asum += dA[q];
+    rsum += dR[q];
+  }
+  const int cinc = wave_incl_prefix_int(csum, lane);
+  const double ainc = wave_incl_prefix(asum, lane);
+  const double rinc = wave_incl_suffix(rsum, lane);
+  if (lane == 63) { wsC[wid] = cinc; wsA[wid] = ainc; }
+  if (lane == 0) wsR[wid] = rinc;
+  __syncthreads();
+  int P = cinc - csum;
+  double Ab = ainc - asum, Ra = rinc - rsum;
+  for (int w = 0; w < wid; ++w) { P += wsC[w]; Ab += wsA[w]; }
+  for (int w = NW - 1; w > wid; --w) Ra += wsR[w];
+  double Atot = 0.0;
+  for (int w = 0; w < NW; ++w) Atot += wsA[w];
+  int Pq[BPT];
+  double Abq[BPT], Raq[BPT];
+  {
+    int pp = P;
+    double aa = Ab, rr = Ra + rsum;
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      Pq[q] = pp;
+      Abq[q] = aa;
+      rr -= dR[q];
+      Raq[q] = rr;
+      pp += c[q];
+      aa += dA[q];
+    }
+  }
+  const double Nbd = (double)Nb;
+  double endv[BPT];
+  double umin = __builtin_huge_val();
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    endv[q] = __builtin_huge_val();
+    const float kx = __uint_as_float((unsigned)kmx[tid * BPT + q]);
+    if (c[q] && kx > 0.f) {
+      const double m = (double)(Pq[q] + c[q]);
+      const double x = (double)__fsqrt_rn(kx);
+      endv[q] = (Abq[q] + dA[q]) - m * tau + (Nbd - m) * ((double)kx + tau) - tau * x * Raq[q];
+      umin = fmin(umin, endv[q]);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) umin = fmin(umin, __shfl_xor(umin, o, 64));
+  if (lane == 0) wsU[wid] = umin;
+  __syncthreads();
+  if (tid == 0) {
+    double u = wsU[0];
+    for (int w = 1; w < NW; ++w) u = fmin(u, wsU[w]);
+    ustar_sh = u;
+    mag_sh = Atot;
+  }
+  __syncthreads();
+  const double ustar = ustar_sh;
+  const double margin = 1e-9 * (fabs(ustar) + Nbd * tau + mag_sh) + 1e-300;
+  bool surv[BPT];
+  int ssum = 0, nseg = 0, big = 0;
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    surv[q] = false;
+    const int bk = tid * BPT + q;
+    const float kx = __uint_as_float((unsigned)kmx[bk]);
+    if (!c[q] || !(kx > 0.f)) continue;  // empty, or every key zero: no candidate
+    bool sv = endv[q] <= ustar + margin;
+    if (c[q] >= 2) {
+      const float kn = __uint_as_float((unsigned)kmn[bk]);
+      const double kminA = (bk == 0) ? 0.0 : (double)kn;  // zero keys only in bucket 0
+      const double rmax = (double)__frsqrt_rn(kn);
+      const double sx = (double)__fsqrt_rn(kx);
+      double lb = __builtin_huge_val();
+      for (int e2 = 0; e2 < 2; ++e2) {
+        const int t = e2 ? c[q] - 1 : 1;
+        const double m = (double)(Pq[q] + t);
+        lb = fmin(lb, Abq[q] + t * kminA - m * tau + (Nbd - m) * (kminA + tau) -
+                          tau * sx * (Raq[q] + (c[q] - t) * rmax));
+      }
+      sv = sv || lb <= ustar + margin;
+    }
+    surv[q] = sv;
+    if (sv) {
+      ssum += c[q];
+      nseg += 1;
+      big = max(big, c[q]);
+    }
+  }
+  const int sinc = wave_incl_prefix_int(ssum, lane);
+  const int ginc = wave_incl_prefix_int(nseg, lane);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) big = max(big, __shfl_xor(big, o, 64));
+  if (lane == 63) { wsS[wid] = sinc; wsC[wid] = ginc; }
+  if (lane == 0) wsM[wid] = big;
+  __syncthreads();
+  int soff = sinc - ssum, goff = ginc - nseg, gtot = 0;
+  for (int w = 0; w < wid; ++w) { soff += wsS[w]; goff += wsC[w]; }
+  for (int w = 0; w < NW; ++w) gtot += wsC[w];
+  const bool fits = gtot <= kSureBigMaxSeg;
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int bk = tid * BPT + q;
+    coff[bk] = surv[q] ? soff : -1;
+    cnt[bk] = 0;  // fill counter of the gather
+    if (surv[q]) {
+      if (fits) {
+        seg_off[goff] = soff;
+        seg_n[goff] = c[q];
+        seg_p[goff] = Pq[q];
+        seg_a[goff] = Abq[q];
+        seg_r[goff] = Raq[q];
+      }
+      soff += c[q];
+      goff += 1;
+    }
+  }
+  if (tid == NT - 1) tot_sh = soff;
+  if (tid == 0) {
+    int m = 0;
+    for (int w = 0; w < NW; ++w) m = max(m, wsM[w]);
+    bigc_sh = m;
+    nseg_sh = gtot;
+  }
+  __syncthreads();
+  double best = __builtin_huge_val(), bestR = 0.0;
+  int besti = 0x7fffffff;
+  float bestK = 0.f;
+  if (tot_sh <= CAP && bigc_sh <= kSureBigBucketLimit && nseg_sh <= kSureBigMaxSeg) {
+    for (int i = tid; i < Nb; i += NT) {
+      const float k = KEY_AT(i);
+      const int bk = sure_bucket<NB>(k, inv_tau);
+      const int o = coff[bk];
+      if (o >= 0) comp[o + atomicAdd(&cnt[bk], 1)] = k;
+    }
+    __syncthreads();
+    // one wave per surviving bucket: rank its keys (every lane reads the same key in
+    // turn), put them in order, then walk them with wave prefix sums
+    for (int g = wid; g < nseg_sh; g += NW) {
+      const int off0 = seg_off[g], n = seg_n[g];
+      constexpr int MAXL = kSureBigBucketLimit / 64;
+      float v[MAXL];
+      int rk[MAXL];
+#pragma unroll
+      for (int h = 0; h < MAXL; ++h) {
+        const int l = lane + 64 * h;
+        v[h] = (l < n) ? comp[off0 + l] : __builtin_huge_valf();
+        rk[h] = 0;
+      }
+      for (int x = 0; x < n; ++x) {
+        const float u = comp[off0 + x];
+#pragma unroll
+        for (int h = 0; h < MAXL; ++h) rk[h] += (u < v[h]) || (u == v[h] && x < lane + 64 * h);
+      }
+#pragma unroll
+      for (int h = 0; h < MAXL; ++h)
+        if (lane + 64 * h < n) comp[off0 + rk[h]] = v[h];
+      __builtin_amdgcn_wave_barrier();
+      double A = seg_a[g], R = seg_r[g], rtot = 0.0;
+#pragma unroll
+      for (int h = 0; h < MAXL; ++h) {
+        const int l = lane + 64 * h;
+        v[h] = (l < n) ? comp[off0 + l] : 0.f;
+        rtot += (l < n && v[h] > 0.f) ? (double)__frsqrt_rn(v[h]) : 0.0;
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) rtot += __shfl_xor(rtot, o, 64);
+      R += rtot;  // 1/a over this bucket and above
+      const int P0 = seg_p[g];
+#pragma unroll
+      for (int h = 0; h < MAXL; ++h) {
+        if (64 * h >= n) break;
+        const int l = lane + 64 * h;
+        const float k2 = v[h];
+        const double ka = (l < n) ? (double)k2 : 0.0;
+        const double ra = (l < n && k2 > 0.f) ? (double)__frsqrt_rn(k2) : 0.0;
+        const double pa = wave_incl_prefix(ka, lane);
+        const double pr = wave_incl_prefix(ra, lane);
+        const double chA = __shfl(pa, 63, 64), chR = __shfl(pr, 63, 64);
+        if (l < n && k2 > 0.f) {
+          const float kn = (l + 1 < n) ? comp[off0 + l + 1] : __builtin_huge_valf();
+          if (kn > k2) {  // last index of a run of equal keys
+            const double Am = A + pa, Rm = R - pr;
+            const double xx = (double)__fsqrt_rn(k2);
+            const double m = (double)(P0 + l + 1);
+            const double sv = Am - m * tau + (Nbd - m) * ((double)k2 + tau) - tau * xx * Rm;
+            if (sv < best || (sv == best && P0 + l < besti)) {
+              best = sv;
+              besti = P0 + l;
+              bestR = Rm;
+              bestK = k2;
+            }
+          }
+        }
+        A += chA;
+        R -= chR;
+      }
+    }
+  } else {
+    // sort the whole band in its scratch region and walk it there
+    float* sk = scratch + (long long)blockIdx.x * stride;
+    int npad = 1;
+    while (npad < Nb) npad <<= 1;
+    for (int i = tid; i < Nb; i += NT) sk[skx(i)] = KEY_AT(i);
+    __syncthreads();
+    sure_bitonic<NT>(sk, Nb, npad);
+    sure_walk<NT>(sk, Nb, tau, wsA, wsR, best, besti, bestR, bestK);
+  }
+#undef KEY_AT
+  sure_finish<NT>(a, sl, b, Nb, tau_sh, best, besti, bestR, bestK, bv, bi, bR, bK);
+}
+
 // Size classes: up to 4096 keys (256 threads, 2560 buckets), up to 16384 keys
 // (1024 threads, 16 keys each) and up to kSureMaxKeys keys (1024 threads, 32 keys each),
 // the last two with 10240 buckets.  All LDS is static: the largest class uses about
 // 158 KB of the 160 KB a gfx950 workgroup may hold.
-hipError_t launch_sure(const KArgs& a, int cls, hipStream_t st) {
-  if (cls == 2)
+hipError_t launch_sure(const KArgs& a, int cls, float* scratch, hipStream_t st) {
+  if (cls == 3)
+    hipLaunchKernelGGL((k_sure_big<1024, kSureBigNB, kSureBigCap>), dim3(a.nwork), dim3(1024), 0, st, a,
+                       scratch, kSureBigStride);
+  else if (cls == 2)
     hipLaunchKernelGGL((k_sure<1024, 32, 10240, kSureMaxKeys>), dim3(a.nwork), dim3(1024), 0, st, a);
   else if (cls == 1)
     hipLaunchKernelGGL((k_sure<1024, 16, 10240, 4 * kSureSmall>), dim3(a.nwork), dim3(1024), 0, st, a);

@@ -220,3 +220,13 @@ def workload_mixed(n_per_size: int = 128, sizes=(128, 192, 256, 320), cfg_id: in
         n = sizes[order[i] % len(sizes)]
         out.append(make_slice(cfg_id, i, n, n, 16, Rs[i], 6.0, 16, snrs[i]))
     return out, 4, 50
+
+
+def workload_batch512(batch: int, cfg_id: int = 5, Rs=(8.0, 12.0), first_slice: int = 0):
+    """512x512 slices: 32 ellipses plus textured regions (filtered Gaussian noise),
+    p ~ (1-r)^6 with a 32x32 centre, R cycling over Rs (8x and 12x), 40 dB, 4 Haar levels,
+    50 iterations."""
+    out = []
+    for b in range(first_slice, first_slice + batch):
+        out.append(make_slice(cfg_id, b, 512, 512, 32, Rs[b % len(Rs)], 6.0, 32, 40.0, texture=True))
+    return out, 4, 50

@@ -54,6 +54,7 @@ def _plan_status(batch, ny, nx, levels, wavelet=0, flags=0, null=None):
     ((2, [64, 64], [64, 4], 3), 2),          # second slice smaller than 2^s
     ((1, [64], [64], 3, 1), 3),              # unknown wavelet
     ((1, [64], [64], 3, 0, 1 << 30), 1),     # unknown flag
+    ((1, [64], [48], 4), 3),                 # nx / 2^s odd: a coefficient pair would straddle two bands
 ])
 def test_plan_rejects_bad_arguments(args, code):
     st, msg = _plan_status(*args)
@@ -83,3 +84,18 @@ def test_python_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(V, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         V.load_library()
+
+
+def test_plan_accepts_512_slices():
+    """512 x 512 with 4 levels: finest band of 65536 coefficients (the large-band search)
+    passes every host check; without a GPU the plan then stops at its device upload."""
+    lib = V.load_library()
+    h = ctypes.c_void_p()
+    wsb = ctypes.c_size_t()
+    n = (ctypes.c_int32 * 2)(512, 256)
+    st = lib.vdamp_plan(ctypes.byref(h), 2, n, n, 4, 0, 0, ctypes.byref(wsb))
+    msg = lib.vdamp_last_error().decode()
+    if st == 0:
+        assert lib.vdamp_plan_destroy(h) == 0
+    else:
+        assert st == 5 and "upload" in msg, msg

@@ -341,3 +341,36 @@ def test_mixed_size_batch_sampled():
         seen.setdefault(sl.y.shape[0], b)
     for n, b in sorted(seen.items()):
         sampled_trace_parity(g, b, slices[b], s, K)
+
+
+def test_free_running_512_large_bands():
+    """512x512 (32 ellipses with texture, R = 8): finest bands of 65536 keys, searched
+    without a full sort (k_sure_big)."""
+    sl = synth.workload_batch512(1)[0][0]
+    free_running(sl, 4, 10)
+
+
+def test_batch_512_sampled():
+    """A batch of 8 slices of 512x512 (R = 8 and 12) as one plan: sampled slices against
+    the oracle over 20 iterations."""
+    slices, s, _ = synth.workload_batch512(8)
+    K = 20
+    g = run_vdamp(slices, s, K)
+    for b in (0, 7):
+        sampled_trace_parity(g, b, slices[b], s, K)
+
+
+def test_noise_free_full_sampling_512():
+    """tau = 0 at 512x512: every key of a band falls in one bucket, so the large-band
+    search sorts the band in full in its workspace scratch."""
+    sl = synth.workload_batch512(1)[0][0]
+    sl.mask = np.ones_like(sl.mask)
+    sl.p = np.ones_like(sl.p)
+    sl.sigma2 = 0.0
+    sl.y = o.fft2u(sl.x0)
+    g = run_vdamp([sl], 4, 2)
+    assert np.all(g["trace"][:, 0, :, 0] == 0)
+    ref = o.vdamp(sl.y, sl.mask, sl.p, 0.0, 4, 2)
+    e = rel_l2(g["x_hat"][0], ref["x_hat"])
+    print(f"tau = 0 at 512: x_hat rel L2 {e:.2e}")
+    assert e <= TOL_ITER
