@@ -50,23 +50,63 @@ __global__ void __launch_bounds__(kThr) k_conv(ConvArgs a) {
     *reinterpret_cast<uint4*>(&s_w[row * WS + c8 * 8]) =
         *reinterpret_cast<const uint4*>(&a.w[row * KPAD + c8 * 8]);
   }
+  // the halo of the next tile is fetched into registers while the current one is
+  // computed (software pipelining across the persistent tile loop)
+  constexpr int HV = 18 * 18 * CH8;                 // 16-byte vectors of a halo
+  constexpr int HPT = (HV + kThr - 1) / kThr;       // ... per thread
+  uint4 pre[HPT];
+#define CONV_FETCH(TI)                                                                   \
+  {                                                                                      \
+    const int2 tf = a.tiles[TI];                                                         \
+    const SliceDev Sf = a.slices[tf.x];                                                  \
+    const int fnx = Sf.nx, fny = Sf.ny, ftpr = fnx >> 4;                                 \
+    const int fty0 = (tf.y / ftpr) * 16, ftx0 = (tf.y - (tf.y / ftpr) * ftpr) * 16;      \
+    _Pragma("unroll") for (int q = 0; q < HPT; ++q) {                                    \
+      const int i = tid + q * kThr;                                                      \
+      pre[q] = make_uint4(0u, 0u, 0u, 0u);                                               \
+      if (i < HV) {                                                                      \
+        const int hp = i / CH8, c8 = i - hp * CH8;                                       \
+        const int hy = hp / 18, hx = hp - hy * 18;                                       \
+        int gy = fty0 + hy - 1, gx = ftx0 + hx - 1;                                      \
+        gy += (gy < 0) ? fny : 0; gy -= (gy >= fny) ? fny : 0;                           \
+        gx += (gx < 0) ? fnx : 0; gx -= (gx >= fnx) ? fnx : 0;                           \
+        const long long pix = Sf.off + (long long)gy * fnx + gx;                         \
+        pre[q] = *reinterpret_cast<const uint4*>(&a.in[pix * CIN + c8 * 8]);             \
+      }                                                                                  \
+    }                                                                                    \
+  }
+  if (blockIdx.x < a.ntiles) CONV_FETCH(blockIdx.x);
+  // bias of this lane's output channels (mt * 16 + 4 g + i), loaded once
+  float bias_r[MT][4];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = mt * 16 + 4 * g + i;
+      bias_r[mt][i] = (a.bias && (MODE == CV_RELU || co < 2)) ? a.bias[co] : 0.f;
+    }
   for (int ti = blockIdx.x; ti < a.ntiles; ti += gridDim.x) {
     const int2 t = a.tiles[ti];
     const SliceDev S = a.slices[t.x];
-    const int nx = S.nx, ny = S.ny, tpr = nx >> 4;
+    const int nx = S.nx, tpr = nx >> 4;
     const int ty0 = (t.y / tpr) * 16, tx0 = (t.y - (t.y / tpr) * tpr) * 16;
     __syncthreads();  // weights staged / previous tile done with s_in
-    for (int i = tid; i < 18 * 18 * CH8; i += kThr) {
-      const int hp = i / CH8, c8 = i - hp * CH8;
-      const int hy = hp / 18, hx = hp - hy * 18;
-      int gy = ty0 + hy - 1, gx = tx0 + hx - 1;
-      gy += (gy < 0) ? ny : 0; gy -= (gy >= ny) ? ny : 0;
-      gx += (gx < 0) ? nx : 0; gx -= (gx >= nx) ? nx : 0;
-      const long long pix = S.off + (long long)gy * nx + gx;
-      *reinterpret_cast<uint4*>(&s_in[hp * PS + c8 * 8]) =
-          *reinterpret_cast<const uint4*>(&a.in[pix * CIN + c8 * 8]);
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+      const int i = tid + q * kThr;
+      if (i < HV) {
+        const int hp = i / CH8, c8 = i - hp * CH8;
+        *reinterpret_cast<uint4*>(&s_in[hp * PS + c8 * 8]) = pre[q];
+      }
     }
     __syncthreads();
+    if (ti + (int)gridDim.x < a.ntiles) CONV_FETCH(ti + gridDim.x);
+    float sb[MT][4];  // per-slice bias of the first layer
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        sb[mt][i] = (MODE == CV_RELU && a.sbias) ? a.sbias[t.x * kCh + mt * 16 + 4 * g + i] : 0.f;
     f32x4 acc[MT][4];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -109,11 +149,7 @@ __global__ void __launch_bounds__(kThr) k_conv(ConvArgs a) {
           for (int i = 0; i < 4; ++i) z[i] = acc[mt][nt][i];
           if (MODE == CV_RELU) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              if (a.bias) z[i] += a.bias[co0 + i];
-              if (a.sbias) z[i] += a.sbias[t.x * kCh + co0 + i];
-              z[i] = fmaxf(z[i], 0.f);
-            }
+            for (int i = 0; i < 4; ++i) z[i] = fmaxf(z[i] + bias_r[mt][i] + sb[mt][i], 0.f);
           } else {
             const uint2 mk = *reinterpret_cast<const uint2*>(&a.mask[gp * kCh + co0]);
             const u16 m4[4] = {(u16)(mk.x & 0xFFFF), (u16)(mk.x >> 16), (u16)(mk.y & 0xFFFF), (u16)(mk.y >> 16)};
@@ -130,13 +166,14 @@ __global__ void __launch_bounds__(kThr) k_conv(ConvArgs a) {
         float o0 = acc[0][nt][0], o1 = acc[0][nt][1];
         if (MODE == CV_LAST) {
           const float s = a.s0[t.x];
-          o0 = s * (o0 + a.bias[0]);
-          o1 = s * (o1 + a.bias[1]);
+          o0 = s * (o0 + bias_r[0][0]);
+          o1 = s * (o1 + bias_r[0][1]);
         }
         a.img_out[gp] = make_float2(rin.x - o0, rin.y - o1);
       }
     }
   }
+#undef CONV_FETCH
 }
 
 // ------------------------------------------------------------------ weight gradient
