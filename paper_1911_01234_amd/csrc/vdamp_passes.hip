@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
   constexpr int P2 = N + ((M % 2) ? 0 : 16);         // LDS pitch of an inverse block
   constexpr int TB = (M * P1 > 16 * P2) ? M * P1 : 16 * P2;
   __shared__ float2 tw_s[N];
-  __shared__ float ytab_s[8 * N];
+  __shared__ __align__(16) float ytab_s[8 * N];  // [row][table], 8 tables a row
   __shared__ float2 tb[TB];
   __shared__ float red[kThreads / 64][kMaxBands];
   const int2 item = a.work[blockIdx.x];
@@ -322,7 +322,10 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
   for (int i = tid; i < N; i += kThreads) tw_s[i] = a.twiddles[P.tw_off + i];
   const int ntab = 2 * s;
   if (vd)
-    for (int i = tid; i < ntab * N; i += kThreads) ytab_s[i] = a.tables[S.ytab_off + i];
+    for (int i = tid; i < 8 * N; i += kThreads) {
+      const int row = i >> 3, t = i & 7;
+      ytab_s[i] = (t < ntab) ? a.tables[S.ytab_off + t * N + row] : 0.f;
+    }
   __syncthreads();
   if (!first) {
     RegFft<M, false>::run(xin, tw_s, 16);
@@ -364,9 +367,16 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
             const float2 z = csub(yy, X);
             o = cscale(z, w);
             const float cc = w * ((w - 1.0f) * (z.x * z.x + z.y * z.y) + sig2);
-#pragma unroll
-            for (int t = 0; t < 8; ++t)
-              if (t < ntab) Q[t] = fmaf(ytab_s[t * N + row], cc, Q[t]);
+            const float4 y0 = *reinterpret_cast<const float4*>(&ytab_s[row * 8]);
+            const float4 y1 = *reinterpret_cast<const float4*>(&ytab_s[row * 8 + 4]);
+            Q[0] = fmaf(y0.x, cc, Q[0]);
+            Q[1] = fmaf(y0.y, cc, Q[1]);
+            Q[2] = fmaf(y0.z, cc, Q[2]);
+            Q[3] = fmaf(y0.w, cc, Q[3]);
+            Q[4] = fmaf(y1.x, cc, Q[4]);
+            Q[5] = fmaf(y1.y, cc, Q[5]);
+            Q[6] = fmaf(y1.z, cc, Q[6]);
+            Q[7] = fmaf(y1.w, cc, Q[7]);
           }
         } else if (mode == CM_OUTPUT) {
           o = (w > 0.f) ? yy : X;
