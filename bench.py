@@ -68,6 +68,68 @@ def algorithmic_bytes_per_solve(npx, iters):
             "rows_anal": (ra, iters + 1), "sure": (su, iters)}
 
 
+def pass_rooflines(times, npx, iters, steps):
+    """Per kernel class: average launch time and algorithmic bytes / time against the
+    HBM peak (times from the plan's per-kernel HIP events over `steps` solves)."""
+    alg = algorithmic_bytes_per_solve(npx, iters)
+    out = {}
+    for k, (b, _) in alg.items():
+        ms, launches = times[k]
+        if launches == 0:
+            continue
+        gbs = b * steps / (ms / 1e3) / 1e9
+        out[k] = {"us_per_launch": round(1e3 * ms / launches, 2), "achieved_GBs": round(gbs, 1),
+                  "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def other_workloads(stream, reps=3):
+    """Throughput of the other batch shapes the library is built for: the ragged batch of
+    512 slices (128 each of 128^2, 192^2, 256^2, 320^2) and 128 slices of 512^2 (whose
+    finest bands take the large-band threshold search).  One warm-up solve, then `reps`
+    timed solves of 50 iterations each, eager with per-kernel events."""
+    import torch
+    from paper_1911_01234_amd import synth, vdamp as V
+    res = {}
+    for name, gen in (("mixed_512_slices_128_to_320", lambda: synth.workload_mixed(128)),
+                      ("batch_128_slices_512x512", lambda: synth.workload_batch512(128))):
+        t = time.perf_counter()
+        slices, s, K = gen()
+        tg = time.perf_counter() - t
+        ny = [sl.y.shape[0] for sl in slices]
+        nx = [sl.y.shape[1] for sl in slices]
+        npx = int(sum(u * v for u, v in zip(ny, nx)))
+        with torch.cuda.stream(stream):
+            plan = V.Plan(ny, nx, s, V.VDAMP_FLAG_TIMING)
+            ws = plan.workspace()
+            y, mask, p, sigma2 = V.to_device(plan, slices)
+            xh = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+            x0 = torch.from_numpy(plan.pack([sl.x0 for sl in slices], np.complex64)).cuda()
+            seg = torch.from_numpy(np.repeat(np.arange(len(slices)), [u * v for u, v in zip(ny, nx)])).cuda()
+            plan.vdamp_solve(ws, y, mask, p, sigma2, K, xh, stream=stream)
+            stream.synchronize()
+            plan.vdamp_pass_times()
+            t = time.perf_counter()
+            for _ in range(reps):
+                plan.vdamp_solve(ws, y, mask, p, sigma2, K, xh, stream=stream)
+            stream.synchronize()
+            dt = (time.perf_counter() - t) / reps
+            times = plan.vdamp_pass_times()
+            nm = float(nmse_db_batch(xh, x0, seg, len(slices)).mean())
+            plan.close()
+        del ws, y, mask, p, sigma2, xh, x0, seg
+        torch.cuda.empty_cache()
+        res[name] = {"slices": len(slices), "pixels": npx, "iters": K,
+                     "seconds_per_solve": round(dt, 5),
+                     "slice_iterations_per_s": round(len(slices) * K / dt, 1),
+                     "mpx_iterations_per_s": round(npx * K / dt / 1e6, 1),
+                     "nmse_db_mean": round(nm, 3),
+                     "passes": pass_rooflines(times, npx, K, reps)}
+        print(f"[bench] {name}: generated in {tg:.1f} s, {res[name]['slice_iterations_per_s']} slice-it/s",
+              file=sys.stderr, flush=True)
+    return res
+
+
 def make_batch(B):
     from paper_1911_01234_amd import synth
     slices, s, K = synth.workload_batch256(B)
@@ -116,20 +178,32 @@ def measured_traffic(kernel_class):
     return rec["traffic_bytes_per_launch"] if h.hexdigest()[:16] == rec["source_sha"] else None
 
 
-def cpu_baseline(slices, s, iters, budget_s):
-    """FP64 oracle on the host, one slice at a time, until about budget_s seconds."""
+def cpu_baseline(slices, s, iters, budget_s, gpu_nmse=None):
+    """FP64 oracle on the host, one slice at a time, until about budget_s seconds.  With
+    the GPU's per-slice NMSE after the same iteration count, the sample's oracle NMSE is
+    reported beside it."""
     from oracle import vdamp_ref as o
     t0 = time.perf_counter()
     done = 0
+    nm = []
     for sl in slices:
-        o.vdamp(sl.y, sl.mask, sl.p, sl.sigma2, s, iters)
+        xr = o.vdamp(sl.y, sl.mask, sl.p, sl.sigma2, s, iters)["x_hat"]
         done += 1
+        nm.append(10.0 * np.log10(np.sum(np.abs(xr - sl.x0) ** 2) / np.sum(np.abs(sl.x0) ** 2)))
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": done * iters / dt, "unit": "slice-iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of the batch's 256x256 slices x {iters} iterations, FP64 NumPy, "
-                      f"one process (pocketfft and sort single-threaded), {dt:.1f} s"}
+    out = {"value": done * iters / dt, "unit": "slice-iterations/s", "cores": 1, "kind": "oracle",
+           "sample": f"{done} of the batch's 256x256 slices x {iters} iterations, FP64 NumPy, "
+                     f"one process (pocketfft and sort single-threaded), {dt:.1f} s"}
+    if gpu_nmse is not None:
+        g = np.asarray(gpu_nmse[:done], dtype=np.float64)
+        d = g - np.asarray(nm)
+        out["nmse_check"] = {"slices": done, "oracle_db_mean": round(float(np.mean(nm)), 3),
+                             "gpu_db_mean": round(float(np.mean(g)), 3),
+                             "median_abs_diff_db": round(float(np.median(np.abs(d))), 4),
+                             "max_abs_diff_db": round(float(np.max(np.abs(d))), 4)}
+    return out
 
 
 def learned_section(args, test, s, K, stream):
@@ -301,6 +375,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="time hipGraph replays instead of eager launches")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-denoiser section")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mixed and 512x512 batches")
     ap.add_argument("--train-slices", type=int, default=64)
     ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--test-slices", type=int, default=64)
@@ -365,9 +440,11 @@ def main():
     dt = time.perf_counter() - t0
     ms_per_step = 1e3 * dt / args.steps
     value = B * K * args.steps / dt
+    nmse_k = nmse_db_batch(x_hat, x0, seg, B)  # after the K-iteration solves
 
     roofline = None
     pass_ms = None
+    passes = None
     if flags & V.VDAMP_FLAG_TIMING:
         times = plan.vdamp_pass_times()
         pass_ms = {k: v[0] / args.steps for k, v in times.items()}
@@ -385,6 +462,7 @@ def main():
         allb = sum(v[0] for v in alg.values()) * args.steps
         allt = sum(times[k][0] for k in alg) / 1e3
         roofline["all_passes_achieved_GBs"] = round(allb / allt / 1e9, 1)
+        passes = pass_rooflines(times, npx, K, args.steps)
 
     # time-to-NMSE: smallest iteration count whose batch-mean NMSE is within 0.1 dB of
     # the 50-iteration value (monitored runs), timed unmonitored
@@ -408,6 +486,10 @@ def main():
     if flags & V.VDAMP_FLAG_TIMING:
         plan.vdamp_pass_times()
 
+    extra = None
+    if not args.no_extra:
+        extra = other_workloads(stream)
+
     learned = None
     if not args.no_learned:
         learned = learned_section(args, slices[:args.test_slices], s, K, stream)
@@ -415,7 +497,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(slices, s, K, args.cpu_budget)
+        cpu = cpu_baseline(slices, s, K, args.cpu_budget, nmse_k)
 
     out = {
         "metric": METRIC,
@@ -439,6 +521,8 @@ def main():
         "plan_seconds": round(t_plan, 4),
         "roofline": roofline,
         "pass_ms_per_step": {k: round(v, 4) for k, v in pass_ms.items()} if pass_ms else None,
+        "passes": passes,
+        "other_workloads": extra,
         "cpu_baseline": cpu,
         "learned": learned,
     }

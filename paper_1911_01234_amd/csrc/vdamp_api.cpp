@@ -287,6 +287,13 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
         haar_power(n, l, wv == 1, pw);
         for (int k = 0; k < n; ++k) tables.push_back((float)pw[k]);
       }
+    // then (cos^2, sin^2)(pi k / n) per k: the factors the four-step column pass builds
+    // the same products from (D_{2^m}(k) = 2^m prod_{j<m} cos(pi k 2^j / n))
+    for (int k = 0; k < n; ++k) {
+      const double t = M_PI * (double)k / (double)n;
+      tables.push_back((float)(std::cos(t) * std::cos(t)));
+      tables.push_back((float)(std::sin(t) * std::sin(t)));
+    }
     tab_index[n] = o;
     return o;
   };

@@ -389,20 +389,29 @@ __global__ void __launch_bounds__(kThr) k_sum_all(const float* __restrict__ v, l
 }
 
 // Gradient of the per-slice bias weights: dWt[co][b] = sum_slices S[slice][co] t[slice][b],
-// with S the per-slice sums of the first layer's pre-activation gradient (summed from
-// per-tile sums in tile order).
-__global__ void k_wt_grad(const float* __restrict__ tile_sums, const int* __restrict__ tile_off,
-                          const float* __restrict__ tau, const float* __restrict__ s0, int nb,
-                          int batch, float* __restrict__ dwt) {
-  const int co = blockIdx.x, b = threadIdx.x;
-  if (co >= kCh || b >= nb) return;
+// with S the per-slice sums of the first layer's pre-activation gradient (the slice's
+// per-tile sums, added in a fixed order: lane-strided, then a wave tree).
+__global__ void __launch_bounds__(256) k_wt_grad(const float* __restrict__ tile_sums,
+                                                 const int* __restrict__ tile_off,
+                                                 const float* __restrict__ tau,
+                                                 const float* __restrict__ s0, int nb, int batch,
+                                                 float* __restrict__ dwt) {
+  // one workgroup per output channel; wave w takes slices w, w + 4, ...: its lanes sum
+  // the slice's tile partials, and lane b < nb accumulates the band-b term
+  __shared__ float red[4][kMaxBands];
+  const int co = blockIdx.x, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (co >= kCh) return;
   float acc = 0.f;
-  for (int sl = 0; sl < batch; ++sl) {
+  for (int sl = wid; sl < batch; sl += 4) {
     float ssum = 0.f;
-    for (int ti = tile_off[sl]; ti < tile_off[sl + 1]; ++ti) ssum += tile_sums[(long long)ti * kCh + co];
-    acc += ssum * tau_feature(tau[sl * kMaxBands + b], s0[sl]);
+    for (int ti = tile_off[sl] + lane; ti < tile_off[sl + 1]; ti += 64) ssum += tile_sums[(long long)ti * kCh + co];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) ssum += __shfl_xor(ssum, o, 64);
+    if (lane < nb) acc += ssum * tau_feature(tau[sl * kMaxBands + lane], s0[sl]);
   }
-  dwt[co * nb + b] = acc;
+  if (lane < kMaxBands) red[wid][lane] = acc;
+  __syncthreads();
+  if (threadIdx.x < nb) dwt[co * nb + threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
 // Adam on the flat FP32 parameters.
@@ -503,7 +512,7 @@ hipError_t launch_loss_grad(const SliceDev* slices, int batch, const float2* xo,
 }
 hipError_t launch_wt_grad(const float* tile_sums, const int* tile_off, const float* tau,
                           const float* s0, int nb, int batch, float* dwt, hipStream_t st) {
-  hipLaunchKernelGGL(k_wt_grad, dim3(kCh), dim3(64), 0, st, tile_sums, tile_off, tau, s0, nb,
+  hipLaunchKernelGGL(k_wt_grad, dim3(kCh), dim3(256), 0, st, tile_sums, tile_off, tau, s0, nb,
                      batch, dwt);
   return hipGetLastError();
 }

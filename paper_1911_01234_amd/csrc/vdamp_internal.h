@@ -30,7 +30,8 @@ struct SliceDev {
   long long off;         // pixel offset in packed arrays
   int ny, nx;
   int fft_y, fft_x;      // FFT plan index for column (length ny) / row (length nx)
-  int ytab_off;          // 2 s tables of ny floats: L_1..L_s, H_1..H_s (y axis)
+  int ytab_off;          // 2 s tables of ny floats: L_1..L_s, H_1..H_s (y axis), then
+                         // ny pairs (cos^2, sin^2)(pi k / ny)
   int xtab_off;          // 2 s tables of nx floats (x axis)
   int colstrip0;         // index of this slice's first column strip in tau_part
   int rowstrip0;         // index of this slice's first row strip (learned-denoiser partials)

@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
   constexpr int P2 = N + ((M % 2) ? 0 : 16);         // LDS pitch of an inverse block
   constexpr int TB = (M * P1 > 16 * P2) ? M * P1 : 16 * P2;
   __shared__ float2 tw_s[N];
-  __shared__ __align__(16) float ytab_s[8 * N];  // [row][table], 8 tables a row
+  __shared__ float2 cs_s[N];  // (cos^2, sin^2)(pi ky / N) per k-space row
   __shared__ float2 tb[TB];
   __shared__ float red[kThreads / 64][kMaxBands];
   const int2 item = a.work[blockIdx.x];
@@ -320,12 +320,10 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
   }
   const FftPlanDev& P = a.ffts[S.fft_y];
   for (int i = tid; i < N; i += kThreads) tw_s[i] = a.twiddles[P.tw_off + i];
-  const int ntab = 2 * s;
-  if (vd)
-    for (int i = tid; i < 8 * N; i += kThreads) {
-      const int row = i >> 3, t = i & 7;
-      ytab_s[i] = (t < ntab) ? a.tables[S.ytab_off + t * N + row] : 0.f;
-    }
+  if (vd) {
+    const float* cs = a.tables + S.ytab_off + 2 * s * N;
+    for (int i = tid; i < N; i += kThreads) cs_s[i] = make_float2(cs[2 * i], cs[2 * i + 1]);
+  }
   __syncthreads();
   if (!first) {
     RegFft<M, false>::run(xin, tw_s, 16);
@@ -339,9 +337,15 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
   __syncthreads();
   const float isq = rsqrtf((float)N * (float)nx);
   const float sig2 = a.sigma2 ? a.sigma2[sl] : 0.f;
-  float Q[8];
+  // QL[j] = sum_ky P_{j+1}(ky) c, QH[j] = sum_ky P_j(ky) s_j(ky) c with c_j, s_j =
+  // (cos^2, sin^2)(pi ky 2^j / N) and P_m = prod_{j<m} c_j: the y-axis tau-weight tables
+  // L_{j+1} and H_{j+1} up to their factor 2^{j+1} / N, built from the row's (c_0, s_0)
+  // by the double-angle identities s_{j+1} = 4 c_j s_j and c_{j+1} = 1 - s_{j+1} =
+  // (c_j - s_j)^2 (products in FP32: within 3e-7 of the largest table value, against
+  // 6e-8 for tables rounded from FP64)
+  float QL[4], QH[4];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) Q[t] = 0.f;
+  for (int t = 0; t < 4; ++t) { QL[t] = 0.f; QH[t] = 0.f; }
   float2 d[NI][16];
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
@@ -367,16 +371,19 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
             const float2 z = csub(yy, X);
             o = cscale(z, w);
             const float cc = w * ((w - 1.0f) * (z.x * z.x + z.y * z.y) + sig2);
-            const float4 y0 = *reinterpret_cast<const float4*>(&ytab_s[row * 8]);
-            const float4 y1 = *reinterpret_cast<const float4*>(&ytab_s[row * 8 + 4]);
-            Q[0] = fmaf(y0.x, cc, Q[0]);
-            Q[1] = fmaf(y0.y, cc, Q[1]);
-            Q[2] = fmaf(y0.z, cc, Q[2]);
-            Q[3] = fmaf(y0.w, cc, Q[3]);
-            Q[4] = fmaf(y1.x, cc, Q[4]);
-            Q[5] = fmaf(y1.y, cc, Q[5]);
-            Q[6] = fmaf(y1.z, cc, Q[6]);
-            Q[7] = fmaf(y1.w, cc, Q[7]);
+            const float2 cs = cs_s[row];
+            float cj = cs.x, sj = cs.y, pj = cs.x;
+            QH[0] = fmaf(sj, cc, QH[0]);
+            QL[0] = fmaf(pj, cc, QL[0]);
+#pragma unroll
+            for (int t = 1; t < 4; ++t) {
+              const float dj = cj - sj;
+              sj = 4.0f * cj * sj;
+              cj = (sj < 0.5f) ? 1.0f - sj : dj * dj;  // the form without cancellation
+              QH[t] = fmaf(pj * sj, cc, QH[t]);
+              pj *= cj;
+              QL[t] = fmaf(pj, cc, QL[t]);
+            }
           }
         } else if (mode == CM_OUTPUT) {
           o = (w > 0.f) ? yy : X;
@@ -403,10 +410,13 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
         ty = (kind == 0) ? L : Hh;
         tx = (kind == 1) ? L : Hh;
       }
+      const bool hb = ty >= s;
+      const int tt = hb ? ty - s : ty;
       float q0 = 0.f;
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-        if (t == ty) q0 = Q[t];
+      for (int t = 0; t < 4; ++t)
+        if (t == tt) q0 = hb ? QH[t] : QL[t];
+      q0 *= (float)(2 << tt) / (float)N;
       const float part = wave_sum(q0 * xtab[tx * nx + kx]);
       if (lane == 0) red[wid][b] = part;
     }
