@@ -522,6 +522,30 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
     __syncthreads();
     fft_lines<true, false, EPT>(lds, P, H, nx, 1, tw_s);
   }
+  float2* r = a.r + S.off;
+  float2* r2 = a.r2 ? a.r2 + S.off : nullptr;
+  const float lam = a.lambda ? a.lambda[item.x] : 0.f;
+  const float lam2 = __fmul_rn(lam, lam);
+  const bool need_r = (mode == RA_VDAMP || mode == RA_FISTA || mode == RA_LEARNED);
+  int gi[U];  // offset in the slice
+  int bnd[U];
+  float4 ro[U], rw[U];
+#define RA_LOAD_R()                                                                          \
+  _Pragma("unroll") for (int u = 0; u < U; ++u) {                                            \
+    const int p = tid + u * kThreads;                                                        \
+    bnd[u] = 0;                                                                              \
+    gi[u] = 0;                                                                               \
+    ro[u] = make_float4(0.f, 0.f, 0.f, 0.f);                                                 \
+    rw[u] = make_float4(0.f, 0.f, 0.f, 0.f);                                                 \
+    if (p < npairs) {                                                                        \
+      const int lr = p / half, lc = 2 * (p - lr * half);                                     \
+      int b;                                                                                 \
+      const int gr = strip_to_global(lr, lc, strip, s, ny, nx, b);                           \
+      bnd[u] = b;                                                                            \
+      gi[u] = gr * nx + lc;                                                                  \
+      if (need_r) ro[u] = *reinterpret_cast<const float4*>(r + gi[u]);                       \
+    }                                                                                        \
+  }
   if (mode == RA_IMAGE) {
     float4* dst = reinterpret_cast<float4*>(a.out + S.off + (long long)strip * H * nx);
 #pragma unroll
@@ -531,31 +555,21 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
     }
     return;
   }
-  haar_strip_anal<EPT>(lds, H, nx, s);
-  float2* r = a.r + S.off;
-  float2* r2 = a.r2 ? a.r2 + S.off : nullptr;
-  const float lam = a.lambda ? a.lambda[item.x] : 0.f;
-  const float lam2 = __fmul_rn(lam, lam);
-  const bool need_r = (mode == RA_VDAMP || mode == RA_FISTA || mode == RA_LEARNED);
-  long long gi[U];
-  int bnd[U];
-  float4 ro[U], rw[U];
+  // With up to 16 elements a thread, r is fetched before the Haar analysis so that the
+  // loads are in flight while it runs; with 32 the registers it would hold through it
+  // cost more occupancy than the overlap gains.
+  if constexpr (EPT <= 16) {
+    RA_LOAD_R();
+    haar_strip_anal<EPT>(lds, H, nx, s);
+  } else {
+    haar_strip_anal<EPT>(lds, H, nx, s);
+    RA_LOAD_R();
+  }
+#undef RA_LOAD_R
+  if (mode == RA_FISTA || mode == RA_LEARNED) {  // the second iterate
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int p = tid + u * kThreads;
-    bnd[u] = 0;
-    gi[u] = 0;
-    ro[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-    rw[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (p < npairs) {
-      const int lr = p / half, lc = 2 * (p - lr * half);
-      int b;
-      const int gr = strip_to_global(lr, lc, strip, s, ny, nx, b);
-      bnd[u] = b;
-      gi[u] = (long long)gr * nx + lc;
-      if (need_r) ro[u] = *reinterpret_cast<const float4*>(r + gi[u]);
-      if (mode == RA_FISTA || mode == RA_LEARNED) rw[u] = *reinterpret_cast<const float4*>(r2 + gi[u]);
-    }
+    for (int u = 0; u < U; ++u)
+      if (tid + u * kThreads < npairs) rw[u] = *reinterpret_cast<const float4*>(r2 + gi[u]);
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
