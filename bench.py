@@ -86,8 +86,9 @@ def pass_rooflines(times, npx, iters, steps):
 def other_workloads(stream, reps=3):
     """Throughput of the other batch shapes the library is built for: the ragged batch of
     512 slices (128 each of 128^2, 192^2, 256^2, 320^2) and 128 slices of 512^2 (whose
-    finest bands take the large-band threshold search).  One warm-up solve, then `reps`
-    timed solves of 50 iterations each, eager with per-kernel events."""
+    finest bands take the large-band threshold search), each planned with the plan-time
+    tuner.  One warm-up solve, then `reps` timed solves of 50 iterations each, eager with
+    per-kernel events."""
     import torch
     from paper_1911_01234_amd import synth, vdamp as V
     res = {}
@@ -100,7 +101,10 @@ def other_workloads(stream, reps=3):
         nx = [sl.y.shape[1] for sl in slices]
         npx = int(sum(u * v for u, v in zip(ny, nx)))
         with torch.cuda.stream(stream):
-            plan = V.Plan(ny, nx, s, V.VDAMP_FLAG_TIMING)
+            t = time.perf_counter()
+            plan = V.Plan(ny, nx, s, V.VDAMP_FLAG_TIMING | V.VDAMP_FLAG_AUTOTUNE)
+            t_plan = time.perf_counter() - t
+            desc = plan.describe()
             ws = plan.workspace()
             y, mask, p, sigma2 = V.to_device(plan, slices)
             xh = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
@@ -124,7 +128,9 @@ def other_workloads(stream, reps=3):
                      "slice_iterations_per_s": round(len(slices) * K / dt, 1),
                      "mpx_iterations_per_s": round(npx * K / dt / 1e6, 1),
                      "nmse_db_mean": round(nm, 3),
-                     "passes": pass_rooflines(times, npx, K, reps)}
+                     "passes": pass_rooflines(times, npx, K, reps),
+                     "plan_seconds_with_autotune": round(t_plan, 3),
+                     "autotune": desc[desc.index("autotune:") + 10:] if "autotune:" in desc else None}
         print(f"[bench] {name}: generated in {tg:.1f} s, {res[name]['slice_iterations_per_s']} slice-it/s",
               file=sys.stderr, flush=True)
     return res

@@ -67,7 +67,15 @@ enum {
   VDAMP_FLAG_CHECK_FINITE = 1u << 2,
   /* Record HIP events around every kernel launch (eager launches only; overrides
      VDAMP_FLAG_USE_GRAPH) so that vdamp_pass_times() can report per-pass times. */
-  VDAMP_FLAG_TIMING = 1u << 5
+  VDAMP_FLAG_TIMING = 1u << 5,
+  /* Tune the launch configuration when the plan is built: for every size group, time
+     the four-step register FFT against the in-LDS Stockham FFT in the row and column
+     passes, and every threshold-search size class that holds the band size, on synthetic
+     data in temporary device buffers (allocated and freed inside vdamp_plan, which
+     synchronises), and keep the fastest (3 % margin in favour of the default).  The FFT
+     choice changes results at FP32 rounding level; the choice is fixed for the plan.
+     vdamp_plan_describe() reports the measurements. */
+  VDAMP_FLAG_AUTOTUNE = 1u << 6
 };
 
 /* Kernel classes reported by vdamp_pass_times(). */
@@ -100,6 +108,17 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
                         int32_t levels, int32_t wavelet, uint32_t flags, size_t* workspace_bytes);
 
 vdamp_status vdamp_plan_destroy(vdamp_plan_h plan);
+
+/*
+ * vdamp_plan_describe -- the plan's launch configuration as text: per run of equal slice
+ * size the row/column kernel (four-step M or Stockham) and its work items, the
+ * threshold-search size classes and their band counts, the workspace size, and with
+ * VDAMP_FLAG_AUTOTUNE what the tuner measured.
+ *   buf, len        host buffer receiving at most len - 1 characters and a NUL
+ *                   (nothing is written when buf is null or len is 0)
+ *   needed          nullable out: characters of the full text plus the NUL
+ */
+vdamp_status vdamp_plan_describe(vdamp_plan_h plan, char* buf, size_t len, size_t* needed);
 
 /*
  * vdamp_solve -- run `iters` iterations of Algorithm 1 on every slice, then line 10.

@@ -83,6 +83,32 @@ vdamp_status fail(vdamp_status st, const std::string& msg) {
   return st;
 }
 
+int sure_class_capacity(int cls) {
+  return cls == 0 ? kSureSmall : cls == 1 ? 4 * kSureSmall : cls == 2 ? kSureMaxKeys : kSureBigMaxKeys;
+}
+int sure_default_class(long long nb) {
+  return nb > kSureMaxKeys ? 3 : nb > 4 * kSureSmall ? 2 : nb > kSureSmall ? 1 : 0;
+}
+
+std::vector<int2> sure_work_list(vdamp_plan_t* P) {
+  std::vector<std::pair<long long, int2>> wsc[kSureClasses];
+  for (int b = 0; b < P->B; ++b)
+    for (int band = 0; band < P->nbands; ++band) {
+      const int l = band == 0 ? P->levels : P->levels - (band - 1) / 3;
+      const long long nb = (long long)(P->ny[b] >> l) * (P->nx[b] >> l);
+      auto it = P->sure_cls_of_size.find(nb);
+      const int cls = it != P->sure_cls_of_size.end() ? it->second : sure_default_class(nb);
+      wsc[cls].push_back({nb, make_int2(b, band)});
+    }
+  std::vector<int2> out;
+  for (int c = kSureClasses - 1; c >= 0; --c) {  // largest class first, as launched
+    std::stable_sort(wsc[c].begin(), wsc[c].end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    P->nsure_cls[c] = (int)wsc[c].size();
+    for (auto& e : wsc[c]) out.push_back(e.second);
+  }
+  return out;
+}
+
 Ws layout(const vdamp_plan_t* P, void* ws) {
   char* b = static_cast<char*>(ws);
   Ws w;
@@ -217,7 +243,7 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   if (batch < 1) return fail(VDAMP_ERR_ARG, "batch must be >= 1");
   if (wavelet != VDAMP_WAVELET_HAAR) return fail(VDAMP_ERR_UNSUPPORTED, "only the Haar wavelet is implemented");
   if (levels < 1 || levels > 4) return fail(VDAMP_ERR_UNSUPPORTED, "levels must be in 1..4");
-  const uint32_t known = VDAMP_FLAG_USE_GRAPH | VDAMP_FLAG_CHECK_FINITE | VDAMP_FLAG_TIMING;
+  const uint32_t known = VDAMP_FLAG_USE_GRAPH | VDAMP_FLAG_CHECK_FINITE | VDAMP_FLAG_TIMING | VDAMP_FLAG_AUTOTUNE;
   if (flags & ~known) return fail(VDAMP_ERR_ARG, "unknown flag bits");
   const int H = 1 << levels;
   std::vector<int> rad;
@@ -336,19 +362,13 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   P->ntiles = (int)tiles.size();
 
   // work lists, heaviest items first
-  std::vector<std::pair<long long, int2>> wr, wc, wsc[kSureClasses];
+  std::vector<std::pair<long long, int2>> wr, wc;
   int maxnx = 0, maxny = 0;
   for (int b = 0; b < batch; ++b) {
     maxnx = std::max(maxnx, nx[b]);
     maxny = std::max(maxny, ny[b]);
     for (int i = 0; i < ny[b] / H; ++i) wr.push_back({(long long)nx[b], make_int2(b, i)});
     for (int i = 0; i < nx[b] / kColW; ++i) wc.push_back({(long long)ny[b], make_int2(b, i)});
-    for (int band = 0; band < P->nbands; ++band) {
-      int l = band == 0 ? levels : levels - (band - 1) / 3;
-      long long nbsz = (long long)(ny[b] >> l) * (nx[b] >> l);
-      const int cls = nbsz > kSureMaxKeys ? 3 : nbsz > 4 * kSureSmall ? 2 : nbsz > kSureSmall ? 1 : 0;
-      wsc[cls].push_back({nbsz, make_int2(b, band)});
-    }
   }
   auto sort_items = [](std::vector<std::pair<long long, int2>>& v) {
     std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
@@ -356,26 +376,21 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     for (auto& e : v) out.push_back(e.second);
     return out;
   };
-  std::vector<int2> vr = sort_items(wr), vc = sort_items(wc), vs;
-  for (int c = kSureClasses - 1; c >= 0; --c) {  // largest class first, as launched
-    std::vector<int2> v = sort_items(wsc[c]);
-    P->nsure_cls[c] = (int)v.size();
-    vs.insert(vs.end(), v.begin(), v.end());
-  }
+  std::vector<int2> vr = sort_items(wr), vc = sort_items(wc), vs = sure_work_list(P);
   P->nrows = (int)vr.size();
   P->ncols = (int)vc.size();
   for (int i = 0; i < P->nrows;) {
     const int n = nx[vr[i].x];
     int j = i;
     while (j < P->nrows && nx[vr[j].x] == n) ++j;
-    P->row_groups.push_back({i, j - i, cols4_supported(n) ? n / 16 : 0});
+    P->row_groups.push_back({i, j - i, cols4_supported(n) ? n / 16 : 0, n});
     i = j;
   }
   for (int i = 0; i < P->ncols;) {
     const int n = ny[vc[i].x];
     int j = i;
     while (j < P->ncols && ny[vc[j].x] == n) ++j;
-    P->col_groups.push_back({i, j - i, cols4_supported(n) ? n / 16 : 0});
+    P->col_groups.push_back({i, j - i, cols4_supported(n) ? n / 16 : 0, n});
     i = j;
   }
   P->lds_rows = sizeof(float2) * (size_t)H * maxnx;
@@ -419,8 +434,40 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     free_plan(P);
     return fail(VDAMP_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));
   }
+  if (flags & VDAMP_FLAG_AUTOTUNE) {
+    e = autotune(P);
+    if (e != hipSuccess) {
+      free_plan(P);
+      return fail(VDAMP_ERR_HIP, std::string("plan autotune: ") + hipGetErrorString(e));
+    }
+  }
   *plan = P;
   *workspace_bytes = P->ws_bytes;
+  return VDAMP_OK;
+}
+
+vdamp_status vdamp_plan_describe(vdamp_plan_h plan, char* buf, size_t len, size_t* needed) {
+  g_err.clear();
+  if (!plan) return fail(VDAMP_ERR_ARG, "plan is null");
+  const vdamp_plan_t* P = plan;
+  std::string s = "slices " + std::to_string(P->B) + ", levels " + std::to_string(P->levels) + ", pixels " +
+                  std::to_string(P->ntot) + ", workspace " + std::to_string(P->ws_bytes) + " bytes;";
+  auto group = [&](const char* what, const std::array<int, 4>& g) {
+    s += std::string(" ") + what + std::to_string(g[3]) + ": " + std::to_string(g[1]) + " strips, " +
+         (g[2] ? "four-step M=" + std::to_string(g[2]) : std::string("Stockham")) + ";";
+  };
+  for (const auto& g : P->row_groups) group("rows nx=", g);
+  for (const auto& g : P->col_groups) group("cols ny=", g);
+  for (int c = kSureClasses - 1; c >= 0; --c)
+    if (P->nsure_cls[c])
+      s += " sure class " + std::to_string(c) + ": " + std::to_string(P->nsure_cls[c]) + " bands;";
+  if (!P->tune_log.empty()) s += " " + P->tune_log;
+  if (needed) *needed = s.size() + 1;
+  if (buf && len) {
+    const size_t n = std::min(len - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+  }
   return VDAMP_OK;
 }
 

@@ -6,6 +6,7 @@
 
 #include <array>
 #include <cstring>
+#include <map>
 #include <string>
 #include <utility>
 #include <vector>
@@ -71,12 +72,12 @@ struct vdamp_plan_t {
   int2* d_work_sure = nullptr;      // bands by size class: > 27648, > 16384, > 4096, the rest
   int nrows = 0, ncols = 0, nsure_cls[vdamp::kSureClasses] = {};
   int nrowstrips = 0;
-  // column launches: runs of the column work list with one ny each (first, count, M),
+  // column launches: runs of the column work list with one ny each (first, count, M, ny),
   // M = ny / 16 for the four-step kernel, 0 for the LDS Stockham kernel
-  std::vector<std::array<int, 3>> col_groups;
-  // row launches: runs of the row work list with one nx each (first, count, M), M = nx / 16
-  // for the four-step row kernels, 0 for the LDS Stockham ones
-  std::vector<std::array<int, 3>> row_groups;
+  std::vector<std::array<int, 4>> col_groups;
+  // row launches: runs of the row work list with one nx each (first, count, M, nx),
+  // M = nx / 16 for the four-step row kernels, 0 for the LDS Stockham ones
+  std::vector<std::array<int, 4>> row_groups;
   // learned denoiser: 16x16 tiles (slice, tile index), slice-major; tile_off[b] = first
   // tile of slice b
   bool tiles_ok = false;
@@ -84,6 +85,9 @@ struct vdamp_plan_t {
   std::vector<int> tile_off;
   int2* d_tiles = nullptr;
   int* d_tile_off = nullptr;
+  // threshold-search size class chosen per band size (absent: the default by size)
+  std::map<long long, int> sure_cls_of_size;
+  std::string tune_log;             // what the plan-time tuner measured and chose
   int ept = 16;                     // complex elements per thread of the LDS passes
   size_t lds_rows = 0, lds_cols = 0;
   // workspace layout (byte offsets)
@@ -104,6 +108,15 @@ struct vdamp_plan_t {
 
 namespace vdamp {
 Ws layout(const vdamp_plan_t* P, void* ws);
+// Threshold-search work list of the plan's bands grouped by size class (largest class
+// first, heaviest bands first within a class), with P->nsure_cls set; classes from
+// P->sure_cls_of_size where present, else by size.
+std::vector<int2> sure_work_list(vdamp_plan_t* P);
+int sure_default_class(long long nb);
+int sure_class_capacity(int cls);
+// Plan-time tuning (VDAMP_FLAG_AUTOTUNE): times the alternatives of every size group on
+// synthetic data and keeps the fastest; rewrites P's groups and threshold-search list.
+hipError_t autotune(vdamp_plan_t* P);
 hipError_t launch_rows_synth(const KArgs& a, int ept, int do_fft, size_t lds, hipStream_t st);
 hipError_t launch_cols(const KArgs& a, int ept, size_t lds, hipStream_t st);
 hipError_t launch_rows_anal(const KArgs& a, int ept, size_t lds, hipStream_t st);
@@ -111,6 +124,8 @@ hipError_t launch_sure(const KArgs& a, int cls, float* scratch, hipStream_t st);
 hipError_t launch_prep(const uint8_t* mask, const float* p, const float2* y, float* wgt,
                        long long n, int check, int* bad, hipStream_t st);
 hipError_t launch_zero(float2* x, long long n, hipStream_t st);
+hipError_t launch_tune_fill(float2* r, float2* X, float2* y, float* wgt, long long n, hipStream_t st);
+hipError_t launch_fill_f32(float* x, long long n, float v, hipStream_t st);
 hipError_t set_lds_limits_passes(size_t rows, size_t cols);
 hipError_t launch_cols4(const KArgs& a, int m, hipStream_t st);
 hipError_t launch_rows_synth4(const KArgs& a, int m, size_t lds, hipStream_t st);

@@ -58,6 +58,56 @@ hipError_t launch_zero(float2* x, long long n, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Plan-time tuning data (no part of any solve): iterate-like values for timing the
+// passes' alternatives.  r, X, y get components with a standard normal distribution (so
+// |r|^2 / tau is Exp(1) with tau = 1, the distribution of noise-only coefficients the
+// threshold search sees most), wgt = 4 on about a quarter of k-space and 0 elsewhere.
+// Normal values by Box-Muller from a 64-bit integer hash of (stream, index).
+__device__ __forceinline__ unsigned long long tune_hash(unsigned long long z) {
+  z ^= z >> 33;
+  z *= 0xff51afd7ed558ccdull;
+  z ^= z >> 33;
+  z *= 0xc4ceb9fe1a85ec53ull;
+  return z ^ (z >> 33);
+}
+__device__ __forceinline__ float2 tune_normal2(unsigned long long key) {
+  const unsigned long long h = tune_hash(key);
+  const float u1 = ((float)(h >> 40) + 0.5f) * (1.0f / 16777216.0f);
+  const float u2 = (float)((h >> 16) & 0xFFFFFF) * (1.0f / 16777216.0f);
+  const float rr = sqrtf(-2.0f * logf(u1));
+  float sn, cs;
+  sincosf(6.283185307f * u2, &sn, &cs);
+  return make_float2(rr * cs, rr * sn);
+}
+__global__ void __launch_bounds__(kThreads) k_tune_fill(float2* __restrict__ r, float2* __restrict__ X,
+                                                        float2* __restrict__ y, float* __restrict__ wgt,
+                                                        long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const unsigned long long k = (unsigned long long)i * 4ull;
+    r[i] = tune_normal2(k);
+    X[i] = tune_normal2(k + 1);
+    y[i] = tune_normal2(k + 2);
+    wgt[i] = (tune_hash(k + 3) & 3ull) == 0 ? 4.0f : 0.0f;
+  }
+}
+__global__ void k_fill_f32(float* __restrict__ x, long long n, float v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+hipError_t launch_tune_fill(float2* r, float2* X, float2* y, float* wgt, long long n, hipStream_t st) {
+  long long blocks = (n + kThreads - 1) / kThreads;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_tune_fill, dim3((unsigned)blocks), dim3(kThreads), 0, st, r, X, y, wgt, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f32(float* x, long long n, float v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, v);
+  return hipGetLastError();
+}
+
 // Per-slice input scale of the learned denoiser: s0^2 = (1/N) sum_j w_j |y_j|^2 with
 // w = m / p (an unbiased estimate of the mean |x0|^2 plus noise, since E[m/p] = 1);
 // s0 = 1 when that sum is not positive.  One block per slice, fixed-order reduction.

@@ -21,6 +21,7 @@ VDAMP_WAVELET_HAAR = 0
 VDAMP_FLAG_CHECK_FINITE = 1 << 2
 VDAMP_FLAG_USE_GRAPH = 1 << 3
 VDAMP_FLAG_TIMING = 1 << 5
+VDAMP_FLAG_AUTOTUNE = 1 << 6
 PASS_NAMES = ("prep", "rows_synth", "cols", "rows_anal", "sure", "denoiser", "cnn")
 VDAMP_CNN_WS_FORWARD = 0
 VDAMP_CNN_WS_TRAIN = 1
@@ -37,7 +38,7 @@ EXPORTED = ("vdamp_plan", "vdamp_plan_destroy", "vdamp_solve", "fista_solve",
             "vdamp_state_export", "vdamp_pass_times", "vdamp_status_string", "vdamp_last_error",
             "vdamp_cnn_create", "vdamp_cnn_destroy", "vdamp_cnn_param_count", "vdamp_cnn_set_params",
             "vdamp_cnn_get_params", "vdamp_cnn_workspace", "vdamp_cnn_forward", "vdamp_cnn_train_step",
-            "vdamp_solve_learned", "vdamp_learned_export", "vdamp_wavelet")
+            "vdamp_solve_learned", "vdamp_learned_export", "vdamp_wavelet", "vdamp_plan_describe")
 
 
 class VdampError(RuntimeError):
@@ -56,6 +57,14 @@ def load_library() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch's HIP context first: torch brings its own HIP runtime, which fails to find the
+    # device when the library's runtime initialised it before
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
     lib.vdamp_plan.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -72,6 +81,8 @@ def load_library() -> ctypes.CDLL:
     lib.vdamp_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int64), i32]
     lib.vdamp_pass_times.restype = ctypes.c_int
+    lib.vdamp_plan_describe.argtypes = [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]
+    lib.vdamp_plan_describe.restype = ctypes.c_int
     lib.vdamp_status_string.argtypes = [ctypes.c_int]
     lib.vdamp_status_string.restype = ctypes.c_char_p
     lib.vdamp_last_error.argtypes = []
@@ -177,6 +188,15 @@ class Plan:
         cnt = (ctypes.c_int64 * n)()
         _check(load_library().vdamp_pass_times(self._h, ms, cnt, n))
         return {PASS_NAMES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+    def describe(self) -> str:
+        """The plan's launch configuration (and the tuner's measurements) as text."""
+        lib = load_library()
+        need = ctypes.c_size_t(0)
+        _check(lib.vdamp_plan_describe(self._h, None, 0, ctypes.byref(need)))
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib.vdamp_plan_describe(self._h, buf, need.value, None))
+        return buf.value.decode()
 
     def vdamp_wavelet(self, x, out, inverse, stream=None):
         _check(load_library().vdamp_wavelet(self._h, _stream_handle(stream), int(bool(inverse)),
