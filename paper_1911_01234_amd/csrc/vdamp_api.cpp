@@ -87,7 +87,7 @@ int sure_class_capacity(int cls) {
   return cls == 0 ? kSureSmall : cls == 1 ? 4 * kSureSmall : cls == 2 ? kSureMaxKeys : kSureBigMaxKeys;
 }
 int sure_default_class(long long nb) {
-  return nb > kSureMaxKeys ? 3 : nb > 4 * kSureSmall ? 2 : nb > kSureSmall ? 1 : 0;
+  return nb > kSureMaxKeys ? 3 : nb > 4 * kSureSmall ? 2 : nb > kSureSmall / 2 ? 1 : 0;
 }
 
 std::vector<int2> sure_work_list(vdamp_plan_t* P) {
