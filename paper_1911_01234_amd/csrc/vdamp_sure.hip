@@ -30,6 +30,28 @@ __device__ __forceinline__ int wave_incl_prefix_int(int v, int lane) {
   return v;
 }
 
+// Exclusive prefix (and suffix) over the NW per-wave totals tot[0..NW) at wave wid, for
+// every lane of the wave: lanes load one total each and scan with shuffles (no per-thread
+// loop over the waves, which would hold the totals in registers).
+template <int NW>
+__device__ __forceinline__ int wave_offset_int(const int* tot, int wid, int lane) {
+  const int v = wave_incl_prefix_int(lane < NW ? tot[lane] : 0, lane);
+  const int o = __shfl(v, wid > 0 ? wid - 1 : 0, 64);
+  return wid > 0 ? o : 0;
+}
+template <int NW>
+__device__ __forceinline__ double wave_offset_prefix(const double* tot, int wid, int lane) {
+  const double v = wave_incl_prefix(lane < NW ? tot[lane] : 0.0, lane);
+  const double o = __shfl(v, wid > 0 ? wid - 1 : 0, 64);
+  return wid > 0 ? o : 0.0;
+}
+template <int NW>
+__device__ __forceinline__ double wave_offset_suffix(const double* tot, int wid, int lane) {
+  const double v = wave_incl_suffix(lane < NW ? tot[lane] : 0.0, lane);
+  const double o = __shfl(v, wid + 1 < NW ? wid + 1 : 0, 64);
+  return wid + 1 < NW ? o : 0.0;
+}
+
 // Bucket of a key for the counting sort, from the FP32 bit pattern of v = key/tau.
 // Monotone in key: multiplying by a positive constant with round-to-nearest is
 // monotone, and so is the bit pattern of a non-negative float.  The buckets are
@@ -142,21 +164,29 @@ k_sure(KArgs a) {
   }
   __syncthreads();
   const float inv_tau = 1.0f / tau_sh;
-  int pos[KPT];
+  // slot of each key in its bucket, one byte per key, four to a register (slots above
+  // 255 saturate: such a bucket exceeds kSureBucketLimit and takes the bitonic path)
+  constexpr int KP = (KPT + 3) / 4;
+  unsigned pk[KP];
+#pragma unroll
+  for (int q = 0; q < KP; ++q) pk[q] = 0u;
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
     const int i = tid + j * NT;
-    if (i < Nb) pos[j] = atomicAdd(&off[sure_bucket<NB>(kk[j], inv_tau)], 1);
+    if (i < Nb) {
+      const unsigned sl = (unsigned)atomicAdd(&off[sure_bucket<NB>(kk[j], inv_tau)], 1);
+      pk[j >> 2] |= min(sl, 255u) << (8 * (j & 3));
+    }
   }
   __syncthreads();
-  // exclusive scan of the bucket counts, and the largest count
-  int cnt[BPT];
+  // exclusive scan of the bucket counts, and the largest count (the counts are read
+  // from LDS twice rather than held in registers)
   int sum = 0, mx = 0;
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
-    cnt[q] = off[tid * BPT + q];
-    sum += cnt[q];
-    mx = max(mx, cnt[q]);
+    const int c = off[tid * BPT + q];
+    sum += c;
+    mx = max(mx, c);
   }
   const int incl = wave_incl_prefix_int(sum, lane);
 #pragma unroll
@@ -164,12 +194,12 @@ k_sure(KArgs a) {
   if (lane == 63) wsC[wid] = incl;
   if (lane == 0) wsM[wid] = mx;
   __syncthreads();
-  int excl = incl - sum;
-  for (int w = 0; w < wid; ++w) excl += wsC[w];
+  int excl = incl - sum + wave_offset_int<NW>(wsC, wid, lane);
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
+    const int c = off[tid * BPT + q];
     off[tid * BPT + q] = excl;
-    excl += cnt[q];
+    excl += c;
   }
   if (tid == NT - 1) off[NB] = excl;
   if (tid == 0) {
@@ -179,34 +209,36 @@ k_sure(KArgs a) {
   }
   __syncthreads();
   if (maxc_sh <= kSureBucketLimit) {
-    // bucket bounds and slot into registers, packed as offset | count << 15 | slot << 22
-    // (offsets < 2^15, counts and slots <= kSureBucketLimit < 2^7); the table is then
-    // overwritten by the keys
+#define SURE_SLOT(j) ((int)((pk[(j) >> 2] >> (8 * ((j) & 3))) & 0xFFu))
+    // per key: bucket bounds and slot, packed as offset | count << 15 | slot << 22
+    // (offsets < 2^15, counts and slots <= kSureBucketLimit < 2^7); with the overlay
+    // they are taken into registers before the keys overwrite the table, later the
+    // same registers hold the final positions
     static_assert(MAXK < (1 << 15) && kSureBucketLimit < (1 << 7), "packed bucket bounds");
-    int bpk[OV ? KPT : 1];
+    int pos[KPT];
     if constexpr (OV) {
 #pragma unroll
       for (int j = 0; j < KPT; ++j) {
         const int i = tid + j * NT;
-        bpk[j] = 0;
+        pos[j] = 0;
         if (i < Nb) {
           const int bk = sure_bucket<NB>(kk[j], inv_tau);
           const int lo = off[bk];
-          bpk[j] = lo | ((off[bk + 1] - lo) << 15) | (pos[j] << 22);
+          pos[j] = lo | ((off[bk + 1] - lo) << 15) | (SURE_SLOT(j) << 22);
         }
       }
       __syncthreads();
     }
 #define SURE_BOUNDS(j, lo, hi, slot)                 \
   if constexpr (OV) {                                \
-    lo = bpk[j] & 0x7FFF;                            \
-    hi = lo + ((bpk[j] >> 15) & 0x7F);               \
-    slot = bpk[j] >> 22;                             \
+    lo = pos[j] & 0x7FFF;                            \
+    hi = lo + ((pos[j] >> 15) & 0x7F);               \
+    slot = pos[j] >> 22;                             \
   } else {                                           \
     const int bk_ = sure_bucket<NB>(kk[j], inv_tau); \
     lo = off[bk_];                                   \
     hi = off[bk_ + 1];                               \
-    slot = pos[j];                                   \
+    slot = SURE_SLOT(j);                             \
   }
     // scatter into bucket slots
 #pragma unroll
@@ -234,18 +266,18 @@ k_sure(KArgs a) {
           const float u = sk[skx(x)];
           rank += (u < v) || (u == v && x < me);
         }
-        if constexpr (OV) bpk[j] = lo + rank;  // final position
-        else pos[j] = lo + rank;
+        pos[j] = lo + rank;
       }
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const int i = tid + j * NT;
-      if (i < Nb) sk[skx(OV ? bpk[j] : pos[j])] = kk[j];
+      if (i < Nb) sk[skx(pos[j])] = kk[j];
     }
     __syncthreads();
 #undef SURE_BOUNDS
+#undef SURE_SLOT
   } else {
     // Full sort: a bitonic network whose compare-exchanges all put the smaller key
     // first (each merge starts by comparing mirrored positions), so +inf padding up to
@@ -297,9 +329,8 @@ k_sure(KArgs a) {
   if (lane == 63) wsA[wid] = pA;
   if (lane == 0) wsR[wid] = sR;
   __syncthreads();
-  double offA = 0.0, offR = 0.0;
-  for (int w = 0; w < wid; ++w) offA += wsA[w];
-  for (int w = NW - 1; w > wid; --w) offR += wsR[w];
+  const double offA = wave_offset_prefix<NW>(wsA, wid, lane);
+  const double offR = wave_offset_suffix<NW>(wsR, wid, lane);
   double A = offA + pA - cA;          // sum of a^2 over indices < i0
   double Rrun = offR + sR;            // sum of 1/a over indices >= i0
   double best = __builtin_huge_val(), bestR = 0.0;
@@ -416,9 +447,8 @@ __device__ void sure_walk(const float* sk, int Nb, double tau, double* wsA, doub
   if (lane == 63) wsA[wid] = pA;
   if (lane == 0) wsR[wid] = sR;
   __syncthreads();
-  double offA = 0.0, offR = 0.0;
-  for (int w = 0; w < wid; ++w) offA += wsA[w];
-  for (int w = NW - 1; w > wid; --w) offR += wsR[w];
+  const double offA = wave_offset_prefix<NW>(wsA, wid, lane);
+  const double offR = wave_offset_suffix<NW>(wsR, wid, lane);
   double A = offA + pA - cA;          // sum of a^2 over indices < i0
   double Rrun = offR + sR;            // sum of 1/a over indices >= i0
   best = __builtin_huge_val();
