@@ -83,11 +83,16 @@ vdamp_status fail(vdamp_status st, const std::string& msg) {
   return st;
 }
 
+// Threshold-search size classes (launch shapes in launch_sure): 0 = 256 threads x 16
+// keys, 1 = 512 x 8, 2 = 1024 x 16, 3 = 1024 x 32, kSureBigClass = the large-band search.
 int sure_class_capacity(int cls) {
-  return cls == 0 ? kSureSmall : cls == 1 ? 4 * kSureSmall : cls == 2 ? kSureMaxKeys : kSureBigMaxKeys;
+  return cls <= 1 ? kSureSmall : cls == 2 ? 4 * kSureSmall : cls == 3 ? kSureMaxKeys : kSureBigMaxKeys;
 }
 int sure_default_class(long long nb) {
-  return nb > kSureMaxKeys ? 3 : nb > 4 * kSureSmall ? 2 : nb > kSureSmall / 2 ? 1 : 0;
+  return nb > kSureMaxKeys ? kSureBigClass
+         : nb > 4 * kSureSmall ? 3
+         : nb > kSureSmall / 2 ? 2
+                               : 0;
 }
 
 std::vector<int2> sure_work_list(vdamp_plan_t* P) {
@@ -97,7 +102,8 @@ std::vector<int2> sure_work_list(vdamp_plan_t* P) {
       const int l = band == 0 ? P->levels : P->levels - (band - 1) / 3;
       const long long nb = (long long)(P->ny[b] >> l) * (P->nx[b] >> l);
       auto it = P->sure_cls_of_size.find(nb);
-      const int cls = it != P->sure_cls_of_size.end() ? it->second : sure_default_class(nb);
+      int cls = it != P->sure_cls_of_size.end() ? it->second : sure_default_class(nb);
+      if (cls < 0 || cls >= kSureClasses || nb > sure_class_capacity(cls)) cls = sure_default_class(nb);
       wsc[cls].push_back({nb, make_int2(b, band)});
     }
   std::vector<int2> out;
@@ -410,7 +416,10 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   P->o_tau = o; o = align256(o + 4 * (size_t)batch * kMaxBands);
   P->o_taup = o; o = align256(o + 4 * (size_t)colstrip * kMaxBands);
   P->o_bad = o; o = align256(o + 4);
-  if (P->nsure_cls[3]) { P->o_big = o; o = align256(o + 4 * (size_t)P->nsure_cls[3] * kSureBigStride); }
+  if (P->nsure_cls[kSureBigClass]) {
+    P->o_big = o;
+    o = align256(o + 4 * (size_t)P->nsure_cls[kSureBigClass] * kSureBigStride);
+  }
   P->ws_bytes = o;
 
   auto upload = [&](auto*& dst, const auto& vec) -> hipError_t {

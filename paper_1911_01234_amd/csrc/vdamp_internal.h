@@ -14,7 +14,8 @@ constexpr int kColW = 16;          // columns per column strip (16 complex = 128
 constexpr int kMaxRadices = 8;
 constexpr int kMaxN = 512;         // largest ny / nx
 constexpr int kSureSmall = 4096;   // bands up to this size use the 256-thread search
-constexpr int kSureClasses = 4;
+constexpr int kSureClasses = 5;  // LDS classes 0..3 and the large-band search
+constexpr int kSureBigClass = kSureClasses - 1;
 constexpr int kSureBigMaxKeys = 65536;  // largest subband (the finest band of 512 x 512)
 constexpr int kSureBigStride = kSureBigMaxKeys + kSureBigMaxKeys / 16 + 1;  // scratch floats per band
 constexpr int kSureMaxKeys = 27648;// largest subband the LDS threshold search holds

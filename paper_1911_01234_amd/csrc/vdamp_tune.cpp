@@ -155,12 +155,12 @@ hipError_t autotune(vdamp_plan_t* P) {
   for (auto& kv : by_size) {
     const long long nb = kv.first;
     const int def = sure_default_class(nb);
-    if (def == 3) continue;
+    if (def == kSureBigClass) continue;
     if ((e = hipMemcpy(T.work, kv.second.data(), sizeof(int2) * kv.second.size(), hipMemcpyHostToDevice)) != hipSuccess)
       return e;
     std::vector<std::pair<int, double>> times;
     double tdef = 0;
-    for (int c = 0; c <= 2; ++c) {
+    for (int c = 0; c < kSureBigClass; ++c) {
       if (nb > sure_class_capacity(c)) continue;
       KArgs a = base;
       a.work = T.work;

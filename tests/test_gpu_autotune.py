@@ -24,7 +24,7 @@ def test_describe_default_plan():
     assert "slices 2, levels 4" in d
     assert "rows nx=320" in d and "rows nx=256" in d and "cols ny=256" in d
     assert "four-step M=16" in d and "four-step M=20" in d
-    assert "sure class 2: 3 bands" in d  # the three 160x160 bands of the 320 slice
+    assert "sure class 3: 3 bands" in d  # the three 160x160 bands of the 320 slice
     assert "autotune" not in d
     plan.close()
 
@@ -40,7 +40,7 @@ def test_autotuned_plan_matches_default_and_oracle():
     assert "autotune:" in d
     for n in (128, 192, 256, 320):
         assert f"rows nx={n} (four-step" in d and f"cols ny={n} (four-step" in d
-    assert "sure N_b=16384 (class 1" in d  # the 256 slices' finest bands: classes 1 and 2
+    assert "sure N_b=16384 (class 2" in d  # the 256 slices' finest bands: classes 2 and 3
     worst = 0.0
     for i in range(len(slices)):
         e = rel_l2(g1["x_hat"][i], g0["x_hat"][i])
