@@ -7,6 +7,18 @@
 
 namespace vdamp {
 
+// Work item of workgroup b in a launch of n workgroups, arranged so that the workgroups
+// the dispatcher sends to one XCD (ids x, x + 8, x + 16, ...: round-robin over the 8
+// XCDs) take consecutive items.  Neighbouring column strips share the 128-byte lines of
+// the 4-byte weight rows (64 bytes each); on one XCD they share its L2 instead of each
+// fetching the line from HBM.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  constexpr int kXcd = 8;
+  const int q = n / kXcd, r = n % kXcd, x = b % kXcd;
+  return x * q + min(x, r) + b / kXcd;
+}
+
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kThreads) k_cols(KArgs a) {
   __shared__ float2 tw_s[kMaxN];
   __shared__ float ytab_s[8 * kMaxN];
   __shared__ float red[kThreads / 64][kMaxBands];
-  const int2 item = a.work[blockIdx.x];
+  const int2 item = a.work[xcd_item(blockIdx.x, gridDim.x)];
   const int sl = item.x;
   const SliceDev S = a.slices[sl];
   const int ny = S.ny, nx = S.nx, c0 = item.y * kColW, s = a.levels;
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
   __shared__ float2 cs_s[N];  // (cos^2, sin^2)(pi ky / N) per k-space row
   __shared__ float2 tb[TB];
   __shared__ float red[kThreads / 64][kMaxBands];
-  const int2 item = a.work[blockIdx.x];
+  const int2 item = a.work[xcd_item(blockIdx.x, gridDim.x)];
   const int sl = item.x;
   const SliceDev S = a.slices[sl];
   const int nx = S.nx, c0 = item.y * kColW, s = a.levels;
