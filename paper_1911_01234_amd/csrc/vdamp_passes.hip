@@ -756,7 +756,9 @@ size_t rows4_lds_bytes(int m, int H) {
 }
 
 #define ROWS4_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(15) X(16) X(20) X(24) X(30) X(32)
-#define EPT_OF(MM) ((MM) <= 16 ? 16 : 32)
+// elements a thread: 16 up to nx = 256, else nx / 16 where the Haar loops (EPT / 4 blocks a
+// thread) cover the strip exactly, else 32
+#define EPT_OF(MM) ((MM) <= 16 ? 16 : ((MM) % 4 == 0 ? (MM) : 32))
 
 hipError_t launch_rows_synth4(const KArgs& a, int m, size_t lds, hipStream_t st) {
   switch (m) {
