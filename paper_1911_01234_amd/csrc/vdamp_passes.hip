@@ -269,6 +269,10 @@ __global__ void __launch_bounds__(kThreads) k_cols(KArgs a) {
 }
 
 // ------------------------------------------------------------------ cols, four-step
+// Threads of a column workgroup: 256, or one 16-point item each (16 M) for columns
+// longer than 256.
+constexpr int cols4_threads(int m) { return 16 * m > kThreads ? 16 * m : kThreads; }
+
 // Column strip of 16 columns with ny = 16 M, as two-level FFTs held in registers: the
 // forward transform factors ny = 16 x M (thread (a, c) transforms rows a + 16 b,
 // b < M, of column c, scales by W_ny^{a kb}, one LDS transpose, then 16-point DFTs give
@@ -277,16 +281,17 @@ __global__ void __launch_bounds__(kThreads) k_cols(KArgs a) {
 // ends, after one more transpose, on the rows the forward transform started from.
 // Loads of X, y and m/p are all issued at the start.
 template <int M>
-__global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
+__global__ void __launch_bounds__(cols4_threads(M)) k_cols4(KArgs a) {
   constexpr int N = 16 * M;
-  constexpr int NI = (N + kThreads - 1) / kThreads;  // 16-point DFT items per thread
+  constexpr int NT = cols4_threads(M);
+  constexpr int NI = (N + NT - 1) / NT;  // 16-point DFT items per thread
   constexpr int P1 = 256 + 16;                       // LDS pitch of a forward kb block
   constexpr int P2 = N + ((M % 2) ? 0 : 16);         // LDS pitch of an inverse block
   constexpr int TB = (M * P1 > 16 * P2) ? M * P1 : 16 * P2;
   __shared__ float2 tw_s[N];
   __shared__ float2 cs_s[N];  // (cos^2, sin^2)(pi ky / N) per k-space row
   __shared__ float2 tb[TB];
-  __shared__ float red[kThreads / 64][kMaxBands];
+  __shared__ float red[NT / 64][kMaxBands];
   const int2 item = a.work[xcd_item(blockIdx.x, gridDim.x)];
   const int sl = item.x;
   const SliceDev S = a.slices[sl];
@@ -296,36 +301,40 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
   const bool vd = (mode == CM_VDAMP || mode == CM_VDAMP_FIRST);
   const long long base = S.off + c0;
   const int c = tid & 15, a1 = tid >> 4;
+  const bool s1 = a1 < 16;  // threads of the M-point stage (all of them when NT = 256)
   // forward input: rows a1 + 16 b of column c
   float2 xin[M];
 #pragma unroll
   for (int b = 0; b < M; ++b)
-    xin[b] = first ? make_float2(0.f, 0.f) : a.X[base + (long long)(a1 + 16 * b) * nx + c];
-  // y and m/p at the k-space rows kb + M ka of this thread's items
+    xin[b] = (first || !s1) ? make_float2(0.f, 0.f) : a.X[base + (long long)(a1 + 16 * b) * nx + c];
+  // y and m/p at the k-space rows kb + M ka of this thread's items: issued with the X
+  // loads up to M = 20; for longer columns after the M-point stage, whose inputs then no
+  // longer hold registers (two workgroups of 16 M threads fit a CU)
+  constexpr bool kEarlyY = M <= 20;
   float2 yv[NI][16];
   float wv[NI][16];
-#pragma unroll
-  for (int j = 0; j < NI; ++j) {
-    const int it = tid + j * kThreads, kb = it >> 4;
-#pragma unroll
-    for (int ka = 0; ka < 16; ++ka) {
-      yv[j][ka] = make_float2(0.f, 0.f);
-      wv[j][ka] = 0.f;
-      if (it < N) {
-        const long long g = base + (long long)(kb + M * ka) * nx + c;
-        yv[j][ka] = a.y[g];
-        wv[j][ka] = a.wgt[g];
-      }
-    }
+#define COLS4_LOAD_YW()                                                  \
+  _Pragma("unroll") for (int j = 0; j < NI; ++j) {                       \
+    const int it = tid + j * NT, kb = it >> 4;                           \
+    _Pragma("unroll") for (int ka = 0; ka < 16; ++ka) {                  \
+      yv[j][ka] = make_float2(0.f, 0.f);                                 \
+      wv[j][ka] = 0.f;                                                   \
+      if (it < N) {                                                      \
+        const long long g = base + (long long)(kb + M * ka) * nx + c;    \
+        yv[j][ka] = a.y[g];                                              \
+        wv[j][ka] = a.wgt[g];                                            \
+      }                                                                  \
+    }                                                                    \
   }
+  if constexpr (kEarlyY) COLS4_LOAD_YW();
   const FftPlanDev& P = a.ffts[S.fft_y];
-  for (int i = tid; i < N; i += kThreads) tw_s[i] = a.twiddles[P.tw_off + i];
+  for (int i = tid; i < N; i += NT) tw_s[i] = a.twiddles[P.tw_off + i];
   if (vd) {
     const float* cs = a.tables + S.ytab_off + 2 * s * N;
-    for (int i = tid; i < N; i += kThreads) cs_s[i] = make_float2(cs[2 * i], cs[2 * i + 1]);
+    for (int i = tid; i < N; i += NT) cs_s[i] = make_float2(cs[2 * i], cs[2 * i + 1]);
   }
   __syncthreads();
-  if (!first) {
+  if (!first && s1) {
     RegFft<M, false>::run(xin, tw_s, 16);
 #pragma unroll
     for (int kb = 0; kb < M; ++kb) {
@@ -334,6 +343,8 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
       tb[kb * P1 + a1 * 16 + c] = v;
     }
   }
+  if constexpr (!kEarlyY) COLS4_LOAD_YW();
+#undef COLS4_LOAD_YW
   __syncthreads();
   const float isq = rsqrtf((float)N * (float)nx);
   const float sig2 = a.sigma2 ? a.sigma2[sl] : 0.f;
@@ -349,7 +360,7 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
   float2 d[NI][16];
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
-    const int it = tid + j * kThreads, kb = it >> 4;
+    const int it = tid + j * NT, kb = it >> 4;
 #pragma unroll
     for (int q = 0; q < 16; ++q) d[j][q] = make_float2(0.f, 0.f);
     if (it < N) {
@@ -425,13 +436,13 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
   if (vd && tid < a.nbands) {
     float acc = 0.f;
 #pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) acc += red[w][tid];
+    for (int w = 0; w < NT / 64; ++w) acc += red[w][tid];
     a.tau_part[(S.colstrip0 + item.y) * kMaxBands + tid] = acc;
   }
   // inverse: 16-point DFTs over ka (rows kb + M ka), twiddle, transpose
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
-    const int it = tid + j * kThreads, kb = it >> 4;
+    const int it = tid + j * NT, kb = it >> 4;
     if (it < N) {
       RegFft<16, true>::run(d[j], tw_s, M);
 #pragma unroll
@@ -447,6 +458,7 @@ __global__ void __launch_bounds__(kThreads) k_cols4(KArgs a) {
     }
   }
   __syncthreads();
+  if (!s1) return;
   float2 f[M];
 #pragma unroll
   for (int kb = 0; kb < M; ++kb) f[kb] = tb[a1 * P2 + kb * 16 + c];
@@ -719,7 +731,7 @@ hipError_t launch_cols(const KArgs& a, int ept, size_t lds, hipStream_t st) {
   return hipGetLastError();
 }
 #define COLS4_CASE(MM) \
-  case MM: hipLaunchKernelGGL(k_cols4<MM>, dim3(a.nwork), dim3(kThreads), 0, st, a); break
+  case MM: hipLaunchKernelGGL(k_cols4<MM>, dim3(a.nwork), dim3(cols4_threads(MM)), 0, st, a); break
 
 hipError_t launch_cols4(const KArgs& a, int m, hipStream_t st) {
   switch (m) {
