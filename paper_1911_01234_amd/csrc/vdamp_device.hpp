@@ -218,9 +218,10 @@ template <bool INV> struct RegFft<5, INV> {
 };
 
 // Copy a plan's twiddle table into LDS (issued alongside the tile loads).
+template <int NT = kThreads>
 __device__ __forceinline__ void load_twiddles(float2* tw_s, const FftPlanDev& P,
                                               const float2* __restrict__ pool) {
-  for (int i = threadIdx.x; i < P.n; i += kThreads) tw_s[i] = pool[P.tw_off + i];
+  for (int i = threadIdx.x; i < P.n; i += NT) tw_s[i] = pool[P.tw_off + i];
 }
 
 // ------------------------------------------------------------------ four-step row FFTs
@@ -230,11 +231,11 @@ __device__ __forceinline__ void load_twiddles(float2* tw_s, const FftPlanDev& P,
 // outputs kb + M ka.  The transpose buffer (pitch PR, odd, so that the lanes of a step
 // hit distinct banks) aliases the strip buffer; every thread has read its inputs before
 // the first write.
-template <int M>
+template <int M, int NT = kThreads>
 struct RowFft4 {
   static constexpr int N = 16 * M;
   static constexpr int PR = (M % 2) ? M : M + 1;
-  static constexpr int NI = (16 * M + kThreads - 1) / kThreads;
+  static constexpr int NI = (16 * M + NT - 1) / NT;
   static constexpr int LDS_ELEMS = (16 * N > 256 * PR) ? 16 * N : 256 * PR;
 
   // step 1 (inputs in v, lanes with line >= H idle) and the transpose
@@ -260,7 +261,7 @@ struct RowFft4 {
   template <bool INV>
   static __device__ __forceinline__ bool step2(int j, int H, const float2* __restrict__ tw,
                                                const float2* buf, float2 (&d)[16], int& kb, int& line) {
-    const int it = threadIdx.x + j * kThreads;
+    const int it = threadIdx.x + j * NT;
     kb = it % M;
     line = it / M;
     if (line >= H) return false;
@@ -278,7 +279,7 @@ struct RowFft4 {
 //   x00 = (a + b + c + d)/2, x01 = (a - b + c - d)/2,
 //   x10 = (a + b - c - d)/2, x11 = (a - b - c + d)/2,
 // with a = LL, b = LH (low y, high x), c = HL (high y, low x), d = HH.
-template <int EPT>
+template <int EPT, int NT = kThreads>
 __device__ void haar_strip_synth(float2* buf, int H, int nx, int s) {
   constexpr int MAXQ = EPT / 4;
   for (int l = s; l >= 1; --l) {
@@ -287,7 +288,7 @@ __device__ void haar_strip_synth(float2* buf, int H, int nx, int s) {
     float2 o[MAXQ][4];
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
-      const int t = threadIdx.x + q * kThreads;
+      const int t = threadIdx.x + q * NT;
       if (t < nblk) {
         const int i = t / w, j = t - (t / w) * w;
         const float2 a = buf[i * nx + j], b = buf[i * nx + w + j];
@@ -302,7 +303,7 @@ __device__ void haar_strip_synth(float2* buf, int H, int nx, int s) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
-      const int t = threadIdx.x + q * kThreads;
+      const int t = threadIdx.x + q * NT;
       if (t < nblk) {
         const int i = t / w, j = t - (t / w) * w;
         float4* row0 = reinterpret_cast<float4*>(buf + (2 * i) * nx + 2 * j);
@@ -315,7 +316,7 @@ __device__ void haar_strip_synth(float2* buf, int H, int nx, int s) {
   }
 }
 
-template <int EPT>
+template <int EPT, int NT = kThreads>
 __device__ void haar_strip_anal(float2* buf, int H, int nx, int s) {
   constexpr int MAXQ = EPT / 4;
   for (int l = 1; l <= s; ++l) {
@@ -324,7 +325,7 @@ __device__ void haar_strip_anal(float2* buf, int H, int nx, int s) {
     float2 o[MAXQ][4];
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
-      const int t = threadIdx.x + q * kThreads;
+      const int t = threadIdx.x + q * NT;
       if (t < nblk) {
         const int i = t / w, j = t - (t / w) * w;
         const float4 r0 = *reinterpret_cast<const float4*>(buf + (2 * i) * nx + 2 * j);
@@ -340,7 +341,7 @@ __device__ void haar_strip_anal(float2* buf, int H, int nx, int s) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < MAXQ; ++q) {
-      const int t = threadIdx.x + q * kThreads;
+      const int t = threadIdx.x + q * NT;
       if (t < nblk) {
         const int i = t / w, j = t - (t / w) * w;
         buf[i * nx + j] = o[q][0];

@@ -17,8 +17,8 @@ namespace vdamp {
 
 // ------------------------------------------------------------------ rows_synth
 // do_fft = 0 writes the image rows Psi^H r (the FISTA output).
-template <int EPT, int M>
-__global__ void __launch_bounds__(kThreads) k_rows_synth(KArgs a, int do_fft) {
+template <int EPT, int M, int NT = kThreads>
+__global__ void __launch_bounds__(NT) k_rows_synth(KArgs a, int do_fft) {
   extern __shared__ float4 lds4[];
   float2* lds = reinterpret_cast<float2*>(lds4);
   __shared__ float2 tw_s[kMaxN];
@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_synth(KArgs a, int do_fft) {
     al_s[tid] = a.alpha[item.x * kMaxBands + tid];
   }
   const FftPlanDev& P = a.ffts[S.fft_x];
-  if (do_fft) load_twiddles(tw_s, P, a.twiddles);
+  if (do_fft) load_twiddles<NT>(tw_s, P, a.twiddles);
   constexpr int U = EPT / 2;
   const int half = nx >> 1, npairs = H * half;
   const float2* r = a.r + S.off;
@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_synth(KArgs a, int do_fft) {
   long long gi[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int p = tid + u * kThreads;
+    const int p = tid + u * NT;
     bnd[u] = 0;
     gi[u] = 0;
     v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_synth(KArgs a, int do_fft) {
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int p = tid + u * kThreads;
+    const int p = tid + u * NT;
     if (p < npairs) {
       const int b = bnd[u];
       float2 x0 = lo2(v[u]), x1 = hi2(v[u]);
@@ -93,10 +93,10 @@ __global__ void __launch_bounds__(kThreads) k_rows_synth(KArgs a, int do_fft) {
     }
   }
   __syncthreads();
-  haar_strip_synth<EPT>(lds, H, nx, s);
+  haar_strip_synth<EPT, NT>(lds, H, nx, s);
   if constexpr (M > 0) {
     if (do_fft) {  // four-step row FFT, outputs straight to X
-      using F = RowFft4<M>;
+      using F = RowFft4<M, NT>;
       float2 v[M];
       const int a16 = tid & 15, line = tid >> 4;
       if (line < H) {
@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_synth(KArgs a, int do_fft) {
   float4* dst = reinterpret_cast<float4*>((do_fft ? a.X : a.out) + S.off + (long long)strip * H * nx);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int p = tid + u * kThreads;
+    const int p = tid + u * NT;
     if (p < npairs) dst[p] = lds4[p];
   }
 }
@@ -468,8 +468,8 @@ __global__ void __launch_bounds__(cols4_threads(M)) k_cols4(KArgs a) {
 }
 
 // ------------------------------------------------------------------ rows_anal
-template <int EPT, int M>
-__global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
+template <int EPT, int M, int NT = kThreads>
+__global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
   extern __shared__ float4 lds4[];
   float2* lds = reinterpret_cast<float2*>(lds4);
   __shared__ float2 tw_s[kMaxN];
@@ -494,7 +494,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
   } else {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int p = tid + u * kThreads;
+      const int p = tid + u * NT;
       v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (p < npairs) v[u] = src[p];
     }
@@ -506,9 +506,9 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
     if (mode == RA_LEARNED) sel_s[tid] = a.sel[item.x * kMaxBands + tid];
   }
   const FftPlanDev& P = a.ffts[S.fft_x];
-  load_twiddles(tw_s, P, a.twiddles);
+  load_twiddles<NT>(tw_s, P, a.twiddles);
   if constexpr (M > 0) {
-    using F = RowFft4<M>;
+    using F = RowFft4<M, NT>;
     __syncthreads();  // twiddles
     F::template step1<true>(v4, H, tw_s, lds);
     __syncthreads();
@@ -528,7 +528,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
   } else {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int p = tid + u * kThreads;
+      const int p = tid + u * NT;
       if (p < npairs) lds4[p] = v[u];
     }
     __syncthreads();
@@ -544,7 +544,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
   float4 ro[U], rw[U];
 #define RA_LOAD_R()                                                                          \
   _Pragma("unroll") for (int u = 0; u < U; ++u) {                                            \
-    const int p = tid + u * kThreads;                                                        \
+    const int p = tid + u * NT;                                                        \
     bnd[u] = 0;                                                                              \
     gi[u] = 0;                                                                               \
     ro[u] = make_float4(0.f, 0.f, 0.f, 0.f);                                                 \
@@ -562,7 +562,7 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
     float4* dst = reinterpret_cast<float4*>(a.out + S.off + (long long)strip * H * nx);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int p = tid + u * kThreads;
+      const int p = tid + u * NT;
       if (p < npairs) dst[p] = lds4[p];
     }
     return;
@@ -572,20 +572,20 @@ __global__ void __launch_bounds__(kThreads) k_rows_anal(KArgs a) {
   // cost more occupancy than the overlap gains.
   if constexpr (EPT <= 16) {
     RA_LOAD_R();
-    haar_strip_anal<EPT>(lds, H, nx, s);
+    haar_strip_anal<EPT, NT>(lds, H, nx, s);
   } else {
-    haar_strip_anal<EPT>(lds, H, nx, s);
+    haar_strip_anal<EPT, NT>(lds, H, nx, s);
     RA_LOAD_R();
   }
 #undef RA_LOAD_R
   if (mode == RA_FISTA || mode == RA_LEARNED) {  // the second iterate
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (tid + u * kThreads < npairs) rw[u] = *reinterpret_cast<const float4*>(r2 + gi[u]);
+      if (tid + u * NT < npairs) rw[u] = *reinterpret_cast<const float4*>(r2 + gi[u]);
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int p = tid + u * kThreads;
+    const int p = tid + u * NT;
     if (p < npairs) {
       const int b = bnd[u];
       const float4 gv = lds4[p];
@@ -768,15 +768,18 @@ size_t rows4_lds_bytes(int m, int H) {
 }
 
 #define ROWS4_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(8) X(10) X(12) X(15) X(16) X(20) X(24) X(30) X(32)
-// elements a thread: 16 up to nx = 256, else nx / 16 where the Haar loops (EPT / 4 blocks a
-// thread) cover the strip exactly, else 32
-#define EPT_OF(MM) ((MM) <= 16 ? 16 : ((MM) % 4 == 0 ? (MM) : 32))
+// threads and elements a thread: 256 x 16 up to nx = 256; 256 x nx/16 for nx = 320 and
+// 384 (the Haar loops, EPT / 4 blocks a thread, cover the strip exactly); 256 x 32 for
+// nx = 480 and 512 (512 x 16 measured no better there: the M-point stage alone holds
+// 2 M registers a thread, 166 VGPRs, so only one 8-wave workgroup fits a CU)
+#define NT_OF(MM) kThreads
+#define EPT_OF(MM) ((MM) <= 16 ? 16 : ((MM) <= 24 ? (MM) : 32))
 
 hipError_t launch_rows_synth4(const KArgs& a, int m, size_t lds, hipStream_t st) {
   switch (m) {
 #define RS4(MM)                                                                                \
   case MM:                                                                                     \
-    hipLaunchKernelGGL((k_rows_synth<EPT_OF(MM), MM>), dim3(a.nwork), dim3(kThreads), lds, st, a, 1); \
+    hipLaunchKernelGGL((k_rows_synth<EPT_OF(MM), MM, NT_OF(MM)>), dim3(a.nwork), dim3(NT_OF(MM)), lds, st, a, 1); \
     break;
     ROWS4_CASES(RS4)
 #undef RS4
@@ -789,7 +792,7 @@ hipError_t launch_rows_anal4(const KArgs& a, int m, size_t lds, hipStream_t st) 
   switch (m) {
 #define RA4(MM)                                                                                \
   case MM:                                                                                     \
-    hipLaunchKernelGGL((k_rows_anal<EPT_OF(MM), MM>), dim3(a.nwork), dim3(kThreads), lds, st, a); \
+    hipLaunchKernelGGL((k_rows_anal<EPT_OF(MM), MM, NT_OF(MM)>), dim3(a.nwork), dim3(NT_OF(MM)), lds, st, a); \
     break;
     ROWS4_CASES(RA4)
 #undef RA4
@@ -817,10 +820,10 @@ hipError_t set_lds_limits_passes(size_t rows, size_t cols) {
   const int r4 = (int)rows4_lds_bytes(32, 16);  // the largest four-step row tile
 #define LIM4(MM)                                                                                      \
   {                                                                                                   \
-    hipError_t e = hipFuncSetAttribute((const void*)k_rows_synth<EPT_OF(MM), MM>,                     \
+    hipError_t e = hipFuncSetAttribute((const void*)k_rows_synth<EPT_OF(MM), MM, NT_OF(MM)>,                     \
                                        hipFuncAttributeMaxDynamicSharedMemorySize, r4);               \
     if (e == hipSuccess)                                                                              \
-      e = hipFuncSetAttribute((const void*)k_rows_anal<EPT_OF(MM), MM>,                               \
+      e = hipFuncSetAttribute((const void*)k_rows_anal<EPT_OF(MM), MM, NT_OF(MM)>,                               \
                               hipFuncAttributeMaxDynamicSharedMemorySize, r4);                        \
     if (e != hipSuccess) return e;                                                                    \
   }
