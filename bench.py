@@ -84,15 +84,17 @@ def pass_rooflines(times, npx, iters, steps):
 
 
 def other_workloads(stream, reps=3):
-    """Throughput of the other batch shapes the library is built for: the ragged batch of
-    512 slices (128 each of 128^2, 192^2, 256^2, 320^2) and 128 slices of 512^2 (whose
-    finest bands take the large-band threshold search), each planned with the plan-time
-    tuner.  One warm-up solve, then `reps` timed solves of 50 iterations each, eager with
+    """Throughput of the other batch shapes the library is built for: 64 and 512 slices of
+    256^2, the ragged batch of 512 slices (128 each of 128^2, 192^2, 256^2, 320^2) and 128
+    slices of 512^2 (whose finest bands take the large-band threshold search), each
+    planned with the plan-time tuner.  One warm-up solve, then `reps` timed solves of 50 iterations each, eager with
     per-kernel events."""
     import torch
     from paper_1911_01234_amd import synth, vdamp as V
     res = {}
-    for name, gen in (("mixed_512_slices_128_to_320", lambda: synth.workload_mixed(128)),
+    for name, gen in (("batch_64_slices_256x256", lambda: synth.workload_batch256(64)),
+                      ("batch_512_slices_256x256", lambda: synth.workload_batch256(512)),
+                      ("mixed_512_slices_128_to_320", lambda: synth.workload_mixed(128)),
                       ("batch_128_slices_512x512", lambda: synth.workload_batch512(128))):
         t = time.perf_counter()
         slices, s, K = gen()
