@@ -36,8 +36,12 @@ __device__ __forceinline__ float tau_feature(float tau, float s0) {
   return logf(fmaxf(tau / (s0 * s0), 1e-12f));
 }
 
+// Waves a SIMD the register budget is sized for (the k-loop is fully unrolled so that
+// fragment loads run ahead of the MFMAs; at 3 waves the 1-tile output layer spills).
+constexpr int conv_waves(int) { return 2; }
+
 template <int CIN, int KSTEPS, int MT, int MODE>
-__global__ void __launch_bounds__(kThr) k_conv(ConvArgs a) {
+__global__ void __launch_bounds__(kThr) __attribute__((amdgpu_waves_per_eu(conv_waves(MT)))) k_conv(ConvArgs a) {
   constexpr int KPAD = KSTEPS * 32;
   // LDS pitches chosen for the 128-bank LDS, which serves a 16-byte read as two 8-byte
   // halves for 32 lanes at a time: 16 lanes read rows c of a fragment 16 bytes apart per
@@ -116,7 +120,7 @@ __global__ void __launch_bounds__(kThr) k_conv(ConvArgs a) {
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+#pragma unroll
     for (int ks = 0; ks < KSTEPS; ++ks) {
       const int k = ks * 32 + g * 8;
       const int tap = k / CIN, ci0 = k - tap * CIN;
