@@ -69,7 +69,7 @@ struct vdamp_plan_t {
   float* d_tables = nullptr;
   int2* d_work_rows = nullptr;
   int2* d_work_cols = nullptr;
-  int2* d_work_sure = nullptr;      // bands by size class: > 27648, > 16384, > 4096, the rest
+  int2* d_work_sure = nullptr;      // bands grouped by threshold-search class, largest class first
   int nrows = 0, ncols = 0, nsure_cls[vdamp::kSureClasses] = {};
   int nrowstrips = 0;
   // column launches: runs of the column work list with one ny each (first, count, M, ny),

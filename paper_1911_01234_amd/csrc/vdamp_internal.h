@@ -13,7 +13,7 @@ constexpr int kMaxBands = 16;      // per-slice band slots (1 + 3 s, s <= 4 uses
 constexpr int kColW = 16;          // columns per column strip (16 complex = 128 B per row)
 constexpr int kMaxRadices = 8;
 constexpr int kMaxN = 512;         // largest ny / nx
-constexpr int kSureSmall = 4096;   // bands up to this size use the 256-thread search
+constexpr int kSureSmall = 4096;   // capacity of the 256- and 512-thread search classes
 constexpr int kSureClasses = 5;  // LDS classes 0..3 and the large-band search
 constexpr int kSureBigClass = kSureClasses - 1;
 constexpr int kSureBigMaxKeys = 65536;  // largest subband (the finest band of 512 x 512)
