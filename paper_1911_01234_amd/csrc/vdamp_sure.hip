@@ -64,6 +64,7 @@ template <int NB> struct SureBuckets;
 template <> struct SureBuckets<10240> { static constexpr int LB = 5, MB = 10; };
 template <> struct SureBuckets<2560> { static constexpr int LB = 3, MB = 8; };
 template <> struct SureBuckets<5120> { static constexpr int LB = 3, MB = 9; };
+template <> struct SureBuckets<19456> { static constexpr int LB = 5, MB = 11; };
 template <> struct SureBuckets<3072> { static constexpr int LB = 4, MB = 8; };
 
 template <int NB>
@@ -854,8 +855,9 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
 }
 
 // Size classes: up to 4096 keys (0: 256 threads x 16 keys, 2560 buckets; 1: 512 x 8,
-// 5120 buckets), up to 16384 keys (2: 1024 x 16) and up to kSureMaxKeys keys (3:
-// 1024 x 32), the last two with 10240 buckets.  By default bands of up to 2048 keys take
+// 5120 buckets), up to 16384 keys (2: 1024 x 16, 19456 buckets, the most whose table
+// still lets two workgroups share a CU) and up to kSureMaxKeys keys (3: 1024 x 32,
+// 10240 buckets).  By default bands of up to 2048 keys take
 // class 0 and bands of 2049-16384 keys class 2 (measured faster than classes 0 and 1 on
 // 4096-key bands of VDAMP iterates; class 1 is left to the plan-time tuner).  All LDS is static: the largest class uses about
 // 158 KB of the 160 KB a gfx950 workgroup may hold.
@@ -866,7 +868,7 @@ hipError_t launch_sure(const KArgs& a, int cls, float* scratch, hipStream_t st) 
   else if (cls == 3)
     hipLaunchKernelGGL((k_sure<1024, 32, 10240, kSureMaxKeys>), dim3(a.nwork), dim3(1024), 0, st, a);
   else if (cls == 2)
-    hipLaunchKernelGGL((k_sure<1024, 16, 10240, 4 * kSureSmall>), dim3(a.nwork), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL((k_sure<1024, 16, 19456, 4 * kSureSmall>), dim3(a.nwork), dim3(1024), 0, st, a);
   else if (cls == 1)
     hipLaunchKernelGGL((k_sure<512, 8, 5120, kSureSmall>), dim3(a.nwork), dim3(512), 0, st, a);
   else
