@@ -24,8 +24,9 @@ of 256x256 slices (same generator), then 64 held-out slices of the timed batch a
 solved with plain VDAMP and with the SURE-judged learned form: mean NMSE at 50
 iterations, the learned form's NMSE at the wall-clock of the plain 50-iteration solve,
 and each form's time to reach the plain form's 50-iteration NMSE.  `cnn_roofline`: the
-network's forward + JVP kernels (algorithmic FLOPs with the real channel counts) per
-learned iteration against the MI355X dense BF16 MFMA peak.
+network pass of a learned iteration (input packing, forward and JVP) against its binding
+roofline, HBM (algorithmic activation bytes per pixel, CNN_BYTES_PER_PX, at 8 TB/s take
+about 2.3x as long as its FLOPs at the dense BF16 MFMA peak), with the MFMA rate beside.
 """
 from __future__ import annotations
 
@@ -45,6 +46,12 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 # FLOPs per pixel of the network's forward pass: 3x3 convolutions 2->48, 4 x 48->48, 48->2
 CNN_FLOP_PER_PX = 2 * 9 * (2 * 48 + 4 * 48 * 48 + 48 * 2)
+# Algorithmic HBM bytes per pixel of one learned iteration's network pass (forward + JVP),
+# activations BF16 [pixel][channel]: packing the image and the probe into 8-channel
+# inputs (read 8, write 16, twice); forward: layer 1 reads 16 and writes 96, layers 2-5
+# read and write 96, layer 6 reads 96 plus the 8-byte residual and writes 8; JVP: the
+# same with each layer's ReLU pattern (its forward activation, 96) read as well.
+CNN_BYTES_PER_PX = 2 * 24 + (112 + 4 * 192 + 112) + (208 + 4 * 288 + 112)
 ITERS = 50
 LEVELS = 4
 
@@ -349,6 +356,7 @@ def learned_section(args, test, s, K, stream):
     cnn_ms, cnn_launch = times["cnn"]
     reps = 3
     flop = 2 * CNN_FLOP_PER_PX * plan.ntot  # forward + JVP per learned iteration
+    cnn_bytes = CNN_BYTES_PER_PX * plan.ntot
     per_iter_s = cnn_ms / 1e3 / (reps * K)
     ach = flop / per_iter_s / 1e12
     out = {
@@ -367,9 +375,15 @@ def learned_section(args, test, s, K, stream):
                                  "learned": {"iters": k_hit, "seconds": round(t_hit, 5) if t_hit else None}},
         "learned_band_fraction_last_iter": [round(float(v), 3) for v in sel_frac],
         "pass_ms_per_learned_solve": {k: round(v[0] / reps, 3) for k, v in times.items()},
-        "cnn_roofline": {"bound": "mfma", "achieved": round(ach, 2), "peak": BF16_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": round(ach / BF16_PEAK_TFLOPS, 4),
-                         "flop_per_learned_iter": int(flop), "ms_per_learned_iter": round(per_iter_s * 1e3, 3)},
+        # the binding roofline of the network pass: HBM (its bytes at 8 TB/s take longer
+        # than its FLOPs at the dense BF16 peak); the MFMA rate is reported beside it
+        "cnn_roofline": {"bound": "hbm" if cnn_bytes / HBM_PEAK_GBS / 1e9 > flop / BF16_PEAK_TFLOPS / 1e12 else "mfma",
+                         "achieved": round(cnn_bytes / per_iter_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(cnn_bytes / per_iter_s / 1e9 / HBM_PEAK_GBS, 4),
+                         "bytes_per_learned_iter": int(cnn_bytes),
+                         "mfma": {"achieved": round(ach, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": round(ach / BF16_PEAK_TFLOPS, 4), "flop_per_learned_iter": int(flop)},
+                         "ms_per_learned_iter": round(per_iter_s * 1e3, 3)},
     }
     log(f"learned: {json.dumps(out['nmse_db_at_50'])}, equal wall-clock {json.dumps(out['equal_wallclock'])}")
     return out
