@@ -49,9 +49,10 @@ CNN_FLOP_PER_PX = 2 * 9 * (2 * 48 + 4 * 48 * 48 + 48 * 2)
 # Algorithmic HBM bytes per pixel of one learned iteration's network pass (forward + JVP),
 # activations BF16 [pixel][channel]: packing the image and the probe into 8-channel
 # inputs (read 8, write 16, twice); forward: layer 1 reads 16 and writes 96, layers 2-5
-# read and write 96, layer 6 reads 96 plus the 8-byte residual and writes 8; JVP: the
-# same with each layer's ReLU pattern (its forward activation, 96) read as well.
-CNN_BYTES_PER_PX = 2 * 24 + (112 + 4 * 192 + 112) + (208 + 4 * 288 + 112)
+# read and write 96, layers 1-5 also write their 8-byte ReLU pattern, layer 6 reads 96
+# plus the 8-byte residual and writes 8; JVP: the same with the pattern read instead
+# of written.
+CNN_BYTES_PER_PX = 2 * 24 + 2 * ((16 + 96 + 8) + 4 * (96 + 96 + 8) + (96 + 8 + 8))
 ITERS = 50
 LEVELS = 4
 

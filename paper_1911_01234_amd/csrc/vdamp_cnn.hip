@@ -149,6 +149,8 @@ __global__ void __launch_bounds__(kThr) __attribute__((amdgpu_waves_per_eu(conv_
     for (int nt = 0; nt < 4; ++nt) {
       const long long gp = S.off + (long long)(ty0 + wv * 4 + nt) * nx + tx0 + c;
       if (MODE == CV_RELU || MODE == CV_MASK) {
+        uint2 bw = make_uint2(0u, 0u);  // this pixel's ReLU pattern (read, or built)
+        if (MODE == CV_MASK && a.bits) bw = a.bits[gp];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
           const int co0 = mt * 16 + 4 * g;
@@ -158,6 +160,10 @@ __global__ void __launch_bounds__(kThr) __attribute__((amdgpu_waves_per_eu(conv_
           if (MODE == CV_RELU) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) z[i] = fmaxf(z[i] + bias_r[mt][i] + sb[mt][i], 0.f);
+          } else if (a.bits) {
+            const unsigned word = (mt < 2 ? bw.x >> (16 * mt) : bw.y) >> (4 * g);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) z[i] = ((word >> i) & 1u) ? z[i] : 0.f;
           } else {
             const uint2 mk = *reinterpret_cast<const uint2*>(&a.mask[gp * kCh + co0]);
             const u16 m4[4] = {(u16)(mk.x & 0xFFFF), (u16)(mk.x >> 16), (u16)(mk.y & 0xFFFF), (u16)(mk.y >> 16)};
@@ -168,6 +174,20 @@ __global__ void __launch_bounds__(kThr) __attribute__((amdgpu_waves_per_eu(conv_
           o.x = (unsigned)f2bf(z[0]) | ((unsigned)f2bf(z[1]) << 16);
           o.y = (unsigned)f2bf(z[2]) | ((unsigned)f2bf(z[3]) << 16);
           *reinterpret_cast<uint2*>(&a.out[gp * kCh + co0]) = o;
+          if (MODE == CV_RELU) {  // bit set where the stored BF16 activation is > 0
+            const unsigned b4 = ((o.x & 0xFFFFu) ? 1u : 0u) | ((o.x >> 16) ? 2u : 0u) |
+                                ((o.y & 0xFFFFu) ? 4u : 0u) | ((o.y >> 16) ? 8u : 0u);
+            if (mt < 2) bw.x |= b4 << (16 * mt + 4 * g);
+            else bw.y |= b4 << (4 * g);
+          }
+        }
+        if (MODE == CV_RELU && a.bits_out) {  // uniform branch: every lane shuffles
+          // the four lanes c + 16 g of a pixel hold its channel groups g
+          bw.x |= __shfl_xor(bw.x, 16, 64);
+          bw.y |= __shfl_xor(bw.y, 16, 64);
+          bw.x |= __shfl_xor(bw.x, 32, 64);
+          bw.y |= __shfl_xor(bw.y, 32, 64);
+          if (g == 0) a.bits_out[gp] = bw;
         }
       } else if (g == 0) {  // channels 0 (real) and 1 (imaginary) of the output
         const float2 rin = a.resid[gp];

@@ -90,6 +90,7 @@ struct CnnWs {
   size_t a0 = 0, t0 = 0, act[kLayers] = {}, ta = 0, tb = 0, g6 = 0, ga = 0, gb = 0;
   size_t sbias = 0, lpart = 0, part = 0, pbias = 0, tsums = 0, xo = 0;
   size_t xi = 0, ti = 0, xo2 = 0, to = 0, jpart = 0, sel = 0, smin = 0, s0 = 0, jout = 0;
+  size_t bits = 0;  // ReLU pattern of the current layer (forward and solve kinds)
   size_t bytes = 0;
 };
 
@@ -116,6 +117,7 @@ CnnWs cnn_layout(const vdamp_plan_t* P, int kind) {
     take(L.act[2], 2 * (size_t)kC * N);
     take(L.ta, 2 * (size_t)kC * N);      // ping-pong tangents
     take(L.tb, 2 * (size_t)kC * N);
+    take(L.bits, 8 * N);
   }
   if (kind == VDAMP_CNN_WS_SOLVE) {
     take(L.xi, 8 * N);
@@ -195,12 +197,17 @@ vdamp_status enqueue_forward(const vdamp_cnn_t* C, const vdamp_plan_t* P, const 
       a.bias = l == 1 ? nullptr : C->d_p + C->ob[l];
       a.sbias = l == 1 ? sbias : nullptr;
       a.out = out;
+      // with a tangent the layer also writes its ReLU pattern, which the tangent's
+      // masked convolution reads (8 bytes a pixel instead of the 96-byte activation)
+      uint2* bits = tangent ? at<uint2>(ws, L.bits) : nullptr;
+      a.bits_out = bits;
       HIP_TRY(cnn::launch_conv(a, cin, 3, cnn::CV_RELU, grid, st));
       if (tangent) {
         cnn::ConvArgs t = conv_args(P);
         t.in = tcur;
         t.w = C->d_wf[l];
         t.mask = out;
+        t.bits = bits;
         t.out = tan[l & 1];
         HIP_TRY(cnn::launch_conv(t, cin, 3, cnn::CV_MASK, grid, st));
         tcur = tan[l & 1];

@@ -25,6 +25,11 @@ struct ConvArgs {
   const float* sbias;   // [B][48] per-slice bias (layer 1) or null
   const u16* mask;      // [pixel][48] or null
   u16* out;             // [pixel][48]
+  // ReLU pattern, [pixel] of 4 16-bit words: bit 4 g + i of word t is channel
+  // 16 t + 4 g + i (word 3 unused).  CV_RELU writes it when bits_out is set; CV_MASK
+  // reads it instead of mask when bits is set.
+  uint2* bits_out;
+  const uint2* bits;
   const float2* resid;  // complex image (last layer)
   const float* s0;      // [B]
   float2* img_out;      // complex image (last layer)
