@@ -99,3 +99,28 @@ def test_plan_accepts_512_slices():
         assert lib.vdamp_plan_destroy(h) == 0
     else:
         assert st == 5 and "upload" in msg, msg
+
+
+def test_plan_accepts_every_documented_flag():
+    """All VDAMP_FLAG_* bits pass the host checks together (the autotune flag included);
+    an undocumented bit is rejected before anything touches the device."""
+    flags = V.VDAMP_FLAG_USE_GRAPH | V.VDAMP_FLAG_CHECK_FINITE | V.VDAMP_FLAG_TIMING | V.VDAMP_FLAG_AUTOTUNE
+    lib = V.load_library()
+    h = ctypes.c_void_p()
+    wsb = ctypes.c_size_t()
+    n = (ctypes.c_int32 * 1)(64)
+    st = lib.vdamp_plan(ctypes.byref(h), 1, n, n, 3, 0, flags, ctypes.byref(wsb))
+    msg = lib.vdamp_last_error().decode()
+    if st == 0:
+        assert lib.vdamp_plan_destroy(h) == 0
+    else:
+        assert st == 5 and "upload" in msg, msg
+    st, msg = _plan_status(1, [64], [64], 3, 0, 1 << 7)
+    assert st == 1 and "flag" in msg, msg
+
+
+def test_describe_rejects_null_plan():
+    lib = V.load_library()
+    need = ctypes.c_size_t(0)
+    assert lib.vdamp_plan_describe(None, None, 0, ctypes.byref(need)) == 1
+    assert lib.vdamp_last_error()
