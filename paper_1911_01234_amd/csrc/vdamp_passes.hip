@@ -279,7 +279,8 @@ constexpr int cols4_threads(int m) { return 16 * m > kThreads ? 16 * m : kThread
 // k-space rows kb + M ka), the k-space step runs on those registers, and the inverse
 // factors ny = M x 16 so that it starts from exactly the rows each thread holds and
 // ends, after one more transpose, on the rows the forward transform started from.
-// Loads of X, y and m/p are all issued at the start.
+// Loads of X, y and m/p are issued at the start (y and m/p after the M-point stage for
+// M > 20).
 template <int M>
 __global__ void __launch_bounds__(cols4_threads(M)) k_cols4(KArgs a) {
   constexpr int N = 16 * M;
