@@ -258,6 +258,14 @@ def test_free_running_mixed_sizes(n):
     free_running(sl, 4, 20)
 
 
+@pytest.mark.parametrize("ny,nx", [(128, 256), (320, 96)])
+def test_free_running_non_square(ny, nx):
+    """Non-square slices: the row and column passes run different lengths (320 x 96 also
+    different radix plans, 2^6 5 and 2^5 3), and every band is (ny/2^j) x (nx/2^j)."""
+    sl = synth.make_slice(8, ny + nx, ny, nx, 16, 6.0, 6.0, 16, 35.0)
+    free_running(sl, 4, 20)
+
+
 def test_all_zero_measurements():
     """y = 0: every band is all zeros (one bucket holds every key, so the search takes
     its full-sort path); theta = alpha = 0 and x_hat = 0."""
