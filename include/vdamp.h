@@ -58,6 +58,10 @@ typedef enum {
 enum { VDAMP_WAVELET_HAAR = 0 };
 
 enum {
+  /* Bitwise reproducible results.  Every path of this library already is (fixed-order
+     reductions, no floating-point atomics, plan-time kernel choices fixed for the plan),
+     so the flag is accepted and changes nothing. */
+  VDAMP_FLAG_DETERMINISTIC = 1u << 0,
   /* Capture the whole solve (all iterations) in one hipGraph on first use and replay
      it while pointers and iteration count stay the same; re-captured otherwise.  The
      stream must not be the legacy null stream. */
@@ -144,25 +148,60 @@ vdamp_status vdamp_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
                          float* trace);
 
 /*
+ * vdamp_solve_resume -- vdamp_solve from a given state, with an optional per-iteration
+ * output.  The state of Algorithm 1 between iterations is (r_k, theta_k, alpha_k): lines
+ * 6-8 rebuild r_tilde_{k+1} from it, and lines 3-5 need nothing else.
+ *   r_init          nullable complex64[sum N]: r_k (Mallat layout per slice).  Null: a
+ *                   fresh start (r_tilde_0 = 0), exactly vdamp_solve; theta_init,
+ *                   theta2_init and alpha_init must then be null too.
+ *   theta_init      float32[B][nb] (required with r_init): theta_k per band, >= 0
+ *   theta2_init     nullable float32[B][nb]: the FP32 key of each threshold, the squared
+ *                   magnitude thresholding compares |r|^2 (rounded FP32 x*x + y*y)
+ *                   against; vdamp_state_export returns it.  Null: fl(theta * theta).
+ *                   With it, a solve split into two calls is bitwise equal to one call.
+ *   alpha_init      float32[B][nb] (required with r_init): alpha_k per band, in [0, 1)
+ *   iters           K >= 0 further iterations; each starts with line 8 applied to the
+ *                   previous state.  K = 0 with r_init gives line 10 with w = eta(r_k; theta_k).
+ *   x_hat, trace    as in vdamp_solve (trace rows count this call's iterations)
+ *   x_monitor       nullable complex64[iters][sum N] out: line 10 evaluated after every
+ *                   iteration (the estimate x_hat_k a solve stopped there would return);
+ *                   costs one more transform pass per iteration
+ * Under VDAMP_FLAG_CHECK_FINITE the imported theta and alpha are validated too.
+ * The input arrays are read on the stream; the caller may reuse them once it has synchronised.
+ */
+vdamp_status vdamp_solve_resume(vdamp_plan_h plan, hipStream_t stream, void* workspace,
+                                size_t workspace_bytes, const float* y, const uint8_t* mask,
+                                const float* p, const float* sigma2, const float* r_init,
+                                const float* theta_init, const float* theta2_init,
+                                const float* alpha_init, int32_t iters, float* x_hat, float* trace,
+                                float* x_monitor);
+
+/*
  * fista_solve -- FISTA on 1/2 ||y - M_Omega F Psi^H w||^2 + lambda ||w||_1 (eq. 2 with
  * f = lambda ||Psi x||_1, in synthesis form), step size 1, zero start, every band
  * thresholded (Section 3's comparator).
  *   lambda          float32[B]: sparse weighting per slice
  *   x_hat           complex64[sum N] out: Psi^H w_K (K = 0 gives zeros)
+ *   objective       nullable float32[iters][B] out: eq. 2's objective at each iterate
+ *                   w_k, 1/2 ||y - M_Omega F Psi^H w_k||^2 + lambda ||w_k||_1 (costs one
+ *                   more forward transform per iteration)
  * Other arguments as in vdamp_solve (p and sigma2 are not used).
  */
 vdamp_status fista_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
                          size_t workspace_bytes, const float* y, const uint8_t* mask,
-                         const float* lambda, int32_t iters, float* x_hat);
+                         const float* lambda, int32_t iters, float* x_hat, float* objective);
 
 /*
- * vdamp_state_export -- copy the state left by the last vdamp_solve on this workspace:
+ * vdamp_state_export -- copy the state left by the last vdamp_solve (or
+ * vdamp_solve_resume, or vdamp_solve_learned) on this workspace:
  *   r               nullable complex64[sum N] out: r_{K-1} (Mallat layout per slice)
- *   theta, alpha, tau  nullable float32[B][nb] out: the last iteration's values
- * Returns VDAMP_ERR_STATE if no vdamp_solve with iters >= 1 ran on this plan.
+ *   theta, theta2, alpha, tau  nullable float32[B][nb] out: the last iteration's
+ *                   threshold, its FP32 key (see vdamp_solve_resume), alpha and tau
+ * (r, theta, theta2, alpha) passed to vdamp_solve_resume continue the solve exactly.
+ * Returns VDAMP_ERR_STATE if no solve with iters >= 1 (or a resume) ran on this workspace.
  */
 vdamp_status vdamp_state_export(vdamp_plan_h plan, hipStream_t stream, const void* workspace,
-                                float* r, float* theta, float* alpha, float* tau);
+                                float* r, float* theta, float* theta2, float* alpha, float* tau);
 
 /*
  * vdamp_pass_times -- with VDAMP_FLAG_TIMING: synchronise the recorded events and return,

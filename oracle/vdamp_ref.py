@@ -300,6 +300,35 @@ def vdamp(y, mask, p, sigma2, s, iters, record=False):
     return out
 
 
+def vdamp_resume(y, mask, p, sigma2, s, r, theta, alpha, iters, record=False):
+    """Algorithm 1 continued from the state (r_k, theta_k, alpha_k) of an earlier
+    iteration: every further iteration starts with lines 6-8 applied to the previous
+    state (eta with the given thresholds, line 8 with the given alpha), then lines 3-7.
+    With iters = 0 the output is line 10 with w = eta(r_k; theta_k).  Returns the same
+    dict as vdamp(); the per-iteration entries count the iterations of this call."""
+    y = np.asarray(y, dtype=np.complex128)
+    p = np.asarray(p, dtype=np.float64)
+    r = np.asarray(r, dtype=np.complex128)
+    ny, nx = y.shape
+    check_shape(ny, nx, s)
+    S = tau_weights(ny, nx, s)
+    w_hat, rt, _, _ = denoise(r, None, s, theta_override=theta, alpha_override=alpha)
+    taus, thetas, alphas, rs = [], [], [], []
+    for _ in range(iters):
+        r, tau = vdamp_step(rt, y, mask, p, sigma2, s, S)
+        w_hat, rt, th, al = denoise(r, tau, s)
+        taus.append(tau)
+        thetas.append(th)
+        alphas.append(al)
+        if record:
+            rs.append(r)
+    out = dict(x_hat=output_step(w_hat, y, mask, s), tau=np.array(taus), theta=np.array(thetas),
+               alpha=np.array(alphas))
+    if record:
+        out["r"] = rs
+    return out
+
+
 # ----------------------------------------------------------------------------------
 # FISTA comparator (Section 1, eq. 2 with f = lambda ||Psi x||_1; Section 3 setup):
 # synthesis form over w = Psi x (equal to the analysis form since Psi is orthogonal),

@@ -127,6 +127,7 @@ Ws layout(const vdamp_plan_t* P, void* ws) {
   w.alpha = reinterpret_cast<float*>(b + P->o_alpha);
   w.tau = reinterpret_cast<float*>(b + P->o_tau);
   w.taup = reinterpret_cast<float*>(b + P->o_taup);
+  w.rpart = reinterpret_cast<float*>(b + P->o_rpart);
   w.bad = reinterpret_cast<int*>(b + P->o_bad);
   w.big = P->o_big ? reinterpret_cast<float*>(b + P->o_big) : nullptr;
   return w;
@@ -148,13 +149,26 @@ vdamp_status check_common(vdamp_plan_h plan, void* ws, size_t wsb, const void* y
   return VDAMP_OK;
 }
 
+// State a resumed solve starts from (all null: a fresh start with r_tilde_0 = 0).
+struct Resume {
+  const float2* r = nullptr;
+  const float *theta = nullptr, *theta2 = nullptr, *alpha = nullptr;
+};
+
 vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const float2* y,
                            const uint8_t* mask, const float* p, const float* sigma2, int iters,
-                           float2* x_hat, float* trace, bool timing) {
+                           float2* x_hat, float* trace, bool timing, const Resume& rs,
+                           float2* x_monitor) {
   const Ws w = layout(P, ws);
   Launcher L{P, st, timing};
   const int check = (P->flags & VDAMP_FLAG_CHECK_FINITE) ? 1 : 0;
+  const bool resume = rs.r != nullptr;
   LAUNCH(L, VDAMP_PASS_PREP, launch_prep(mask, p, y, w.wgt, P->ntot, check, w.bad, st));
+  if (resume) {  // r_k, theta_k, alpha_k of an earlier iteration: line 8 starts from them
+    HIP_TRY(hipMemcpyAsync(w.r, rs.r, sizeof(float2) * (size_t)P->ntot, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(launch_import_state(rs.theta, rs.theta2, rs.alpha, P->B, P->nbands, w.theta, w.thr2,
+                                w.alpha, check, w.bad, st));
+  }
   KArgs a = base_args(P, w);
   a.y = y;
   a.sigma2 = sigma2;
@@ -162,22 +176,34 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
   a.trace = trace;
   for (int k = 0; k < iters; ++k) {
     a.iter = k;
-    if (k > 0) {
+    const bool has_prev = k > 0 || resume;  // r_tilde_k from the previous r, theta, alpha
+    if (has_prev) {
       a.mode = RS_RTILDE;
       LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, a, st));
     }
-    a.mode = k ? CM_VDAMP : CM_VDAMP_FIRST;
+    a.mode = has_prev ? CM_VDAMP : CM_VDAMP_FIRST;
     LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
-    a.mode = k ? RA_VDAMP : RA_VDAMP_FIRST;
+    a.mode = has_prev ? RA_VDAMP : RA_VDAMP_FIRST;
     LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
     LAUNCH(L, VDAMP_PASS_SURE, launch_sure_all(P, a, w.big, st));
+    if (x_monitor) {  // line 10 at this iteration (X is free between iterations)
+      KArgs m = a;
+      m.out = x_monitor + (long long)k * P->ntot;
+      m.mode = RS_WHAT;
+      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, m, st));
+      m.mode = CM_OUTPUT;
+      LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, m, st));
+      m.mode = RA_IMAGE;
+      LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, m, st));
+    }
   }
   // line 10: x_hat = F^H [ (1 - m) F Psi^H w + m y ]
-  if (iters > 0) {
+  const bool has_w = iters > 0 || resume;
+  if (has_w) {
     a.mode = RS_WHAT;
     LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, a, st));
   }
-  a.mode = iters > 0 ? CM_OUTPUT : CM_ZEROFILL;
+  a.mode = has_w ? CM_OUTPUT : CM_ZEROFILL;
   LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
   a.mode = RA_IMAGE;
   LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
@@ -186,7 +212,7 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
 
 vdamp_status enqueue_fista(vdamp_plan_t* P, hipStream_t st, void* ws, const float2* y,
                            const uint8_t* mask, const float* lambda, int iters, float2* x_hat,
-                           bool timing) {
+                           float* objective, bool timing) {
   const Ws w = layout(P, ws);
   Launcher L{P, st, timing};
   // weights: m (p taken as 1)
@@ -195,10 +221,12 @@ vdamp_status enqueue_fista(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
   a.y = y;
   a.lambda = lambda;
   a.out = x_hat;
+  a.jpart = objective ? w.rpart : nullptr;  // per row strip ||w_k||_1 for the objective
   double t = 1.0;
   for (int k = 0; k < iters; ++k) {
     const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
     a.beta = (float)((t - 1.0) / tn);
+    a.iter = k;
     t = tn;
     if (k > 0) {
       a.mode = RS_PLAIN;
@@ -208,6 +236,15 @@ vdamp_status enqueue_fista(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
     LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
     a.mode = k ? RA_FISTA : RA_FISTA_FIRST;
     LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
+    if (objective) {  // eq. 2 at w_k (in r2): forward transform of w_k, residual on Omega
+      KArgs o = a;
+      o.r = w.r2;
+      o.mode = RS_PLAIN;
+      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, o, st));
+      o.mode = CM_FISTA_OBJ;
+      LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, o, st));
+      LAUNCH(L, VDAMP_PASS_PREP, launch_fista_obj(o, objective, st));
+    }
   }
   // x_hat = Psi^H w_K (w_K lives in r2); K = 0 gives zeros (a fill kernel, so that a
   // captured graph holds no memset node)
@@ -249,7 +286,8 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   if (batch < 1) return fail(VDAMP_ERR_ARG, "batch must be >= 1");
   if (wavelet != VDAMP_WAVELET_HAAR) return fail(VDAMP_ERR_UNSUPPORTED, "only the Haar wavelet is implemented");
   if (levels < 1 || levels > 4) return fail(VDAMP_ERR_UNSUPPORTED, "levels must be in 1..4");
-  const uint32_t known = VDAMP_FLAG_USE_GRAPH | VDAMP_FLAG_CHECK_FINITE | VDAMP_FLAG_TIMING | VDAMP_FLAG_AUTOTUNE;
+  const uint32_t known = VDAMP_FLAG_DETERMINISTIC | VDAMP_FLAG_USE_GRAPH | VDAMP_FLAG_CHECK_FINITE |
+                         VDAMP_FLAG_TIMING | VDAMP_FLAG_AUTOTUNE;
   if (flags & ~known) return fail(VDAMP_ERR_ARG, "unknown flag bits");
   const int H = 1 << levels;
   std::vector<int> rad;
@@ -415,6 +453,7 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   P->o_alpha = o; o = align256(o + 4 * (size_t)batch * kMaxBands);
   P->o_tau = o; o = align256(o + 4 * (size_t)batch * kMaxBands);
   P->o_taup = o; o = align256(o + 4 * (size_t)colstrip * kMaxBands);
+  P->o_rpart = o; o = align256(o + 4 * (size_t)rowstrip);
   P->o_bad = o; o = align256(o + 4);
   if (P->nsure_cls[kSureBigClass]) {
     P->o_big = o;
@@ -487,20 +526,27 @@ vdamp_status vdamp_plan_destroy(vdamp_plan_h plan) {
   return VDAMP_OK;
 }
 
-vdamp_status vdamp_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
-                         size_t workspace_bytes, const float* y, const uint8_t* mask,
-                         const float* p, const float* sigma2, int32_t iters, float* x_hat,
-                         float* trace) {
-  g_err.clear();
+namespace {
+vdamp_status solve_common(vdamp_plan_h plan, hipStream_t stream, void* workspace,
+                          size_t workspace_bytes, const float* y, const uint8_t* mask,
+                          const float* p, const float* sigma2, const Resume& rs, int32_t iters,
+                          float* x_hat, float* trace, float* x_monitor) {
   vdamp_status s = check_common(plan, workspace, workspace_bytes, y, mask, iters, x_hat);
   if (s != VDAMP_OK) return s;
   if (!p || !sigma2) return fail(VDAMP_ERR_ARG, "p and sigma2 must be non-null");
+  if (rs.r && (!rs.theta || !rs.alpha))
+    return fail(VDAMP_ERR_ARG, "r_init needs theta_init and alpha_init");
+  if (!rs.r && (rs.theta || rs.theta2 || rs.alpha))
+    return fail(VDAMP_ERR_ARG, "theta_init, theta2_init and alpha_init are read only with r_init");
   GraphKey key;
   key.kind = 0; key.ws = workspace; key.y = y; key.mask = mask; key.p = p; key.sig = sigma2;
   key.x = x_hat; key.trace = trace; key.iters = iters; key.stream = stream;
+  key.r_init = rs.r; key.th_init = rs.theta; key.th2_init = rs.theta2; key.al_init = rs.alpha;
+  key.mon = x_monitor;
   s = run_maybe_graph(plan, stream, key, [&](bool timing) {
     return enqueue_vdamp(plan, stream, workspace, reinterpret_cast<const float2*>(y), mask, p,
-                         sigma2, iters, reinterpret_cast<float2*>(x_hat), trace, timing);
+                         sigma2, iters, reinterpret_cast<float2*>(x_hat), trace, timing, rs,
+                         reinterpret_cast<float2*>(x_monitor));
   });
   if (s != VDAMP_OK) return s;
   if (plan->flags & VDAMP_FLAG_CHECK_FINITE) {
@@ -508,26 +554,54 @@ vdamp_status vdamp_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
     const Ws w = layout(plan, workspace);
     HIP_TRY(hipMemcpyAsync(&bad, w.bad, sizeof(int), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    if (bad) return fail(VDAMP_ERR_NONFINITE, "p outside (0, 1] on the mask or non-finite y");
+    if (bad)
+      return fail(VDAMP_ERR_NONFINITE,
+                  "p outside (0, 1] on the mask, non-finite y, or an imported theta/alpha out of range");
   }
   plan->state_ws = workspace;
-  plan->has_state = iters > 0;
+  plan->has_state = iters > 0 || rs.r;
   return VDAMP_OK;
+}
+}  // namespace
+
+vdamp_status vdamp_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
+                         size_t workspace_bytes, const float* y, const uint8_t* mask,
+                         const float* p, const float* sigma2, int32_t iters, float* x_hat,
+                         float* trace) {
+  g_err.clear();
+  return solve_common(plan, stream, workspace, workspace_bytes, y, mask, p, sigma2, Resume(), iters,
+                      x_hat, trace, nullptr);
+}
+
+vdamp_status vdamp_solve_resume(vdamp_plan_h plan, hipStream_t stream, void* workspace,
+                                size_t workspace_bytes, const float* y, const uint8_t* mask,
+                                const float* p, const float* sigma2, const float* r_init,
+                                const float* theta_init, const float* theta2_init,
+                                const float* alpha_init, int32_t iters, float* x_hat, float* trace,
+                                float* x_monitor) {
+  g_err.clear();
+  Resume rs;
+  rs.r = reinterpret_cast<const float2*>(r_init);
+  rs.theta = theta_init;
+  rs.theta2 = theta2_init;
+  rs.alpha = alpha_init;
+  return solve_common(plan, stream, workspace, workspace_bytes, y, mask, p, sigma2, rs, iters, x_hat,
+                      trace, x_monitor);
 }
 
 vdamp_status fista_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
                          size_t workspace_bytes, const float* y, const uint8_t* mask,
-                         const float* lambda, int32_t iters, float* x_hat) {
+                         const float* lambda, int32_t iters, float* x_hat, float* objective) {
   g_err.clear();
   vdamp_status s = check_common(plan, workspace, workspace_bytes, y, mask, iters, x_hat);
   if (s != VDAMP_OK) return s;
   if (!lambda) return fail(VDAMP_ERR_ARG, "lambda must be non-null");
   GraphKey key;
   key.kind = 1; key.ws = workspace; key.y = y; key.mask = mask; key.lam = lambda;
-  key.x = x_hat; key.iters = iters; key.stream = stream;
+  key.x = x_hat; key.iters = iters; key.stream = stream; key.obj = objective;
   s = run_maybe_graph(plan, stream, key, [&](bool timing) {
     return enqueue_fista(plan, stream, workspace, reinterpret_cast<const float2*>(y), mask,
-                         lambda, iters, reinterpret_cast<float2*>(x_hat), timing);
+                         lambda, iters, reinterpret_cast<float2*>(x_hat), objective, timing);
   });
   if (s != VDAMP_OK) return s;
   plan->has_state = false;
@@ -535,7 +609,7 @@ vdamp_status fista_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
 }
 
 vdamp_status vdamp_state_export(vdamp_plan_h plan, hipStream_t stream, const void* workspace,
-                                float* r, float* theta, float* alpha, float* tau) {
+                                float* r, float* theta, float* theta2, float* alpha, float* tau) {
   g_err.clear();
   if (!plan || !workspace) return fail(VDAMP_ERR_ARG, "plan and workspace must be non-null");
   if (!plan->has_state || plan->state_ws != workspace)
@@ -544,9 +618,9 @@ vdamp_status vdamp_state_export(vdamp_plan_h plan, hipStream_t stream, const voi
   if (r)
     HIP_TRY(hipMemcpyAsync(r, w.r, sizeof(float2) * (size_t)plan->ntot, hipMemcpyDeviceToDevice, stream));
   const int nb = plan->nbands;
-  float* outs[3] = {theta, alpha, tau};
-  float* srcs[3] = {w.theta, w.alpha, w.tau};
-  for (int i = 0; i < 3; ++i) {
+  float* outs[4] = {theta, theta2, alpha, tau};
+  float* srcs[4] = {w.theta, w.thr2, w.alpha, w.tau};
+  for (int i = 0; i < 4; ++i) {
     if (!outs[i]) continue;
     HIP_TRY(hipMemcpy2DAsync(outs[i], sizeof(float) * nb, srcs[i], sizeof(float) * kMaxBands,
                              sizeof(float) * nb, plan->B, hipMemcpyDeviceToDevice, stream));

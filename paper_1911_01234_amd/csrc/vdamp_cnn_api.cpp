@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -68,6 +69,7 @@ struct vdamp_cnn_t {
   u16* d_wf[kLayers + 1] = {};
   u16* d_wd[kLayers + 1] = {};
   int step = 0;
+  unsigned long long id = 0;  // unique per denoiser object, never reused (graph cache key)
 };
 
 namespace {
@@ -393,6 +395,8 @@ vdamp_status vdamp_cnn_create(vdamp_cnn_h* cnn, int32_t nbands) {
   if (nbands < 4 || nbands > 13 || (nbands - 1) % 3)
     return fail(VDAMP_ERR_ARG, "nbands must be 1 + 3 levels with levels in 1..4");
   vdamp_cnn_t* C = new vdamp_cnn_t();
+  static std::atomic<unsigned long long> next_id{1};
+  C->id = next_id.fetch_add(1);
   C->nb = nbands;
   long long o = 0;
   for (int l = 1; l <= kLayers; ++l) {
@@ -530,9 +534,12 @@ vdamp_status vdamp_solve_learned(vdamp_plan_h plan, vdamp_cnn_h cnn, hipStream_t
   key.sig = sigma2;
   key.x = x_hat;
   key.trace = trace;
-  key.aux = cnn;
+  // the captured graph holds the denoiser's device buffers: key on its unique id, not on
+  // the handle's address (which a destroyed and re-created denoiser may reuse)
+  key.aux_id = cnn->id;
   key.aux_ws = cnn_workspace;
-  key.seed = seed ^ ((unsigned long long)judge << 63);
+  key.seed = seed;
+  key.judge = judge;
   key.iters = iters;
   key.extra = learned_from;
   key.stream = stream;

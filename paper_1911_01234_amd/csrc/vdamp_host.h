@@ -20,23 +20,29 @@ struct GraphKey {
   int kind = -1;
   const void *ws = nullptr, *y = nullptr, *mask = nullptr, *p = nullptr, *sig = nullptr,
              *lam = nullptr, *x = nullptr, *trace = nullptr;
-  const void* aux = nullptr;   // learned solve: the denoiser and its workspace
-  const void* aux_ws = nullptr;
+  const void* aux_ws = nullptr;  // learned solve: the denoiser's workspace
+  unsigned long long aux_id = 0; // learned solve: the denoiser's unique id (never reused)
+  int judge = -1;
+  // resumed solve: the imported state; monitor output; FISTA objective
+  const void *r_init = nullptr, *th_init = nullptr, *th2_init = nullptr, *al_init = nullptr,
+             *mon = nullptr, *obj = nullptr;
   unsigned long long seed = 0;
   int extra = 0;
   int iters = -1;
   hipStream_t stream = nullptr;
   bool operator==(const GraphKey& o) const {
     return kind == o.kind && ws == o.ws && y == o.y && mask == o.mask && p == o.p &&
-           sig == o.sig && lam == o.lam && x == o.x && trace == o.trace && aux == o.aux &&
-           aux_ws == o.aux_ws && seed == o.seed && extra == o.extra && iters == o.iters && stream == o.stream;
+           sig == o.sig && lam == o.lam && x == o.x && trace == o.trace && aux_ws == o.aux_ws &&
+           aux_id == o.aux_id && judge == o.judge && r_init == o.r_init && th_init == o.th_init &&
+           th2_init == o.th2_init && al_init == o.al_init && mon == o.mon && obj == o.obj &&
+           seed == o.seed && extra == o.extra && iters == o.iters && stream == o.stream;
   }
 };
 
 struct Ws {
   float* wgt;
   float2 *r, *X, *r2;
-  float *theta, *thr2, *alpha, *tau, *taup;
+  float *theta, *thr2, *alpha, *tau, *taup, *rpart;
   int* bad;
   float* big;  // full-sort scratch of the bands larger than the LDS search (or null)
 };
@@ -92,7 +98,7 @@ struct vdamp_plan_t {
   size_t lds_rows = 0, lds_cols = 0;
   // workspace layout (byte offsets)
   size_t o_wgt = 0, o_r = 0, o_X = 0, o_r2 = 0, o_theta = 0, o_thr2 = 0, o_alpha = 0, o_tau = 0,
-         o_taup = 0, o_bad = 0, o_big = 0, ws_bytes = 0;
+         o_taup = 0, o_rpart = 0, o_bad = 0, o_big = 0, ws_bytes = 0;
   // last solve
   const void* state_ws = nullptr;
   bool has_state = false;
@@ -124,6 +130,10 @@ hipError_t launch_sure(const KArgs& a, int cls, float* scratch, hipStream_t st);
 hipError_t launch_prep(const uint8_t* mask, const float* p, const float2* y, float* wgt,
                        long long n, int check, int* bad, hipStream_t st);
 hipError_t launch_zero(float2* x, long long n, hipStream_t st);
+hipError_t launch_import_state(const float* th, const float* th2, const float* al, int batch,
+                               int nb, float* theta, float* thr2, float* alpha, int check, int* bad,
+                               hipStream_t st);
+hipError_t launch_fista_obj(const KArgs& a, float* obj, hipStream_t st);
 hipError_t launch_tune_fill(float2* r, float2* X, float2* y, float* wgt, long long n, hipStream_t st);
 hipError_t launch_fill_f32(float* x, long long n, float v, hipStream_t st);
 hipError_t set_lds_limits_passes(size_t rows, size_t cols);

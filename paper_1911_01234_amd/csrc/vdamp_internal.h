@@ -55,7 +55,8 @@ enum ColMode : int {
   CM_OUTPUT = 2,       // (1 - m) X + m y (line 10)
   CM_ZEROFILL = 3,     // y (iters = 0)
   CM_FISTA = 4,        // m (y - X)
-  CM_FISTA_FIRST = 5   // m y
+  CM_FISTA_FIRST = 5,  // m y
+  CM_FISTA_OBJ = 6     // forward column FFT only: sum over Omega of |y - X|^2 per strip
 };
 
 // Modes of the row-analysis pass (row IFFT, then Psi on row strips).
@@ -95,7 +96,8 @@ struct KArgs {
   float* trace;              // nullable [iters][B][nb][3]
   float* smin;               // nullable [B][kMaxBands]: minimum SURE of soft thresholding
   const int* sel;            // [B][kMaxBands]: 1 where the learned denoiser is used
-  float* jpart;              // [2][total row strips][kMaxBands] learned-denoiser partial sums
+  float* jpart;              // [2][total row strips][kMaxBands] learned-denoiser partial sums;
+                             // FISTA with an objective trace: [total row strips] sums of |w|
   unsigned long long seed;   // probe generator seed
   int iter;
   float beta;                // FISTA momentum factor for this iteration

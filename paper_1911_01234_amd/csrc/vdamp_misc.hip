@@ -166,6 +166,54 @@ __global__ void k_judge(KArgs a, int nrowstrips, int always, int* __restrict__ s
   if (use) a.alpha[sl * kMaxBands + b] = (float)al;
 }
 
+// State import of a resumed solve: per slice and band the threshold theta, its key
+// (the FP32 squared magnitude thresholding compares |r|^2 against; fl(theta * theta)
+// when th2 is null) and alpha, from dense [B][nb] arrays into the plan's [B][kMaxBands]
+// slots.  With check != 0, bad[0] |= 1 for a non-finite or negative theta or an alpha
+// outside [0, 1) (line 8 divides by 1 - alpha).
+__global__ void k_import_state(const float* __restrict__ th, const float* __restrict__ th2,
+                               const float* __restrict__ al, int batch, int nb,
+                               float* __restrict__ theta, float* __restrict__ thr2,
+                               float* __restrict__ alpha, int check, int* bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= batch * nb) return;
+  const int sl = i / nb, b = i - sl * nb;
+  const float t = th[i], a = al[i];
+  const float t2 = th2 ? th2[i] : __fmul_rn(t, t);
+  if (check && !(t >= 0.f && isfinite(t) && t2 >= 0.f && isfinite(t2) && a >= 0.f && a < 1.f))
+    atomicOr(bad, 1);
+  theta[sl * kMaxBands + b] = t;
+  thr2[sl * kMaxBands + b] = t2;
+  alpha[sl * kMaxBands + b] = a;
+}
+
+hipError_t launch_import_state(const float* th, const float* th2, const float* al, int batch,
+                               int nb, float* theta, float* thr2, float* alpha, int check, int* bad,
+                               hipStream_t st) {
+  const int n = batch * nb;
+  hipLaunchKernelGGL(k_import_state, dim3((n + 255) / 256), dim3(256), 0, st, th, th2, al, batch, nb,
+                     theta, thr2, alpha, check, bad);
+  return hipGetLastError();
+}
+
+// FISTA objective of eq. 2 at w_k, per slice: 1/2 ||y - M F Psi^H w_k||^2 + lambda ||w_k||_1,
+// from the column strips' residual sums (slot 0 of tau_part) and the row strips' sums of
+// |w| (jpart), added in a fixed order in FP64.
+__global__ void k_fista_obj(KArgs a, float* __restrict__ obj) {
+  const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl >= a.batch) return;
+  const SliceDev S = a.slices[sl];
+  double res = 0.0, l1 = 0.0;
+  for (int i = 0; i < S.nx / kColW; ++i) res += (double)a.tau_part[(long long)(S.colstrip0 + i) * kMaxBands];
+  for (int i = 0; i < (S.ny >> a.levels); ++i) l1 += (double)a.jpart[S.rowstrip0 + i];
+  obj[(long long)a.iter * a.batch + sl] = (float)(0.5 * res + (double)a.lambda[sl] * l1);
+}
+
+hipError_t launch_fista_obj(const KArgs& a, float* obj, hipStream_t st) {
+  hipLaunchKernelGGL(k_fista_obj, dim3((a.batch + 63) / 64), dim3(64), 0, st, a, obj);
+  return hipGetLastError();
+}
+
 hipError_t launch_scale(const SliceDev* slices, int batch, const float2* y, const float* wgt,
                         float* s0, hipStream_t st) {
   hipLaunchKernelGGL(k_scale, dim3(batch), dim3(kThreads), 0, st, slices, y, wgt, s0);

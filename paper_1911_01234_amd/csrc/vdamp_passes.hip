@@ -192,6 +192,7 @@ __global__ void __launch_bounds__(kThreads) k_cols(KArgs a) {
   float Q0[8], Q1[8];
 #pragma unroll
   for (int t = 0; t < 8; ++t) { Q0[t] = 0.f; Q1[t] = 0.f; }
+  float rsum = 0.f;  // CM_FISTA_OBJ: sum over Omega of |y - X|^2
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int p = tid + u * kThreads;
@@ -222,6 +223,12 @@ __global__ void __launch_bounds__(kThreads) k_cols(KArgs a) {
           o = (w > 0.f) ? yy : X;
         } else if (mode == CM_ZEROFILL) {
           o = yy;
+        } else if (mode == CM_FISTA_OBJ) {
+          o = make_float2(0.f, 0.f);
+          if (w > 0.f) {
+            const float2 z = csub(yy, X);
+            rsum = fmaf(z.x, z.x, fmaf(z.y, z.y, rsum));
+          }
         } else {  // FISTA: m (y - X)
           o = (w > 0.f) ? csub(yy, X) : make_float2(0.f, 0.f);
         }
@@ -251,6 +258,18 @@ __global__ void __launch_bounds__(kThreads) k_cols(KArgs a) {
       const float part = wave_sum(q0 * xtab[tx * nx + kx] + q1 * xtab[tx * nx + kx + 1]);
       if (lane == 0) red[wid][b] = part;
     }
+  }
+  if (mode == CM_FISTA_OBJ) {  // the residual's partial sum is all this mode writes
+    const float part = wave_sum(rsum);
+    if ((tid & 63) == 0) red[tid >> 6][0] = part;
+    __syncthreads();
+    if (tid == 0) {
+      float acc = 0.f;
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w) acc += red[w][0];
+      a.tau_part[(S.colstrip0 + item.y) * kMaxBands] = acc;
+    }
+    return;
   }
   __syncthreads();
   if (vd && tid < a.nbands) {
@@ -358,6 +377,7 @@ __global__ void __launch_bounds__(cols4_threads(M)) k_cols4(KArgs a) {
   float QL[4], QH[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) { QL[t] = 0.f; QH[t] = 0.f; }
+  float rsum = 0.f;  // CM_FISTA_OBJ: sum over Omega of |y - X|^2
   float2 d[NI][16];
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
@@ -401,6 +421,12 @@ __global__ void __launch_bounds__(cols4_threads(M)) k_cols4(KArgs a) {
           o = (w > 0.f) ? yy : X;
         } else if (mode == CM_ZEROFILL) {
           o = yy;
+        } else if (mode == CM_FISTA_OBJ) {
+          o = make_float2(0.f, 0.f);
+          if (w > 0.f) {
+            const float2 z = csub(yy, X);
+            rsum = fmaf(z.x, z.x, fmaf(z.y, z.y, rsum));
+          }
         } else {  // FISTA: m (y - X)
           o = (w > 0.f) ? csub(yy, X) : make_float2(0.f, 0.f);
         }
@@ -432,6 +458,18 @@ __global__ void __launch_bounds__(cols4_threads(M)) k_cols4(KArgs a) {
       const float part = wave_sum(q0 * xtab[tx * nx + kx]);
       if (lane == 0) red[wid][b] = part;
     }
+  }
+  if (mode == CM_FISTA_OBJ) {  // the residual's partial sum is all this mode writes
+    const float part = wave_sum(rsum);
+    if ((tid & 63) == 0) red[tid >> 6][0] = part;
+    __syncthreads();
+    if (tid == 0) {
+      float acc = 0.f;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) acc += red[w][0];
+      a.tau_part[(S.colstrip0 + item.y) * kMaxBands] = acc;
+    }
+    return;
   }
   __syncthreads();  // tau partials visible; every forward read of tb done
   if (vd && tid < a.nbands) {
@@ -476,6 +514,7 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
   __shared__ float2 tw_s[kMaxN];
   __shared__ float th_s[kMaxBands], t2_s[kMaxBands], al_s[kMaxBands];
   __shared__ int sel_s[kMaxBands];
+  __shared__ float l1_s[NT / 64];
   const int2 item = a.work[blockIdx.x];
   const SliceDev S = a.slices[item.x];
   const int strip = item.y, s = a.levels, H = 1 << s, nx = S.nx, ny = S.ny;
@@ -579,6 +618,7 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
     RA_LOAD_R();
   }
 #undef RA_LOAD_R
+  float l1 = 0.f;
   if (mode == RA_FISTA || mode == RA_LEARNED) {  // the second iterate
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -618,8 +658,22 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
         }
       }
       *reinterpret_cast<float4*>(r + gi[u]) = pack4(o[0], o[1]);
-      if (mode == RA_FISTA || mode == RA_FISTA_FIRST)
+      if (mode == RA_FISTA || mode == RA_FISTA_FIRST) {
         *reinterpret_cast<float4*>(r2 + gi[u]) = pack4(w2[0], w2[1]);
+        if (a.jpart)
+          l1 += sqrtf(key_rn(w2[0])) + sqrtf(key_rn(w2[1]));
+      }
+    }
+  }
+  if ((mode == RA_FISTA || mode == RA_FISTA_FIRST) && a.jpart) {  // this strip's ||w||_1
+    const float part = wave_sum(l1);
+    if ((tid & 63) == 0) l1_s[tid >> 6] = part;
+    __syncthreads();
+    if (tid == 0) {
+      float acc = 0.f;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) acc += l1_s[w];
+      a.jpart[S.rowstrip0 + strip] = acc;
     }
   }
 }

@@ -2,7 +2,8 @@
 solve runs in the library's HIP kernels; torch supplies device memory and streams.
 
 The names follow the C ABI in ``include/vdamp.h``: ``vdamp_plan``, ``vdamp_solve``,
-``fista_solve``, ``vdamp_state_export``, ``vdamp_pass_times``, ``vdamp_wavelet``, the
+``vdamp_solve_resume``, ``fista_solve``, ``vdamp_state_export``, ``vdamp_pass_times``,
+``vdamp_wavelet``, the
 learned denoiser ``vdamp_cnn_*`` and ``vdamp_solve_learned``.
 """
 from __future__ import annotations
@@ -18,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libvdamp.so")
 
 VDAMP_OK = 0
 VDAMP_WAVELET_HAAR = 0
+VDAMP_FLAG_DETERMINISTIC = 1 << 0
 VDAMP_FLAG_CHECK_FINITE = 1 << 2
 VDAMP_FLAG_USE_GRAPH = 1 << 3
 VDAMP_FLAG_TIMING = 1 << 5
@@ -34,7 +36,7 @@ STATUS_NAMES = {0: "VDAMP_OK", 1: "VDAMP_ERR_ARG", 2: "VDAMP_ERR_SHAPE", 3: "VDA
                 4: "VDAMP_ERR_WORKSPACE", 5: "VDAMP_ERR_HIP", 6: "VDAMP_ERR_NONFINITE",
                 7: "VDAMP_ERR_STATE"}
 
-EXPORTED = ("vdamp_plan", "vdamp_plan_destroy", "vdamp_solve", "fista_solve",
+EXPORTED = ("vdamp_plan", "vdamp_plan_destroy", "vdamp_solve", "vdamp_solve_resume", "fista_solve",
             "vdamp_state_export", "vdamp_pass_times", "vdamp_status_string", "vdamp_last_error",
             "vdamp_cnn_create", "vdamp_cnn_destroy", "vdamp_cnn_param_count", "vdamp_cnn_set_params",
             "vdamp_cnn_get_params", "vdamp_cnn_workspace", "vdamp_cnn_forward", "vdamp_cnn_train_step",
@@ -74,9 +76,11 @@ def load_library() -> ctypes.CDLL:
     lib.vdamp_plan_destroy.restype = ctypes.c_int
     lib.vdamp_solve.argtypes = [vp, vp, vp, sz, vp, vp, vp, vp, i32, vp, vp]
     lib.vdamp_solve.restype = ctypes.c_int
-    lib.fista_solve.argtypes = [vp, vp, vp, sz, vp, vp, vp, i32, vp]
+    lib.vdamp_solve_resume.argtypes = [vp, vp, vp, sz, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp]
+    lib.vdamp_solve_resume.restype = ctypes.c_int
+    lib.fista_solve.argtypes = [vp, vp, vp, sz, vp, vp, vp, i32, vp, vp]
     lib.fista_solve.restype = ctypes.c_int
-    lib.vdamp_state_export.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.vdamp_state_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.vdamp_state_export.restype = ctypes.c_int
     lib.vdamp_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_int64), i32]
@@ -174,13 +178,23 @@ class Plan:
                                           _ptr(y), _ptr(mask), _ptr(p), _ptr(sigma2), int(iters),
                                           _ptr(x_hat), _ptr(trace)))
 
-    def fista_solve(self, ws, y, mask, lam, iters, x_hat, stream=None):
-        _check(load_library().fista_solve(self._h, _stream_handle(stream), _ptr(ws), ws.numel(),
-                                          _ptr(y), _ptr(mask), _ptr(lam), int(iters), _ptr(x_hat)))
+    def vdamp_solve_resume(self, ws, y, mask, p, sigma2, r_init, theta_init, theta2_init, alpha_init,
+                           iters, x_hat, trace=None, x_monitor=None, stream=None):
+        _check(load_library().vdamp_solve_resume(
+            self._h, _stream_handle(stream), _ptr(ws), ws.numel(), _ptr(y), _ptr(mask), _ptr(p),
+            _ptr(sigma2), _ptr(r_init), _ptr(theta_init), _ptr(theta2_init), _ptr(alpha_init),
+            int(iters), _ptr(x_hat), _ptr(trace), _ptr(x_monitor)))
 
-    def vdamp_state_export(self, ws, r=None, theta=None, alpha=None, tau=None, stream=None):
+    def fista_solve(self, ws, y, mask, lam, iters, x_hat, objective=None, stream=None):
+        _check(load_library().fista_solve(self._h, _stream_handle(stream), _ptr(ws), ws.numel(),
+                                          _ptr(y), _ptr(mask), _ptr(lam), int(iters), _ptr(x_hat),
+                                          _ptr(objective)))
+
+    def vdamp_state_export(self, ws, r=None, theta=None, alpha=None, tau=None, theta2=None,
+                           stream=None):
         _check(load_library().vdamp_state_export(self._h, _stream_handle(stream), _ptr(ws),
-                                                 _ptr(r), _ptr(theta), _ptr(alpha), _ptr(tau)))
+                                                 _ptr(r), _ptr(theta), _ptr(theta2), _ptr(alpha),
+                                                 _ptr(tau)))
 
     def vdamp_pass_times(self):
         n = len(PASS_NAMES)

@@ -15,6 +15,69 @@ def gpu_available() -> bool:
         return False
 
 
+def fp32_inputs(sl):
+    """The measurements exactly as the library reads them (y as complex64, p and sigma^2
+    as float32), upcast to FP64 for the oracle: rounding of the inputs is then not
+    booked as an error of the kernels."""
+    y = np.asarray(sl.y).astype(np.complex64).astype(np.complex128)
+    p = np.asarray(sl.p).astype(np.float32).astype(np.float64)
+    return y, sl.mask, p, float(np.float32(sl.sigma2))
+
+
+def fp32_state(r, theta, alpha):
+    """An oracle state (r_k, theta_k, alpha_k) rounded to the FP32 values the library
+    takes, upcast again for the oracle."""
+    return (np.asarray(r).astype(np.complex64).astype(np.complex128),
+            np.asarray(theta).astype(np.float32).astype(np.float64),
+            np.asarray(alpha).astype(np.float32).astype(np.float64))
+
+
+def run_resume(plan, slices, states, iters, want_state=True, x_monitor=False, stream=None):
+    """vdamp_solve_resume on every slice of the plan: states maps slice index b to an
+    FP32 state (r_k [ny][nx], theta_k [nb], alpha_k [nb]); slices not in states start
+    from r = 0, theta = 0, alpha = 0 (line 8 then gives r_tilde = 0)."""
+    import torch
+    from paper_1911_01234_amd import vdamp as V
+    ws = plan.workspace()
+    y, mask, p, sigma2 = V.to_device(plan, slices)
+    r0 = [np.zeros((plan.ny[b], plan.nx[b]), np.complex64) for b in range(plan.batch)]
+    th0 = np.zeros((plan.batch, plan.nbands), np.float32)
+    al0 = np.zeros((plan.batch, plan.nbands), np.float32)
+    for b, (r, th, al) in states.items():
+        r0[b] = np.asarray(r).astype(np.complex64)
+        th0[b] = np.asarray(th, dtype=np.float32)
+        al0[b] = np.asarray(al, dtype=np.float32)
+    r_in = torch.from_numpy(plan.pack(r0, np.complex64)).cuda()
+    th_in = torch.from_numpy(th0.ravel()).cuda()
+    al_in = torch.from_numpy(al0.ravel()).cuda()
+    x_hat = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+    trace = torch.empty(max(iters, 1) * plan.batch * plan.nbands * 3, dtype=torch.float32, device="cuda")
+    mon = (torch.empty(max(iters, 1) * plan.ntot, dtype=torch.complex64, device="cuda")
+           if x_monitor else None)
+    plan.vdamp_solve_resume(ws, y, mask, p, sigma2, r_in, th_in, None, al_in, iters, x_hat, trace,
+                            mon, stream=stream)
+    out = {}
+    if want_state:
+        r = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+        th = torch.empty(plan.batch * plan.nbands, dtype=torch.float32, device="cuda")
+        al = torch.empty_like(th)
+        ta = torch.empty_like(th)
+        plan.vdamp_state_export(ws, r, th, al, ta, stream=stream)
+        torch.cuda.synchronize()
+        out["r"] = plan.unpack(r.cpu().numpy())
+        out["theta"] = th.cpu().numpy().reshape(plan.batch, plan.nbands)
+        out["alpha"] = al.cpu().numpy().reshape(plan.batch, plan.nbands)
+        out["tau"] = ta.cpu().numpy().reshape(plan.batch, plan.nbands)
+    torch.cuda.synchronize()
+    out["x_hat"] = plan.unpack(x_hat.cpu().numpy())
+    out["trace"] = trace.cpu().numpy()[: iters * plan.batch * plan.nbands * 3].reshape(
+        iters, plan.batch, plan.nbands, 3)
+    if x_monitor:
+        m = mon.cpu().numpy()
+        out["monitor"] = [plan.unpack(m[k * plan.ntot:(k + 1) * plan.ntot]) for k in range(iters)]
+    return out
+
+
 def run_vdamp(slices, s, iters, flags=0, want_state=False, plan=None, stream=None):
     import torch
     from paper_1911_01234_amd import vdamp as V
@@ -32,10 +95,12 @@ def run_vdamp(slices, s, iters, flags=0, want_state=False, plan=None, stream=Non
         th = torch.empty(plan.batch * plan.nbands, dtype=torch.float32, device="cuda")
         al = torch.empty_like(th)
         ta = torch.empty_like(th)
-        plan.vdamp_state_export(ws, r, th, al, ta, stream=stream)
+        t2 = torch.empty_like(th)
+        plan.vdamp_state_export(ws, r, th, al, ta, theta2=t2, stream=stream)
         torch.cuda.synchronize()
         out["r"] = plan.unpack(r.cpu().numpy())
         out["theta"] = th.cpu().numpy().reshape(plan.batch, plan.nbands)
+        out["theta2"] = t2.cpu().numpy().reshape(plan.batch, plan.nbands)
         out["alpha"] = al.cpu().numpy().reshape(plan.batch, plan.nbands)
         out["tau"] = ta.cpu().numpy().reshape(plan.batch, plan.nbands)
     torch.cuda.synchronize()
@@ -46,7 +111,7 @@ def run_vdamp(slices, s, iters, flags=0, want_state=False, plan=None, stream=Non
     return out
 
 
-def run_fista(slices, s, lams, iters):
+def run_fista(slices, s, lams, iters, objective=False):
     import torch
     from paper_1911_01234_amd import vdamp as V
     plan = V.Plan([sl.y.shape[0] for sl in slices], [sl.y.shape[1] for sl in slices], s)
@@ -54,9 +119,13 @@ def run_fista(slices, s, lams, iters):
     y, mask, _, _ = V.to_device(plan, slices)
     lam = torch.tensor(lams, dtype=torch.float32, device="cuda")
     x_hat = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
-    plan.fista_solve(ws, y, mask, lam, iters, x_hat)
+    obj = torch.empty(max(iters, 1) * plan.batch, dtype=torch.float32, device="cuda") if objective else None
+    plan.fista_solve(ws, y, mask, lam, iters, x_hat, objective=obj)
     torch.cuda.synchronize()
-    return plan.unpack(x_hat.cpu().numpy())
+    xs = plan.unpack(x_hat.cpu().numpy())
+    if objective:
+        return xs, obj.cpu().numpy()[: iters * plan.batch].reshape(iters, plan.batch)
+    return xs
 
 
 def rel_l2(a, b):

@@ -72,9 +72,12 @@ def test_solve_rejects_null_plan_and_workspace():
     lib = V.load_library()
     st = lib.vdamp_solve(None, None, None, 0, None, None, None, None, 1, None, None)
     assert st == 1
-    st = lib.fista_solve(None, None, None, 0, None, None, None, 1, None)
+    st = lib.fista_solve(None, None, None, 0, None, None, None, 1, None, None)
     assert st == 1
-    st = lib.vdamp_state_export(None, None, None, None, None, None, None)
+    st = lib.vdamp_solve_resume(None, None, None, 0, None, None, None, None, None, None, None, None,
+                                1, None, None, None)
+    assert st == 1
+    st = lib.vdamp_state_export(None, None, None, None, None, None, None, None)
     assert st == 1
     assert lib.vdamp_plan_destroy(None) == 1
 
@@ -104,7 +107,8 @@ def test_plan_accepts_512_slices():
 def test_plan_accepts_every_documented_flag():
     """All VDAMP_FLAG_* bits pass the host checks together (the autotune flag included);
     an undocumented bit is rejected before anything touches the device."""
-    flags = V.VDAMP_FLAG_USE_GRAPH | V.VDAMP_FLAG_CHECK_FINITE | V.VDAMP_FLAG_TIMING | V.VDAMP_FLAG_AUTOTUNE
+    flags = (V.VDAMP_FLAG_DETERMINISTIC | V.VDAMP_FLAG_USE_GRAPH | V.VDAMP_FLAG_CHECK_FINITE
+             | V.VDAMP_FLAG_TIMING | V.VDAMP_FLAG_AUTOTUNE)
     lib = V.load_library()
     h = ctypes.c_void_p()
     wsb = ctypes.c_size_t()

@@ -96,6 +96,27 @@ def test_adam_first_step_closed_form():
     assert np.allclose(p["w"], np.array([1.0, -2.0, 0.5]) - 0.1 * np.sign(g["w"]))
 
 
+def test_adam_second_step_hand_worked():
+    """Two Adam steps on one parameter (p = 1, gradients 0.3 then -0.1, lr 0.1,
+    beta1 = 0.9, beta2 = 0.999, eps = 0), worked by hand in exact fractions:
+      step 1: m = 3/100, v = 9/100000; m_hat = 3/10, v_hat = 9/100 -> p = 1 - 0.1 = 9/10
+      step 2: m = 0.9 (3/100) - 1/100 = 17/1000, v = 0.999 (9/100000) + 1/100000
+              = 9991/100000000; m_hat = (17/1000) / (19/100) = 17/190,
+              v_hat = (9991/100000000) / (1999/1000000) = 9991/199900
+              -> p = 9/10 - 0.1 (17/190) / sqrt(9991/199900) = 0.8599781428045573.
+    At step 1 bias correction makes the update lr sign(g) whatever the betas are; step 2
+    separates them (swapping the roles of beta1 and beta2 gives 0.85435...)."""
+    p = {"w": np.array([1.0])}
+    m = {"w": np.zeros(1)}
+    v = {"w": np.zeros(1)}
+    cr.adam_step(p, {"w": np.array([0.3])}, m, v, 1, lr=0.1, eps=0.0)
+    assert abs(p["w"][0] - 0.9) < 1e-15
+    cr.adam_step(p, {"w": np.array([-0.1])}, m, v, 2, lr=0.1, eps=0.0)
+    assert abs(m["w"][0] - 17 / 1000) < 1e-16
+    assert abs(v["w"][0] - 9991 / 100000000) < 1e-18
+    assert abs(p["w"][0] - 0.8599781428045573) < 1e-14
+
+
 def test_rademacher_divergence_estimates_wirtinger_mean():
     """E Re(conj(b) (J b)) over b in {+-1 +- i}/sqrt2 equals the mean Wirtinger derivative
     1/2 (du/dx + dv/dy) of the map, computed here from the brute-force Jacobian."""

@@ -174,6 +174,36 @@ def test_identity_network_reduces_to_plain_vdamp():
     assert np.abs(got["x_hat"] - ref["x_hat"]).max() < 1e-12
 
 
+def test_input_scale_hand_example():
+    """s0^2 = (1/N) sum_j (m_j / p_j) |y_j|^2, worked by hand on a 2 x 2 case: the three
+    sampled entries give (1/0.5) 2 + (1/0.25) 4 + (1/1) 9 = 29, the unsampled y = 5 is
+    ignored, so s0 = sqrt(29/4); an all-zero y gives s0 = 1."""
+    y = np.array([[1 + 1j, 5.0], [2.0, 3j]])
+    mask = np.array([[1, 0], [1, 1]], dtype=np.uint8)
+    p = np.array([[0.5, 0.3], [0.25, 1.0]])
+    assert abs(lr.input_scale(y, mask, p) - np.sqrt(29.0 / 4.0)) < 1e-15
+    assert lr.input_scale(np.zeros_like(y), mask, p) == 1.0
+
+
+def test_input_scale_is_unbiased_for_energy_plus_noise():
+    """E over (Omega, eps) of s0^2 = mean |x0|^2 + sigma^2 (E[m/p] = 1 and the unitary F
+    keeps the energy), by Monte Carlo over fresh masks and noise for a fixed image."""
+    rng = np.random.default_rng(21)
+    n = 32
+    x0 = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    p = synth.density(n, n, 3.0, 4.0, 4)
+    X = o.fft2u(x0)
+    sigma2 = 0.3
+    vals = []
+    for _ in range(3000):
+        mask = (rng.random((n, n)) < p).astype(np.uint8)
+        eps = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) * np.sqrt(sigma2 / 2)
+        vals.append(lr.input_scale(mask * (X + eps), mask, p) ** 2)
+    vals = np.array(vals)
+    truth = np.mean(np.abs(x0) ** 2) + sigma2
+    assert abs(vals.mean() - truth) < 4 * vals.std() / np.sqrt(vals.size)
+
+
 def test_input_scale_estimates_image_energy():
     sl = synth.workload_single64()[0][0]
     s0 = lr.input_scale(sl.y, sl.mask, sl.p)

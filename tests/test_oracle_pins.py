@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import vdamp_ref as o
+from paper_1911_01234_amd import synth
 
 RNG = np.random.default_rng(12345)
 
@@ -389,3 +390,23 @@ def test_fista_reaches_fixed_point_and_lowers_objective():
     for _ in range(5):
         dw = 1e-4 * crandn(ny, nx, rng=rng)
         assert o.fista_objective(w + dw, y, mask, lam, s) >= f0 - 1e-12
+
+
+def test_resume_continues_the_iteration_exactly():
+    """The state between iterations of Algorithm 1 is (r_k, theta_k, alpha_k): lines 6-8
+    rebuild r_tilde_{k+1} from it and lines 3-5 need nothing else.  Resuming the oracle
+    from a recorded state therefore reproduces the rest of the uninterrupted run bit for
+    bit, and a resume with no further iteration returns line 10 at that state."""
+    sl = synth.workload_single64()[0][0]
+    K, k = 9, 4
+    full = o.vdamp(sl.y, sl.mask, sl.p, sl.sigma2, 3, K, record=True)
+    rest = o.vdamp_resume(sl.y, sl.mask, sl.p, sl.sigma2, 3, full["r"][k], full["theta"][k],
+                          full["alpha"][k], K - k - 1, record=True)
+    assert np.array_equal(rest["x_hat"], full["x_hat"])
+    for j in range(K - k - 1):
+        assert np.array_equal(rest["r"][j], full["r"][k + 1 + j])
+        assert np.array_equal(rest["theta"][j], full["theta"][k + 1 + j])
+        assert np.array_equal(rest["alpha"][j], full["alpha"][k + 1 + j])
+    last = o.vdamp_resume(sl.y, sl.mask, sl.p, sl.sigma2, 3, full["r"][-1], full["theta"][-1],
+                          full["alpha"][-1], 0)
+    assert np.array_equal(last["x_hat"], full["x_hat"])

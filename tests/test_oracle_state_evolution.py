@@ -17,11 +17,17 @@ def _run(R, iters):
     return sl, s, out
 
 
-@pytest.mark.parametrize("R", [4.0, 8.0])
+@pytest.mark.parametrize("R", [4.0, 6.0, 8.0])
 def test_colored_state_evolution(R):
     """r_k = w0 + CN(0, Sigma_k^2) with Sigma diagonal, constant per subband (eqs. 5-6),
     and tau_k tracks that variance: |10 log10(N_b tau_b) - 10 log10 ||r_b - w0_b||^2|
-    stays small for k = 0..20."""
+    stays small for k = 0..20.  Under the model ||r_b - w0_b||^2 / tau_b is a sum of N_b
+    unit-mean exponentials, whose relative standard deviation is 1/sqrt(N_b), i.e.
+    (10/ln 10)/sqrt(N_b) dB; the bound for bands of N_b >= 1024 coefficients is four of
+    those (0.54 dB at 1024, 0.27 dB at 4096, 0.14 dB at 16384), and 1.5 dB for the
+    smaller, signal-dominated bands.  The measured deviations scale as 1/sqrt(N_b)
+    (about 0.5, 0.17 and 0.07 dB at the three sizes), the signature of that sampling
+    spread rather than of a bias."""
     sl, s, out = _run(R, 21)
     ny, nx = sl.y.shape
     w0 = o.haar_analysis(sl.x0, s)
@@ -30,7 +36,7 @@ def test_colored_state_evolution(R):
     for k, r in enumerate(out["r"]):
         err = np.array([np.sum(np.abs(r[rs, cs] - w0[rs, cs]) ** 2) for (rs, cs, _, _) in bl])
         dev = np.abs(10 * np.log10(Nb * out["tau"][k]) - 10 * np.log10(err))
-        tol = np.where(Nb >= 1024, 0.75, 1.5)
+        tol = np.where(Nb >= 1024, 4.0 * (10.0 / np.log(10.0)) / np.sqrt(Nb), 1.5)
         assert (dev <= tol).all(), (k, dev)
 
 
