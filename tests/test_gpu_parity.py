@@ -7,15 +7,20 @@ Gates (relative L2 in FP32 against FP64):
 * one step, at every iteration k of the oracle's trajectory: the library resumes from the
   oracle's (r_k, theta_k, alpha_k) rounded to FP32 (vdamp_solve_resume) and its r_{k+1}
   must match the oracle's step from the same rounded state to <= 1e-5, tau_{k+1} to
-  <= 1e-5, and, where both pick the same candidate, theta and alpha to <= 1e-5 (theta
-  relative to the band's RMS magnitude) and the line-10 output x_hat to <= 1e-5.  Where
-  the two pick different candidates (a SURE near tie decided differently in FP32 and
-  FP64, after which both results are valid) the library's threshold must be SURE-optimal
-  up to the near-tie margin on its own r_{k+1} (gpu_helpers.theta_accepted);
-* free-running: r_k to <= 1e-5, alpha to <= 1e-5 and tau to <= 1e-4 at every iterate
-  until the first near-tie flip (tau is quadratic in the residual y - Phi Psi^H r_tilde,
-  a difference of nearly equal terms, so along a trajectory it amplifies iterate
-  differences), final NMSE within 0.05 dB when no flip occurred;
+  <= 1e-5, and, where both pick the same candidate, theta and alpha to the tolerances
+  the iterate's implies (theta_alpha_tols) and the line-10 output x_hat to <= 1e-5.
+  Where the two pick different candidates (a SURE near tie decided differently in FP32
+  and FP64, after which both results are valid) the library's threshold must be
+  SURE-optimal up to the near-tie margin on its own r_{k+1} (gpu_helpers.theta_accepted);
+* free-running: r_k to <= 1e-5 and tau to <= 1e-4 at every iterate until the first
+  near-tie flip and within the FP32 horizon: the iteration amplifies perturbations, and
+  the oracle itself with only its FFTs evaluated in FP32 leaves the FP64 trajectory by
+  more than 5e-6 after some iterations (fp32_horizon); beyond that iteration no FP32
+  implementation can be held to 1e-5 and the one-step gate covers it (tau is quadratic
+  in the residual y - Phi Psi^H r_tilde, a difference of nearly equal terms, so along a
+  trajectory it amplifies iterate differences); at every iterate the library's theta
+  must be SURE-optimal and its alpha line 7's value at that theta, on its own iterate;
+  final NMSE within 0.05 dB when no flip occurred;
 * after a flip the free-running runs are different valid trajectories; the one-step gate
   covers every iteration regardless, and the final NMSE must lie within
   max(0.05 dB, 4 sigma) of the mean of oracle runs on inputs perturbed by 3e-7 relative
@@ -27,8 +32,8 @@ import pytest
 from oracle import vdamp_ref as o
 from paper_1911_01234_amd import synth
 
-from gpu_helpers import (fp32_inputs, fp32_state, rel_l2, run_fista, run_resume, run_vdamp,
-                         snap_theta, theta_accepted)
+from gpu_helpers import (alpha_at_key, fp32_inputs, fp32_state, rel_l2, run_fista, run_resume,
+                         run_vdamp, snap_theta, theta_accepted)
 
 pytestmark = pytest.mark.gpu
 
@@ -41,6 +46,51 @@ TOL_NMSE_DB = 0.05
 
 def _bands(sl, s):
     return o.bands(sl.y.shape[0], sl.y.shape[1], s)
+
+
+def theta_alpha_tols(r_band, theta, alpha):
+    """Tolerances of theta and alpha implied by the iterate's: an iterate within
+    TOL_ITER of the reference (relative to the band's RMS magnitude) moves the order
+    statistic theta by at most TOL_ITER RMS_b, and line 7's alpha =
+    ((N_b - m) - (theta/2) R_m) / N_b moves by at most (1 - alpha) times theta's relative
+    change, plus 1e-5 for the rest of its arithmetic.  In signal-dominated bands
+    (theta << RMS_b) alpha is therefore more sensitive than the iterate."""
+    rms = float(np.sqrt(np.mean(np.abs(r_band) ** 2)))
+    th_tol = TOL_ITER * max(rms, 1e-30)
+    al_tol = TOL_ALPHA + (1.0 - alpha) * th_tol / theta if theta > 0 else TOL_ALPHA
+    return th_tol, al_tol
+
+
+def fp32_horizon(sl, s, K, ref):
+    """How long an FP32 evaluation can follow the FP64 trajectory at all: the oracle's
+    iteration with only its two FFTs evaluated in FP32 (scipy's complex64 FFT, whose
+    one-step error, 3e-7 relative, is that of the library's kernels) against the FP64
+    trajectory.  Returns the first iteration at which it is more than TOL_ITER / 2 away
+    or picks a different candidate in some band.  The iteration amplifies perturbations
+    (density compensation 1/p in line 4, the Onsager correction in line 8), so from there
+    on no FP32 implementation can be held to the FP64 trajectory at TOL_ITER; the
+    one-step gate covers those iterations."""
+    import scipy.fft as sfft
+    y, mask, p, s2 = fp32_inputs(sl)
+    S = o.tau_weights(y.shape[0], y.shape[1], s)
+    om = mask.astype(bool)
+    rt = np.zeros(y.shape, dtype=np.complex128)
+    for k in range(K):
+        X = sfft.fft2(o.haar_synthesis(rt, s).astype(np.complex64), norm="ortho")
+        z = np.where(om, y - X.astype(np.complex128), 0.0)
+        v = np.where(om, z / np.where(om, p, 1.0), 0.0)
+        back = sfft.ifft2(v.astype(np.complex64), norm="ortho").astype(np.complex128)
+        r = rt + o.haar_analysis(back, s)
+        tau = o.tau_estimate(z, mask, p, s2, S)
+        _, rt, th, _ = o.denoise(r, tau, s)
+        if rel_l2(r, ref["r"][k]) > TOL_ITER / 2:
+            return k
+        for b, (rs, cs, _, _) in enumerate(_bands(sl, s)):
+            a = np.abs(r[rs, cs]).ravel()
+            a_ref = np.abs(ref["r"][k][rs, cs]).ravel()
+            if int(np.argmin(np.abs(a - th[b]))) != int(np.argmin(np.abs(a_ref - ref["theta"][k][b]))):
+                return k
+    return K
 
 
 def oracle_run(sl, s, K, record=True):
@@ -79,9 +129,9 @@ def one_step_check(sl, s, ref_k, g, b, k, what=""):
         th_g, al_g = float(tr[bb, 1]), float(tr[bb, 2])
         same = snap_theta(r_ref[rs, cs], th_g) == ref["theta"][0][bb]
         if same:
-            rms = float(np.sqrt(np.mean(np.abs(r_ref[rs, cs]) ** 2)))
-            assert abs(th_g - ref["theta"][0][bb]) <= TOL_ITER * max(rms, 1e-30), (what, k, bb)
-            assert abs(al_g - ref["alpha"][0][bb]) <= TOL_ALPHA, (what, k, bb, al_g, ref["alpha"][0][bb])
+            th_tol, al_tol = theta_alpha_tols(r_ref[rs, cs], ref["theta"][0][bb], ref["alpha"][0][bb])
+            assert abs(th_g - ref["theta"][0][bb]) <= th_tol, (what, k, bb)
+            assert abs(al_g - ref["alpha"][0][bb]) <= al_tol, (what, k, bb, al_g, ref["alpha"][0][bb], al_tol)
         else:
             flips += 1
             assert theta_accepted(rg, float(tr[bb, 0]), rs, cs, th_g, alpha_gpu=al_g), (what, k, bb)
@@ -112,11 +162,17 @@ def one_step_every_iteration(sl, s, K):
 
 def free_running(sl, s, K):
     """Per iterate: the library's thresholds must be SURE-optimal (up to near ties) for
-    its own r_k and tau_k; until the first iteration where it picks a different candidate
-    than the oracle, r_k must match to 1e-5 relative L2, alpha to 1e-5 and tau to 1e-4.
-    The final NMSE must match to 0.05 dB when no flip occurred, else lie within the
-    envelope of perturbed oracle runs."""
+    its own r_k and tau_k, and its alpha line 7's value at that threshold on that
+    iterate (to 1e-6; test code on the library's data).  Up to the first iteration where
+    it picks a different candidate than the oracle, and within the FP32 horizon
+    (fp32_horizon), r_k must match to 1e-5 relative L2 and tau to 1e-4 (r_k at the
+    flip iteration itself still is, since it depends only on the previous thresholds);
+    theta then is the same element of an iterate within that bound.  Beyond the horizon
+    the errors are printed; the one-step gate covers those iterations.  The final NMSE
+    must match to 0.05 dB when no flip occurred, else lie within the envelope of
+    perturbed oracle runs."""
     ref = oracle_run(sl, s, K)
+    hz = fp32_horizon(sl, s, K, ref)
     g = run_vdamp([sl], s, K)
     tr = g["trace"][:, 0]
     errs = []
@@ -126,25 +182,32 @@ def free_running(sl, s, K):
         rg = gk["r"][0].astype(np.complex128)
         e = rel_l2(rg, ref["r"][k])
         errs.append(e)
+        pre_flip = first_flip is None
         for b, (rs, cs, _, _) in enumerate(_bands(sl, s)):
             assert theta_accepted(rg, float(gk["tau"][0][b]), rs, cs, tr[k, b, 1],
                                   alpha_gpu=tr[k, b, 2]), (k, b)
             if first_flip is None and snap_theta(ref["r"][k][rs, cs], tr[k, b, 1]) != ref["theta"][k][b]:
                 first_flip = (k, b)
-        if first_flip is None or first_flip[0] > k:
+        if pre_flip and k < hz:
             assert e <= TOL_ITER, (k, e)
             assert np.max(np.abs(tr[k, :, 0] - ref["tau"][k]) / ref["tau"][k]) <= TOL_TAU_TRAJ, k
-            assert np.max(np.abs(tr[k, :, 2] - ref["alpha"][k])) <= TOL_ALPHA, k
+        for b, (rs, cs, _, _) in enumerate(_bands(sl, s)):
+            # alpha of line 7 at the library's own threshold on its own iterate
+            ok, kth = theta_accepted(rg, float(gk["tau"][0][b]), rs, cs, tr[k, b, 1],
+                                     alpha_gpu=tr[k, b, 2], return_key=True)
+            assert abs(tr[k, b, 2] - alpha_at_key(rg[rs, cs], kth)) <= 1e-6, (k, b)
     n_gpu = o.nmse_db(g["x_hat"][0], sl.x0)
     n_ref = o.nmse_db(ref["x_hat"], sl.x0)
     ex = rel_l2(g["x_hat"][0], ref["x_hat"])
-    upto = K if first_flip is None else first_flip[0] + 1
-    print(f"free-running K={K}: max rel L2 r_k before any flip = {max(errs[:upto]):.2e}; "
-          f"first near-tie flip {first_flip} (iterations compared: {upto}); x_hat rel L2 = {ex:.2e}; "
-          f"NMSE gpu {n_gpu:.3f} dB, oracle {n_ref:.3f} dB")
+    upto = min(hz, K if first_flip is None else first_flip[0] + 1)
+    print(f"free-running K={K}: first near-tie flip {first_flip}, FP32 horizon {hz}; max rel L2 r_k over "
+          f"the {upto} gated iterations = {max(errs[:upto]):.2e}; after them "
+          f"{' '.join(f'{v:.1e}' for v in errs[upto:upto + 6])}{' ...' if K > upto + 6 else ''}; "
+          f"x_hat rel L2 = {ex:.2e}; NMSE gpu {n_gpu:.3f} dB, oracle {n_ref:.3f} dB")
     if first_flip is None:
         assert abs(n_gpu - n_ref) <= TOL_NMSE_DB
-        assert ex <= TOL_ITER
+        if hz == K:
+            assert ex <= TOL_ITER
     elif abs(n_gpu - n_ref) > TOL_NMSE_DB:
         mean, sd = oracle_nmse_envelope(sl, s, K, n_ref)
         print(f"  oracle envelope under 3e-7 input perturbation: mean {mean:.3f} dB, sd {sd:.3f} dB")
@@ -357,6 +420,7 @@ def sampled_trace_parity(g, b, sl, s, K, runs=6):
     and its final NMSE the oracle's (or, after a flip, the envelope of perturbed oracle
     runs).  Returns the oracle trajectory."""
     ref = oracle_run(sl, s, K)
+    hz = fp32_horizon(sl, s, K, ref)
     tr = g["trace"][:, b]
     flip = None
     for k in range(K):
@@ -365,14 +429,20 @@ def sampled_trace_parity(g, b, sl, s, K, runs=6):
         if not same:
             flip = k
             break
+        if k >= hz:
+            continue
         et = np.max(np.abs(tr[k, :, 0] - ref["tau"][k]) / ref["tau"][k])
-        ea = np.max(np.abs(tr[k, :, 2] - ref["alpha"][k]))
         assert et <= TOL_TAU_TRAJ, (b, k, et)
-        assert ea <= TOL_ALPHA, (b, k, ea)
+        for bb in range(1 + 3 * s):
+            # line 7's alpha moves by (1 - alpha) times theta's relative change, and theta
+            # (one element of the iterate) by that element's rounding error
+            th_r, al_r = ref["theta"][k][bb], ref["alpha"][k][bb]
+            al_tol = TOL_ALPHA + ((1.0 - al_r) * abs(tr[k, bb, 1] - th_r) / th_r if th_r > 0 else 0.0)
+            assert abs(tr[k, bb, 2] - al_r) <= al_tol, (b, k, bb, al_tol)
     n_gpu = o.nmse_db(g["x_hat"][b], sl.x0)
     n_ref = o.nmse_db(ref["x_hat"], sl.x0)
     print(f"  slice {b} ({sl.y.shape[0]}x{sl.y.shape[1]}): first theta difference at iteration "
-          f"{flip}; NMSE gpu {n_gpu:.3f} dB, oracle {n_ref:.3f} dB", flush=True)
+          f"{flip}, FP32 horizon {hz}; NMSE gpu {n_gpu:.3f} dB, oracle {n_ref:.3f} dB", flush=True)
     if flip is None:
         assert abs(n_gpu - n_ref) <= TOL_NMSE_DB
     elif abs(n_gpu - n_ref) > TOL_NMSE_DB:
