@@ -73,3 +73,102 @@ def test_fista_graph_replays_match_eager_bitwise():
     assert np.all(np.isfinite(out["eager"][0]))
     for rep, got in enumerate(out["graph"]):
         assert np.array_equal(got, out["eager"][0]), rep
+
+
+def _learned_eager(slices, s, flat, seed, judge):
+    import torch
+    from paper_1911_01234_amd import vdamp as V
+    plan = V.Plan([64, 64], [64, 64], s)
+    cnn = V.Cnn(plan.nbands)
+    cnn.set_params(flat)
+    ws = plan.workspace()
+    cws = cnn.workspace(plan, V.VDAMP_CNN_WS_SOLVE)
+    y, mask, p, sigma2 = V.to_device(plan, slices)
+    x = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+    plan.vdamp_solve_learned(cnn, ws, cws, y, mask, p, sigma2, 3, seed, x, judge=judge)
+    torch.cuda.synchronize()
+    out = x.cpu().numpy().copy()
+    cnn.close()
+    plan.close()
+    return out
+
+
+def test_learned_graph_rekeyed_when_denoiser_recreated_or_seed_judge_change():
+    """The captured learned solve holds the denoiser's device buffers: destroying the
+    denoiser and creating another one (which may reuse the handle's host address)
+    between two graph solves must re-capture, as must a change of seed or judge (also
+    the pair seed ^ 2^63 with the other judge).  Every graph result equals the eager one."""
+    import torch
+    from paper_1911_01234_amd import vdamp as V
+    slices, s = _slices()
+    flats = [torch.from_numpy(V.cnn_flatten(rand_params(1 + 3 * s, seed, scale_last=0.3)).astype(np.float32)).cuda()
+             for seed in (21, 22)]
+    plan = V.Plan([64, 64], [64, 64], s, V.VDAMP_FLAG_USE_GRAPH)
+    ws = plan.workspace()
+    y, mask, p, sigma2 = V.to_device(plan, slices)
+    x = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+    stream = torch.cuda.Stream()
+    cws = None
+    cases = [(0, 5, V.VDAMP_JUDGE_SURE), (1, 5, V.VDAMP_JUDGE_SURE), (1, 5 ^ (1 << 63), V.VDAMP_JUDGE_NONE),
+             (1, 5, V.VDAMP_JUDGE_NONE)]
+    for net, seed, judge in cases:
+        cnn = V.Cnn(plan.nbands)  # a fresh denoiser for every case, the previous one destroyed
+        cnn.set_params(flats[net])
+        if cws is None:
+            cws = cnn.workspace(plan, V.VDAMP_CNN_WS_SOLVE)
+        x.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            plan.vdamp_solve_learned(cnn, ws, cws, y, mask, p, sigma2, 3, seed, x, judge=judge, stream=stream)
+        stream.synchronize()
+        got = x.cpu().numpy().copy()
+        cnn.close()
+        want = _learned_eager(slices, s, flats[net], seed, judge)
+        assert np.all(np.isfinite(want))
+        assert np.array_equal(got, want), (net, seed, judge)
+
+
+def test_resume_and_fista_objective_graph_replays_match_eager_bitwise():
+    """vdamp_solve_resume with a monitor output and fista_solve with its objective output,
+    captured and replayed three times, against eager calls."""
+    import torch
+    from paper_1911_01234_amd import vdamp as V
+    slices, s = _slices()
+    stream = torch.cuda.Stream()
+    out = {}
+    for name, flags in (("eager", 0), ("graph", V.VDAMP_FLAG_USE_GRAPH)):
+        plan = V.Plan([64, 64], [64, 64], s, flags)
+        planf = V.Plan([64, 64], [64, 64], s, flags)  # its own graph cache, so both replay
+        ws = plan.workspace()
+        wsf = planf.workspace()
+        y, mask, p, sigma2 = V.to_device(plan, slices)
+        r = (torch.randn(plan.ntot, dtype=torch.complex64, generator=torch.Generator().manual_seed(3)) * 0.1).cuda()
+        th = torch.full((plan.batch * plan.nbands,), 0.05, dtype=torch.float32, device="cuda")
+        al = torch.full_like(th, 0.3)
+        lam = torch.tensor([0.01, 0.02], dtype=torch.float32, device="cuda")
+        x = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+        mon = torch.empty(4 * plan.ntot, dtype=torch.complex64, device="cuda")
+        obj = torch.empty(6 * plan.batch, dtype=torch.float32, device="cuda")
+        xf = torch.empty_like(x)
+        reps = []
+        for rep in range(3 if flags else 1):
+            for t in (x, mon, xf):
+                t.fill_(float("nan"))
+            obj.fill_(float("nan"))
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                plan.vdamp_solve_resume(ws, y, mask, p, sigma2, r, th, None, al, 4, x, None, mon, stream=stream)
+            stream.synchronize()
+            a = (x.cpu().numpy().copy(), mon.cpu().numpy().copy())
+            with torch.cuda.stream(stream):
+                planf.fista_solve(wsf, y, mask, lam, 6, xf, objective=obj, stream=stream)
+            stream.synchronize()
+            reps.append(a + (xf.cpu().numpy().copy(), obj.cpu().numpy().copy()))
+        out[name] = reps
+        plan.close()
+        planf.close()
+    for arr in out["eager"][0]:
+        assert np.all(np.isfinite(arr))
+    for rep, got in enumerate(out["graph"]):
+        for a, b in zip(got, out["eager"][0]):
+            assert np.array_equal(a, b), rep
