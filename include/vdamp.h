@@ -177,6 +177,27 @@ vdamp_status vdamp_solve_resume(vdamp_plan_h plan, hipStream_t stream, void* wor
                                 float* x_monitor);
 
 /*
+ * vdamp_solve_noalloc -- vdamp_solve for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid allocation).
+ * The workspace is a device array inside the library, VDAMP_NOALLOC_MAX_WORKSPACE bytes
+ * per GPU, held from the first call on that GPU until the process ends; the call itself
+ * allocates nothing (no hipMalloc, hipFree, graph instantiation or events: launches are
+ * always eager, VDAMP_FLAG_USE_GRAPH and VDAMP_FLAG_TIMING of the plan are ignored).
+ *   plan            as for vdamp_solve; its workspace_bytes must not exceed
+ *                   VDAMP_NOALLOC_MAX_WORKSPACE, else VDAMP_ERR_WORKSPACE (nothing enqueued)
+ *   other arguments as in vdamp_solve (caller-owned inputs and outputs)
+ * Every call on one GPU shares that GPU's array, whose contents persist between calls:
+ * nothing the solve reads is taken from an earlier call (every byte is written by the
+ * solve before it is read), but two calls that overlap in time on one GPU (different
+ * streams, or host threads) race on it and give undefined results.
+ * vdamp_state_export is not available after this call (the workspace is not the caller's).
+ */
+#define VDAMP_NOALLOC_MAX_WORKSPACE ((size_t)64 << 20)
+vdamp_status vdamp_solve_noalloc(vdamp_plan_h plan, hipStream_t stream, const float* y,
+                                 const uint8_t* mask, const float* p, const float* sigma2,
+                                 int32_t iters, float* x_hat, float* trace);
+
+/*
  * fista_solve -- FISTA on 1/2 ||y - M_Omega F Psi^H w||^2 + lambda ||w||_1 (eq. 2 with
  * f = lambda ||Psi x||_1, in synthesis form), step size 1, zero start, every band
  * thresholded (Section 3's comparator).

@@ -260,6 +260,32 @@ vdamp_status enqueue_fista(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
 
 }  // namespace
 
+namespace vdamp {
+// vdamp_solve's schedule on a given workspace, always launched eagerly (no graph capture,
+// no timing events): nothing here allocates.
+vdamp_status solve_eager(vdamp_plan_t* plan, hipStream_t stream, void* workspace,
+                         size_t workspace_bytes, const float* y, const uint8_t* mask,
+                         const float* p, const float* sigma2, int32_t iters, float* x_hat,
+                         float* trace) {
+  vdamp_status s = check_common(plan, workspace, workspace_bytes, y, mask, iters, x_hat);
+  if (s != VDAMP_OK) return s;
+  if (!p || !sigma2) return fail(VDAMP_ERR_ARG, "p and sigma2 must be non-null");
+  s = enqueue_vdamp(plan, stream, workspace, reinterpret_cast<const float2*>(y), mask, p, sigma2, iters,
+                    reinterpret_cast<float2*>(x_hat), trace, false, Resume(), nullptr);
+  if (s != VDAMP_OK) return s;
+  if (plan->flags & VDAMP_FLAG_CHECK_FINITE) {
+    int bad = 0;
+    const Ws w = layout(plan, workspace);
+    HIP_TRY(hipMemcpyAsync(&bad, w.bad, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (bad) return fail(VDAMP_ERR_NONFINITE, "p outside (0, 1] on the mask or non-finite y");
+  }
+  plan->state_ws = workspace;
+  plan->has_state = iters > 0;
+  return VDAMP_OK;
+}
+}  // namespace vdamp
+
 extern "C" {
 
 const char* vdamp_status_string(vdamp_status s) {
@@ -563,6 +589,7 @@ vdamp_status solve_common(vdamp_plan_h plan, hipStream_t stream, void* workspace
   return VDAMP_OK;
 }
 }  // namespace
+
 
 vdamp_status vdamp_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
                          size_t workspace_bytes, const float* y, const uint8_t* mask,

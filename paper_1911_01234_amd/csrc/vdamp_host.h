@@ -114,6 +114,10 @@ struct vdamp_plan_t {
 
 namespace vdamp {
 Ws layout(const vdamp_plan_t* P, void* ws);
+vdamp_status solve_eager(vdamp_plan_t* plan, hipStream_t stream, void* workspace,
+                         size_t workspace_bytes, const float* y, const uint8_t* mask,
+                         const float* p, const float* sigma2, int32_t iters, float* x_hat,
+                         float* trace);
 // Threshold-search work list of the plan's bands grouped by size class (largest class
 // first, heaviest bands first within a class), with P->nsure_cls set; classes from
 // P->sure_cls_of_size where present, else by size.

@@ -24,6 +24,7 @@ VDAMP_FLAG_CHECK_FINITE = 1 << 2
 VDAMP_FLAG_USE_GRAPH = 1 << 3
 VDAMP_FLAG_TIMING = 1 << 5
 VDAMP_FLAG_AUTOTUNE = 1 << 6
+VDAMP_NOALLOC_MAX_WORKSPACE = 64 << 20
 PASS_NAMES = ("prep", "rows_synth", "cols", "rows_anal", "sure", "denoiser", "cnn")
 VDAMP_CNN_WS_FORWARD = 0
 VDAMP_CNN_WS_TRAIN = 1
@@ -36,7 +37,8 @@ STATUS_NAMES = {0: "VDAMP_OK", 1: "VDAMP_ERR_ARG", 2: "VDAMP_ERR_SHAPE", 3: "VDA
                 4: "VDAMP_ERR_WORKSPACE", 5: "VDAMP_ERR_HIP", 6: "VDAMP_ERR_NONFINITE",
                 7: "VDAMP_ERR_STATE"}
 
-EXPORTED = ("vdamp_plan", "vdamp_plan_destroy", "vdamp_solve", "vdamp_solve_resume", "fista_solve",
+EXPORTED = ("vdamp_plan", "vdamp_plan_destroy", "vdamp_solve", "vdamp_solve_resume", "vdamp_solve_noalloc",
+            "fista_solve",
             "vdamp_state_export", "vdamp_pass_times", "vdamp_status_string", "vdamp_last_error",
             "vdamp_cnn_create", "vdamp_cnn_destroy", "vdamp_cnn_param_count", "vdamp_cnn_set_params",
             "vdamp_cnn_get_params", "vdamp_cnn_workspace", "vdamp_cnn_forward", "vdamp_cnn_train_step",
@@ -78,6 +80,8 @@ def load_library() -> ctypes.CDLL:
     lib.vdamp_solve.restype = ctypes.c_int
     lib.vdamp_solve_resume.argtypes = [vp, vp, vp, sz, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp]
     lib.vdamp_solve_resume.restype = ctypes.c_int
+    lib.vdamp_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp, vp]
+    lib.vdamp_solve_noalloc.restype = ctypes.c_int
     lib.fista_solve.argtypes = [vp, vp, vp, sz, vp, vp, vp, i32, vp, vp]
     lib.fista_solve.restype = ctypes.c_int
     lib.vdamp_state_export.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
@@ -184,6 +188,11 @@ class Plan:
             self._h, _stream_handle(stream), _ptr(ws), ws.numel(), _ptr(y), _ptr(mask), _ptr(p),
             _ptr(sigma2), _ptr(r_init), _ptr(theta_init), _ptr(theta2_init), _ptr(alpha_init),
             int(iters), _ptr(x_hat), _ptr(trace), _ptr(x_monitor)))
+
+    def vdamp_solve_noalloc(self, y, mask, p, sigma2, iters, x_hat, trace=None, stream=None):
+        _check(load_library().vdamp_solve_noalloc(self._h, _stream_handle(stream), _ptr(y), _ptr(mask),
+                                                  _ptr(p), _ptr(sigma2), int(iters), _ptr(x_hat),
+                                                  _ptr(trace)))
 
     def fista_solve(self, ws, y, mask, lam, iters, x_hat, objective=None, stream=None):
         _check(load_library().fista_solve(self._h, _stream_handle(stream), _ptr(ws), ws.numel(),
