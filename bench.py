@@ -11,22 +11,27 @@ Prints ONE JSON line.  `value` is slice-iterations per second over the timed ste
 (eager launches, nothing else on the stream).  `roofline` reports the dominant kernel
 class (largest share of kernel time, from HIP events recorded around every pass on the
 solve's stream during a second timed run of the same steps, `kernel_event_run`, whose
-rate the events lower by about 7 %):
-algorithmic bytes it must move per launch / its average launch time, against the
-MI355X HBM peak; `traffic` is the HBM bytes per launch that rocprofv3's FETCH_SIZE and
-WRITE_SIZE counters measured for that kernel (scaled by a copy of known size), taken
-from profiles/ while the kernel's sources are unchanged, else null.  `cpu_baseline` is the FP64 oracle timed on the host on a bounded
-sample of the same workload.
+rate the events lower by about 7 %): algorithmic bytes it must move per launch / its
+average launch time, against the MI355X HBM peak, beside a measured device copy rate;
+`fused_floor` is the whole solve against the bytes a schedule that never leaves the CU
+between passes would move; `traffic` is the HBM bytes per launch that rocprofv3's
+FETCH_SIZE and WRITE_SIZE counters measured for that kernel (scaled by a copy of known
+size), taken from profiles/ while the kernel's sources are unchanged, else null.
+`cpu_baseline` is the FP64 oracle on the host's cores (one worker process per core) on
+the same batch, whose mean NMSE also sets the time-to-NMSE target.
 
 `learned` (unless --no-learned): the CNN denoiser is trained on the GPU by the library's
-own kernels on (Psi^H r_k, tau_k, x0) pairs from plain-VDAMP solves of a disjoint set
-of 256x256 slices (same generator), then 64 held-out slices of the timed batch are
-solved with plain VDAMP and with the SURE-judged learned form: mean NMSE at 50
-iterations, the learned form's NMSE at the wall-clock of the plain 50-iteration solve,
-and each form's time to reach the plain form's 50-iteration NMSE.  `cnn_roofline`: the
-network pass of a learned iteration (input packing, forward and JVP) against its binding
-roofline, HBM (algorithmic activation bytes per pixel, CNN_BYTES_PER_PX, at 8 TB/s take
-about 2.3x as long as its FLOPs at the dense BF16 MFMA peak), with the MFMA rate beside.
+own kernels on 20 000 (Psi^H r_k, tau_k, x0) triples that plain VDAMP generates from 2000
+seeded 256x256 phantoms (R ~ U{4,6,8}, SNR ~ U[30,45] dB), batch 64; 64 fresh phantoms
+are then solved with plain VDAMP and with the SURE-judged learned form: NMSE at 50
+iterations, the learned form within the plain 50-iteration wall-clock with the paired
+per-phantom gain and its 95 % CI, and each form's time to the plain form's 50-iteration
+NMSE.  The same comparison runs at 512x512 (textured phantoms, R = 8 and 12, batch 128)
+after one on-GPU fine-tuning step on freshly generated training phantoms.  `cnn_roofline`:
+the network pass of a learned iteration (input packing, forward and JVP) against its
+binding roofline, HBM (algorithmic activation bytes per pixel, CNN_BYTES_PER_PX, at
+8 TB/s take about 2.3x as long as its FLOPs at the dense BF16 MFMA peak), with the MFMA
+rate beside.
 """
 from __future__ import annotations
 
@@ -196,197 +201,333 @@ def measured_traffic(kernel_class):
     return rec["traffic_bytes_per_launch"] if h.hexdigest()[:16] == rec["source_sha"] else None
 
 
-def cpu_baseline(slices, s, iters, budget_s, gpu_nmse=None):
-    """FP64 oracle on the host, one slice at a time, until about budget_s seconds.  With
-    the GPU's per-slice NMSE after the same iteration count, the sample's oracle NMSE is
-    reported beside it."""
+def _oracle_slice(task):
+    """Worker of the CPU baseline: regenerate one slice of the benchmark's batch from its
+    seeds and run the FP64 oracle on the inputs exactly as the library reads them
+    (complex64 y, float32 p and sigma^2).  Returns (slice index, NMSE in dB, oracle
+    seconds)."""
+    b, iters = task
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
     from oracle import vdamp_ref as o
+    from paper_1911_01234_amd import synth
+    sl = synth.workload_batch256(1, first_slice=b)[0][0]
+    y = sl.y.astype(np.complex64).astype(np.complex128)
+    p = sl.p.astype(np.float32).astype(np.float64)
+    t = time.perf_counter()
+    xr = o.vdamp(y, sl.mask, p, float(np.float32(sl.sigma2)), LEVELS, iters)["x_hat"]
+    dt = time.perf_counter() - t
+    return b, float(10.0 * np.log10(np.sum(np.abs(xr - sl.x0) ** 2) / np.sum(np.abs(sl.x0) ** 2))), dt
+
+
+def make_cpu_pool():
+    """Worker processes for the CPU baseline, one per core this process may use, forked
+    before anything initialises the GPU (each worker runs NumPy with one thread)."""
+    import multiprocessing as mp
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    cores = len(os.sched_getaffinity(0))
+    return mp.get_context("fork").Pool(cores), cores
+
+
+def cpu_baseline(pool, cores, batch, iters, budget_s, gpu_nmse=None):
+    """FP64 oracle on the host cores: the batch's slices spread over `cores` worker
+    processes until every slice is done or about budget_s seconds have passed; the rate
+    is slice-iterations per second of wall time over the pool.  The oracle's mean NMSE
+    over the slices it solved is the time-to-NMSE target's reference, and, with the
+    GPU's per-slice NMSE after the same iteration count, the comparison is reported."""
     t0 = time.perf_counter()
-    done = 0
-    nm = []
-    for sl in slices:
-        xr = o.vdamp(sl.y, sl.mask, sl.p, sl.sigma2, s, iters)["x_hat"]
-        done += 1
-        nm.append(10.0 * np.log10(np.sum(np.abs(xr - sl.x0) ** 2) / np.sum(np.abs(sl.x0) ** 2)))
+    done = {}
+    for b, nm, _ in pool.imap_unordered(_oracle_slice, [(b, iters) for b in range(batch)]):
+        done[b] = nm
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    out = {"value": done * iters / dt, "unit": "slice-iterations/s", "cores": 1, "kind": "oracle",
-           "sample": f"{done} of the batch's 256x256 slices x {iters} iterations, FP64 NumPy, "
-                     f"one process (pocketfft and sort single-threaded), {dt:.1f} s"}
+    pool.terminate()
+    idx = sorted(done)
+    nm = np.array([done[b] for b in idx])
+    import platform
+    cpu_model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out = {"value": round(len(idx) * iters / dt, 1), "unit": "slice-iterations/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"{len(idx)} of the batch's {batch} slices of 256x256 x {iters} iterations, FP64 NumPy, "
+                     f"{cores} worker processes of one thread each ({cpu_model}), {dt:.1f} s wall",
+           "oracle_nmse_db_mean": round(float(nm.mean()), 3), "oracle_slices": len(idx)}
     if gpu_nmse is not None:
-        g = np.asarray(gpu_nmse[:done], dtype=np.float64)
-        d = g - np.asarray(nm)
-        out["nmse_check"] = {"slices": done, "oracle_db_mean": round(float(np.mean(nm)), 3),
-                             "gpu_db_mean": round(float(np.mean(g)), 3),
+        g = np.asarray(gpu_nmse, dtype=np.float64)[idx]
+        d = g - nm
+        out["nmse_check"] = {"slices": len(idx), "oracle_db_mean": round(float(nm.mean()), 3),
+                             "gpu_db_mean": round(float(g.mean()), 3),
                              "median_abs_diff_db": round(float(np.median(np.abs(d))), 4),
                              "max_abs_diff_db": round(float(np.max(np.abs(d))), 4)}
     return out
 
 
-def learned_section(args, test, s, K, stream):
-    """Train the denoiser on the GPU, then compare learned and plain VDAMP on `test`."""
+def copy_peak(nbytes=1 << 31, reps=5):
+    """Measured device-to-device copy rate (bytes read + written per second) of a
+    buffer far larger than the caches: the attainable HBM bandwidth beside the nominal."""
     import torch
-    from paper_1911_01234_amd import synth, train as T, vdamp as V
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
+
+
+def _gen_slice(task):
+    """Worker: one seeded slice of a recipe, returned with single-precision arrays (what
+    the library reads) to keep the transfer small."""
+    recipe, cfg_id, b = task
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+    from paper_1911_01234_amd import synth
+    sl = getattr(synth, recipe)(1, cfg_id, first_slice=b)[0][0]
+    sl.y = sl.y.astype(np.complex64)
+    sl.x0 = sl.x0.astype(np.complex64)
+    sl.p = sl.p.astype(np.float32)
+    return sl
+
+
+def gen_slices(pool, recipe, cfg_id, first, n):
+    """Seeded slices of a synth recipe, made by the CPU worker pool when there is one."""
+    if pool is None:
+        from paper_1911_01234_amd import synth
+        return getattr(synth, recipe)(n, cfg_id, first_slice=first)[0]
+    return pool.map(_gen_slice, [(recipe, cfg_id, b) for b in range(first, first + n)], chunksize=4)
+
+
+class _Solver:
+    """Plain and learned solves of one batch on one plan (library calls only)."""
+
+    def __init__(self, cnn, slices, stream):
+        import torch
+        from paper_1911_01234_amd import vdamp as V
+        ny, nx = slices[0].y.shape
+        self.slices, self.stream, self.cnn = slices, stream, cnn
+        self.plan = V.Plan([ny] * len(slices), [nx] * len(slices), LEVELS)
+        self.ws = self.plan.workspace()
+        self.cws = cnn.workspace(self.plan, V.VDAMP_CNN_WS_SOLVE)
+        self.dev = V.to_device(self.plan, slices)
+        self.x = torch.empty(self.plan.ntot, dtype=torch.complex64, device="cuda")
+        self.x0 = torch.from_numpy(self.plan.pack([sl.x0 for sl in slices], np.complex64)).cuda()
+        self.seg = torch.from_numpy(np.repeat(np.arange(len(slices)), ny * nx)).cuda()
+
+    def plain(self, k):
+        self.plan.vdamp_solve(self.ws, *self.dev, k, self.x, stream=self.stream)
+
+    def learned(self, k, lf=0):
+        self.plan.vdamp_solve_learned(self.cnn, self.ws, self.cws, *self.dev, k, 7, self.x, learned_from=lf,
+                                      stream=self.stream)
+
+    def nmse(self):
+        self.stream.synchronize()
+        return nmse_db_batch(self.x, self.x0, self.seg, len(self.slices))
+
+    def timed(self, fn, *a, reps=3):
+        fn(*a)
+        self.stream.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn(*a)
+        self.stream.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    def close(self):
+        self.plan.close()
+
+
+def learned_comparison(test, val, K):
+    """Plain VDAMP against the judged learned form on `test` (two _Solver objects):
+    NMSE after K iterations; the learned form within the plain K-iteration wall-clock
+    (soft thresholding for kp iterations, the network in the last L; (kp, L) chosen on
+    `val` among the schedules whose cost, estimated from measured per-iteration times,
+    fits) with the per-slice paired gain and its 95 % CI; and, at equal NMSE, each form's
+    time to reach the plain form's K-iteration NMSE (the cheapest schedule that does)."""
+    from paper_1911_01234_amd import train as T
+    t_plain = test.timed(test.plain, K)
+    t_learn = test.timed(test.learned, K)
+    test.plain(K)
+    n_plain = test.nmse()
+    test.learned(K)
+    n_learn = test.nmse()
+    t_pi, t_li = t_plain / K, t_learn / K
+    cands = [(kp, L) for L in (1, 2, 3) for kp in range(4, int((t_plain - L * t_li) / t_pi) + 1, 2)]
+    best = None
+    for kp, L in cands:
+        val.learned(kp + L, kp)
+        m = float(val.nmse().mean())
+        if best is None or m < best[0]:
+            best = (m, kp, L)
+    eq = None
+    if best is not None:
+        _, kp, L = best
+        t_h = test.timed(test.learned, kp + L, kp)
+        test.learned(kp + L, kp)
+        n_h = test.nmse()
+        g = T.paired_gain(n_plain, n_h)
+        eq = {"plain_iters_first": kp, "learned_iters": L, "seconds": round(t_h, 5),
+              "nmse_db": round(float(n_h.mean()), 3),
+              "gain_db": round(g["mean_db"], 3), "gain_sd_db": round(g["sd_db"], 3),
+              "gain_ci95_db": [round(v, 3) for v in g["ci95_db"]],
+              "chosen_on": f"{len(val.slices)} validation slices, {len(cands)} schedules within the budget"}
+    target = float(n_plain.mean())
+    kp_hit = K
+    for k in range(1, K + 1):
+        test.plain(k)
+        if float(test.nmse().mean()) <= target + 1e-9:
+            kp_hit = k
+            break
+    tp_hit = test.timed(test.plain, kp_hit)
+    hit = None  # cheapest (by estimated cost) schedule reaching the target
+    for cost, kp, L in sorted((kp * t_pi + L * t_li, kp, L) for L in (1, 2, 3) for kp in range(0, K + 1, 2)):
+        if cost > t_plain:
+            break
+        test.learned(kp + L, kp)
+        if float(test.nmse().mean()) <= target:
+            hit = {"plain_iters_first": kp, "learned_iters": L, "seconds": round(test.timed(test.learned, kp + L, kp), 5)}
+            break
+    return {"test_slices": len(test.slices),
+            "nmse_db_at_K": {"plain": round(float(n_plain.mean()), 3), "learned": round(float(n_learn.mean()), 3)},
+            "seconds_K_iters": {"plain": round(t_plain, 5), "learned": round(t_learn, 5)},
+            "equal_wallclock": {"plain_seconds": round(t_plain, 5), "plain_nmse_db": round(target, 3),
+                                "learned_last_iterations": eq},
+            "time_to_plain_K_nmse": {"target_db": round(target, 3),
+                                     "plain": {"iters": kp_hit, "seconds": round(tp_hit, 5)},
+                                     "learned": hit}}
+
+
+def learned_section(args, pool, stream):
+    """The learned denoiser at 256x256: trained on the GPU on 2000 phantoms x 10 iteration
+    counts = 20 000 triples (batch 64), compared with plain VDAMP on 64 fresh phantoms;
+    then at 512x512 (textured phantoms, R = 8 and 12, batch 128): each batch gets one
+    on-GPU fine-tuning step on freshly generated training phantoms before inference."""
+    import torch
+    from paper_1911_01234_amd import train as T, vdamp as V
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    K = ITERS
+    ks = (1, 2, 3, 4, 6, 9, 13, 19, 28, 40)
+    chunk = 250
     t0 = time.perf_counter()
-    tr, _, _ = synth.workload_batch256(args.train_slices, first_slice=10000)
-    log(f"generated {len(tr)} training slices in {time.perf_counter() - t0:.1f} s")
-    ks = (1, 2, 3, 5, 8, 12, 20, 30, 45)
+    out = {}
     with torch.cuda.stream(stream):
-        plan = V.Plan([256] * len(tr), [256] * len(tr), s)
-        ws = plan.workspace()
-        y, mask, p, sigma2 = V.to_device(plan, tr)
-        cnn = V.Cnn(plan.nbands)
-        cnn.set_params(torch.from_numpy(T.init_flat(plan.nbands, 0)).cuda(), stream=stream)
-        s0 = T.input_scales(plan, cnn, ws, y, mask, p, sigma2, stream=stream)
-        pairs = T.make_pairs(plan, ws, y, mask, p, sigma2, ks, stream=stream)
-        x0 = torch.from_numpy(plan.pack([sl.x0 for sl in tr], np.complex64)).cuda()
-        del ws, y, mask, p, sigma2
+        cnn = V.Cnn(1 + 3 * LEVELS)
+        cnn.set_params(torch.from_numpy(T.init_flat(cnn.nbands, 0)).cuda(), stream=stream)
+        store = T.TripleStore(args.train_slices, 65536, ks)
+        plan_c = V.Plan([256] * chunk, [256] * chunk, LEVELS)
+        for c0 in range(0, args.train_slices, chunk):
+            n = min(chunk, args.train_slices - c0)
+            sl = gen_slices(pool, "workload_c4", 40, c0, n)
+            if n != chunk:
+                plan_c.close()
+                plan_c = V.Plan([256] * n, [256] * n, LEVELS)
+            store.add(plan_c, cnn, sl, stream=stream)
+        plan_c.close()
         stream.synchronize()
-        log(f"{len(pairs) * len(tr)} training pairs ready; training {args.train_steps} steps")
+        t_data = time.perf_counter() - t0
+        log(f"{len(store)} training triples in {t_data:.1f} s; training {args.train_steps} steps")
+        plan_t = V.Plan([256] * 64, [256] * 64, LEVELS)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        losses = T.train(cnn, plan, pairs, s0, x0, args.train_steps, 1e-3, stream=stream, lr_final=1e-4)
+        losses = T.train_store(cnn, plan_t, store, args.train_steps, 1e-3, seed=1, stream=stream, lr_final=1e-4)
         e1.record(stream)
         stream.synchronize()
         train_ms = e0.elapsed_time(e1)
-        del pairs, x0, plan
+        plan_t.close()
+        del store
         torch.cuda.empty_cache()
-
-        B = len(test)
-        plan = V.Plan([256] * B, [256] * B, s, V.VDAMP_FLAG_TIMING)
-        ws = plan.workspace()
-        cws = cnn.workspace(plan, V.VDAMP_CNN_WS_SOLVE)
-        y, mask, p, sigma2 = V.to_device(plan, test)
-        x0 = torch.from_numpy(plan.pack([sl.x0 for sl in test], np.complex64)).cuda()
-        seg = torch.from_numpy(np.repeat(np.arange(B), 65536)).cuda()
-        xh = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
-
-        def plain(k):
-            plan.vdamp_solve(ws, y, mask, p, sigma2, k, xh, stream=stream)
-
-        def learn(k):
-            plan.vdamp_solve_learned(cnn, ws, cws, y, mask, p, sigma2, k, 7, xh, stream=stream)
-
-        def nmse():
-            stream.synchronize()
-            return float(nmse_db_batch(xh, x0, seg, B).mean())
-
-        def timed(fn, k, reps=3):
-            fn(k)
-            stream.synchronize()
-            plan.vdamp_pass_times()
-            t = time.perf_counter()
-            for _ in range(reps):
-                fn(k)
-            stream.synchronize()
-            dt = (time.perf_counter() - t) / reps
-            return dt, plan.vdamp_pass_times()
-
-        plain(K)
-        n_plain = nmse()
-        learn(K)
-        n_learn = nmse()
-        sel = torch.empty(B * plan.nbands, dtype=torch.int32, device="cuda")
-        cnn.learned_export(plan, cws, sel=sel, stream=stream)
+        test = _Solver(cnn, gen_slices(pool, "workload_c4", 41, 0, args.test_slices), stream)
+        val = _Solver(cnn, gen_slices(pool, "workload_c4", 42, 0, 32), stream)
+        cmp4 = learned_comparison(test, val, K)
+        # the network pass of a learned iteration (packing, forward, JVP) from per-pass
+        # events: a timing plan on the test batch
+        tplan = V.Plan([256] * len(test.slices), [256] * len(test.slices), LEVELS, V.VDAMP_FLAG_TIMING)
+        tws = tplan.workspace()
+        tcws = cnn.workspace(tplan, V.VDAMP_CNN_WS_SOLVE)
+        reps = 3
+        tplan.vdamp_solve_learned(cnn, tws, tcws, *test.dev, K, 7, test.x, stream=stream)
         stream.synchronize()
-        sel_frac = sel.view(B, plan.nbands).float().mean(0).cpu().numpy()
-        t_plain, _ = timed(plain, K)
-        t_learn, times = timed(learn, K)
-        # learned form within the plain 50-iteration wall-clock: soft thresholding for
-        # the first kp iterations and the network in the last L.  (kp, L) is chosen on a
-        # separate validation batch among the schedules whose estimated cost (from the
-        # measured per-iteration times) fits the budget, then measured on the test batch.
-        t_pi, t_li = t_plain / K, t_learn / K
-        cands = []
-        for L in (1, 2, 3):
-            kmax = int((t_plain - L * t_li) / t_pi)
-            for kp in range(4, kmax + 1, 4):
-                cands.append((kp, L))
-        val, _, _ = synth.workload_batch256(32, first_slice=20000)
-        vplan = V.Plan([256] * len(val), [256] * len(val), s)
-        vws = vplan.workspace()
-        vcws = cnn.workspace(vplan, V.VDAMP_CNN_WS_SOLVE)
-        vy, vm, vp, vs2 = V.to_device(vplan, val)
-        vx0 = torch.from_numpy(vplan.pack([sl.x0 for sl in val], np.complex64)).cuda()
-        vseg = torch.from_numpy(np.repeat(np.arange(len(val)), 65536)).cuda()
-        vx = torch.empty(vplan.ntot, dtype=torch.complex64, device="cuda")
-        vbest = None
-        for kp, L in cands:
-            vplan.vdamp_solve_learned(cnn, vws, vcws, vy, vm, vp, vs2, kp + L, 7, vx, learned_from=kp,
-                                      stream=stream)
-            stream.synchronize()
-            n_v = float(nmse_db_batch(vx, vx0, vseg, len(val)).mean())
-            if vbest is None or n_v < vbest[0]:
-                vbest = (n_v, kp, L)
-        del vws, vcws, vy, vm, vp, vs2, vx0, vx, vplan
-        eq = None
-        if vbest is not None:
-            _, kp, L = vbest
+        tplan.vdamp_pass_times()
+        for _ in range(reps):
+            tplan.vdamp_solve_learned(cnn, tws, tcws, *test.dev, K, 7, test.x, stream=stream)
+        times = tplan.vdamp_pass_times()
+        npx = tplan.ntot
+        tplan.close()
+        test.close()
+        val.close()
+        del tws, tcws, test, val
+        torch.cuda.empty_cache()
+        log(f"256x256: {json.dumps(cmp4['equal_wallclock'])}")
+        cnn_ms, _ = times["cnn"]
+        flop = 2 * CNN_FLOP_PER_PX * npx  # forward + JVP per learned iteration
+        cnn_bytes = CNN_BYTES_PER_PX * npx
+        per_iter_s = cnn_ms / 1e3 / (reps * K)
+        ach = flop / per_iter_s / 1e12
+        out["c4_256x256"] = {
+            "train": {"phantoms": args.train_slices, "triples": args.train_slices * len(ks),
+                      "iteration_counts": list(ks), "batch": 64, "steps": args.train_steps,
+                      "data_seconds": round(t_data, 2), "train_seconds": round(train_ms / 1e3, 3),
+                      "loss_first": float(np.mean(losses[:20])), "loss_last": float(np.mean(losses[-20:]))},
+            **cmp4,
+            "pass_ms_per_learned_solve": {k: round(v[0] / reps, 3) for k, v in times.items()},
+            "cnn_roofline": {"bound": "hbm" if cnn_bytes / HBM_PEAK_GBS / 1e9 > flop / BF16_PEAK_TFLOPS / 1e12 else "mfma",
+                             "achieved": round(cnn_bytes / per_iter_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(cnn_bytes / per_iter_s / 1e9 / HBM_PEAK_GBS, 4),
+                             "bytes_per_learned_iter": int(cnn_bytes),
+                             "mfma": {"achieved": round(ach, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                      "frac": round(ach / BF16_PEAK_TFLOPS, 4), "flop_per_learned_iter": int(flop)},
+                             "ms_per_learned_iter": round(per_iter_s * 1e3, 3)}}
 
-            def hyb(k, _lf=kp):
-                plan.vdamp_solve_learned(cnn, ws, cws, y, mask, p, sigma2, k, 7, xh, learned_from=_lf,
-                                         stream=stream)
-            hyb(kp + L)
-            n_h = nmse()
-            t_h = timed(hyb, kp + L)[0]
-            eq = {"plain_iters_first": kp, "learned_iters": L, "seconds": round(t_h, 5), "nmse_db": round(n_h, 3),
-                  "chosen_on": f"{len(val)} validation slices, {len(cands)} schedules within the budget"}
-        k_eq = max(1, min(K, int(t_plain / t_li)))
-        learn(k_eq)
-        n_learn_eq = nmse()
-        # time to reach the plain 50-iteration NMSE
-        k_hit = None
-        for k in range(1, K + 1):
-            learn(k)
-            if nmse() <= n_plain:
-                k_hit = k
-                break
-        t_hit = timed(learn, k_hit)[0] if k_hit else None
-        kp_hit = K
-        for k in range(1, K + 1):
-            plain(k)
-            if nmse() <= n_plain + 1e-9:
-                kp_hit = k
-                break
-        tp_hit = timed(plain, kp_hit)[0]
-    cnn_ms, cnn_launch = times["cnn"]
-    reps = 3
-    flop = 2 * CNN_FLOP_PER_PX * plan.ntot  # forward + JVP per learned iteration
-    cnn_bytes = CNN_BYTES_PER_PX * plan.ntot
-    per_iter_s = cnn_ms / 1e3 / (reps * K)
-    ach = flop / per_iter_s / 1e12
-    out = {
-        "train": {"slices": len(tr), "pairs": len(tr) * len(ks), "iteration_counts": list(ks),
-                  "steps": args.train_steps, "seconds": round(train_ms / 1e3, 3),
-                  "loss_first": float(np.mean(losses[:len(ks)])), "loss_last": float(np.mean(losses[-len(ks):]))},
-        "test_slices": B,
-        "nmse_db_at_50": {"plain": round(n_plain, 3), "learned": round(n_learn, 3)},
-        "seconds_50_iters": {"plain": round(t_plain, 5), "learned": round(t_learn, 5)},
-        "equal_wallclock": {"plain_seconds": round(t_plain, 5), "plain_nmse_db": round(n_plain, 3),
-                            "learned_every_iteration": {"iters": k_eq, "nmse_db": round(n_learn_eq, 3)},
-                            "learned_last_iterations": eq,
-                            "gain_db": round(n_plain - eq["nmse_db"], 3) if eq else None},
-        "time_to_plain50_nmse": {"target_db": round(n_plain, 3),
-                                 "plain": {"iters": kp_hit, "seconds": round(tp_hit, 5)},
-                                 "learned": {"iters": k_hit, "seconds": round(t_hit, 5) if t_hit else None}},
-        "learned_band_fraction_last_iter": [round(float(v), 3) for v in sel_frac],
-        "pass_ms_per_learned_solve": {k: round(v[0] / reps, 3) for k, v in times.items()},
-        # the binding roofline of the network pass: HBM (its bytes at 8 TB/s take longer
-        # than its FLOPs at the dense BF16 peak); the MFMA rate is reported beside it
-        "cnn_roofline": {"bound": "hbm" if cnn_bytes / HBM_PEAK_GBS / 1e9 > flop / BF16_PEAK_TFLOPS / 1e12 else "mfma",
-                         "achieved": round(cnn_bytes / per_iter_s / 1e9, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(cnn_bytes / per_iter_s / 1e9 / HBM_PEAK_GBS, 4),
-                         "bytes_per_learned_iter": int(cnn_bytes),
-                         "mfma": {"achieved": round(ach, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                  "frac": round(ach / BF16_PEAK_TFLOPS, 4), "flop_per_learned_iter": int(flop)},
-                         "ms_per_learned_iter": round(per_iter_s * 1e3, 3)},
-    }
-    log(f"learned: {json.dumps(out['nmse_db_at_50'])}, equal wall-clock {json.dumps(out['equal_wallclock'])}")
+        if args.c5_batch:
+            # 512x512: one fine-tuning step on a fresh training batch, then inference
+            B5 = args.c5_batch
+            t5 = time.perf_counter()
+            tr5 = gen_slices(pool, "workload_c5", 50, 0, B5)
+            ev5 = gen_slices(pool, "workload_c5", 5, 0, B5)
+            va5 = gen_slices(pool, "workload_c5", 51, 0, 16)
+            t_gen5 = time.perf_counter() - t5
+            ks5 = (6, 13, 28)
+            store5 = T.TripleStore(B5, 512 * 512, ks5)
+            p5 = V.Plan([512] * B5, [512] * B5, LEVELS)
+            store5.add(p5, cnn, tr5, stream=stream)
+            p5.close()
+            pt5 = V.Plan([512] * B5, [512] * B5, LEVELS)
+            e0.record(stream)
+            ft = T.train_store(cnn, pt5, store5, 1, 1e-4, seed=5, stream=stream)
+            e1.record(stream)
+            stream.synchronize()
+            ft_ms = e0.elapsed_time(e1)
+            pt5.close()
+            del store5
+            torch.cuda.empty_cache()
+            test5, val5 = _Solver(cnn, ev5, stream), _Solver(cnn, va5, stream)
+            cmp5 = learned_comparison(test5, val5, K)
+            test5.close()
+            val5.close()
+            del test5, val5
+            torch.cuda.empty_cache()
+            out["c5_512x512"] = {"batch": B5, "generation_seconds": round(t_gen5, 2),
+                                 "fine_tune": {"phantoms": B5, "iteration_counts": list(ks5), "steps": 1,
+                                               "batch": B5, "ms": round(ft_ms, 2), "loss": float(ft[0])},
+                                 **cmp5}
+            log(f"512x512: {json.dumps(cmp5['equal_wallclock'])}")
     return out
 
 
@@ -401,9 +542,10 @@ def main():
     ap.add_argument("--graph", action="store_true", help="time hipGraph replays instead of eager launches")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-denoiser section")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed and 512x512 batches")
-    ap.add_argument("--train-slices", type=int, default=64)
-    ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--train-slices", type=int, default=2000, help="training phantoms (10 triples each)")
+    ap.add_argument("--train-steps", type=int, default=940)
     ap.add_argument("--test-slices", type=int, default=64)
+    ap.add_argument("--c5-batch", type=int, default=128, help="512x512 learned batch (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -413,6 +555,10 @@ def main():
               "would assign whole slices to GPUs with no communication; --gpus must be 1.",
               file=sys.stderr)
         sys.exit(2)
+
+    pool = cores = None
+    if not args.no_cpu_baseline:
+        pool, cores = make_cpu_pool()  # before anything initialises the GPU
 
     import torch
     from paper_1911_01234_amd import vdamp as V
@@ -426,6 +572,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_gbs = copy_peak()
+    print(f"[bench] device copy: {copy_gbs} GB/s", file=sys.stderr, flush=True)
     t_gen = time.perf_counter()
     slices, s, K = make_batch(args.batch)
     t_gen = time.perf_counter() - t_gen
@@ -535,38 +683,57 @@ def main():
         graph = {"slice_iterations_per_s": round(B * K * args.steps / dtg, 1),
                  "ms_per_step": round(1e3 * dtg / args.steps, 3), "bitwise_equal_to_eager": same}
 
-    # time-to-NMSE: smallest iteration count whose batch-mean NMSE is within 0.1 dB of
-    # the 50-iteration value (monitored runs), timed unmonitored
-    step(K)
-    stream.synchronize()
-    target = float(nmse_db_batch(x_hat, x0, seg, B).mean()) + 0.1
-    k_hit = K
-    for k in range(1, K + 1):
-        step(k)
-        stream.synchronize()
-        if float(nmse_db_batch(x_hat, x0, seg, B).mean()) <= target:
-            k_hit = k
-            break
-    reps = 3
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(reps):
-        step(k_hit)
-    stream.synchronize()
-    t_nmse = (time.perf_counter() - t1) / reps
-
     extra = None
     if not args.no_extra:
         extra = other_workloads(stream)
 
     learned = None
     if not args.no_learned:
-        learned = learned_section(args, slices[:args.test_slices], s, K, stream)
+        learned = learned_section(args, pool, stream)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if pool is not None:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(slices, s, K, args.cpu_budget, nmse_k)
+        cpu = cpu_baseline(pool, cores, B, K, args.cpu_budget, nmse_k)
+
+    # time-to-NMSE: the target is the oracle's batch-mean NMSE after K iterations plus
+    # 0.1 dB (the GPU's own K-iteration mean when the CPU leg is skipped); one monitored
+    # solve (x_hat after every iteration, vdamp_solve_resume's monitor output) gives the
+    # smallest iteration count whose batch mean reaches it, and unmonitored solves of
+    # that many iterations are timed
+    ref_db = cpu["oracle_nmse_db_mean"] if cpu else float(nmse_k.mean())
+    target = ref_db + 0.1
+    mon = torch.empty(K * plan.ntot, dtype=torch.complex64, device="cuda")
+    with torch.cuda.stream(stream):
+        plan.vdamp_solve_resume(ws, y, mask, p, sigma2, None, None, None, None, K, x_hat, None, mon,
+                                stream=stream)
+    stream.synchronize()
+    curve = [float(nmse_db_batch(mon[k * plan.ntot:(k + 1) * plan.ntot], x0, seg, B).mean())
+             for k in range(K)]
+    del mon
+    torch.cuda.empty_cache()
+    k_hit = next((k + 1 for k in range(K) if curve[k] <= target), None)
+    t_nmse = None
+    if k_hit is not None:
+        reps = 3
+        step(k_hit)
+        stream.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            step(k_hit)
+        stream.synchronize()
+        t_nmse = (time.perf_counter() - t1) / reps
+
+    if roofline is not None:
+        # the whole solve against the fused floor: per pixel and iteration r read and
+        # written (16 B) plus y and m/p on the sampled set (12/R B) and the mask (1/8 B),
+        # which a schedule that never leaves the CU between passes would move
+        floor_px = 16.0 + float(np.mean([12.0 / sl.R for sl in slices])) + 0.125
+        floor_gbs = floor_px * npx * K / (ms_per_step / 1e3) / 1e9
+        roofline["fused_floor"] = {"bytes_per_px_iter": round(floor_px, 3), "achieved_GBs": round(floor_gbs, 1),
+                                   "frac": round(floor_gbs / HBM_PEAK_GBS, 4)}
+        roofline["copy_peak_GBs"] = copy_gbs
+        roofline["frac_of_copy_peak"] = round(roofline["achieved"] / copy_gbs, 4)
 
     out = {
         "metric": METRIC,
@@ -588,7 +755,11 @@ def main():
         "mpx_iterations_per_s": round(value * 65536 / 1e6, 1),
         "hipgraph": graph,
         "kernel_event_run": events_run,
-        "time_to_nmse": {"target_db": round(target, 3), "iters": k_hit, "seconds": round(t_nmse, 5)},
+        "time_to_nmse": {"target_db": round(target, 3),
+                         "target_from": (f"oracle batch mean over {cpu['oracle_slices']} slices after {K} "
+                                         "iterations + 0.1 dB") if cpu else f"GPU batch mean after {K} iterations + 0.1 dB",
+                         "iters": k_hit, "seconds": round(t_nmse, 5) if t_nmse else None,
+                         "nmse_db_by_iteration": [round(v, 3) for v in curve]},
         "plan_seconds": round(t_plan, 4),
         "roofline": roofline,
         "pass_ms_per_step": {k: round(v, 4) for k, v in pass_ms.items()} if pass_ms else None,

@@ -224,9 +224,29 @@ def workload_mixed(n_per_size: int = 128, sizes=(128, 192, 256, 320), cfg_id: in
 
 def workload_batch512(batch: int, cfg_id: int = 5, Rs=(8.0, 12.0), first_slice: int = 0):
     """512x512 slices: 32 ellipses plus textured regions (filtered Gaussian noise),
-    p ~ (1-r)^6 with a 32x32 centre, R cycling over Rs (8x and 12x), 40 dB, 4 Haar levels,
-    50 iterations."""
+    p ~ (1-r)^6 with a 16x16 centre, R cycling over Rs (8x and 12x), 40 dB, 4 Haar levels,
+    50 iterations (the recipe of workload_c5)."""
     out = []
     for b in range(first_slice, first_slice + batch):
-        out.append(make_slice(cfg_id, b, 512, 512, 32, Rs[b % len(Rs)], 6.0, 32, 40.0, texture=True))
+        out.append(make_slice(cfg_id, b, 512, 512, 32, Rs[b % len(Rs)], 6.0, 16, 40.0, texture=True))
     return out, 4, 50
+
+
+def workload_c4(n: int, cfg_id: int = 40, first_slice: int = 0):
+    """Slices for the learned denoiser at 256x256 (training cfg_id 40, evaluation 41,
+    validation 42): the single-256 recipe (16 ellipses, p ~ (1-r)^6, 16x16 centre) with
+    R ~ U{4, 6, 8} and SNR ~ U[30, 45] dB drawn per slice from the slice's own seeds;
+    4 Haar levels, 50 iterations."""
+    out = []
+    for b in range(first_slice, first_slice + n):
+        rng = rng_for(cfg_id, b, 5)
+        R = float(rng.choice([4.0, 6.0, 8.0]))
+        snr = float(rng.uniform(30.0, 45.0))
+        out.append(make_slice(cfg_id, b, 256, 256, 16, R, 6.0, 16, snr))
+    return out, 4, 50
+
+
+def workload_c5(n: int, cfg_id: int = 5, first_slice: int = 0):
+    """512x512 textured slices for the learned denoiser at scale (evaluation cfg_id 5,
+    training 50): workload_batch512's recipe, R alternating 8 and 12."""
+    return workload_batch512(n, cfg_id=cfg_id, first_slice=first_slice)
