@@ -138,12 +138,27 @@ def other_workloads(stream, reps=3):
             times = plan.vdamp_pass_times()
             nm = float(nmse_db_batch(xh, x0, seg, len(slices)).mean())
             plan.close()
-        del ws, y, mask, p, sigma2, xh, x0, seg
+            # the same solves captured once in a hipGraph (VDAMP_FLAG_USE_GRAPH) and replayed
+            gplan = V.Plan(ny, nx, s, V.VDAMP_FLAG_USE_GRAPH | V.VDAMP_FLAG_AUTOTUNE)
+            gws = gplan.workspace()
+            gx = torch.empty_like(xh)
+            gplan.vdamp_solve(gws, y, mask, p, sigma2, K, gx, stream=stream)
+            stream.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                gplan.vdamp_solve(gws, y, mask, p, sigma2, K, gx, stream=stream)
+            stream.synchronize()
+            dtg = (time.perf_counter() - t) / reps
+            gsame = bool(torch.equal(gx, xh))
+            gplan.close()
+        del ws, y, mask, p, sigma2, xh, x0, seg, gws, gx
         torch.cuda.empty_cache()
         res[name] = {"slices": len(slices), "pixels": npx, "iters": K,
                      "seconds_per_solve": round(dt, 5),
                      "slice_iterations_per_s": round(len(slices) * K / dt, 1),
                      "mpx_iterations_per_s": round(npx * K / dt / 1e6, 1),
+                     "hipgraph": {"slice_iterations_per_s": round(len(slices) * K / dtg, 1),
+                                  "bitwise_equal_to_eager": gsame},
                      "nmse_db_mean": round(nm, 3),
                      "passes": pass_rooflines(times, npx, K, reps),
                      "plan_seconds_with_autotune": round(t_plan, 3),

@@ -181,7 +181,7 @@ vdamp_status vdamp_solve_resume(vdamp_plan_h plan, hipStream_t stream, void* wor
  * (code under hipGraph capture, tight serving loops, harnesses that forbid allocation).
  * The workspace is a device array inside the library, VDAMP_NOALLOC_MAX_WORKSPACE bytes
  * per GPU, held from the first call on that GPU until the process ends; the call itself
- * allocates nothing (no hipMalloc, hipFree, graph instantiation or events: launches are
+ * allocates nothing (no hipMalloc, hipFree, graph instantiation or event creation: launches are
  * always eager, VDAMP_FLAG_USE_GRAPH and VDAMP_FLAG_TIMING of the plan are ignored).
  *   plan            as for vdamp_solve; its workspace_bytes must not exceed
  *                   VDAMP_NOALLOC_MAX_WORKSPACE, else VDAMP_ERR_WORKSPACE (nothing enqueued)

@@ -60,6 +60,11 @@ void free_plan(vdamp_plan_t* P) {
   if (P->gexec) hipGraphExecDestroy(P->gexec);
   if (P->graph) hipGraphDestroy(P->graph);
   for (auto e : P->ev_pool) hipEventDestroy(e);
+  for (int i = 0; i < vdamp_plan_t::kForks; ++i) {
+    if (P->side[i]) hipStreamDestroy(P->side[i]);
+    if (P->ev_join[i]) hipEventDestroy(P->ev_join[i]);
+  }
+  if (P->ev_fork) hipEventDestroy(P->ev_fork);
   hipFree(P->d_slices);
   hipFree(P->d_ffts);
   hipFree(P->d_tw);
@@ -504,6 +509,13 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   if (e == hipSuccess) e = upload(P->d_tiles, tiles);
   if (e == hipSuccess) e = upload(P->d_tile_off, P->tile_off);
   if (e == hipSuccess) e = set_lds_limits_passes(sizeof(float2) * kMaxElems, sizeof(float2) * kMaxElems);
+  if (e == hipSuccess && (P->row_groups.size() > 1 || P->col_groups.size() > 1)) {
+    for (int i = 0; i < vdamp_plan_t::kForks && e == hipSuccess; ++i) {
+      e = hipStreamCreateWithFlags(&P->side[i], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
     free_plan(P);
     return fail(VDAMP_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));

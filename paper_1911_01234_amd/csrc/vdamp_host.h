@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cstring>
 #include <map>
@@ -102,6 +103,12 @@ struct vdamp_plan_t {
   // last solve
   const void* state_ws = nullptr;
   bool has_state = false;
+  // side streams (default priority) on which the launches of a pass's other size groups
+  // run beside the first group's, forked from and joined back into the caller's stream
+  // with events; created at plan time only for plans with more than one size group
+  static constexpr int kForks = 3;
+  hipStream_t side[kForks] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kForks] = {};
   // graph cache
   GraphKey gkey;
   hipGraphExec_t gexec = nullptr;
@@ -185,38 +192,64 @@ struct Launcher {
     HIP_TRY((L).end());                                                                 \
   } while (0)
 
-// Every column strip of the plan: one launch per run of equal ny.
-inline hipError_t launch_cols_all(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
-  for (const auto& g : P->col_groups) {
-    a.work = P->d_work_cols + g[0];
-    a.nwork = g[1];
-    hipError_t e = g[2] ? launch_cols4(a, g[2], st) : launch_cols(a, P->ept, P->lds_cols, st);
-    if (e != hipSuccess) return e;
+// The launches of a pass, one per size group, with group i on stream i mod (1 + kForks)
+// (stream 0 the caller's): the side streams wait for everything enqueued before the
+// pass and the caller's stream waits for them after it, so the groups of a ragged batch
+// fill each other's tails while the pass as a whole stays ordered; under graph capture
+// the same events make parallel branches.  With one group (or no side streams) every
+// launch goes to the caller's stream.
+template <class F>
+inline hipError_t launch_groups(const vdamp_plan_t* P, int ngroups, hipStream_t st, F&& launch) {
+  const int nside = (ngroups > 1 && P->side[0]) ? std::min(ngroups - 1, (int)vdamp_plan_t::kForks) : 0;
+  hipError_t e = hipSuccess;
+  if (nside) {
+    if ((e = hipEventRecord(P->ev_fork, st)) != hipSuccess) return e;
+    for (int i = 0; i < nside; ++i)
+      if ((e = hipStreamWaitEvent(P->side[i], P->ev_fork, 0)) != hipSuccess) return e;
+  }
+  for (int g = 0; g < ngroups; ++g) {
+    const int lane = nside ? g % (nside + 1) : 0;
+    if ((e = launch(g, lane ? P->side[lane - 1] : st)) != hipSuccess) return e;
+  }
+  for (int i = 0; i < nside; ++i) {
+    if ((e = hipEventRecord(P->ev_join[i], P->side[i])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(st, P->ev_join[i], 0)) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// Every column strip of the plan: one launch per run of equal ny.
+inline hipError_t launch_cols_all(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
+  return launch_groups(P, (int)P->col_groups.size(), st, [&](int i, hipStream_t s) {
+    const auto& g = P->col_groups[i];
+    KArgs b = a;
+    b.work = P->d_work_cols + g[0];
+    b.nwork = g[1];
+    return g[2] ? launch_cols4(b, g[2], s) : launch_cols(b, P->ept, P->lds_cols, s);
+  });
 }
 
 // Every row strip of the plan through the transform passes: one launch per run of equal
 // nx (line 8 + Psi^H + row FFT, and row IFFT + Psi + line 4).
 inline hipError_t launch_rows_synth_all(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
-  for (const auto& g : P->row_groups) {
-    a.work = P->d_work_rows + g[0];
-    a.nwork = g[1];
-    hipError_t e = g[2] ? launch_rows_synth4(a, g[2], rows4_lds_bytes(g[2], 1 << P->levels), st)
-                        : launch_rows_synth(a, P->ept, 1, P->lds_rows, st);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return launch_groups(P, (int)P->row_groups.size(), st, [&](int i, hipStream_t s) {
+    const auto& g = P->row_groups[i];
+    KArgs b = a;
+    b.work = P->d_work_rows + g[0];
+    b.nwork = g[1];
+    return g[2] ? launch_rows_synth4(b, g[2], rows4_lds_bytes(g[2], 1 << P->levels), s)
+                : launch_rows_synth(b, P->ept, 1, P->lds_rows, s);
+  });
 }
 inline hipError_t launch_rows_anal_all(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
-  for (const auto& g : P->row_groups) {
-    a.work = P->d_work_rows + g[0];
-    a.nwork = g[1];
-    hipError_t e = g[2] ? launch_rows_anal4(a, g[2], rows4_lds_bytes(g[2], 1 << P->levels), st)
-                        : launch_rows_anal(a, P->ept, P->lds_rows, st);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return launch_groups(P, (int)P->row_groups.size(), st, [&](int i, hipStream_t s) {
+    const auto& g = P->row_groups[i];
+    KArgs b = a;
+    b.work = P->d_work_rows + g[0];
+    b.nwork = g[1];
+    return g[2] ? launch_rows_anal4(b, g[2], rows4_lds_bytes(g[2], 1 << P->levels), s)
+                : launch_rows_anal(b, P->ept, P->lds_rows, s);
+  });
 }
 
 // Every band's threshold search (line 6): one launch per size class, largest first.
