@@ -79,7 +79,13 @@ enum {
      synchronises), and keep the fastest (3 % margin in favour of the default).  The FFT
      choice changes results at FP32 rounding level; the choice is fixed for the plan.
      vdamp_plan_describe() reports the measurements. */
-  VDAMP_FLAG_AUTOTUNE = 1u << 6
+  VDAMP_FLAG_AUTOTUNE = 1u << 6,
+  /* Threshold search over every theta > 0 instead of the candidates theta in {|r_i|}
+     (Section 3 solves the SURE problem "approximately"; this is its exact minimiser):
+     between consecutive distinct magnitudes SURE is a convex quadratic in theta, whose
+     minimum tau R_m / (2 (N_b - m)) competes with the candidates when it lies inside its
+     interval.  Line 7's alpha and line 6's eta use the threshold found. */
+  VDAMP_FLAG_SURE_CONTINUOUS = 1u << 7
 };
 
 /* Kernel classes reported by vdamp_pass_times(). */

@@ -196,6 +196,44 @@ def sure_threshold(a, tau):
     return theta, alpha, mm, float(sure_v[i])
 
 
+def sure_threshold_continuous(a, tau):
+    """SURE-minimising threshold over every theta > 0, not only the candidates |r_i|
+    (the paper's SURE step is solved "approximately"; this is the exact minimiser).
+
+    Between consecutive distinct sorted magnitudes, theta in (a_(m), a_(m+1)) with m
+    magnitudes at or below theta, SURE(theta) = A_m - m tau + (N_b - m)(theta^2 + tau)
+    - tau theta R_m is a convex quadratic, minimised at theta* = tau R_m / (2 (N_b - m));
+    theta* counts where it lies strictly inside its interval (the interval below the
+    smallest positive magnitude starts at 0).  The candidates a_(m) themselves are those
+    of sure_threshold.  The smallest value wins, ties to the smaller theta.
+    Returns (theta, alpha, m, sure_min), alpha = ((N_b - m) - (theta/2) R_m) / N_b."""
+    a = np.sort(np.asarray(a, dtype=np.float64).ravel())
+    n = a.size
+    th_d, al_d, m_d, v_d = sure_threshold(a, tau)
+    if a[-1] == 0.0:
+        return th_d, al_d, m_d, v_d
+    best = (v_d, th_d, m_d)
+    A = np.concatenate([[0.0], np.cumsum(a ** 2)])          # A[m] = sum of the m smallest
+    inv = np.where(a > 0, 1.0 / np.where(a > 0, a, 1.0), 0.0)
+    Rs = np.concatenate([np.cumsum(inv[::-1])[::-1], [0.0]])  # Rs[m] = sum over indices >= m
+    for m in range(n):
+        if m > 0 and not a[m - 1] < a[m]:
+            continue                                          # m must end a run
+        lo = a[m - 1] if m > 0 else 0.0
+        hi = a[m]
+        if hi == 0.0:
+            continue
+        R = Rs[m]
+        t = tau * R / (2.0 * (n - m))
+        if lo < t < hi:
+            v = A[m] - m * tau + (n - m) * (t * t + tau) - tau * t * R
+            if v < best[0] or (v == best[0] and t < best[1]):
+                best = (v, t, m)
+    v, t, m = best
+    R = Rs[m]
+    return float(t), float(((n - m) - 0.5 * t * R) / n), int(m), float(v)
+
+
 def sure_threshold_brute(a, tau):
     """O(N_b^2) reference for sure_threshold: evaluate sure_value at every candidate."""
     a = np.asarray(a, dtype=np.float64).ravel()
@@ -239,11 +277,12 @@ def vdamp_step(rt, y, mask, p, sigma2, s, S):
     return r, tau
 
 
-def denoise(r, tau, s, theta_override=None, alpha_override=None):
+def denoise(r, tau, s, theta_override=None, alpha_override=None, continuous=False):
     """Lines 6-8: per band SURE threshold, eta, alpha, and the corrected r_tilde_{k+1}.
     theta_override (optional, per band) replaces the SURE search; alpha then follows
     from its definition at that threshold unless alpha_override gives it too (a test
-    that replays another implementation's decisions supplies both)."""
+    that replays another implementation's decisions supplies both).  continuous=True
+    minimises SURE over every theta > 0 (sure_threshold_continuous)."""
     ny, nx = r.shape
     w_hat = np.zeros_like(r)
     rt_next = np.zeros_like(r)
@@ -251,7 +290,8 @@ def denoise(r, tau, s, theta_override=None, alpha_override=None):
     for b, (rs, cs, _, _) in enumerate(bands(ny, nx, s)):
         rb = r[rs, cs]
         if theta_override is None:
-            th, al, _, _ = sure_threshold(np.abs(rb), tau[b])
+            search = sure_threshold_continuous if continuous else sure_threshold
+            th, al, _, _ = search(np.abs(rb), tau[b])
         else:
             th = float(theta_override[b])
             al = (wirtinger_mean_soft(rb, th) if alpha_override is None
@@ -272,9 +312,10 @@ def output_step(w_hat, y, mask, s):
     return x + ifft2u(resid)
 
 
-def vdamp(y, mask, p, sigma2, s, iters, record=False):
+def vdamp(y, mask, p, sigma2, s, iters, record=False, continuous=False):
     """Algorithm 1 in FP64.  y: zero-filled measurements (natural order), mask: 0/1,
     p: sampling probabilities (used on Omega), sigma2: E|eps_j|^2, s: Haar levels.
+    continuous=True takes each threshold as SURE's minimiser over every theta > 0.
     Returns dict with x_hat and, per iteration, tau, theta, alpha (and r if record)."""
     y = np.asarray(y, dtype=np.complex128)
     p = np.asarray(p, dtype=np.float64)
@@ -286,7 +327,7 @@ def vdamp(y, mask, p, sigma2, s, iters, record=False):
     taus, thetas, alphas, rs = [], [], [], []
     for _ in range(iters):
         r, tau = vdamp_step(rt, y, mask, p, sigma2, s, S)
-        w_hat, rt, th, al = denoise(r, tau, s)
+        w_hat, rt, th, al = denoise(r, tau, s, continuous=continuous)
         taus.append(tau)
         thetas.append(th)
         alphas.append(al)
@@ -300,7 +341,7 @@ def vdamp(y, mask, p, sigma2, s, iters, record=False):
     return out
 
 
-def vdamp_resume(y, mask, p, sigma2, s, r, theta, alpha, iters, record=False):
+def vdamp_resume(y, mask, p, sigma2, s, r, theta, alpha, iters, record=False, continuous=False):
     """Algorithm 1 continued from the state (r_k, theta_k, alpha_k) of an earlier
     iteration: every further iteration starts with lines 6-8 applied to the previous
     state (eta with the given thresholds, line 8 with the given alpha), then lines 3-7.
@@ -316,7 +357,7 @@ def vdamp_resume(y, mask, p, sigma2, s, r, theta, alpha, iters, record=False):
     taus, thetas, alphas, rs = [], [], [], []
     for _ in range(iters):
         r, tau = vdamp_step(rt, y, mask, p, sigma2, s, S)
-        w_hat, rt, th, al = denoise(r, tau, s)
+        w_hat, rt, th, al = denoise(r, tau, s, continuous=continuous)
         taus.append(tau)
         thetas.append(th)
         alphas.append(al)

@@ -318,7 +318,7 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   if (wavelet != VDAMP_WAVELET_HAAR) return fail(VDAMP_ERR_UNSUPPORTED, "only the Haar wavelet is implemented");
   if (levels < 1 || levels > 4) return fail(VDAMP_ERR_UNSUPPORTED, "levels must be in 1..4");
   const uint32_t known = VDAMP_FLAG_DETERMINISTIC | VDAMP_FLAG_USE_GRAPH | VDAMP_FLAG_CHECK_FINITE |
-                         VDAMP_FLAG_TIMING | VDAMP_FLAG_AUTOTUNE;
+                         VDAMP_FLAG_TIMING | VDAMP_FLAG_AUTOTUNE | VDAMP_FLAG_SURE_CONTINUOUS;
   if (flags & ~known) return fail(VDAMP_ERR_ARG, "unknown flag bits");
   const int H = 1 << levels;
   std::vector<int> rad;

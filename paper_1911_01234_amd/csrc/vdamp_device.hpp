@@ -379,7 +379,12 @@ __device__ __forceinline__ int strip_to_global(int lr, int lc, int strip, int s,
 // membership, so both see bit-identical values (as does any host computing
 // x*x + y*y in IEEE FP32).
 __device__ __forceinline__ float key_rn(float2 v) {
-  return __fadd_rn(__fmul_rn(v.x, v.x), __fmul_rn(v.y, v.y));
+#pragma clang fp contract(off)
+  // (without the pragma the compiler fuses the add into the second multiply, an FMA
+  // with a single rounding, and the key differs from x*x + y*y by an ulp)
+  const float xx = v.x * v.x;
+  const float yy = v.y * v.y;
+  return xx + yy;
 }
 
 // eta(r; theta) = r max(0, 1 - theta/|r|); zero when |r|^2 <= theta^2 (th2 is the

@@ -284,6 +284,7 @@ inline KArgs base_args(const vdamp_plan_t* P, const Ws& w) {
   a.alpha = w.alpha;
   a.tau = w.tau;
   a.tau_part = w.taup;
+  a.sure_cont = (P->flags & VDAMP_FLAG_SURE_CONTINUOUS) ? 1 : 0;
   return a;
 }
 

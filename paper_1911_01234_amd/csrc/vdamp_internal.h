@@ -102,6 +102,7 @@ struct KArgs {
   int iter;
   float beta;                // FISTA momentum factor for this iteration
   int mode;
+  int sure_cont;             // threshold search over every theta > 0, not only the keys
 };
 
 }  // namespace vdamp

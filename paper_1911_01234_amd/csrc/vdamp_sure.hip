@@ -84,6 +84,179 @@ __device__ __forceinline__ int sure_bucket(float key, float inv_tau) {
 // contiguous 16-key chunks hit distinct banks.
 __device__ __forceinline__ int skx(int i) { return i + (i >> 4); }
 
+// The best threshold found so far by a thread: SURE value v; m keys at or below the
+// threshold; R = sum of 1/a over the keys above it; key = the FP32 key thresholding
+// compares |r|^2 against; for a threshold strictly between two keys (continuous search)
+// inner = 1 and th its value, else theta = sqrt(key).  Order: smaller v, then smaller m,
+// then a key before a threshold just above it (ties go to the smaller theta).
+struct SureBest {
+  double v, R, th;
+  int m, inner;
+  float key;
+};
+__device__ __forceinline__ bool sure_better(double v, int m, int inner, const SureBest& b) {
+  return v < b.v || (v == b.v && (m < b.m || (m == b.m && inner < b.inner)));
+}
+__device__ __forceinline__ SureBest sure_none() {
+  SureBest b;
+  b.v = __builtin_huge_val();
+  b.R = 0.0;
+  b.th = 0.0;
+  b.m = 0x7fffffff;
+  b.inner = 0;
+  b.key = 0.f;
+  return b;
+}
+
+// Continuous search inside an open interval between keys klo < khi holding m keys at or
+// below it, with A = sum of those keys and R = sum of 1/a above: SURE is the convex
+// quadratic A - m tau + (N_b - m)(theta^2 + tau) - tau theta R, minimised at
+// theta* = tau R / (2 (N_b - m)); it counts when sqrt(klo) < theta* < sqrt(khi).  Its key
+// is fl(theta*)^2 kept inside [klo, khi) so that thresholding keeps exactly the keys
+// above the interval.
+__device__ __forceinline__ void sure_inner(float klo, float khi, double A, int m, double R, double tau,
+                                           double Nbd, SureBest& best) {
+  const double nm = Nbd - (double)m;
+  if (!(nm > 0.0) || !(R > 0.0)) return;
+  const double t = tau * R / (2.0 * nm);
+  if (!(t > sqrt((double)klo)) || !(t < sqrt((double)khi))) return;
+  const double v = A - (double)m * tau + nm * (t * t + tau) - tau * t * R;
+  if (!sure_better(v, m, 1, best)) return;
+  const float tf = (float)t;
+  float key = __fmul_rn(tf, tf);
+  if (!(key < khi)) key = __uint_as_float(__float_as_uint(khi) - 1u);  // largest float below khi
+  if (key < klo) key = klo;
+  best.v = v;
+  best.m = m;
+  best.inner = 1;
+  best.R = R;
+  best.key = key;
+  best.th = t;
+}
+
+// SURE at every candidate of the sorted keys: each thread walks a contiguous chunk with
+// a = sqrt(key), A_m = sum_{i<=m} a_i^2 and R_m = sum_{i>m} 1/a_i (FP64 accumulation of
+// FP32 terms, chunk offsets from FP64 prefix/suffix scans) and evaluates
+// SURE(m) = A_m - m tau + (N_b - m)(a_m^2 + tau) - tau a_m R_m at the last index of each
+// run of equal keys with a > 0; with cont, also the quadratic's minimum inside every
+// interval between distinct keys (sure_inner), from 0 up to the smallest positive key
+// onwards.  Per thread the best (SureBest).
+template <int NT, bool CONT>
+__device__ void sure_walk_t(const float* sk, int Nb, double tau, double* wsA, double* wsR, SureBest& best) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int E = (Nb + NT - 1) / NT;
+  const int i0 = tid * E;
+  const int i1 = min(i0 + E, Nb);
+  double cA = 0.0, cR = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    const float k2 = sk[skx(i)];
+    cA += (double)k2;
+    if (k2 > 0.f) cR += (double)__frsqrt_rn(k2);
+  }
+  const double pA = wave_incl_prefix(cA, lane);
+  const double sR = wave_incl_suffix(cR, lane);
+  if (lane == 63) wsA[wid] = pA;
+  if (lane == 0) wsR[wid] = sR;
+  __syncthreads();
+  const double offA = wave_offset_prefix<NW>(wsA, wid, lane);
+  const double offR = wave_offset_suffix<NW>(wsR, wid, lane);
+  double A = offA + pA - cA;          // sum of a^2 over indices < i0
+  double Rrun = offR + sR;            // sum of 1/a over indices >= i0
+  best = sure_none();
+  const double Nbd = (double)Nb;
+  float knext = (i0 < i1) ? sk[skx(i0)] : 0.f;
+  float kprev = (CONT && i0 > 0 && i0 < i1) ? sk[skx(i0 - 1)] : 0.f;
+  for (int i = i0; i < i1; ++i) {
+    const float k2 = knext;
+    knext = (i + 1 < Nb) ? sk[skx(i + 1)] : __builtin_huge_valf();
+    if (CONT && k2 > 0.f && !(kprev > 0.f))  // the interval (0, a_i) below the first positive key
+      sure_inner(0.f, k2, A, i, Rrun, tau, Nbd, best);
+    A += (double)k2;
+    if (k2 > 0.f) {
+      Rrun -= (double)__frsqrt_rn(k2);  // now the sum over indices > i
+      if (knext > k2) {                 // last index of a run of equal keys
+        const double x = (double)__fsqrt_rn(k2);
+        const double m = (double)(i + 1);
+        const double sv = A - m * tau + (Nbd - m) * ((double)k2 + tau) - tau * x * Rrun;
+        // a thread's candidates come in increasing m, so without inner thresholds a
+        // strictly smaller value is the only way to win
+        if (CONT ? sure_better(sv, i + 1, 0, best) : sv < best.v) {
+          best.v = sv;
+          best.m = i + 1;
+          best.inner = 0;
+          best.R = Rrun;
+          best.key = k2;
+        }
+        if (CONT && i + 1 < Nb) sure_inner(k2, knext, A, i + 1, Rrun, tau, Nbd, best);
+      }
+    }
+    if (CONT) kprev = k2;
+  }
+}
+template <int NT>
+__device__ void sure_walk(const float* sk, int Nb, double tau, bool cont, double* wsA, double* wsR,
+                          SureBest& best) {
+  if (cont)
+    sure_walk_t<NT, true>(sk, Nb, tau, wsA, wsR, best);
+  else
+    sure_walk_t<NT, false>(sk, Nb, tau, wsA, wsR, best);
+}
+
+// Workgroup argmin of the per-thread bests (sure_better), then theta (sqrt(key) for a
+// key, the continuous minimiser otherwise), its key and alpha = ((N_b - m) - theta R /
+// 2) / N_b (line 7) for the band, and the band's outputs.  No candidate (every key
+// zero): eta = 0, alpha = 0.
+template <int NT>
+__device__ void sure_finish(const KArgs& a, int sl, int b, int Nb, float tau_f, SureBest best,
+                            SureBest* fin) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    SureBest ob;
+    ob.v = __shfl_xor(best.v, o, 64);
+    ob.m = __shfl_xor(best.m, o, 64);
+    ob.inner = __shfl_xor(best.inner, o, 64);
+    ob.R = __shfl_xor(best.R, o, 64);
+    ob.th = __shfl_xor(best.th, o, 64);
+    ob.key = __shfl_xor(best.key, o, 64);
+    if (sure_better(ob.v, ob.m, ob.inner, best)) best = ob;
+  }
+  if (lane == 0) fin[wid] = best;
+  __syncthreads();
+  if (tid == 0) {
+    SureBest f = fin[0];
+    for (int w = 1; w < NW; ++w)
+      if (sure_better(fin[w].v, fin[w].m, fin[w].inner, f)) f = fin[w];
+    const double Nbd = (double)Nb, tau = (double)tau_f;
+    const bool none = f.m == 0x7fffffff;
+    float th, th2, al;
+    if (none) {
+      th = 0.f;
+      th2 = 0.f;
+      al = 0.f;
+    } else {
+      th2 = f.key;
+      th = f.inner ? (float)f.th : __fsqrt_rn(th2);
+      const double m = (double)f.m;
+      al = (float)(((Nbd - m) - 0.5 * (double)th * f.R) / Nbd);
+    }
+    if (a.smin)  // every key zero: eta = 0 gives SURE = -N_b tau
+      a.smin[sl * kMaxBands + b] = none ? (float)(-Nbd * tau) : (float)f.v;
+    a.theta[sl * kMaxBands + b] = th;
+    a.thr2[sl * kMaxBands + b] = th2;
+    a.alpha[sl * kMaxBands + b] = al;
+    a.tau[sl * kMaxBands + b] = tau_f;
+    if (a.trace) {
+      float* t = a.trace + (((long long)a.iter * a.batch + sl) * a.nbands + b) * 3;
+      t[0] = tau_f;
+      t[1] = th;
+      t[2] = al;
+    }
+  }
+}
+
 // Exact SURE threshold search for one band (Section 3), one workgroup per band.
 //   1. tau_b from the column-strip partials (FP64, fixed order).
 //   2. keys = |r|^2 (FP32, see key_rn) held in registers; counting sort by
@@ -124,8 +297,9 @@ k_sure(KArgs a) {
   __shared__ __align__(16) int sure_smem[sure_smem_words(NB, MAXK, KPT)];
   constexpr int NW = NT / 64;
   constexpr int BPT = NB / NT;
-  __shared__ double wsA[NW], wsR[NW], bv[NW], bR[NW];
-  __shared__ int bi[NW], wsC[NW], wsM[NW];
+  __shared__ double wsA[NW], wsR[NW];
+  __shared__ int wsC[NW], wsM[NW];
+  __shared__ SureBest fin[NW];
   __shared__ float tau_sh;
   __shared__ int maxc_sh;
   int* off = sure_smem;                                                 // [NB + 1]
@@ -315,82 +489,9 @@ k_sure(KArgs a) {
       }
     }
   }
-  const double tau = (double)tau_sh;
-  const float kmax = sk[skx(Nb - 1)];
-  const int E = (Nb + NT - 1) / NT;
-  const int i0 = tid * E;
-  const int i1 = min(i0 + E, Nb);
-  double cA = 0.0, cR = 0.0;
-  for (int i = i0; i < i1; ++i) {
-    const float k2 = sk[skx(i)];
-    cA += (double)k2;
-    if (k2 > 0.f) cR += (double)__frsqrt_rn(k2);
-  }
-  const double pA = wave_incl_prefix(cA, lane);
-  const double sR = wave_incl_suffix(cR, lane);
-  if (lane == 63) wsA[wid] = pA;
-  if (lane == 0) wsR[wid] = sR;
-  __syncthreads();
-  const double offA = wave_offset_prefix<NW>(wsA, wid, lane);
-  const double offR = wave_offset_suffix<NW>(wsR, wid, lane);
-  double A = offA + pA - cA;          // sum of a^2 over indices < i0
-  double Rrun = offR + sR;            // sum of 1/a over indices >= i0
-  double best = __builtin_huge_val(), bestR = 0.0;
-  int besti = 0x7fffffff;
-  const double Nbd = (double)Nb;
-  float knext = (i0 < i1) ? sk[skx(i0)] : 0.f;
-  for (int i = i0; i < i1; ++i) {
-    const float k2 = knext;
-    knext = (i + 1 < Nb) ? sk[skx(i + 1)] : __builtin_huge_valf();
-    A += (double)k2;
-    if (k2 > 0.f) {
-      Rrun -= (double)__frsqrt_rn(k2);  // now the sum over indices > i
-      if (knext > k2) {                 // last index of a run of equal keys
-        const double x = (double)__fsqrt_rn(k2);
-        const double m = (double)(i + 1);
-        const double sv = A - m * tau + (Nbd - m) * ((double)k2 + tau) - tau * x * Rrun;
-        if (sv < best) { best = sv; besti = i; bestR = Rrun; }
-      }
-    }
-  }
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const double ov = __shfl_xor(best, o, 64);
-    const int oi = __shfl_xor(besti, o, 64);
-    const double oR = __shfl_xor(bestR, o, 64);
-    if (ov < best || (ov == best && oi < besti)) { best = ov; besti = oi; bestR = oR; }
-  }
-  if (lane == 0) { bv[wid] = best; bi[wid] = besti; bR[wid] = bestR; }
-  __syncthreads();
-  if (tid == 0) {
-    double fb = bv[0], fR = bR[0];
-    int fi = bi[0];
-    for (int w = 1; w < NW; ++w)
-      if (bv[w] < fb || (bv[w] == fb && bi[w] < fi)) { fb = bv[w]; fi = bi[w]; fR = bR[w]; }
-    float th, th2, al;
-    if (!(kmax > 0.f) || fi == 0x7fffffff) {  // all-zero band: eta = 0, alpha = 0
-      th = 0.f;
-      th2 = 0.f;
-      al = 0.f;
-    } else {
-      th2 = sk[skx(fi)];
-      th = __fsqrt_rn(th2);
-      const double m = (double)(fi + 1);
-      al = (float)(((Nbd - m) - 0.5 * (double)th * fR) / Nbd);
-    }
-    if (a.smin)  // all-zero band: eta = 0 gives SURE = -N_b tau
-      a.smin[sl * kMaxBands + b] = (!(kmax > 0.f) || fi == 0x7fffffff) ? (float)(-Nbd * tau) : (float)fb;
-    a.theta[sl * kMaxBands + b] = th;
-    a.thr2[sl * kMaxBands + b] = th2;
-    a.alpha[sl * kMaxBands + b] = al;
-    a.tau[sl * kMaxBands + b] = tau_sh;
-    if (a.trace) {
-      float* t = a.trace + (((long long)a.iter * a.batch + sl) * a.nbands + b) * 3;
-      t[0] = tau_sh;
-      t[1] = th;
-      t[2] = al;
-    }
-  }
+  SureBest best;
+  sure_walk<NT>(sk, Nb, (double)tau_sh, a.sure_cont != 0, wsA, wsR, best);
+  sure_finish<NT>(a, sl, b, Nb, tau_sh, best, fin);
 }
 
 // In-place ascending sort of the keys sk[skx(0 .. Nb)) by a bitonic network whose
@@ -421,108 +522,6 @@ __device__ void sure_bitonic(float* sk, int Nb, int npad) {
         }
       }
       __syncthreads();
-    }
-  }
-}
-
-// SURE at every candidate of the sorted keys: each thread walks a contiguous chunk with
-// a = sqrt(key), A_m = sum_{i<=m} a_i^2 and R_m = sum_{i>m} 1/a_i (FP64 accumulation of
-// FP32 terms, chunk offsets from FP64 prefix/suffix scans) and evaluates
-// SURE(m) = A_m - m tau + (N_b - m)(a_m^2 + tau) - tau a_m R_m at the last index of each
-// run of equal keys with a > 0; per thread the best (value, index, R_m, key).
-template <int NT>
-__device__ void sure_walk(const float* sk, int Nb, double tau, double* wsA, double* wsR,
-                          double& best, int& besti, double& bestR, float& bestK) {
-  constexpr int NW = NT / 64;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int E = (Nb + NT - 1) / NT;
-  const int i0 = tid * E;
-  const int i1 = min(i0 + E, Nb);
-  double cA = 0.0, cR = 0.0;
-  for (int i = i0; i < i1; ++i) {
-    const float k2 = sk[skx(i)];
-    cA += (double)k2;
-    if (k2 > 0.f) cR += (double)__frsqrt_rn(k2);
-  }
-  const double pA = wave_incl_prefix(cA, lane);
-  const double sR = wave_incl_suffix(cR, lane);
-  if (lane == 63) wsA[wid] = pA;
-  if (lane == 0) wsR[wid] = sR;
-  __syncthreads();
-  const double offA = wave_offset_prefix<NW>(wsA, wid, lane);
-  const double offR = wave_offset_suffix<NW>(wsR, wid, lane);
-  double A = offA + pA - cA;          // sum of a^2 over indices < i0
-  double Rrun = offR + sR;            // sum of 1/a over indices >= i0
-  best = __builtin_huge_val();
-  bestR = 0.0;
-  besti = 0x7fffffff;
-  bestK = 0.f;
-  const double Nbd = (double)Nb;
-  float knext = (i0 < i1) ? sk[skx(i0)] : 0.f;
-  for (int i = i0; i < i1; ++i) {
-    const float k2 = knext;
-    knext = (i + 1 < Nb) ? sk[skx(i + 1)] : __builtin_huge_valf();
-    A += (double)k2;
-    if (k2 > 0.f) {
-      Rrun -= (double)__frsqrt_rn(k2);  // now the sum over indices > i
-      if (knext > k2) {                 // last index of a run of equal keys
-        const double x = (double)__fsqrt_rn(k2);
-        const double m = (double)(i + 1);
-        const double sv = A - m * tau + (Nbd - m) * ((double)k2 + tau) - tau * x * Rrun;
-        if (sv < best) { best = sv; besti = i; bestR = Rrun; bestK = k2; }
-      }
-    }
-  }
-}
-
-// Workgroup argmin of the per-thread bests (ties to the smaller index), then theta =
-// sqrt(key), theta^2 = key and alpha = ((N_b - m) - theta R_m / 2) / N_b (line 7) for
-// the band, and the band's outputs.  No candidate (every key zero): eta = 0, alpha = 0.
-template <int NT>
-__device__ void sure_finish(const KArgs& a, int sl, int b, int Nb, float tau_f, double best, int besti,
-                            double bestR, float bestK, double* bv, int* bi, double* bR, float* bK) {
-  constexpr int NW = NT / 64;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const double ov = __shfl_xor(best, o, 64);
-    const int oi = __shfl_xor(besti, o, 64);
-    const double oR = __shfl_xor(bestR, o, 64);
-    const float oK = __shfl_xor(bestK, o, 64);
-    if (ov < best || (ov == best && oi < besti)) { best = ov; besti = oi; bestR = oR; bestK = oK; }
-  }
-  if (lane == 0) { bv[wid] = best; bi[wid] = besti; bR[wid] = bestR; bK[wid] = bestK; }
-  __syncthreads();
-  if (tid == 0) {
-    double fb = bv[0], fR = bR[0];
-    int fi = bi[0];
-    float fK = bK[0];
-    for (int w = 1; w < NW; ++w)
-      if (bv[w] < fb || (bv[w] == fb && bi[w] < fi)) { fb = bv[w]; fi = bi[w]; fR = bR[w]; fK = bK[w]; }
-    const double Nbd = (double)Nb, tau = (double)tau_f;
-    const bool none = fi == 0x7fffffff;
-    float th, th2, al;
-    if (none) {
-      th = 0.f;
-      th2 = 0.f;
-      al = 0.f;
-    } else {
-      th2 = fK;
-      th = __fsqrt_rn(th2);
-      const double m = (double)(fi + 1);
-      al = (float)(((Nbd - m) - 0.5 * (double)th * fR) / Nbd);
-    }
-    if (a.smin)  // every key zero: eta = 0 gives SURE = -N_b tau
-      a.smin[sl * kMaxBands + b] = none ? (float)(-Nbd * tau) : (float)fb;
-    a.theta[sl * kMaxBands + b] = th;
-    a.thr2[sl * kMaxBands + b] = th2;
-    a.alpha[sl * kMaxBands + b] = al;
-    a.tau[sl * kMaxBands + b] = tau_f;
-    if (a.trace) {
-      float* t = a.trace + (((long long)a.iter * a.batch + sl) * a.nbands + b) * 3;
-      t[0] = tau_f;
-      t[1] = th;
-      t[2] = al;
     }
   }
 }
@@ -564,9 +563,9 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
   unsigned long long* sA = reinterpret_cast<unsigned long long*>(smem + 4 * NB);  // [NB]
   unsigned long long* sRq = sA + NB;                                              // [NB]
   float* comp = reinterpret_cast<float*>(smem + 8 * NB);  // [CAP] surviving keys
-  __shared__ double wsA[NW], wsR[NW], bv[NW], bR[NW], wsU[NW];
-  __shared__ int bi[NW], wsC[NW], wsS[NW], wsM[NW];
-  __shared__ float bK[NW];
+  __shared__ double wsA[NW], wsR[NW], wsU[NW];
+  __shared__ int wsC[NW], wsS[NW], wsM[NW];
+  __shared__ SureBest fin[NW];
   __shared__ float tau_sh;
   __shared__ double ustar_sh, mag_sh;
   __shared__ int tot_sh, bigc_sh, nseg_sh;
@@ -767,10 +766,10 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
     nseg_sh = gtot;
   }
   __syncthreads();
-  double best = __builtin_huge_val(), bestR = 0.0;
-  int besti = 0x7fffffff;
-  float bestK = 0.f;
-  if (tot_sh <= CAP && bigc_sh <= kSureBigBucketLimit && nseg_sh <= kSureBigMaxSeg) {
+  SureBest best = sure_none();
+  // the pruning bounds hold for thresholds at keys; the continuous search walks the
+  // whole band
+  if (!a.sure_cont && tot_sh <= CAP && bigc_sh <= kSureBigBucketLimit && nseg_sh <= kSureBigMaxSeg) {
     for (int i = tid; i < Nb; i += NT) {
       const float k = KEY_AT(i);
       const int bk = sure_bucket<NB>(k, inv_tau);
@@ -828,11 +827,12 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
             const double xx = (double)__fsqrt_rn(k2);
             const double m = (double)(P0 + l + 1);
             const double sv = Am - m * tau + (Nbd - m) * ((double)k2 + tau) - tau * xx * Rm;
-            if (sv < best || (sv == best && P0 + l < besti)) {
-              best = sv;
-              besti = P0 + l;
-              bestR = Rm;
-              bestK = k2;
+            if (sure_better(sv, P0 + l + 1, 0, best)) {
+              best.v = sv;
+              best.m = P0 + l + 1;
+              best.inner = 0;
+              best.R = Rm;
+              best.key = k2;
             }
           }
         }
@@ -848,10 +848,10 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
     for (int i = tid; i < Nb; i += NT) sk[skx(i)] = KEY_AT(i);
     __syncthreads();
     sure_bitonic<NT>(sk, Nb, npad);
-    sure_walk<NT>(sk, Nb, tau, wsA, wsR, best, besti, bestR, bestK);
+    sure_walk<NT>(sk, Nb, tau, a.sure_cont != 0, wsA, wsR, best);
   }
 #undef KEY_AT
-  sure_finish<NT>(a, sl, b, Nb, tau_sh, best, besti, bestR, bestK, bv, bi, bR, bK);
+  sure_finish<NT>(a, sl, b, Nb, tau_sh, best, fin);
 }
 
 // Size classes: up to 4096 keys (0: 256 threads x 16 keys, 2560 buckets; 1: 512 x 8,

@@ -62,10 +62,12 @@ def run_resume(plan, slices, states, iters, want_state=True, x_monitor=False, st
         th = torch.empty(plan.batch * plan.nbands, dtype=torch.float32, device="cuda")
         al = torch.empty_like(th)
         ta = torch.empty_like(th)
-        plan.vdamp_state_export(ws, r, th, al, ta, stream=stream)
+        t2 = torch.empty_like(th)
+        plan.vdamp_state_export(ws, r, th, al, ta, theta2=t2, stream=stream)
         torch.cuda.synchronize()
         out["r"] = plan.unpack(r.cpu().numpy())
         out["theta"] = th.cpu().numpy().reshape(plan.batch, plan.nbands)
+        out["theta2"] = t2.cpu().numpy().reshape(plan.batch, plan.nbands)
         out["alpha"] = al.cpu().numpy().reshape(plan.batch, plan.nbands)
         out["tau"] = ta.cpu().numpy().reshape(plan.batch, plan.nbands)
     torch.cuda.synchronize()
@@ -237,3 +239,46 @@ def alpha_at_key(r_band, kth):
     keep = k > kth
     th = np.sqrt(kth)
     return float(np.sum(1.0 - th / (2.0 * np.sqrt(k[keep]))) / k.size)
+
+
+def sure_min_continuous(a, tau):
+    """The minimum over every theta > 0 of complex soft thresholding's SURE on magnitudes
+    a (test code written from the definition, independently of the oracle): SURE is a
+    quadratic in theta between consecutive distinct magnitudes, n_above (theta^2 + tau)
+    - tau theta R_above + const, so its infimum on each interval is at the clipped vertex
+    or the interval's left end (a magnitude, counted below).  Returns the minimum."""
+    a = np.sort(np.asarray(a, dtype=np.float64).ravel())
+    n = a.size
+    u = np.unique(a[a > 0])
+    if u.size == 0:
+        return -n * tau
+    ends = np.concatenate([[0.0], u])
+    best = np.inf
+    for j in range(u.size):
+        lo, hi = ends[j], ends[j + 1]
+        below = a <= lo
+        nb = int(np.sum(~below))
+        A = float(np.sum(a[below] ** 2))
+        R = float(np.sum(1.0 / a[~below]))
+        c = A - (n - nb) * tau
+        if lo > 0:   # theta = lo itself (a candidate)
+            best = min(best, c + nb * (lo * lo + tau) - tau * lo * R)
+        t = tau * R / (2.0 * nb)
+        if lo < t < hi:
+            best = min(best, c + nb * (t * t + tau) - tau * t * R)
+    return best
+
+
+def theta_accepted_continuous(r, tau_b, rs, cs, theta_gpu, thr2_gpu):
+    """The continuous search's threshold on the library's own iterate: the SURE of what
+    the kernels apply (coefficients whose FP32 key is at most the threshold's key
+    thr2_gpu are zeroed, the others shrunk by theta_gpu), from the definition on the FP32
+    keys, is the continuous minimum up to the near-tie margin 1e-6 (|SURE_min| + N_b tau)."""
+    band = np.asarray(r)[rs, cs]
+    k = key32(band).astype(np.float64).ravel()
+    a = np.sqrt(k)
+    th = float(theta_gpu)
+    below = k <= float(np.float32(thr2_gpu))
+    v = float(np.sum(a[below] ** 2 - tau_b) + np.sum(th * th + tau_b - tau_b * th / a[~below]))
+    m = sure_min_continuous(a, float(tau_b))
+    return v <= m + 1e-6 * (abs(m) + a.size * tau_b)

@@ -108,7 +108,7 @@ def test_plan_accepts_every_documented_flag():
     """All VDAMP_FLAG_* bits pass the host checks together (the autotune flag included);
     an undocumented bit is rejected before anything touches the device."""
     flags = (V.VDAMP_FLAG_DETERMINISTIC | V.VDAMP_FLAG_USE_GRAPH | V.VDAMP_FLAG_CHECK_FINITE
-             | V.VDAMP_FLAG_TIMING | V.VDAMP_FLAG_AUTOTUNE)
+             | V.VDAMP_FLAG_TIMING | V.VDAMP_FLAG_AUTOTUNE | V.VDAMP_FLAG_SURE_CONTINUOUS)
     lib = V.load_library()
     h = ctypes.c_void_p()
     wsb = ctypes.c_size_t()
@@ -119,7 +119,7 @@ def test_plan_accepts_every_documented_flag():
         assert lib.vdamp_plan_destroy(h) == 0
     else:
         assert st == 5 and "upload" in msg, msg
-    st, msg = _plan_status(1, [64], [64], 3, 0, 1 << 7)
+    st, msg = _plan_status(1, [64], [64], 3, 0, 1 << 8)
     assert st == 1 and "flag" in msg, msg
 
 

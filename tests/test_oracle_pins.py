@@ -410,3 +410,43 @@ def test_resume_continues_the_iteration_exactly():
     last = o.vdamp_resume(sl.y, sl.mask, sl.p, sl.sigma2, 3, full["r"][-1], full["theta"][-1],
                           full["alpha"][-1], 0)
     assert np.array_equal(last["x_hat"], full["x_hat"])
+
+
+# ------------------------------------------------------- continuous-theta SURE variant
+
+def test_continuous_sure_hand_example():
+    """a = (2, 3), tau = 1, worked by hand: below a_(1) = 2 no magnitude is at or below
+    theta, R = 1/2 + 1/3 = 5/6, and SURE = 2 (theta^2 + 1) - (5/6) theta has its minimum
+    at theta* = (5/6) / 4 = 5/24 inside (0, 2), value 2 (25/576 + 1) - 25/144 = 551/288;
+    the candidates give SURE(2) = 3 + 5 - 2/3 = 22/3 and SURE(3) = 3 + 8 = 11.  So theta =
+    5/24 and alpha = (2 - (5/24)(5/6)/2) / 2 = 551/576."""
+    th, al, m, v = o.sure_threshold_continuous(np.array([2.0, 3.0]), 1.0)
+    assert abs(th - 5 / 24) < 1e-15 and m == 0
+    assert abs(v - 551 / 288) < 1e-14
+    assert abs(al - 551 / 576) < 1e-15
+    thd, _, md, vd = o.sure_threshold(np.array([2.0, 3.0]), 1.0)
+    assert thd == 2.0 and md == 1 and abs(vd - 22 / 3) < 1e-14
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_continuous_sure_matches_dense_grid(seed):
+    """The continuous minimiser against SURE evaluated from its definition (sure_value) on
+    a dense grid of thresholds plus every magnitude: no grid point is lower, the grid
+    comes within its resolution, the returned value is the definition's at the returned
+    theta, it is at most the candidate search's, and alpha is the Wirtinger mean there."""
+    rng = np.random.default_rng(seed)
+    n = 60
+    r = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) * np.where(rng.random(n) < 0.2, 4.0, 1.0)
+    if seed == 0:
+        r[:5] = 0.0                       # zero magnitudes below every threshold
+    a = np.abs(r)
+    tau = float(rng.uniform(0.5, 2.0))
+    th, al, m, v = o.sure_threshold_continuous(a, tau)
+    grid = np.concatenate([np.linspace(1e-9, a.max() * 1.01, 60001), a[a > 0]])
+    dense = np.array([o.sure_value(a, t, tau) for t in grid])
+    assert dense.min() >= v - 1e-9 * (abs(v) + n * tau)
+    assert dense.min() <= v + 1e-5 * (abs(v) + n * tau)
+    assert abs(o.sure_value(a, th, tau) - v) < 1e-10 * (abs(v) + n * tau)
+    assert v <= o.sure_threshold(a, tau)[3] + 1e-12
+    assert m == int(np.sum(a <= th))
+    assert abs(al - o.wirtinger_mean_soft(r, th)) < 1e-12
