@@ -11,7 +11,9 @@ steps in the order of Algorithm 1, library primitives only for the FFT and the s
 Conventions (readings of the paper where it is silent; each is pinned by a test):
 * F is the unitary 2D DFT in natural order (numpy ``norm="ortho"``); exact consistency
   of the output step (Section 2, final line of Algorithm 1) needs F^H F = I.
-* Psi is the s-level periodic orthonormal 2D Haar transform, Mallat layout.  One level
+* Psi is an s-level periodic orthonormal 2D wavelet transform, Mallat layout: Haar by
+  default, or the transform of any orthonormal lowpass filter h (``wavelet=h``; see
+  dwt2).  For Haar, one level
   acts on the top-left block: along x, a = (x[2i] + x[2i+1]) / sqrt2 goes left and
   d = (x[2i] - x[2i+1]) / sqrt2 goes right; then the same along y (top / bottom).
   Band order b = 0 is LL_s, then for l = s .. 1 the triple (LH_l, HL_l, HH_l), where
@@ -79,6 +81,76 @@ def haar_synthesis(w, s):
     return x
 
 
+# General orthonormal wavelets (Algorithm 1 asks only for an orthogonal Psi).  The
+# textbook periodic Mallat algorithm: one level filters the top-left block along x,
+#   a[j] = sum_t h[t] x[(2j + t) mod M]  (left half),
+#   d[j] = sum_t g[t] x[(2j + t) mod M]  (right half),  g[t] = (-1)^t h[L-1-t],
+# then the same along y (top / bottom); the next level repeats on the top-left quarter.
+# With h = (1, 1)/sqrt2 this is haar_analysis.
+
+def highpass(h):
+    h = np.asarray(h, dtype=np.float64)
+    L = len(h)
+    return np.array([(-1.0) ** t * h[L - 1 - t] for t in range(L)])
+
+
+def _analysis_1d(x, h, g, axis):
+    M = x.shape[axis]
+    j2 = 2 * np.arange(M // 2)
+    lo = sum(h[t] * np.take(x, (j2 + t) % M, axis=axis) for t in range(len(h)))
+    hi = sum(g[t] * np.take(x, (j2 + t) % M, axis=axis) for t in range(len(g)))
+    return np.concatenate([lo, hi], axis=axis)
+
+
+def _synthesis_1d(c, h, g, axis):
+    """Adjoint of _analysis_1d: x[(2j + t) mod M] += h[t] a[j] + g[t] d[j]."""
+    c = np.moveaxis(c, axis, 0)
+    M = c.shape[0]
+    a, d = c[: M // 2], c[M // 2:]
+    x = np.zeros_like(c)
+    j2 = 2 * np.arange(M // 2)
+    for t in range(len(h)):
+        np.add.at(x, (j2 + t) % M, h[t] * a + g[t] * d)
+    return np.moveaxis(x, 0, axis)
+
+
+def dwt2(x, h, s):
+    """w = Psi x for the orthonormal lowpass h: s levels, periodic, Mallat layout."""
+    h = np.asarray(h, dtype=np.float64)
+    g = highpass(h)
+    w = np.array(x, dtype=np.complex128, copy=True)
+    hh, wd = w.shape
+    for _ in range(s):
+        blk = _analysis_1d(w[:hh, :wd], h, g, axis=1)
+        w[:hh, :wd] = _analysis_1d(blk, h, g, axis=0)
+        hh //= 2
+        wd //= 2
+    return w
+
+
+def idwt2(w, h, s):
+    """x = Psi^H w, the inverse (and adjoint) of dwt2."""
+    h = np.asarray(h, dtype=np.float64)
+    g = highpass(h)
+    x = np.array(w, dtype=np.complex128, copy=True)
+    ny, nx = x.shape
+    for l in range(s, 0, -1):
+        hh, wd = ny >> (l - 1), nx >> (l - 1)
+        blk = _synthesis_1d(x[:hh, :wd], h, g, axis=0)
+        x[:hh, :wd] = _synthesis_1d(blk, h, g, axis=1)
+    return x
+
+
+def analysis(x, s, wavelet=None):
+    """Psi x: Haar when wavelet is None, else dwt2 with lowpass filter `wavelet`."""
+    return haar_analysis(x, s) if wavelet is None else dwt2(x, wavelet, s)
+
+
+def synthesis(w, s, wavelet=None):
+    """Psi^H w: Haar when wavelet is None, else idwt2."""
+    return haar_synthesis(w, s) if wavelet is None else idwt2(w, wavelet, s)
+
+
 def bands(ny, nx, s):
     """Subband blocks in band order: LL_s, then (LH_l, HL_l, HH_l) for l = s..1.
     Returns a list of (row slice, column slice, level, kind)."""
@@ -126,8 +198,23 @@ def haar_wavelet_power(n, l):
     return 4.0 * _dirichlet(k, h, n) ** 2 * np.sin(np.pi * k * h / n) ** 2 / (n * 2.0 ** l)
 
 
-def tau_weights(ny, nx, s):
+def tau_weights_filter(ny, nx, s, h):
+    """Line 1 for a general orthonormal Psi, from the definition S = |Phi Psi^H|^2: the
+    squared unitary DFT of the basis function of the first coefficient of each band
+    (periodic filtering makes every coefficient of a band a shift of it, so the column
+    of S is the same for the whole band).  A list of float64 [ny][nx] arrays."""
+    out = []
+    for (rs, cs, _, _) in bands(ny, nx, s):
+        e = np.zeros((ny, nx), dtype=np.complex128)
+        e[rs.start, cs.start] = 1.0
+        out.append(np.abs(fft2u(idwt2(e, h, s))) ** 2)
+    return out
+
+
+def tau_weights(ny, nx, s, wavelet=None):
     """S_b(ky, kx) for every band b, as a list of float64 [ny][nx] arrays."""
+    if wavelet is not None:
+        return tau_weights_filter(ny, nx, s, wavelet)
     out = []
     for (_, _, l, kind) in bands(ny, nx, s):
         Ly, Lx = haar_scaling_power(ny, l), haar_scaling_power(nx, l)
@@ -265,14 +352,14 @@ def tau_estimate(z, mask, p, sigma2, S):
     return np.array([np.sum(Sb * c) for Sb in S])
 
 
-def vdamp_step(rt, y, mask, p, sigma2, s, S):
+def vdamp_step(rt, y, mask, p, sigma2, s, S, wavelet=None):
     """Lines 3-5 for one iteration: from r_tilde_k to (r_k, tau_k)."""
     om = mask.astype(bool)
-    x_t = haar_synthesis(rt, s)
+    x_t = synthesis(rt, s, wavelet)
     z = np.where(om, y - fft2u(x_t), 0.0)                  # line 3 (zero off Omega)
     v = np.zeros_like(z)
     v[om] = z[om] / p[om]                                  # P^-1 z, zero-filled
-    r = rt + haar_analysis(ifft2u(v), s)                   # line 4
+    r = rt + analysis(ifft2u(v), s, wavelet)              # line 4
     tau = tau_estimate(z, mask, p, sigma2, S)              # line 5
     return r, tau
 
@@ -304,36 +391,37 @@ def denoise(r, tau, s, theta_override=None, alpha_override=None, continuous=Fals
     return w_hat, rt_next, np.array(thetas), np.array(alphas)
 
 
-def output_step(w_hat, y, mask, s):
+def output_step(w_hat, y, mask, s, wavelet=None):
     """Line 10: x_hat = Psi^H w + Phi^H (y - Phi Psi^H w)."""
-    x = haar_synthesis(w_hat, s)
+    x = synthesis(w_hat, s, wavelet)
     om = mask.astype(bool)
     resid = np.where(om, y - fft2u(x), 0.0)
     return x + ifft2u(resid)
 
 
-def vdamp(y, mask, p, sigma2, s, iters, record=False, continuous=False):
+def vdamp(y, mask, p, sigma2, s, iters, record=False, continuous=False, wavelet=None):
     """Algorithm 1 in FP64.  y: zero-filled measurements (natural order), mask: 0/1,
-    p: sampling probabilities (used on Omega), sigma2: E|eps_j|^2, s: Haar levels.
-    continuous=True takes each threshold as SURE's minimiser over every theta > 0.
+    p: sampling probabilities (used on Omega), sigma2: E|eps_j|^2, s: wavelet levels.
+    continuous=True takes each threshold as SURE's minimiser over every theta > 0;
+    wavelet: None for Haar, else an orthonormal lowpass filter (dwt2).
     Returns dict with x_hat and, per iteration, tau, theta, alpha (and r if record)."""
     y = np.asarray(y, dtype=np.complex128)
     p = np.asarray(p, dtype=np.float64)
     ny, nx = y.shape
     check_shape(ny, nx, s)
-    S = tau_weights(ny, nx, s)
+    S = tau_weights(ny, nx, s, wavelet)
     rt = np.zeros((ny, nx), dtype=np.complex128)           # line 1: r_tilde_0 = 0
     w_hat = np.zeros_like(rt)
     taus, thetas, alphas, rs = [], [], [], []
     for _ in range(iters):
-        r, tau = vdamp_step(rt, y, mask, p, sigma2, s, S)
+        r, tau = vdamp_step(rt, y, mask, p, sigma2, s, S, wavelet)
         w_hat, rt, th, al = denoise(r, tau, s, continuous=continuous)
         taus.append(tau)
         thetas.append(th)
         alphas.append(al)
         if record:
             rs.append(r)
-    x_hat = output_step(w_hat, y, mask, s)
+    x_hat = output_step(w_hat, y, mask, s, wavelet)
     out = dict(x_hat=x_hat, tau=np.array(taus), theta=np.array(thetas),
                alpha=np.array(alphas))
     if record:
@@ -341,7 +429,8 @@ def vdamp(y, mask, p, sigma2, s, iters, record=False, continuous=False):
     return out
 
 
-def vdamp_resume(y, mask, p, sigma2, s, r, theta, alpha, iters, record=False, continuous=False):
+def vdamp_resume(y, mask, p, sigma2, s, r, theta, alpha, iters, record=False, continuous=False,
+                 wavelet=None):
     """Algorithm 1 continued from the state (r_k, theta_k, alpha_k) of an earlier
     iteration: every further iteration starts with lines 6-8 applied to the previous
     state (eta with the given thresholds, line 8 with the given alpha), then lines 3-7.
@@ -352,18 +441,18 @@ def vdamp_resume(y, mask, p, sigma2, s, r, theta, alpha, iters, record=False, co
     r = np.asarray(r, dtype=np.complex128)
     ny, nx = y.shape
     check_shape(ny, nx, s)
-    S = tau_weights(ny, nx, s)
+    S = tau_weights(ny, nx, s, wavelet)
     w_hat, rt, _, _ = denoise(r, None, s, theta_override=theta, alpha_override=alpha)
     taus, thetas, alphas, rs = [], [], [], []
     for _ in range(iters):
-        r, tau = vdamp_step(rt, y, mask, p, sigma2, s, S)
+        r, tau = vdamp_step(rt, y, mask, p, sigma2, s, S, wavelet)
         w_hat, rt, th, al = denoise(r, tau, s, continuous=continuous)
         taus.append(tau)
         thetas.append(th)
         alphas.append(al)
         if record:
             rs.append(r)
-    out = dict(x_hat=output_step(w_hat, y, mask, s), tau=np.array(taus), theta=np.array(thetas),
+    out = dict(x_hat=output_step(w_hat, y, mask, s, wavelet), tau=np.array(taus), theta=np.array(thetas),
                alpha=np.array(alphas))
     if record:
         out["r"] = rs
