@@ -73,20 +73,33 @@ BYTES = {
 }
 
 
-def algorithmic_bytes_per_solve(npx, iters):
+# The same for a general orthonormal wavelet (vdamp_plan_ortho), whose passes exchange
+# group rows Z: 2 (1 - 2^-s) rows of x frequencies per image row, 15 B/px at s = 4.
+# rows_synth: read r, write Z.  cols: read Z, y, m/p, write Z (first: no Z read; output:
+# write the image rows of X instead).  rows_anal: read Z and r, write r (first: no r
+# read; output: read X, write x_hat).
+def ortho_bytes(levels):
+    z = 8.0 * 2.0 * (1.0 - 2.0 ** -levels)
+    return {"rows_synth": 8.0 + z, "cols": z + 12.0 + z, "cols_first": 12.0 + z,
+            "cols_out": z + 12.0 + 8.0, "rows_anal": z + 16.0, "rows_anal_first": z + 8.0,
+            "rows_anal_out": 16.0, "sure": 8.0}
+
+
+def algorithmic_bytes_per_solve(npx, iters, bytes_=None):
     """Per kernel class: total algorithmic bytes over one solve and the launch count."""
+    BYTES = bytes_ or globals()["BYTES"]
     rs = (iters - 1 + 1) * BYTES["rows_synth"] * npx          # K-1 iterations + output
-    cols = ((iters - 1) * BYTES["cols"] + BYTES["cols_first"] + BYTES["cols"]) * npx
+    cols = ((iters - 1) * BYTES["cols"] + BYTES["cols_first"] + BYTES.get("cols_out", BYTES["cols"])) * npx
     ra = ((iters - 1) * BYTES["rows_anal"] + BYTES["rows_anal_first"] + BYTES["rows_anal_out"]) * npx
     su = iters * BYTES["sure"] * npx
     return {"rows_synth": (rs, iters), "cols": (cols, iters + 1),
             "rows_anal": (ra, iters + 1), "sure": (su, iters)}
 
 
-def pass_rooflines(times, npx, iters, steps):
+def pass_rooflines(times, npx, iters, steps, bytes_=None):
     """Per kernel class: average launch time and algorithmic bytes / time against the
     HBM peak (times from the plan's per-kernel HIP events over `steps` solves)."""
-    alg = algorithmic_bytes_per_solve(npx, iters)
+    alg = algorithmic_bytes_per_solve(npx, iters, bytes_)
     out = {}
     for k, (b, _) in alg.items():
         ms, launches = times[k]
@@ -102,15 +115,18 @@ def other_workloads(stream, reps=3):
     """Throughput of the other batch shapes the library is built for: 64 and 512 slices of
     256^2, the ragged batch of 512 slices (128 each of 128^2, 192^2, 256^2, 320^2) and 128
     slices of 512^2 (whose finest bands take the large-band threshold search), each
-    planned with the plan-time tuner.  One warm-up solve, then `reps` timed solves of 50 iterations each, eager with
-    per-kernel events."""
+    planned with the plan-time tuner, and the benchmark's 256 slices of 256^2 with an
+    8-tap Daubechies wavelet instead of Haar (vdamp_plan_ortho, not tuned).  One warm-up
+    solve, then `reps` timed solves of 50 iterations each, eager with per-kernel events."""
     import torch
-    from paper_1911_01234_amd import synth, vdamp as V
+    from paper_1911_01234_amd import filters, synth, vdamp as V
     res = {}
-    for name, gen in (("batch_64_slices_256x256", lambda: synth.workload_batch256(64)),
-                      ("batch_512_slices_256x256", lambda: synth.workload_batch256(512)),
-                      ("mixed_512_slices_128_to_320", lambda: synth.workload_mixed(128)),
-                      ("batch_128_slices_512x512", lambda: synth.workload_batch512(128))):
+    for name, gen, low in (("batch_64_slices_256x256", lambda: synth.workload_batch256(64), None),
+                           ("batch_512_slices_256x256", lambda: synth.workload_batch256(512), None),
+                           ("mixed_512_slices_128_to_320", lambda: synth.workload_mixed(128), None),
+                           ("batch_128_slices_512x512", lambda: synth.workload_batch512(128), None),
+                           ("db4_wavelet_256_slices_256x256", lambda: synth.workload_batch256(256),
+                            filters.daubechies(4))):
         t = time.perf_counter()
         slices, s, K = gen()
         tg = time.perf_counter() - t
@@ -119,7 +135,8 @@ def other_workloads(stream, reps=3):
         npx = int(sum(u * v for u, v in zip(ny, nx)))
         with torch.cuda.stream(stream):
             t = time.perf_counter()
-            plan = V.Plan(ny, nx, s, V.VDAMP_FLAG_TIMING | V.VDAMP_FLAG_AUTOTUNE)
+            tune = V.VDAMP_FLAG_AUTOTUNE if low is None else 0
+            plan = V.Plan(ny, nx, s, V.VDAMP_FLAG_TIMING | tune, lowpass=low)
             t_plan = time.perf_counter() - t
             desc = plan.describe()
             ws = plan.workspace()
@@ -139,7 +156,7 @@ def other_workloads(stream, reps=3):
             nm = float(nmse_db_batch(xh, x0, seg, len(slices)).mean())
             plan.close()
             # the same solves captured once in a hipGraph (VDAMP_FLAG_USE_GRAPH) and replayed
-            gplan = V.Plan(ny, nx, s, V.VDAMP_FLAG_USE_GRAPH | V.VDAMP_FLAG_AUTOTUNE)
+            gplan = V.Plan(ny, nx, s, V.VDAMP_FLAG_USE_GRAPH | tune, lowpass=low)
             gws = gplan.workspace()
             gx = torch.empty_like(xh)
             gplan.vdamp_solve(gws, y, mask, p, sigma2, K, gx, stream=stream)
@@ -160,7 +177,7 @@ def other_workloads(stream, reps=3):
                      "hipgraph": {"slice_iterations_per_s": round(len(slices) * K / dtg, 1),
                                   "bitwise_equal_to_eager": gsame},
                      "nmse_db_mean": round(nm, 3),
-                     "passes": pass_rooflines(times, npx, K, reps),
+                     "passes": pass_rooflines(times, npx, K, reps, None if low is None else ortho_bytes(s)),
                      "plan_seconds_with_autotune": round(t_plan, 3),
                      "autotune": desc[desc.index("autotune:") + 10:] if "autotune:" in desc else None}
         print(f"[bench] {name}: generated in {tg:.1f} s, {res[name]['slice_iterations_per_s']} slice-it/s",

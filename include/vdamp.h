@@ -117,6 +117,30 @@ enum {
 vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, const int32_t* nx,
                         int32_t levels, int32_t wavelet, uint32_t flags, size_t* workspace_bytes);
 
+/*
+ * vdamp_plan_ortho -- plan a batch with a general orthonormal wavelet Psi (Algorithm 1
+ * asks only for an orthogonal wavelet transform; Section 2).
+ *   lowpass         host float64[filter_len]: the lowpass filter h of a two-channel
+ *                   orthonormal filter bank (sum h = sqrt 2, sum_t h[t] h[t + 2j] =
+ *                   delta_j, checked to 1e-9); the highpass is g[t] = (-1)^t h[L-1-t].
+ *                   Read during the call only.  h = (1, 1)/sqrt 2 is Haar.
+ *   filter_len      L, even, 2..64
+ *   other arguments as vdamp_plan (levels 1..4; VDAMP_FLAG_AUTOTUNE is not accepted).
+ * Psi is the s-level periodic Mallat transform: one level filters the top-left block
+ * along x, a[j] = sum_t h[t] x[(2j + t) mod M] to the left half and d[j] with g to the
+ * right, then the same along y; band order and layout as for Haar.  Any filter length
+ * works: the filters wrap periodically at the coarse levels.  The tau weights of line 1
+ * are |DFT of each band's basis function|^2, separable, computed on the host in FP64.
+ * The plan serves vdamp_solve, vdamp_solve_resume, vdamp_solve_noalloc,
+ * vdamp_state_export and vdamp_wavelet_ws; fista_solve, vdamp_wavelet and the learned
+ * denoiser return VDAMP_ERR_UNSUPPORTED for it.  Its workspace also holds the group rows
+ * of the Fourier-domain wavelet passes: 15 bytes a pixel more at s = 4.
+ * Errors: VDAMP_ERR_ARG for a null or non-orthonormal filter or a bad length.
+ */
+vdamp_status vdamp_plan_ortho(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, const int32_t* nx,
+                              int32_t levels, const double* lowpass, int32_t filter_len,
+                              uint32_t flags, size_t* workspace_bytes);
+
 vdamp_status vdamp_plan_destroy(vdamp_plan_h plan);
 
 /*
@@ -345,6 +369,15 @@ vdamp_status vdamp_learned_export(vdamp_cnn_h cnn, vdamp_plan_h plan, hipStream_
  */
 vdamp_status vdamp_wavelet(vdamp_plan_h plan, hipStream_t stream, int32_t inverse,
                            const float* in, float* out);
+
+/*
+ * vdamp_wavelet_ws -- Psi (inverse = 0) or Psi^H (inverse = 1) of every slice for any
+ * plan (Haar or vdamp_plan_ortho's wavelet; Section 2's orthogonal Psi), on the plan's
+ * workspace (workspace_bytes >= the plan's size; its contents are overwritten, so a
+ * solve's state on it is lost).  in and out are complex64[sum N] and must not overlap.
+ */
+vdamp_status vdamp_wavelet_ws(vdamp_plan_h plan, hipStream_t stream, void* workspace,
+                              size_t workspace_bytes, int32_t inverse, const float* in, float* out);
 
 /* Static description of a status code. */
 const char* vdamp_status_string(vdamp_status s);

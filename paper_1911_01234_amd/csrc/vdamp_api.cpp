@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -50,6 +51,55 @@ void haar_power(int n, int level, bool wavelet, std::vector<double>& out) {
 }
 
 
+// n-point DFTs of the level-l scaling function and wavelet of the periodic filter bank
+// (lowpass h, highpass g[t] = (-1)^t h[L-1-t]): F_{A_l}(k) = prod_{i<l} H(2^i k) and
+// F_{D_l}(k) = prod_{i<l-1} H(2^i k) G(2^(l-1) k), with H, G the n-point DFTs of h and g
+// (a level-l basis function is the level-(l-1) scaling function filtered by the
+// 2^(l-1)-upsampled h or g).  Out: 2 s rows of n values, A_1..A_s then D_1..D_s, in FP64.
+void filter_responses(const std::vector<double>& h, int n, int s,
+                      std::vector<std::complex<double>>& out) {
+  const int L = (int)h.size();
+  std::vector<std::complex<double>> H(n), G(n);
+  for (int k = 0; k < n; ++k) {
+    std::complex<double> hs = 0.0, gs = 0.0;
+    for (int t = 0; t < L; ++t) {
+      const double ang = -2.0 * M_PI * double((long long)k * t % n) / double(n);
+      const std::complex<double> e(std::cos(ang), std::sin(ang));
+      hs += h[t] * e;
+      gs += ((t % 2) ? -1.0 : 1.0) * h[L - 1 - t] * e;
+    }
+    H[k] = hs;
+    G[k] = gs;
+  }
+  out.assign((size_t)2 * s * n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    std::complex<double> acc = 1.0;  // prod_{i<l-1} H(2^i k)
+    for (int l = 1; l <= s; ++l) {
+      const int k2 = (int)(((long long)k << (l - 1)) % n);
+      out[(size_t)(l - 1) * n + k] = acc * H[k2];
+      out[(size_t)(s + l - 1) * n + k] = acc * G[k2];
+      acc *= H[k2];
+    }
+  }
+}
+
+// max |sum_t h[t] h[t + 2j] - delta_j| and |sum h - sqrt 2|: zero for an orthonormal
+// two-channel lowpass filter.
+double orthonormality_error(const double* h, int L) {
+  double s = 0.0;
+  for (int t = 0; t < L; ++t) s += h[t];
+  double err = std::fabs(s - std::sqrt(2.0));
+  for (int j = 0; 2 * j < L; ++j) {
+    double acc = 0.0;
+    for (int t = 0; t + 2 * j < L; ++t) acc += h[t] * h[t + 2 * j];
+    err = std::max(err, std::fabs(acc - (j == 0 ? 1.0 : 0.0)));
+  }
+  return err;
+}
+
+// Group rows of one work item of the general-wavelet passes (the same rule as the kernels).
+int ortho_rows_per_item(int ng) { return (ng % 8 == 0) ? 8 : (ng % 4 == 0) ? 4 : (ng % 2 == 0) ? 2 : 1; }
+
 }  // namespace
 
 
@@ -74,6 +124,9 @@ void free_plan(vdamp_plan_t* P) {
   hipFree(P->d_work_sure);
   hipFree(P->d_tiles);
   hipFree(P->d_tile_off);
+  hipFree(P->d_resp);
+  hipFree(P->d_work_orows);
+  hipFree(P->d_work_img);
   delete P;
 }
 
@@ -135,6 +188,7 @@ Ws layout(const vdamp_plan_t* P, void* ws) {
   w.rpart = reinterpret_cast<float*>(b + P->o_rpart);
   w.bad = reinterpret_cast<int*>(b + P->o_bad);
   w.big = P->o_big ? reinterpret_cast<float*>(b + P->o_big) : nullptr;
+  w.Z = P->o_Z ? reinterpret_cast<float2*>(b + P->o_Z) : nullptr;
   return w;
 }
 }  // namespace vdamp
@@ -184,34 +238,34 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
     const bool has_prev = k > 0 || resume;  // r_tilde_k from the previous r, theta, alpha
     if (has_prev) {
       a.mode = RS_RTILDE;
-      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, a, st));
+      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, pass_synth(P, a, st));
     }
     a.mode = has_prev ? CM_VDAMP : CM_VDAMP_FIRST;
-    LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
+    LAUNCH(L, VDAMP_PASS_COLS, pass_cols(P, a, st));
     a.mode = has_prev ? RA_VDAMP : RA_VDAMP_FIRST;
-    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
+    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, pass_anal(P, a, st));
     LAUNCH(L, VDAMP_PASS_SURE, launch_sure_all(P, a, w.big, st));
     if (x_monitor) {  // line 10 at this iteration (X is free between iterations)
       KArgs m = a;
       m.out = x_monitor + (long long)k * P->ntot;
       m.mode = RS_WHAT;
-      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, m, st));
+      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, pass_synth(P, m, st));
       m.mode = CM_OUTPUT;
-      LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, m, st));
+      LAUNCH(L, VDAMP_PASS_COLS, pass_cols(P, m, st));
       m.mode = RA_IMAGE;
-      LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, m, st));
+      LAUNCH(L, VDAMP_PASS_ROWS_ANAL, pass_anal(P, m, st));
     }
   }
   // line 10: x_hat = F^H [ (1 - m) F Psi^H w + m y ]
   const bool has_w = iters > 0 || resume;
   if (has_w) {
     a.mode = RS_WHAT;
-    LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, a, st));
+    LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, pass_synth(P, a, st));
   }
   a.mode = has_w ? CM_OUTPUT : CM_ZEROFILL;
-  LAUNCH(L, VDAMP_PASS_COLS, launch_cols_all(P, a, st));
+  LAUNCH(L, VDAMP_PASS_COLS, pass_cols(P, a, st));
   a.mode = RA_IMAGE;
-  LAUNCH(L, VDAMP_PASS_ROWS_ANAL, launch_rows_anal_all(P, a, st));
+  LAUNCH(L, VDAMP_PASS_ROWS_ANAL, pass_anal(P, a, st));
   return VDAMP_OK;
 }
 
@@ -309,14 +363,26 @@ const char* vdamp_status_string(vdamp_status s) {
 
 const char* vdamp_last_error(void) { return g_err.c_str(); }
 
-vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, const int32_t* nx,
-                        int32_t levels, int32_t wavelet, uint32_t flags, size_t* workspace_bytes) {
+static vdamp_status make_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny,
+                              const int32_t* nx, int32_t levels, const double* filt, int32_t flen,
+                              uint32_t flags, size_t* workspace_bytes) {
   g_err.clear();
   if (!plan || !ny || !nx || !workspace_bytes) return fail(VDAMP_ERR_ARG, "null pointer argument");
   *plan = nullptr;
   if (batch < 1) return fail(VDAMP_ERR_ARG, "batch must be >= 1");
-  if (wavelet != VDAMP_WAVELET_HAAR) return fail(VDAMP_ERR_UNSUPPORTED, "only the Haar wavelet is implemented");
   if (levels < 1 || levels > 4) return fail(VDAMP_ERR_UNSUPPORTED, "levels must be in 1..4");
+  const bool ortho = filt != nullptr;
+  if (ortho) {
+    if (flen < 2 || flen > kMaxFilter || flen % 2)
+      return fail(VDAMP_ERR_ARG, "filter length must be even, in 2.." + std::to_string(kMaxFilter));
+    for (int t = 0; t < flen; ++t)
+      if (!std::isfinite(filt[t])) return fail(VDAMP_ERR_ARG, "filter taps must be finite");
+    const double oe = orthonormality_error(filt, flen);
+    if (!(oe <= 1e-9))
+      return fail(VDAMP_ERR_ARG, "filter is not an orthonormal lowpass filter (error " + std::to_string(oe) + ")");
+    if (flags & VDAMP_FLAG_AUTOTUNE)
+      return fail(VDAMP_ERR_UNSUPPORTED, "VDAMP_FLAG_AUTOTUNE tunes the Haar passes only");
+  }
   const uint32_t known = VDAMP_FLAG_DETERMINISTIC | VDAMP_FLAG_USE_GRAPH | VDAMP_FLAG_CHECK_FINITE |
                          VDAMP_FLAG_TIMING | VDAMP_FLAG_AUTOTUNE | VDAMP_FLAG_SURE_CONTINUOUS;
   if (flags & ~known) return fail(VDAMP_ERR_ARG, "unknown flag bits");
@@ -351,6 +417,8 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   P->ny.assign(ny, ny + batch);
   P->nx.assign(nx, nx + batch);
   P->off.resize(batch);
+  P->ortho = ortho;
+  if (ortho) P->filt.assign(filt, filt + flen);
 
   // FFT plans and twiddles, one per distinct length
   std::map<int, int> fft_index;
@@ -383,11 +451,17 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     if (it != tab_index.end()) return it->second;
     const int o = (int)tables.size();
     std::vector<double> pw;
-    for (int wv = 0; wv < 2; ++wv)
-      for (int l = 1; l <= levels; ++l) {
-        haar_power(n, l, wv == 1, pw);
-        for (int k = 0; k < n; ++k) tables.push_back((float)pw[k]);
-      }
+    if (ortho) {  // |F_{A_l}|^2 / n, then |F_{D_l}|^2 / n
+      std::vector<std::complex<double>> F;
+      filter_responses(P->filt, n, levels, F);
+      for (size_t i = 0; i < F.size(); ++i) tables.push_back((float)(std::norm(F[i]) / n));
+    } else {
+      for (int wv = 0; wv < 2; ++wv)
+        for (int l = 1; l <= levels; ++l) {
+          haar_power(n, l, wv == 1, pw);
+          for (int k = 0; k < n; ++k) tables.push_back((float)pw[k]);
+        }
+    }
     // then (cos^2, sin^2)(pi k / n) per k: the factors the four-step column pass builds
     // the same products from (D_{2^m}(k) = 2^m prod_{j<m} cos(pi k 2^j / n))
     for (int k = 0; k < n; ++k) {
@@ -399,8 +473,22 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     return o;
   };
 
+  // complex filter responses (general wavelets), one set per distinct length
+  std::map<int, int> resp_index;
+  std::vector<float2> resp;
+  auto get_resp = [&](int n) {
+    auto it = resp_index.find(n);
+    if (it != resp_index.end()) return it->second;
+    const int o = (int)resp.size();
+    std::vector<std::complex<double>> F;
+    filter_responses(P->filt, n, levels, F);
+    for (auto& f : F) resp.push_back(make_float2((float)f.real(), (float)f.imag()));
+    resp_index[n] = o;
+    return o;
+  };
+
   std::vector<SliceDev> sl(batch);
-  long long off = 0;
+  long long off = 0, zoff = 0;
   int colstrip = 0, rowstrip = 0;
   for (int b = 0; b < batch; ++b) {
     SliceDev& S = sl[b];
@@ -414,6 +502,18 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     S.xtab_off = get_tab(nx[b]);
     S.colstrip0 = colstrip;
     S.rowstrip0 = rowstrip;
+    if (ortho) {
+      for (int l = 0; l <= levels; ++l) {
+        S.fft_yl[l] = get_fft(ny[b] >> l);
+        S.fft_xl[l] = get_fft(nx[b] >> l);
+      }
+      S.zoff = zoff;
+      S.zrows = 0;
+      for (int l = 1; l <= levels; ++l) S.zrows += 2 * (ny[b] >> l);
+      zoff += (long long)S.zrows * nx[b];
+      S.yresp_off = get_resp(ny[b]);
+      S.xresp_off = get_resp(nx[b]);
+    }
     P->off[b] = off;
     off += (long long)ny[b] * nx[b];
     colstrip += nx[b] / kColW;
@@ -468,6 +568,31 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
     P->col_groups.push_back({i, j - i, cols4_supported(n) ? n / 16 : 0, n});
     i = j;
   }
+  // general wavelets: group-row items (slice, first group row) and image-row items
+  // (slice, first image row), heaviest (widest) first
+  std::vector<int2> vor, vimg;
+  if (ortho) {
+    std::vector<std::pair<long long, int2>> wo, wi;
+    for (int b = 0; b < batch; ++b) {
+      int goff = 0;
+      for (int l = 1; l <= levels; ++l)
+        for (int kind = 0; kind < 2; ++kind) {
+          const int ng = ny[b] >> l, rpi = ortho_rows_per_item(ng);
+          for (int i = 0; i < ng; i += rpi) wo.push_back({(long long)nx[b] * rpi, make_int2(b, goff + i)});
+          goff += ng;
+        }
+      const int rpi = ortho_rows_per_item(ny[b]);
+      for (int i = 0; i < ny[b]; i += rpi) wi.push_back({(long long)nx[b] * rpi, make_int2(b, i)});
+    }
+    vor = sort_items(wo);
+    vimg = sort_items(wi);
+    P->n_orows = (int)vor.size();
+    P->n_img = (int)vimg.size();
+    P->lds_osynth = sizeof(float2) * (size_t)8 * maxnx;
+    P->lds_oanal = 2 * P->lds_osynth;
+    P->lds_ocols = ocols_lds_bytes(maxny, levels);
+    P->ocols_ept = maxny * kColW <= 16 * kThreads ? 16 : 32;
+  }
   P->lds_rows = sizeof(float2) * (size_t)H * maxnx;
   P->lds_cols = sizeof(float2) * (size_t)maxny * kColW;
   P->ept = (H * maxnx <= 16 * kThreads && maxny * kColW <= 16 * kThreads) ? 16 : 32;
@@ -486,6 +611,10 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   P->o_taup = o; o = align256(o + 4 * (size_t)colstrip * kMaxBands);
   P->o_rpart = o; o = align256(o + 4 * (size_t)rowstrip);
   P->o_bad = o; o = align256(o + 4);
+  if (ortho) {
+    P->o_Z = o;
+    o = align256(o + sizeof(float2) * (size_t)zoff);
+  }
   if (P->nsure_cls[kSureBigClass]) {
     P->o_big = o;
     o = align256(o + 4 * (size_t)P->nsure_cls[kSureBigClass] * kSureBigStride);
@@ -509,6 +638,12 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   if (e == hipSuccess) e = upload(P->d_tiles, tiles);
   if (e == hipSuccess) e = upload(P->d_tile_off, P->tile_off);
   if (e == hipSuccess) e = set_lds_limits_passes(sizeof(float2) * kMaxElems, sizeof(float2) * kMaxElems);
+  if (e == hipSuccess && ortho) {
+    e = upload(P->d_resp, resp);
+    if (e == hipSuccess) e = upload(P->d_work_orows, vor);
+    if (e == hipSuccess) e = upload(P->d_work_img, vimg);
+    if (e == hipSuccess) e = set_lds_limits_ortho(P->lds_osynth, P->lds_ocols, P->lds_oanal);
+  }
   if (e == hipSuccess && (P->row_groups.size() > 1 || P->col_groups.size() > 1)) {
     for (int i = 0; i < vdamp_plan_t::kForks && e == hipSuccess; ++i) {
       e = hipStreamCreateWithFlags(&P->side[i], hipStreamNonBlocking);
@@ -532,11 +667,35 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   return VDAMP_OK;
 }
 
+vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, const int32_t* nx,
+                        int32_t levels, int32_t wavelet, uint32_t flags, size_t* workspace_bytes) {
+  if (wavelet != VDAMP_WAVELET_HAAR) {
+    g_err.clear();
+    if (plan) *plan = nullptr;
+    return fail(VDAMP_ERR_UNSUPPORTED, "wavelet must be VDAMP_WAVELET_HAAR (other wavelets: vdamp_plan_ortho)");
+  }
+  return make_plan(plan, batch, ny, nx, levels, nullptr, 0, flags, workspace_bytes);
+}
+
+vdamp_status vdamp_plan_ortho(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, const int32_t* nx,
+                              int32_t levels, const double* lowpass, int32_t filter_len,
+                              uint32_t flags, size_t* workspace_bytes) {
+  if (!lowpass) {
+    g_err.clear();
+    if (plan) *plan = nullptr;
+    return fail(VDAMP_ERR_ARG, "lowpass is null");
+  }
+  return make_plan(plan, batch, ny, nx, levels, lowpass, filter_len, flags, workspace_bytes);
+}
+
 vdamp_status vdamp_plan_describe(vdamp_plan_h plan, char* buf, size_t len, size_t* needed) {
   g_err.clear();
   if (!plan) return fail(VDAMP_ERR_ARG, "plan is null");
   const vdamp_plan_t* P = plan;
-  std::string s = "slices " + std::to_string(P->B) + ", levels " + std::to_string(P->levels) + ", pixels " +
+  std::string s = std::string(P->ortho ? "wavelet: orthonormal filter of " + std::to_string(P->filt.size()) +
+                                            " taps (Fourier-domain passes); "
+                                      : "wavelet: Haar; ") +
+                  "slices " + std::to_string(P->B) + ", levels " + std::to_string(P->levels) + ", pixels " +
                   std::to_string(P->ntot) + ", workspace " + std::to_string(P->ws_bytes) + " bytes;";
   auto group = [&](const char* what, const std::array<int, 4>& g) {
     s += std::string(" ") + what + std::to_string(g[3]) + ": " + std::to_string(g[1]) + " strips, " +
@@ -635,6 +794,7 @@ vdamp_status fista_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
   vdamp_status s = check_common(plan, workspace, workspace_bytes, y, mask, iters, x_hat);
   if (s != VDAMP_OK) return s;
   if (!lambda) return fail(VDAMP_ERR_ARG, "lambda must be non-null");
+  if (plan->ortho) return fail(VDAMP_ERR_UNSUPPORTED, "fista_solve runs on Haar plans only");
   GraphKey key;
   key.kind = 1; key.ws = workspace; key.y = y; key.mask = mask; key.lam = lambda;
   key.x = x_hat; key.iters = iters; key.stream = stream; key.obj = objective;
@@ -663,6 +823,42 @@ vdamp_status vdamp_state_export(vdamp_plan_h plan, hipStream_t stream, const voi
     if (!outs[i]) continue;
     HIP_TRY(hipMemcpy2DAsync(outs[i], sizeof(float) * nb, srcs[i], sizeof(float) * kMaxBands,
                              sizeof(float) * nb, plan->B, hipMemcpyDeviceToDevice, stream));
+  }
+  return VDAMP_OK;
+}
+
+vdamp_status vdamp_wavelet_ws(vdamp_plan_h plan, hipStream_t stream, void* workspace,
+                              size_t workspace_bytes, int32_t inverse, const float* in, float* out) {
+  g_err.clear();
+  if (!plan || !in || !out) return fail(VDAMP_ERR_ARG, "null pointer argument");
+  if (in == out) return fail(VDAMP_ERR_ARG, "in and out must not overlap");
+  if (!plan->ortho) return vdamp_wavelet(plan, stream, inverse, in, out);
+  if (!workspace) return fail(VDAMP_ERR_WORKSPACE, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(VDAMP_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (workspace_bytes < plan->ws_bytes)
+    return fail(VDAMP_ERR_WORKSPACE, "workspace has " + std::to_string(workspace_bytes) + " bytes, needs " +
+                                         std::to_string(plan->ws_bytes));
+  const Ws w = layout(plan, workspace);
+  KArgs a = base_args(plan, w);
+  if (plan->state_ws == workspace) plan->has_state = false;  // the workspace's state is overwritten
+  if (inverse) {  // Psi^H: coefficient rows -> group rows -> image rows of X -> image
+    a.r = reinterpret_cast<float2*>(const_cast<float*>(in));
+    a.mode = RS_PLAIN;
+    HIP_TRY(pass_synth(plan, a, stream));
+    a.mode = OC_SYNTH;
+    HIP_TRY(pass_cols(plan, a, stream));
+    a.mode = RA_IMAGE;
+    a.out = reinterpret_cast<float2*>(out);
+    HIP_TRY(pass_anal(plan, a, stream));
+  } else {  // Psi: image rows -> row DFTs in X -> group rows -> coefficients
+    a.r = reinterpret_cast<float2*>(const_cast<float*>(in));
+    a.mode = OS_IMAGE;
+    HIP_TRY(pass_synth(plan, a, stream));
+    a.mode = OC_ANAL;
+    HIP_TRY(pass_cols(plan, a, stream));
+    a.mode = OA_COEF;
+    a.out = reinterpret_cast<float2*>(out);
+    HIP_TRY(pass_anal(plan, a, stream));
   }
   return VDAMP_OK;
 }

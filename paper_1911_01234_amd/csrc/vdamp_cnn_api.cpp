@@ -142,6 +142,7 @@ T* at(void* ws, size_t off) {
 }
 
 vdamp_status check_cnn_ws(const vdamp_plan_t* P, int kind, void* ws, size_t wsb) {
+  if (P->ortho) return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser runs on Haar plans only");
   if (!P->tiles_ok) return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser needs ny and nx multiples of 16");
   if (!ws) return fail(VDAMP_ERR_WORKSPACE, "denoiser workspace is null");
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(VDAMP_ERR_WORKSPACE, "denoiser workspace not 256-byte aligned");
@@ -378,6 +379,7 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
 
 vdamp_status check_cnn(vdamp_cnn_h cnn, vdamp_plan_h plan) {
   if (!cnn || !plan) return fail(VDAMP_ERR_ARG, "denoiser and plan must be non-null");
+  if (plan->ortho) return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser runs on Haar plans only");
   if (cnn->nb != plan->nbands)
     return fail(VDAMP_ERR_ARG, "denoiser built for " + std::to_string(cnn->nb) + " bands, plan has " +
                                    std::to_string(plan->nbands));
@@ -589,6 +591,7 @@ vdamp_status vdamp_wavelet(vdamp_plan_h plan, hipStream_t stream, int32_t invers
   g_err.clear();
   if (!plan || !in || !out) return fail(VDAMP_ERR_ARG, "null pointer argument");
   if (in == out) return fail(VDAMP_ERR_ARG, "in and out must not overlap");
+  if (plan->ortho) return fail(VDAMP_ERR_UNSUPPORTED, "general-wavelet plans need a workspace: vdamp_wavelet_ws");
   KArgs a;
   std::memset(&a, 0, sizeof(a));
   a.slices = plan->d_slices;

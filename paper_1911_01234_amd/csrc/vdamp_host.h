@@ -46,6 +46,7 @@ struct Ws {
   float *theta, *thr2, *alpha, *tau, *taup, *rpart;
   int* bad;
   float* big;  // full-sort scratch of the bands larger than the LDS search (or null)
+  float2* Z;   // group rows of the general-wavelet passes (or null)
 };
 
 extern thread_local std::string g_err;  // detail of the last failure on this thread
@@ -97,6 +98,18 @@ struct vdamp_plan_t {
   std::string tune_log;             // what the plan-time tuner measured and chose
   int ept = 16;                     // complex elements per thread of the LDS passes
   size_t lds_rows = 0, lds_cols = 0;
+  // general orthonormal wavelet (plans made with a filter): lowpass filter, complex filter
+  // responses, group-row and image-row work lists, LDS sizes of its passes
+  bool ortho = false;
+  std::vector<double> filt;
+  float2* d_resp = nullptr;
+  int2* d_work_orows = nullptr;
+  int n_orows = 0;
+  int2* d_work_img = nullptr;
+  int n_img = 0;
+  size_t lds_osynth = 0, lds_ocols = 0, lds_oanal = 0;
+  int ocols_ept = 16;
+  size_t o_Z = 0;
   // workspace layout (byte offsets)
   size_t o_wgt = 0, o_r = 0, o_X = 0, o_r2 = 0, o_theta = 0, o_thr2 = 0, o_alpha = 0, o_tau = 0,
          o_taup = 0, o_rpart = 0, o_bad = 0, o_big = 0, ws_bytes = 0;
@@ -158,6 +171,12 @@ hipError_t launch_scale(const SliceDev* slices, int batch, const float2* y, cons
                         float* s0, hipStream_t st);
 hipError_t launch_judge(const KArgs& a, int nrowstrips, int always, int* sel, float* jout,
                         hipStream_t st);
+// general orthonormal wavelets
+size_t ocols_lds_bytes(int maxny, int s);
+hipError_t set_lds_limits_ortho(size_t synth, size_t cols, size_t anal);
+hipError_t launch_osynth(const KArgs& a, size_t lds, hipStream_t st);
+hipError_t launch_ocols(const KArgs& a, int ept, size_t lds, hipStream_t st);
+hipError_t launch_oanal(const KArgs& a, size_t lds, hipStream_t st);
 
 // Launch helper that records timing events around each kernel when asked.
 struct Launcher {
@@ -285,7 +304,34 @@ inline KArgs base_args(const vdamp_plan_t* P, const Ws& w) {
   a.tau = w.tau;
   a.tau_part = w.taup;
   a.sure_cont = (P->flags & VDAMP_FLAG_SURE_CONTINUOUS) ? 1 : 0;
+  a.resp = P->d_resp;
+  a.Z = w.Z;
   return a;
+}
+
+// The three transform passes of an iteration, for either wavelet: Haar plans run the
+// strip kernels (one launch per size group), general-wavelet plans the Fourier-domain
+// kernels (one launch over the plan's group rows or column strips; OS_IMAGE and RA_IMAGE
+// work on image rows).
+inline hipError_t pass_synth(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
+  if (!P->ortho) return launch_rows_synth_all(P, a, st);
+  const bool img = a.mode == OS_IMAGE;
+  a.work = img ? P->d_work_img : P->d_work_orows;
+  a.nwork = img ? P->n_img : P->n_orows;
+  return launch_osynth(a, P->lds_osynth, st);
+}
+inline hipError_t pass_cols(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
+  if (!P->ortho) return launch_cols_all(P, a, st);
+  a.work = P->d_work_cols;
+  a.nwork = P->ncols;
+  return launch_ocols(a, P->ocols_ept, P->lds_ocols, st);
+}
+inline hipError_t pass_anal(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
+  if (!P->ortho) return launch_rows_anal_all(P, a, st);
+  const bool img = a.mode == RA_IMAGE;
+  a.work = img ? P->d_work_img : P->d_work_orows;
+  a.nwork = img ? P->n_img : P->n_orows;
+  return launch_oanal(a, P->lds_oanal, st);
 }
 
 

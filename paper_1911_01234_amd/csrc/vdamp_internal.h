@@ -19,6 +19,7 @@ constexpr int kSureBigClass = kSureClasses - 1;
 constexpr int kSureBigMaxKeys = 65536;  // largest subband (the finest band of 512 x 512)
 constexpr int kSureBigStride = kSureBigMaxKeys + kSureBigMaxKeys / 16 + 1;  // scratch floats per band
 constexpr int kSureMaxKeys = 27648;// largest subband the LDS threshold search holds
+constexpr int kMaxFilter = 64;     // longest lowpass filter of a general-wavelet plan
 
 struct FftPlanDev {
   int n;                 // transform length
@@ -36,6 +37,13 @@ struct SliceDev {
   int xtab_off;          // 2 s tables of nx floats (x axis)
   int colstrip0;         // index of this slice's first column strip in tau_part
   int rowstrip0;         // index of this slice's first row strip (learned-denoiser partials)
+  // general orthonormal wavelets (plans with a filter): FFT plans of the lengths n >> l
+  // (l = 0..s), the slice's group rows in Z, and the filter responses
+  int fft_yl[5], fft_xl[5];
+  long long zoff;        // offset of the slice's group rows in Z (complex elements)
+  int zrows;             // group rows: sum over l = 1..s of 2 (ny >> l)
+  int yresp_off;         // 2 s tables of ny complex: F_{A_1..A_s}, F_{D_1..D_s} (y axis)
+  int xresp_off;         // the same for nx (x axis)
 };
 
 // Modes of the row-synthesis pass (Psi^H on row strips, then row FFT).
@@ -67,6 +75,14 @@ enum RowAnalMode : int {
   RA_FISTA = 3,        // w = eta(v + g; lambda); v' = w + beta (w - w_prev)
   RA_FISTA_FIRST = 4,
   RA_LEARNED = 5       // as RA_VDAMP with r_tilde from the judged denoiser (RS_RTILDE_L)
+};
+
+// Extra modes of the general-wavelet passes (Psi and Psi^H on their own).
+enum OrthoMode : int {
+  OS_IMAGE = 10,   // synthesis pass: row DFTs of image rows (a.r) into X
+  OC_SYNTH = 11,   // column pass: from the group rows to the image rows of X (no k-space step)
+  OC_ANAL = 12,    // column pass: from the row DFTs in X to the group rows (no k-space step)
+  OA_COEF = 13     // analysis pass: the coefficients themselves, into a.out
 };
 
 struct KArgs {
@@ -103,6 +119,9 @@ struct KArgs {
   float beta;                // FISTA momentum factor for this iteration
   int mode;
   int sure_cont;             // threshold search over every theta > 0, not only the keys
+  // general orthonormal wavelets
+  const float2* resp;        // filter responses (SliceDev yresp_off / xresp_off)
+  float2* Z;                 // group rows: every band's row DFT times its x filter response
 };
 
 }  // namespace vdamp

@@ -1,0 +1,362 @@
+// General orthonormal wavelets (Algorithm 1 needs only an orthogonal Psi), applied in
+// the Fourier domain and fused with the passes of the iteration.
+//
+// For a periodic two-channel orthonormal filter bank (lowpass h, highpass g), the
+// level-l basis functions of a band are the 2^l-shifts of one function whose n-point
+// (unnormalised) DFT is F_{A_l}(k) = prod_{i<l} H(2^i k) for the scaling function and
+// F_{D_l}(k) = prod_{i<l-1} H(2^i k) G(2^(l-1) k) for the wavelet, H and G the n-point
+// DFTs of h and g.  Synthesis along one axis is therefore
+//     X(k) = sum_b F_b(k) W_b(k mod m_b)      (W_b: m_b-point DFT of band b's samples),
+// and analysis, its adjoint up to the factor 1/n, folds the 2^l aliases of a band:
+//     W_b(k') = sum_{j < 2^l} conj(F_b(k' + j m_b)) X(k' + j m_b).
+// Any filter length works, the periodic wrap included, and no strip needs a halo.
+//
+// In 2D every band of the Mallat layout is a y-filter times an x-filter of one level.
+// Bands sharing a y-filter form a group: A_l = {LH_l} (plus LL_s when l = s) and
+// D_l = {HL_l, HH_l}.  A group row i is the sum over the group's bands of
+// F^x_b(kx) x (DFT of row i of band b)(kx mod m): a full row of x frequencies.
+//   k_osynth: line 8 (or line 6) on the coefficients, band-row DFTs, group rows -> Z;
+//   k_ocols:  per 16-column strip, each group column's DFT times its y response summed
+//             into k-space, the k-space step of lines 3-5 with its tau partials, then
+//             the fold back into group columns and their inverse DFTs -> Z (or, for
+//             line 10, the full inverse column DFT -> X);
+//   k_oanal:  each group row folded back into its bands, inverse DFTs, + r_tilde (line 4).
+// Scaling: every DFT here is unnormalised; the column pass applies (ny nx)^(-1/2) once
+// on the way into k-space and once on the way out, so the round trip is unitary.
+#include "vdamp_device.hpp"
+#include "vdamp_host.h"
+
+namespace vdamp {
+namespace {
+
+// Group rows of one work item: the largest of 8, 4, 2, 1 that divides the group's rows.
+__device__ __forceinline__ int rows_per_item(int ng) {
+  return (ng % 8 == 0) ? 8 : (ng % 4 == 0) ? 4 : (ng % 2 == 0) ? 2 : 1;
+}
+
+// Group of group row `grow` of a slice (groups in the order A_1, D_1, A_2, ..., D_s):
+// level l, kind (0: y filter A_l, 1: D_l), its rows ng = ny >> l, its first row goff.
+__device__ __forceinline__ void group_of(int grow, int ny, int s, int& l, int& kind, int& ng,
+                                         int& goff) {
+  int off = 0;
+  l = s; kind = 1; ng = ny >> s; goff = 0;
+  for (int L = 1; L <= s; ++L)
+    for (int k = 0; k < 2; ++k) {
+      const int n = ny >> L;
+      if (grow >= off && grow < off + n) { l = L; kind = k; ng = n; goff = off; }
+      off += n;
+    }
+}
+
+// Segment j of a group row: j = 0 lies at column 0 with x filter A_l, j = 1 at column
+// m = nx >> l with x filter D_l.  Group A_l (l < s) has only segment 1 (LH_l); group
+// A_s has LL_s and LH_s; group D_l has HL_l and HH_l.
+__device__ __forceinline__ int seg_band(int l, int kind, int j, int s) {
+  const int base = 1 + 3 * (s - l);
+  return kind ? base + 1 + j : (j ? base : 0);
+}
+// response / tau-table index of a filter: A_l -> l - 1, D_l -> s + l - 1
+__device__ __forceinline__ int filt_index(int l, int hi, int s) { return hi ? s + l - 1 : l - 1; }
+
+__device__ __forceinline__ float2 conj_mul(float2 f, float2 v) {  // conj(f) v
+  return make_float2(f.x * v.x + f.y * v.y, f.x * v.y - f.y * v.x);
+}
+
+// ------------------------------------------------------------------ synthesis
+__global__ void __launch_bounds__(kThreads) k_osynth(KArgs a) {
+  extern __shared__ float4 lds4[];
+  float2* buf = reinterpret_cast<float2*>(lds4);
+  __shared__ float2 tw_s[kMaxN];
+  const int2 item = a.work[blockIdx.x];
+  const int sl = item.x;
+  const SliceDev S = a.slices[sl];
+  const int ny = S.ny, nx = S.nx, s = a.levels, tid = threadIdx.x, mode = a.mode;
+  if (mode == OS_IMAGE) {  // row DFTs of image rows item.y .. item.y + rpi - 1, into X
+    const int rpi = rows_per_item(ny);
+    const FftPlanDev& P = a.ffts[S.fft_x];
+    load_twiddles(tw_s, P, a.twiddles);
+    const long long base = S.off + (long long)item.y * nx;
+    for (int e = tid; e < rpi * nx; e += kThreads) buf[e] = a.r[base + e];
+    __syncthreads();
+    fft_lines<false, false, 16>(buf, P, rpi, nx, 1, tw_s);
+    for (int e = tid; e < rpi * nx; e += kThreads) a.X[base + e] = buf[e];
+    return;
+  }
+  int l, kind, ng, goff;
+  group_of(item.y, ny, s, l, kind, ng, goff);
+  const int rpi = rows_per_item(ng), i0 = item.y - goff;
+  const int mx = nx >> l, nseg = (kind || l == s) ? 2 : 1, j0 = 2 - nseg, seglen = nseg * mx;
+  const int row0 = (kind ? (ny >> l) : 0) + i0;  // coefficient row of group row i0
+  const FftPlanDev& P = a.ffts[S.fft_xl[l]];
+  load_twiddles(tw_s, P, a.twiddles);
+  const float* th = a.theta + sl * kMaxBands;
+  const float* t2 = a.thr2 + sl * kMaxBands;
+  const float* al = a.alpha + sl * kMaxBands;
+  for (int e = tid; e < rpi * seglen; e += kThreads) {
+    const int rr = e / seglen, rem = e - rr * seglen, js = rem / mx, c = rem - js * mx;
+    const int j = j0 + js, b = seg_band(l, kind, j, s);
+    const float2 v = a.r[S.off + (long long)(row0 + rr) * nx + j * mx + c];
+    float2 o = v;
+    if (mode == RS_RTILDE) o = rtilde_c(v, th[b], t2[b], al[b]);
+    else if (mode == RS_WHAT) o = soft_c(v, th[b], t2[b]);
+    buf[e] = o;  // line rr * nseg + js, sample c
+  }
+  __syncthreads();
+  fft_lines<false, false, 16>(buf, P, rpi * nseg, mx, 1, tw_s);
+  const float2* rx = a.resp + S.xresp_off;
+  for (int e = tid; e < rpi * nx; e += kThreads) {
+    const int rr = e / nx, kx = e - rr * nx, k = kx % mx;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int js = 0; js < nseg; ++js)
+      acc = cadd(acc, cmul(rx[filt_index(l, j0 + js, s) * nx + kx], buf[(rr * nseg + js) * mx + k]));
+    a.Z[S.zoff + (long long)(item.y + rr) * nx + kx] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ columns
+// Dynamic LDS: the k-space strip V (ny x 16), one group column block G (ny/2 x 16), the
+// 2 s y-axis tau tables (ny floats each).
+template <int EPT>
+__global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
+  extern __shared__ float4 lds4[];
+  __shared__ float2 tw_s[2 * kMaxN];
+  __shared__ float red[kThreads / 64][kMaxBands];
+  const int2 item = a.work[xcd_item(blockIdx.x, gridDim.x)];
+  const int sl = item.x;
+  const SliceDev S = a.slices[sl];
+  const int ny = S.ny, nx = S.nx, c0 = item.y * kColW, s = a.levels;
+  const int tid = threadIdx.x, mode = a.mode;
+  float2* V = reinterpret_cast<float2*>(lds4);
+  float2* G = V + ny * kColW;
+  float* ytab_s = reinterpret_cast<float*>(G + (ny / 2) * kColW);
+  const bool vd = (mode == CM_VDAMP || mode == CM_VDAMP_FIRST);
+  const bool in_zero = (mode == CM_VDAMP_FIRST || mode == CM_ZEROFILL);
+  const bool in_plain = (mode == OC_ANAL);
+  const bool out_plain = (mode == CM_OUTPUT || mode == CM_ZEROFILL || mode == OC_SYNTH);
+  // twiddles of the lengths ny >> l, l = 0..s, one after another
+  int twoff[5];
+  {
+    int o = 0;
+    for (int l = 0; l <= s; ++l) {
+      const FftPlanDev& P = a.ffts[S.fft_yl[l]];
+      twoff[l] = o;
+      for (int i = tid; i < P.n; i += kThreads) tw_s[o + i] = a.twiddles[P.tw_off + i];
+      o += P.n;
+    }
+  }
+  if (vd)
+    for (int i = tid; i < 2 * s * ny; i += kThreads) ytab_s[i] = a.tables[S.ytab_off + i];
+  const float2* ry = a.resp + S.yresp_off;
+  const int n16 = ny * kColW;
+  const int c = tid & (kColW - 1);  // every element this thread touches is in column c
+  // ---- into k-space
+  if (in_plain) {
+    for (int e = tid; e < n16; e += kThreads) V[e] = a.X[S.off + (long long)(e >> 4) * nx + c0 + (e & 15)];
+    __syncthreads();
+    fft_lines<false, true, EPT>(V, a.ffts[S.fft_yl[0]], kColW, 1, kColW, tw_s + twoff[0]);
+  } else {
+    for (int e = tid; e < n16; e += kThreads) V[e] = make_float2(0.f, 0.f);
+    if (!in_zero) {
+      int goff = 0;
+      for (int l = 1; l <= s; ++l)
+        for (int kind = 0; kind < 2; ++kind) {
+          const int ng = ny >> l;
+          __syncthreads();  // G is free
+          for (int e = tid; e < ng * kColW; e += kThreads)
+            G[e] = a.Z[S.zoff + (long long)(goff + (e >> 4)) * nx + c0 + (e & 15)];
+          __syncthreads();
+          fft_lines<false, true, EPT>(G, a.ffts[S.fft_yl[l]], kColW, 1, kColW, tw_s + twoff[l]);
+          const float2* F = ry + filt_index(l, kind, s) * ny;
+          for (int e = tid; e < n16; e += kThreads) {
+            const int ky = e >> 4;
+            V[e] = cadd(V[e], cmul(F[ky], G[(ky % ng) * kColW + (e & 15)]));
+          }
+          goff += ng;
+        }
+    }
+  }
+  __syncthreads();
+  // ---- lines 3-5 (or line 10, or nothing) on the strip
+  const float isq = rsqrtf((float)ny * (float)nx);
+  const float sig2 = a.sigma2 ? a.sigma2[sl] : 0.f;
+  const int kx = c0 + c;
+  float Q[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) Q[t] = 0.f;
+  for (int e = tid; e < n16; e += kThreads) {
+    const int ky = e >> 4;
+    const float2 X = cscale(V[e], isq);
+    float2 o = X;
+    if (mode != OC_SYNTH && mode != OC_ANAL) {
+      const long long g = S.off + (long long)ky * nx + kx;
+      const float2 yy = a.y[g];
+      const float w = a.wgt[g];
+      if (vd) {
+        o = make_float2(0.f, 0.f);
+        if (w > 0.f) {
+          const float2 z = csub(yy, X);
+          o = cscale(z, w);
+          const float cc = w * ((w - 1.0f) * (z.x * z.x + z.y * z.y) + sig2);
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (t < 2 * s) Q[t] = fmaf(ytab_s[t * ny + ky], cc, Q[t]);
+        }
+      } else if (mode == CM_OUTPUT) {
+        o = (w > 0.f) ? yy : X;
+      } else {  // CM_ZEROFILL
+        o = yy;
+      }
+    }
+    V[e] = cscale(o, isq);
+  }
+  if (vd) {
+    // tau_b partial = sum over this strip's columns of Xtab_b(kx) sum_ky Ytab_b(ky) c
+    const float* xtab = a.tables + S.xtab_off;
+    const int lane = tid & 63, wid = tid >> 6;
+    for (int b = 0; b < a.nbands; ++b) {
+      int ty, tx;
+      if (b == 0) { ty = s - 1; tx = s - 1; }
+      else {
+        const int l = s - (b - 1) / 3, k3 = (b - 1) % 3;
+        ty = (k3 == 0) ? l - 1 : s + l - 1;
+        tx = (k3 == 1) ? l - 1 : s + l - 1;
+      }
+      float q = 0.f;
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (t == ty) q = Q[t];
+      const float part = wave_sum(q * xtab[tx * nx + kx]);
+      if (lane == 0) red[wid][b] = part;
+    }
+  }
+  __syncthreads();
+  if (vd && tid < a.nbands) {
+    float acc = 0.f;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) acc += red[w][tid];
+    a.tau_part[(S.colstrip0 + item.y) * kMaxBands + tid] = acc;
+  }
+  // ---- out of k-space
+  if (out_plain) {
+    fft_lines<true, true, EPT>(V, a.ffts[S.fft_yl[0]], kColW, 1, kColW, tw_s + twoff[0]);
+    for (int e = tid; e < n16; e += kThreads) a.X[S.off + (long long)(e >> 4) * nx + c0 + (e & 15)] = V[e];
+    return;
+  }
+  int goff = 0;
+  for (int l = 1; l <= s; ++l)
+    for (int kind = 0; kind < 2; ++kind) {
+      const int ng = ny >> l, nal = 1 << l;
+      const float2* F = ry + filt_index(l, kind, s) * ny;
+      for (int e = tid; e < ng * kColW; e += kThreads) {
+        const int k = e >> 4, cc = e & 15;
+        float2 acc = make_float2(0.f, 0.f);
+        for (int j = 0; j < nal; ++j) {
+          const int ky = k + j * ng;
+          acc = cadd(acc, conj_mul(F[ky], V[ky * kColW + cc]));
+        }
+        G[e] = acc;
+      }
+      __syncthreads();
+      fft_lines<true, true, EPT>(G, a.ffts[S.fft_yl[l]], kColW, 1, kColW, tw_s + twoff[l]);
+      for (int e = tid; e < ng * kColW; e += kThreads)
+        a.Z[S.zoff + (long long)(goff + (e >> 4)) * nx + c0 + (e & 15)] = G[e];
+      __syncthreads();  // G is read before the next group overwrites it
+      goff += ng;
+    }
+}
+
+// ------------------------------------------------------------------ analysis
+// Dynamic LDS: the item's group rows (rpi x nx) and its band rows (rpi x nseg x m).
+__global__ void __launch_bounds__(kThreads) k_oanal(KArgs a) {
+  extern __shared__ float4 lds4[];
+  float2* Zs = reinterpret_cast<float2*>(lds4);
+  __shared__ float2 tw_s[kMaxN];
+  const int2 item = a.work[blockIdx.x];
+  const int sl = item.x;
+  const SliceDev S = a.slices[sl];
+  const int ny = S.ny, nx = S.nx, s = a.levels, tid = threadIdx.x, mode = a.mode;
+  if (mode == RA_IMAGE) {  // inverse row DFTs of X rows item.y .. item.y + rpi - 1
+    const int rpi = rows_per_item(ny);
+    const FftPlanDev& P = a.ffts[S.fft_x];
+    load_twiddles(tw_s, P, a.twiddles);
+    const long long base = S.off + (long long)item.y * nx;
+    for (int e = tid; e < rpi * nx; e += kThreads) Zs[e] = a.X[base + e];
+    __syncthreads();
+    fft_lines<true, false, 16>(Zs, P, rpi, nx, 1, tw_s);
+    for (int e = tid; e < rpi * nx; e += kThreads) a.out[base + e] = Zs[e];
+    return;
+  }
+  int l, kind, ng, goff;
+  group_of(item.y, ny, s, l, kind, ng, goff);
+  const int rpi = rows_per_item(ng), i0 = item.y - goff;
+  const int mx = nx >> l, nseg = (kind || l == s) ? 2 : 1, j0 = 2 - nseg, seglen = nseg * mx;
+  const int row0 = (kind ? (ny >> l) : 0) + i0, nal = 1 << l;
+  float2* Ss = Zs + rpi * nx;
+  const FftPlanDev& P = a.ffts[S.fft_xl[l]];
+  load_twiddles(tw_s, P, a.twiddles);
+  for (int e = tid; e < rpi * nx; e += kThreads) Zs[e] = a.Z[S.zoff + (long long)item.y * nx + e];
+  __syncthreads();
+  const float2* rx = a.resp + S.xresp_off;
+  for (int e = tid; e < rpi * seglen; e += kThreads) {
+    const int rr = e / seglen, rem = e - rr * seglen, js = rem / mx, k = rem - js * mx;
+    const float2* F = rx + filt_index(l, j0 + js, s) * nx;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int j = 0; j < nal; ++j) acc = cadd(acc, conj_mul(F[k + j * mx], Zs[rr * nx + k + j * mx]));
+    Ss[e] = acc;
+  }
+  __syncthreads();
+  fft_lines<true, false, 16>(Ss, P, rpi * nseg, mx, 1, tw_s);
+  const float* th = a.theta + sl * kMaxBands;
+  const float* t2 = a.thr2 + sl * kMaxBands;
+  const float* al = a.alpha + sl * kMaxBands;
+  for (int e = tid; e < rpi * seglen; e += kThreads) {
+    const int rr = e / seglen, rem = e - rr * seglen, js = rem / mx, c = rem - js * mx;
+    const int j = j0 + js, b = seg_band(l, kind, j, s);
+    const long long gi = S.off + (long long)(row0 + rr) * nx + j * mx + c;
+    const float2 coef = Ss[e];
+    if (mode == RA_VDAMP) a.r[gi] = cadd(rtilde_c(a.r[gi], th[b], t2[b], al[b]), coef);
+    else if (mode == RA_VDAMP_FIRST) a.r[gi] = coef;
+    else a.out[gi] = coef;  // OA_COEF
+  }
+}
+
+}  // namespace
+
+size_t ocols_lds_bytes(int maxny, int s) {
+  return sizeof(float2) * (size_t)maxny * kColW + sizeof(float2) * (size_t)(maxny / 2) * kColW +
+         sizeof(float) * (size_t)2 * s * maxny;
+}
+
+hipError_t set_lds_limits_ortho(size_t synth, size_t cols, size_t anal) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_osynth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)synth);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_ocols<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cols);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_ocols<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cols);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_oanal, hipFuncAttributeMaxDynamicSharedMemorySize, (int)anal);
+  return e;
+}
+
+hipError_t launch_osynth(const KArgs& a, size_t lds, hipStream_t st) {
+  if (a.nwork <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_osynth, dim3(a.nwork), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ocols(const KArgs& a, int ept, size_t lds, hipStream_t st) {
+  if (a.nwork <= 0) return hipSuccess;
+  if (ept == 16)
+    hipLaunchKernelGGL((k_ocols<16>), dim3(a.nwork), dim3(kThreads), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_ocols<32>), dim3(a.nwork), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_oanal(const KArgs& a, size_t lds, hipStream_t st) {
+  if (a.nwork <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_oanal, dim3(a.nwork), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace vdamp

@@ -43,7 +43,8 @@ EXPORTED = ("vdamp_plan", "vdamp_plan_destroy", "vdamp_solve", "vdamp_solve_resu
             "vdamp_state_export", "vdamp_pass_times", "vdamp_status_string", "vdamp_last_error",
             "vdamp_cnn_create", "vdamp_cnn_destroy", "vdamp_cnn_param_count", "vdamp_cnn_set_params",
             "vdamp_cnn_get_params", "vdamp_cnn_workspace", "vdamp_cnn_forward", "vdamp_cnn_train_step",
-            "vdamp_solve_learned", "vdamp_learned_export", "vdamp_wavelet", "vdamp_plan_describe")
+            "vdamp_solve_learned", "vdamp_learned_export", "vdamp_wavelet", "vdamp_plan_describe",
+            "vdamp_plan_ortho", "vdamp_wavelet_ws")
 
 
 class VdampError(RuntimeError):
@@ -75,6 +76,9 @@ def load_library() -> ctypes.CDLL:
     lib.vdamp_plan.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                i32, i32, u32, ctypes.POINTER(sz)]
     lib.vdamp_plan.restype = ctypes.c_int
+    lib.vdamp_plan_ortho.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                     i32, ctypes.POINTER(ctypes.c_double), i32, u32, ctypes.POINTER(sz)]
+    lib.vdamp_plan_ortho.restype = ctypes.c_int
     lib.vdamp_plan_destroy.argtypes = [vp]
     lib.vdamp_plan_destroy.restype = ctypes.c_int
     lib.vdamp_solve.argtypes = [vp, vp, vp, sz, vp, vp, vp, vp, i32, vp, vp]
@@ -109,6 +113,7 @@ def load_library() -> ctypes.CDLL:
         "vdamp_solve_learned": [vp, vp, vp, vp, sz, vp, sz, vp, vp, vp, vp, i32, i32, i32, u64, vp, vp],
         "vdamp_learned_export": [vp, vp, vp, vp, vp, vp, vp, vp, vp],
         "vdamp_wavelet": [vp, vp, i32, vp, vp],
+        "vdamp_wavelet_ws": [vp, vp, vp, sz, i32, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -140,9 +145,12 @@ def _stream_handle(stream) -> int:
 
 
 class Plan:
-    """A batch of slices (ragged sizes allowed) planned once; see ``vdamp_plan``."""
+    """A batch of slices (ragged sizes allowed) planned once; see ``vdamp_plan``.  With
+    ``lowpass`` (an orthonormal lowpass filter) the plan uses that wavelet instead of
+    Haar (``vdamp_plan_ortho``)."""
 
-    def __init__(self, ny: Sequence[int], nx: Sequence[int], levels: int, flags: int = 0):
+    def __init__(self, ny: Sequence[int], nx: Sequence[int], levels: int, flags: int = 0,
+                 lowpass=None):
         lib = load_library()
         self.ny = [int(v) for v in ny]
         self.nx = [int(v) for v in nx]
@@ -158,8 +166,14 @@ class Plan:
         a_nx = (ctypes.c_int32 * self.batch)(*self.nx)
         h = ctypes.c_void_p()
         wsb = ctypes.c_size_t()
-        _check(lib.vdamp_plan(ctypes.byref(h), self.batch, a_ny, a_nx, self.levels,
-                              VDAMP_WAVELET_HAAR, self.flags, ctypes.byref(wsb)))
+        if lowpass is None:
+            _check(lib.vdamp_plan(ctypes.byref(h), self.batch, a_ny, a_nx, self.levels,
+                                  VDAMP_WAVELET_HAAR, self.flags, ctypes.byref(wsb)))
+        else:
+            taps = [float(v) for v in lowpass]
+            a_h = (ctypes.c_double * max(len(taps), 1))(*taps)
+            _check(lib.vdamp_plan_ortho(ctypes.byref(h), self.batch, a_ny, a_nx, self.levels,
+                                        a_h, len(taps), self.flags, ctypes.byref(wsb)))
         self._h = h
         self.workspace_bytes = int(wsb.value)
 
@@ -225,6 +239,10 @@ class Plan:
     def vdamp_wavelet(self, x, out, inverse, stream=None):
         _check(load_library().vdamp_wavelet(self._h, _stream_handle(stream), int(bool(inverse)),
                                             _ptr(x), _ptr(out)))
+
+    def vdamp_wavelet_ws(self, ws, x, out, inverse, stream=None):
+        _check(load_library().vdamp_wavelet_ws(self._h, _stream_handle(stream), _ptr(ws), ws.numel(),
+                                               int(bool(inverse)), _ptr(x), _ptr(out)))
 
     def vdamp_solve_learned(self, cnn, ws, cnn_ws, y, mask, p, sigma2, iters, seed, x_hat,
                             trace=None, judge=0, learned_from=0, stream=None):

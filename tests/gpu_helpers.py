@@ -80,12 +80,13 @@ def run_resume(plan, slices, states, iters, want_state=True, x_monitor=False, st
     return out
 
 
-def run_vdamp(slices, s, iters, flags=0, want_state=False, plan=None, stream=None):
+def run_vdamp(slices, s, iters, flags=0, want_state=False, plan=None, stream=None, lowpass=None):
     import torch
     from paper_1911_01234_amd import vdamp as V
     own = plan is None
     if own:
-        plan = V.Plan([sl.y.shape[0] for sl in slices], [sl.y.shape[1] for sl in slices], s, flags)
+        plan = V.Plan([sl.y.shape[0] for sl in slices], [sl.y.shape[1] for sl in slices], s, flags,
+                      lowpass=lowpass)
     ws = plan.workspace()
     y, mask, p, sigma2 = V.to_device(plan, slices)
     x_hat = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")

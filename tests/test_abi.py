@@ -128,3 +128,34 @@ def test_describe_rejects_null_plan():
     need = ctypes.c_size_t(0)
     assert lib.vdamp_plan_describe(None, None, 0, ctypes.byref(need)) == 1
     assert lib.vdamp_last_error()
+
+
+def _ortho_status(taps, flags=0, ny=64, nx=64, levels=3, null_filter=False):
+    lib = V.load_library()
+    h = ctypes.c_void_p()
+    wsb = ctypes.c_size_t()
+    a_ny = (ctypes.c_int32 * 1)(ny)
+    a_nx = (ctypes.c_int32 * 1)(nx)
+    a_h = None if null_filter else (ctypes.c_double * max(len(taps), 1))(*taps)
+    st = lib.vdamp_plan_ortho(ctypes.byref(h), 1, a_ny, a_nx, levels, a_h, len(taps), flags,
+                              ctypes.byref(wsb))
+    return st, lib.vdamp_last_error().decode()
+
+
+def test_plan_ortho_rejects_bad_filters_before_any_launch():
+    """vdamp_plan_ortho checks the filter on the host: null, odd or out-of-range
+    length, non-finite taps and a filter that is not orthonormal are argument errors;
+    the Haar-pass tuner is not offered; shapes follow vdamp_plan's rules."""
+    from paper_1911_01234_amd import filters
+    db2 = list(filters.daubechies(2))
+    assert _ortho_status(db2, null_filter=True)[0] == 1
+    assert _ortho_status(db2[:3])[0] == 1                       # odd length
+    assert _ortho_status([])[0] == 1                            # empty
+    assert _ortho_status([0.0] * 66)[0] == 1                    # longer than 64
+    assert _ortho_status([1.0, 1.0])[0] == 1                    # sum h = 2, not sqrt 2
+    assert _ortho_status([0.5, 0.5, 0.5, 0.5])[0] == 1          # not orthogonal to its shifts
+    assert _ortho_status([float("nan"), 1.0])[0] == 1
+    assert _ortho_status(db2, flags=V.VDAMP_FLAG_AUTOTUNE)[0] == 3
+    assert _ortho_status(db2, ny=60)[0] == 2
+    st, msg = _ortho_status(db2, levels=0)
+    assert st == 3 and msg

@@ -63,15 +63,17 @@ def theta_alpha_tols(r_band, theta, alpha):
     return th_tol, al_tol
 
 
-def fp32_horizon(sl, s, K, ref, realizations=4, step_noise=3e-7):
+def fp32_horizon(sl, s, K, ref, realizations=4, step_noise=3e-7, wavelet=None):
     """How long an FP32 evaluation can follow the FP64 trajectory at all: the oracle's
     iteration with only its two FFTs evaluated in FP32 (scipy's complex64 FFT, whose
     one-step error, 3e-7 relative, is that of the library's kernels) against the FP64
     trajectory, once as it is and in `realizations` more runs that add, after every
     step, a seeded random relative error of `step_noise` to r (another rounding of the
     same size: the library's one-step error measures 3-5.5e-7).  Returns the first
-    iteration at which any of them is more than TOL_ITER / 2 away or picks a different
-    candidate in some band.  The iteration amplifies perturbations (density
+    iteration at which any of them is more than TOL_ITER / 2 away, or at which the run
+    without added error picks a different candidate in some band.  A perturbed run that
+    picks another candidate has left the decision path (the library's own flips are
+    detected directly) and stops counting there.  The iteration amplifies perturbations (density
     compensation 1/p in line 4, the Onsager correction in line 8), and how far a given
     realization drifts varies by several times between realizations (64x64 recipe, k = 10:
     3.6e-6 without the added error, 1e-5 with it, a flipped threshold in two of four), so
@@ -79,7 +81,7 @@ def fp32_horizon(sl, s, K, ref, realizations=4, step_noise=3e-7):
     the one-step gate covers those iterations."""
     import scipy.fft as sfft
     y, mask, p, s2 = fp32_inputs(sl)
-    S = o.tau_weights(y.shape[0], y.shape[1], s)
+    S = o.tau_weights(y.shape[0], y.shape[1], s, wavelet)
     om = mask.astype(bool)
     band_list = _bands(sl, s)
     ref_idx = [[int(np.argmin(np.abs(np.abs(ref["r"][k][rs, cs]).ravel() - ref["theta"][k][b])))
@@ -89,26 +91,29 @@ def fp32_horizon(sl, s, K, ref, realizations=4, step_noise=3e-7):
         rng = np.random.default_rng([7, real])
         rt = np.zeros(y.shape, dtype=np.complex128)
         for k in range(horizon):
-            X = sfft.fft2(o.haar_synthesis(rt, s).astype(np.complex64), norm="ortho")
+            X = sfft.fft2(o.synthesis(rt, s, wavelet).astype(np.complex64), norm="ortho")
             z = np.where(om, y - X.astype(np.complex128), 0.0)
             v = np.where(om, z / np.where(om, p, 1.0), 0.0)
             back = sfft.ifft2(v.astype(np.complex64), norm="ortho").astype(np.complex128)
-            r = rt + o.haar_analysis(back, s)
+            r = rt + o.analysis(back, s, wavelet)
             if real:
                 n = rng.standard_normal(r.shape) + 1j * rng.standard_normal(r.shape)
                 r = r + step_noise * np.linalg.norm(r) / np.linalg.norm(n) * n
             tau = o.tau_estimate(z, mask, p, s2, S)
             _, rt, th, _ = o.denoise(r, tau, s)
-            if rel_l2(r, ref["r"][k]) > TOL_ITER / 2 or any(
-                    int(np.argmin(np.abs(np.abs(r[rs, cs]).ravel() - th[b]))) != ref_idx[k][b]
-                    for b, (rs, cs, _, _) in enumerate(band_list)):
+            if rel_l2(r, ref["r"][k]) > TOL_ITER / 2:
                 horizon = k
+                break
+            if any(int(np.argmin(np.abs(np.abs(r[rs, cs]).ravel() - th[b]))) != ref_idx[k][b]
+                   for b, (rs, cs, _, _) in enumerate(band_list)):
+                if not real:
+                    horizon = k
                 break
     return horizon
 
 
-def oracle_run(sl, s, K, record=True, cont=False):
-    return o.vdamp(*fp32_inputs(sl), s, K, record=record, continuous=cont)
+def oracle_run(sl, s, K, record=True, cont=False, wavelet=None):
+    return o.vdamp(*fp32_inputs(sl), s, K, record=record, continuous=cont, wavelet=wavelet)
 
 
 def test_first_iteration_r0():
@@ -125,14 +130,14 @@ def test_first_iteration_r0():
     assert et <= TOL_TAU
 
 
-def one_step_check(sl, s, ref_k, g, b, k, what="", cont=False):
+def one_step_check(sl, s, ref_k, g, b, k, what="", cont=False, wavelet=None):
     """Compare the library's one step (slice b of g) from the FP32-rounded oracle state
     ref_k = (r, theta, alpha) with the oracle's step from the same state.  Returns
     (r error, number of bands decided differently).  With cont (the continuous threshold
     search) theta is compared directly where both land in the same interval between
     magnitudes (same count m at or below it), else validated on the library's own data."""
     y, mask, p, s2 = fp32_inputs(sl)
-    ref = o.vdamp_resume(y, mask, p, s2, s, *ref_k, 1, record=True, continuous=cont)
+    ref = o.vdamp_resume(y, mask, p, s2, s, *ref_k, 1, record=True, continuous=cont, wavelet=wavelet)
     r_ref = ref["r"][0]
     rg = g["r"][b].astype(np.complex128)
     e = rel_l2(rg, r_ref)
@@ -165,17 +170,19 @@ def one_step_check(sl, s, ref_k, g, b, k, what="", cont=False):
     return e, et, flips
 
 
-def one_step_every_iteration(sl, s, K, cont=False):
+def one_step_every_iteration(sl, s, K, cont=False, wavelet=None):
     """At every k < K: the library's step from the oracle's FP32-rounded state against the
-    oracle's step from the same state."""
+    oracle's step from the same state (wavelet: an orthonormal lowpass filter for a
+    vdamp_plan_ortho plan, None for Haar)."""
     from paper_1911_01234_amd import vdamp as V
-    traj = oracle_run(sl, s, K, cont=cont)
-    plan = V.Plan([sl.y.shape[0]], [sl.y.shape[1]], s, V.VDAMP_FLAG_SURE_CONTINUOUS if cont else 0)
+    traj = oracle_run(sl, s, K, cont=cont, wavelet=wavelet)
+    plan = V.Plan([sl.y.shape[0]], [sl.y.shape[1]], s, V.VDAMP_FLAG_SURE_CONTINUOUS if cont else 0,
+                  lowpass=wavelet)
     errs, terrs, nflip = [], [], 0
     for k in range(K - 1):
         st = fp32_state(traj["r"][k], traj["theta"][k], traj["alpha"][k])
         g = run_resume(plan, [sl], {0: st}, 1)
-        e, et, f = one_step_check(sl, s, st, g, 0, k, cont=cont)
+        e, et, f = one_step_check(sl, s, st, g, 0, k, cont=cont, wavelet=wavelet)
         errs.append(e)
         terrs.append(et)
         nflip += f
@@ -184,7 +191,7 @@ def one_step_every_iteration(sl, s, K, cont=False):
     plan.close()
 
 
-def tau_tolerances(sl, s, K, ref, cont=False):
+def tau_tolerances(sl, s, K, ref, cont=False, wavelet=None):
     """Per iteration, the relative tau error the 1e-5 iterate gate admits along a
     trajectory: tau (line 5) is quadratic in the residual z = y - Phi Psi^H r_tilde, the
     difference of the measurements and the prediction X = Phi Psi^H r_tilde, so an
@@ -195,13 +202,13 @@ def tau_tolerances(sl, s, K, ref, cont=False):
     out = [TOL_TAU_TRAJ]
     for k in range(1, K):
         _, rt, _, _ = o.denoise(ref["r"][k - 1], ref["tau"][k - 1], s, continuous=cont)
-        X = o.fft2u(o.haar_synthesis(rt, s))[om]
+        X = o.fft2u(o.synthesis(rt, s, wavelet))[om]
         kappa = np.linalg.norm(X) / np.linalg.norm(y[om] - X)
         out.append(max(TOL_TAU_TRAJ, 2.0 * kappa * TOL_ITER))
     return out
 
 
-def free_running(sl, s, K):
+def free_running(sl, s, K, wavelet=None):
     """Per iterate: the library's thresholds must be SURE-optimal (up to near ties) for
     its own r_k and tau_k, and its alpha line 7's value at that threshold on that
     iterate (to 1e-6; test code on the library's data).  Up to the first iteration where
@@ -212,15 +219,15 @@ def free_running(sl, s, K):
     the errors are printed; the one-step gate covers those iterations.  The final NMSE
     must match to 0.05 dB when no flip occurred, else lie within the envelope of
     perturbed oracle runs."""
-    ref = oracle_run(sl, s, K)
-    hz = fp32_horizon(sl, s, K, ref)
-    ttol = tau_tolerances(sl, s, K, ref)
-    g = run_vdamp([sl], s, K)
+    ref = oracle_run(sl, s, K, wavelet=wavelet)
+    hz = fp32_horizon(sl, s, K, ref, wavelet=wavelet)
+    ttol = tau_tolerances(sl, s, K, ref, wavelet=wavelet)
+    g = run_vdamp([sl], s, K, lowpass=wavelet)
     tr = g["trace"][:, 0]
     errs = []
     first_flip = None
     for k in range(K):
-        gk = run_vdamp([sl], s, k + 1, want_state=True)
+        gk = run_vdamp([sl], s, k + 1, want_state=True, lowpass=wavelet)
         rg = gk["r"][0].astype(np.complex128)
         e = rel_l2(rg, ref["r"][k])
         errs.append(e)
@@ -243,7 +250,7 @@ def free_running(sl, s, K):
     ex = rel_l2(g["x_hat"][0], ref["x_hat"])
     upto = min(hz, K if first_flip is None else first_flip[0] + 1)
     print(f"free-running K={K}: first near-tie flip {first_flip}, FP32 horizon {hz}; max rel L2 r_k over "
-          f"the {upto} gated iterations = {max(errs[:upto]):.2e}; after them "
+          f"the {upto} gated iterations = {max(errs[:upto], default=0.0):.2e}; after them "
           f"{' '.join(f'{v:.1e}' for v in errs[upto:upto + 6])}{' ...' if K > upto + 6 else ''}; "
           f"x_hat rel L2 = {ex:.2e}; NMSE gpu {n_gpu:.3f} dB, oracle {n_ref:.3f} dB")
     if first_flip is None:
@@ -251,19 +258,19 @@ def free_running(sl, s, K):
         if hz == K:
             assert ex <= TOL_ITER
     elif abs(n_gpu - n_ref) > TOL_NMSE_DB:
-        mean, sd = oracle_nmse_envelope(sl, s, K, n_ref)
+        mean, sd = oracle_nmse_envelope(sl, s, K, n_ref, wavelet=wavelet)
         print(f"  oracle envelope under 3e-7 input perturbation: mean {mean:.3f} dB, sd {sd:.3f} dB")
         assert abs(n_gpu - mean) <= max(TOL_NMSE_DB, 4 * sd)
 
 
-def oracle_nmse_envelope(sl, s, K, n_ref, runs=16, eps=3e-7, cont=False):
+def oracle_nmse_envelope(sl, s, K, n_ref, runs=16, eps=3e-7, cont=False, wavelet=None):
     y, mask, p, s2 = fp32_inputs(sl)
     rng = np.random.default_rng(2024)
     vals = [n_ref]
     for _ in range(runs):
         pert = (rng.standard_normal(y.shape) + 1j * rng.standard_normal(y.shape)) / np.sqrt(2)
-        vals.append(o.nmse_db(o.vdamp(y * (1 + eps * pert), mask, p, s2, s, K, continuous=cont)["x_hat"],
-                              sl.x0))
+        vals.append(o.nmse_db(o.vdamp(y * (1 + eps * pert), mask, p, s2, s, K, continuous=cont,
+                                      wavelet=wavelet)["x_hat"], sl.x0))
     return float(np.mean(vals)), float(np.std(vals))
 
 

@@ -1,0 +1,220 @@
+"""GPU parity of the general orthonormal wavelets (vdamp_plan_ortho: Algorithm 1 with any
+orthogonal Psi, Section 2) against the oracle's spatial-domain periodic Mallat transform
+(oracle.vdamp_ref.dwt2 / idwt2) and its Algorithm 1 with that Psi, at the same gates as
+the Haar path: the transform itself to 1e-5, one step from the oracle's FP32-rounded
+state at every iteration (r, tau to 1e-5; theta, alpha to the tolerances the iterate's
+implies; near ties validated on the library's own data), the free-running trajectory up
+to the FP32 horizon and the first near-tie flip.  The library applies Psi in the Fourier
+domain (filter responses times short DFTs); the oracle filters in space, so the two
+share nothing but the definition of Psi."""
+import numpy as np
+import pytest
+
+from oracle import vdamp_ref as o
+from paper_1911_01234_amd import filters, synth
+
+from gpu_helpers import fp32_inputs, fp32_state, gpu_available, rel_l2, run_resume, run_vdamp
+from test_gpu_parity import (TOL_ITER, TOL_TAU, free_running, one_step_check,
+                             one_step_every_iteration, oracle_run)
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an MI355X")]
+
+DB2, DB4, DB8 = filters.daubechies(2), filters.daubechies(4), filters.daubechies(8)
+
+
+def _plan(ny, nx, s, h, flags=0):
+    from paper_1911_01234_amd import vdamp as V
+    return V.Plan(ny, nx, s, flags, lowpass=h)
+
+
+def _transform(plan, imgs, inverse):
+    import torch
+    ws = plan.workspace()
+    x = torch.from_numpy(plan.pack(imgs, np.complex64)).cuda()
+    out = torch.empty_like(x)
+    plan.vdamp_wavelet_ws(ws, x, out, inverse)
+    torch.cuda.synchronize()
+    return plan.unpack(out.cpu().numpy())
+
+
+@pytest.mark.parametrize("ny,nx,s,name", [
+    ([64], [64], 3, "db2"),
+    ([128, 64], [256, 64], 4, "db4"),     # ragged batch
+    ([96], [160], 3, "db8"),              # radix 3 and 5 lengths
+    ([16], [32], 3, "db8"),               # 16 taps wrapping around 2- and 4-sample levels
+    ([512], [512], 4, "db4"),             # the paper's image size
+])
+def test_transform_matches_oracle(ny, nx, s, name):
+    """Psi and Psi^H through vdamp_wavelet_ws against dwt2 / idwt2 of the FP32-rounded
+    input, per slice, to 1e-5 relative L2."""
+    h = {"db2": DB2, "db4": DB4, "db8": DB8}[name]
+    plan = _plan(ny, nx, s, h)
+    rng = np.random.default_rng(11)
+    imgs = [(rng.standard_normal((a, b)) + 1j * rng.standard_normal((a, b))).astype(np.complex64)
+            for a, b in zip(ny, nx)]
+    fw = _transform(plan, imgs, inverse=False)
+    bw = _transform(plan, imgs, inverse=True)
+    for b, x in enumerate(imgs):
+        ef = rel_l2(fw[b], o.dwt2(x.astype(np.complex128), h, s))
+        eb = rel_l2(bw[b], o.idwt2(x.astype(np.complex128), h, s))
+        print(f"{ny[b]}x{nx[b]} s={s} {name}: Psi {ef:.2e}, Psi^H {eb:.2e}")
+        assert ef <= TOL_ITER and eb <= TOL_ITER
+    plan.close()
+
+
+def test_haar_filter_through_the_general_path_equals_the_haar_path():
+    """The Haar filter given to vdamp_plan_ortho runs the Fourier-domain passes; its
+    transform and its first iterate (r_0, tau_0) match the Haar plan's strip kernels to
+    FP32 rounding, and a 30-iteration solve ends at the same NMSE."""
+    from paper_1911_01234_amd import vdamp as V
+    sl, s, K = synth.workload_single64()
+    sl = sl[0]
+    po = _plan([64], [64], s, filters.haar())
+    ph = V.Plan([64], [64], s)
+    rng = np.random.default_rng(5)
+    x = [(rng.standard_normal((64, 64)) + 1j * rng.standard_normal((64, 64))).astype(np.complex64)]
+    import torch
+    xt = torch.from_numpy(ph.pack(x, np.complex64)).cuda()
+    outh = torch.empty_like(xt)
+    ph.vdamp_wavelet(xt, outh, False)
+    torch.cuda.synchronize()
+    assert rel_l2(_transform(po, x, False)[0], ph.unpack(outh.cpu().numpy())[0]) <= 1e-6
+    go = run_vdamp([sl], s, 1, want_state=True, plan=po)
+    gh = run_vdamp([sl], s, 1, want_state=True, plan=ph)
+    assert rel_l2(go["r"][0], gh["r"][0]) <= 1e-6
+    assert np.max(np.abs(go["tau"] - gh["tau"]) / gh["tau"]) <= 1e-6
+    no = o.nmse_db(run_vdamp([sl], s, K, plan=po)["x_hat"][0], sl.x0)
+    nh = o.nmse_db(run_vdamp([sl], s, K, plan=ph)["x_hat"][0], sl.x0)
+    print(f"NMSE general path {no:.3f} dB, Haar path {nh:.3f} dB")
+    assert abs(no - nh) <= 0.05
+    po.close()
+    ph.close()
+
+
+@pytest.mark.parametrize("name", ["db2", "db4", "db8"])
+def test_first_iteration_r0_tau0(name):
+    """k = 0 at 256x256: r_0 = Psi F^H P^-1 y and tau_0 from line 5 with the filter's S."""
+    h = {"db2": DB2, "db4": DB4, "db8": DB8}[name]
+    sl = synth.workload_single256(6.0)[0][0]
+    g = run_vdamp([sl], 4, 1, want_state=True, lowpass=h)
+    y, mask, p, s2 = fp32_inputs(sl)
+    S = o.tau_weights(256, 256, 4, h)
+    r0, tau0 = o.vdamp_step(np.zeros_like(y), y, mask, p, s2, 4, S, h)
+    e = rel_l2(g["r"][0], r0)
+    et = float(np.max(np.abs(g["tau"][0] - tau0) / tau0))
+    print(f"{name}: r_0 rel L2 {e:.2e}; tau_0 max rel {et:.2e}")
+    assert e <= TOL_ITER and et <= TOL_TAU
+
+
+def test_one_step_64_db4():
+    sl, s, K = synth.workload_single64()
+    one_step_every_iteration(sl[0], s, K, wavelet=DB4)
+
+
+def test_one_step_64_db8():
+    sl, s, K = synth.workload_single64()
+    one_step_every_iteration(sl[0], s, K, wavelet=DB8)
+
+
+@pytest.mark.parametrize("R", [4.0, 8.0])
+def test_one_step_256_db4(R):
+    sl, s, K = synth.workload_single256(R)
+    one_step_every_iteration(sl[0], s, K, wavelet=DB4)
+
+
+def test_one_step_non_square_db2():
+    sl = synth.make_slice(3, 0, 96, 160, 12, 4.0, 5.0, 8, 35.0)
+    one_step_every_iteration(sl, 3, 25, wavelet=DB2)
+
+
+def test_free_running_64_db4():
+    sl, s, K = synth.workload_single64()
+    free_running(sl[0], s, K, wavelet=DB4)
+
+
+def test_free_running_256_db2():
+    sl, s, K = synth.workload_single256(6.0)
+    free_running(sl[0], s, 20, wavelet=DB2)
+
+
+def test_one_step_inside_a_ragged_batch():
+    """Slices of three sizes in one general-wavelet plan: one step from each slice's
+    oracle state at k = 0, 4, 12, all slices resumed together."""
+    from paper_1911_01234_amd import vdamp as V
+    sls = [synth.make_slice(5, 0, 128, 128, 12, 4.0, 6.0, 8, 35.0),
+           synth.make_slice(5, 1, 192, 256, 12, 4.0, 4.0, 16, 40.0),
+           synth.make_slice(5, 2, 64, 96, 8, 4.0, 8.0, 8, 30.0)]
+    s, K = 3, 13
+    h = DB4
+    trajs = [oracle_run(sl, s, K, wavelet=h) for sl in sls]
+    plan = V.Plan([sl.y.shape[0] for sl in sls], [sl.y.shape[1] for sl in sls], s, lowpass=h)
+    for k in (0, 4, 12):
+        states = {b: fp32_state(t["r"][k], t["theta"][k], t["alpha"][k]) for b, t in enumerate(trajs)}
+        g = run_resume(plan, sls, states, 1)
+        for b, sl in enumerate(sls):
+            e, et, _ = one_step_check(sl, s, states[b], g, b, k, what=f"slice {b}", wavelet=h)
+            print(f"k={k} slice {b} ({sl.y.shape[0]}x{sl.y.shape[1]}): r {e:.2e} tau {et:.2e}")
+    plan.close()
+
+
+def test_resume_monitor_graph_and_noalloc_agree_bitwise():
+    """On a general-wavelet plan: a solve split in two calls (the exported r, theta, its
+    key and alpha, then vdamp_solve_resume) equals one call bit for bit, the monitor
+    output's last image is x_hat, three replays of the captured graph equal the eager
+    solve, and vdamp_solve_noalloc equals vdamp_solve."""
+    import torch
+    from paper_1911_01234_amd import vdamp as V
+    sl, s, K = synth.workload_single64()
+    sl = sl[0]
+    h = DB4
+    plan = _plan([64], [64], s, h)
+    full = run_vdamp([sl], s, 10, plan=plan)
+    first = run_vdamp([sl], s, 4, want_state=True, plan=plan)
+    ws = plan.workspace()
+    y, mask, p, sigma2 = V.to_device(plan, [sl])
+    r = torch.from_numpy(plan.pack(first["r"], np.complex64)).cuda()
+    th = torch.from_numpy(first["theta"].ravel().copy()).cuda()
+    t2 = torch.from_numpy(first["theta2"].ravel().copy()).cuda()
+    al = torch.from_numpy(first["alpha"].ravel().copy()).cuda()
+    x = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+    trace = torch.empty(6 * plan.nbands * 3, dtype=torch.float32, device="cuda")
+    mon = torch.empty(6 * plan.ntot, dtype=torch.complex64, device="cuda")
+    plan.vdamp_solve_resume(ws, y, mask, p, sigma2, r, th, t2, al, 6, x, trace, mon)
+    torch.cuda.synchronize()
+    got = plan.unpack(x.cpu().numpy())[0]
+    assert np.array_equal(got, full["x_hat"][0])
+    assert np.array_equal(trace.cpu().numpy().reshape(6, 1, plan.nbands, 3), full["trace"][4:])
+    assert np.array_equal(plan.unpack(mon.cpu().numpy()[5 * plan.ntot:])[0], got)
+    gplan = _plan([64], [64], s, h, V.VDAMP_FLAG_USE_GRAPH)
+    gws = gplan.workspace()
+    stream = torch.cuda.Stream()  # capture needs a stream other than the null stream
+    for _ in range(3):
+        x.zero_()
+        torch.cuda.synchronize()
+        gplan.vdamp_solve(gws, y, mask, p, sigma2, 10, x, stream=stream)
+        torch.cuda.synchronize()
+        assert np.array_equal(gplan.unpack(x.cpu().numpy())[0], full["x_hat"][0])
+    na = torch.empty_like(x)
+    plan.vdamp_solve_noalloc(y, mask, p, sigma2, 10, na)
+    torch.cuda.synchronize()
+    assert np.array_equal(plan.unpack(na.cpu().numpy())[0], full["x_hat"][0])
+    plan.close()
+    gplan.close()
+
+
+def test_entry_points_without_a_general_wavelet_path_refuse():
+    import torch
+    from paper_1911_01234_amd import vdamp as V
+    plan = _plan([64], [64], 3, DB2)
+    ws = plan.workspace()
+    z = torch.zeros(plan.ntot, dtype=torch.complex64, device="cuda")
+    m = torch.zeros(plan.ntot, dtype=torch.uint8, device="cuda")
+    lam = torch.ones(1, dtype=torch.float32, device="cuda")
+    with pytest.raises(V.VdampError) as ei:
+        plan.fista_solve(ws, z, m, lam, 2, torch.empty_like(z))
+    assert ei.value.status == 3
+    with pytest.raises(V.VdampError) as ei:
+        plan.vdamp_wavelet(z, torch.empty_like(z), True)
+    assert ei.value.status == 3
+    plan.close()
