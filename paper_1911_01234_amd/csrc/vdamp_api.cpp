@@ -588,8 +588,8 @@ static vdamp_status make_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* 
     vimg = sort_items(wi);
     P->n_orows = (int)vor.size();
     P->n_img = (int)vimg.size();
-    P->lds_osynth = sizeof(float2) * (size_t)8 * maxnx;
-    P->lds_oanal = 2 * P->lds_osynth;
+    P->lds_osynth = sizeof(float2) * (size_t)10 * maxnx;  // 8 rows + 2 responses
+    P->lds_oanal = sizeof(float2) * (size_t)18 * maxnx;   // 8 group rows + 8 band rows + 2 responses
     P->lds_ocols = ocols_lds_bytes(maxny, levels);
     P->ocols_ept = maxny * kColW <= 16 * kThreads ? 16 : 32;
   }

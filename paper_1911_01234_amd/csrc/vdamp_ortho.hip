@@ -62,6 +62,23 @@ __device__ __forceinline__ float2 conj_mul(float2 f, float2 v) {  // conj(f) v
   return make_float2(f.x * v.x + f.y * v.y, f.x * v.y - f.y * v.x);
 }
 
+// In-LDS FFTs of the 16 columns of a strip block (element (i, c) at buf[16 i + c]): the
+// Stockham stages of fft_lines with the line count fixed at compile time.
+template <bool INV, int EPT>
+__device__ __forceinline__ void fft_cols16(float2* buf, const FftPlanDev& P, const float2* tw) {
+  int Ns = 1;
+  for (int st = 0; st < P.nst; ++st) {
+    const int R = P.rad[st];
+    switch (R) {
+      case 4: fft_stage<4, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
+      case 2: fft_stage<2, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
+      case 3: fft_stage<3, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
+      default: fft_stage<5, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
+    }
+    Ns *= R;
+  }
+}
+
 // ------------------------------------------------------------------ synthesis
 __global__ void __launch_bounds__(kThreads) k_osynth(KArgs a) {
   extern __shared__ float4 lds4[];
@@ -89,6 +106,9 @@ __global__ void __launch_bounds__(kThreads) k_osynth(KArgs a) {
   const int row0 = (kind ? (ny >> l) : 0) + i0;  // coefficient row of group row i0
   const FftPlanDev& P = a.ffts[S.fft_xl[l]];
   load_twiddles(tw_s, P, a.twiddles);
+  float2* Fx = buf + 8 * nx;  // x responses of A_l and D_l
+  for (int i = tid; i < 2 * nx; i += kThreads)
+    Fx[i] = a.resp[S.xresp_off + filt_index(l, i >= nx, s) * nx + (i >= nx ? i - nx : i)];
   const float* th = a.theta + sl * kMaxBands;
   const float* t2 = a.thr2 + sl * kMaxBands;
   const float* al = a.alpha + sl * kMaxBands;
@@ -103,19 +123,21 @@ __global__ void __launch_bounds__(kThreads) k_osynth(KArgs a) {
   }
   __syncthreads();
   fft_lines<false, false, 16>(buf, P, rpi * nseg, mx, 1, tw_s);
-  const float2* rx = a.resp + S.xresp_off;
   for (int e = tid; e < rpi * nx; e += kThreads) {
     const int rr = e / nx, kx = e - rr * nx, k = kx % mx;
     float2 acc = make_float2(0.f, 0.f);
     for (int js = 0; js < nseg; ++js)
-      acc = cadd(acc, cmul(rx[filt_index(l, j0 + js, s) * nx + kx], buf[(rr * nseg + js) * mx + k]));
+      acc = cadd(acc, cmul(Fx[(j0 + js) * nx + kx], buf[(rr * nseg + js) * mx + k]));
     a.Z[S.zoff + (long long)(item.y + rr) * nx + kx] = acc;
   }
 }
 
 // ------------------------------------------------------------------ columns
-// Dynamic LDS: the k-space strip V (ny x 16), one group column block G (ny/2 x 16), the
-// 2 s y-axis tau tables (ny floats each).
+// Thread t owns column c = t mod 16 of the strip and the k-space rows q + 16 j (q = t / 16,
+// j < ny / 16): the sum over groups accumulates in its registers, and the strip goes to
+// LDS once, after the k-space step, for the folds.  Dynamic LDS: the k-space strip V
+// (ny x 16), one group column block G (ny/2 x 16; during the k-space step it holds the
+// 2 s y-axis tau tables instead, ny floats each) and the y responses (2 s x ny complex).
 template <int EPT>
 __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
   extern __shared__ float4 lds4[];
@@ -128,7 +150,8 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
   const int tid = threadIdx.x, mode = a.mode;
   float2* V = reinterpret_cast<float2*>(lds4);
   float2* G = V + ny * kColW;
-  float* ytab_s = reinterpret_cast<float*>(G + (ny / 2) * kColW);
+  float2* Fy = G + (ny / 2) * kColW;
+  float* ytab_s = reinterpret_cast<float*>(G);  // 2 s ny floats <= the ny/2 x 16 block
   const bool vd = (mode == CM_VDAMP || mode == CM_VDAMP_FIRST);
   const bool in_zero = (mode == CM_VDAMP_FIRST || mode == CM_ZEROFILL);
   const bool in_plain = (mode == OC_ANAL);
@@ -144,38 +167,44 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
       o += P.n;
     }
   }
-  if (vd)
-    for (int i = tid; i < 2 * s * ny; i += kThreads) ytab_s[i] = a.tables[S.ytab_off + i];
-  const float2* ry = a.resp + S.yresp_off;
+  for (int i = tid; i < 2 * s * ny; i += kThreads) Fy[i] = a.resp[S.yresp_off + i];
   const int n16 = ny * kColW;
-  const int c = tid & (kColW - 1);  // every element this thread touches is in column c
+  const int c = tid & (kColW - 1), q = tid >> 4;
+  float2 acc[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) acc[j] = make_float2(0.f, 0.f);
   // ---- into k-space
   if (in_plain) {
     for (int e = tid; e < n16; e += kThreads) V[e] = a.X[S.off + (long long)(e >> 4) * nx + c0 + (e & 15)];
     __syncthreads();
-    fft_lines<false, true, EPT>(V, a.ffts[S.fft_yl[0]], kColW, 1, kColW, tw_s + twoff[0]);
-  } else {
-    for (int e = tid; e < n16; e += kThreads) V[e] = make_float2(0.f, 0.f);
-    if (!in_zero) {
-      int goff = 0;
-      for (int l = 1; l <= s; ++l)
-        for (int kind = 0; kind < 2; ++kind) {
-          const int ng = ny >> l;
-          __syncthreads();  // G is free
-          for (int e = tid; e < ng * kColW; e += kThreads)
-            G[e] = a.Z[S.zoff + (long long)(goff + (e >> 4)) * nx + c0 + (e & 15)];
-          __syncthreads();
-          fft_lines<false, true, EPT>(G, a.ffts[S.fft_yl[l]], kColW, 1, kColW, tw_s + twoff[l]);
-          const float2* F = ry + filt_index(l, kind, s) * ny;
-          for (int e = tid; e < n16; e += kThreads) {
-            const int ky = e >> 4;
-            V[e] = cadd(V[e], cmul(F[ky], G[(ky % ng) * kColW + (e & 15)]));
-          }
-          goff += ng;
+    fft_cols16<false, EPT>(V, a.ffts[S.fft_yl[0]], tw_s + twoff[0]);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j)
+      if (q + 16 * j < ny) acc[j] = V[(q + 16 * j) * kColW + c];
+  } else if (!in_zero) {
+    int goff = 0;
+    for (int l = 1; l <= s; ++l)
+      for (int kind = 0; kind < 2; ++kind) {
+        const int ng = ny >> l;
+        __syncthreads();  // G is free (and the tables are in)
+        for (int e = tid; e < ng * kColW; e += kThreads)
+          G[e] = a.Z[S.zoff + (long long)(goff + (e >> 4)) * nx + c0 + (e & 15)];
+        __syncthreads();
+        fft_cols16<false, EPT>(G, a.ffts[S.fft_yl[l]], tw_s + twoff[l]);
+        const float2* F = Fy + filt_index(l, kind, s) * ny;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+          const int ky = q + 16 * j;
+          if (ky < ny) acc[j] = cadd(acc[j], cmul(F[ky], G[(ky % ng) * kColW + c]));
         }
-    }
+        goff += ng;
+      }
   }
-  __syncthreads();
+  __syncthreads();  // V and G free
+  if (vd) {
+    for (int i = tid; i < 2 * s * ny; i += kThreads) ytab_s[i] = a.tables[S.ytab_off + i];
+    __syncthreads();
+  }
   // ---- lines 3-5 (or line 10, or nothing) on the strip
   const float isq = rsqrtf((float)ny * (float)nx);
   const float sig2 = a.sigma2 ? a.sigma2[sl] : 0.f;
@@ -183,9 +212,11 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
   float Q[8];
 #pragma unroll
   for (int t = 0; t < 8; ++t) Q[t] = 0.f;
-  for (int e = tid; e < n16; e += kThreads) {
-    const int ky = e >> 4;
-    const float2 X = cscale(V[e], isq);
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int ky = q + 16 * j;
+    if (ky >= ny) continue;
+    const float2 X = cscale(acc[j], isq);
     float2 o = X;
     if (mode != OC_SYNTH && mode != OC_ANAL) {
       const long long g = S.off + (long long)ky * nx + kx;
@@ -207,7 +238,7 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
         o = yy;
       }
     }
-    V[e] = cscale(o, isq);
+    V[ky * kColW + c] = cscale(o, isq);
   }
   if (vd) {
     // tau_b partial = sum over this strip's columns of Xtab_b(kx) sum_ky Ytab_b(ky) c
@@ -221,24 +252,24 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
         ty = (k3 == 0) ? l - 1 : s + l - 1;
         tx = (k3 == 1) ? l - 1 : s + l - 1;
       }
-      float q = 0.f;
+      float qv = 0.f;
 #pragma unroll
       for (int t = 0; t < 8; ++t)
-        if (t == ty) q = Q[t];
-      const float part = wave_sum(q * xtab[tx * nx + kx]);
+        if (t == ty) qv = Q[t];
+      const float part = wave_sum(qv * xtab[tx * nx + kx]);
       if (lane == 0) red[wid][b] = part;
     }
   }
   __syncthreads();
   if (vd && tid < a.nbands) {
-    float acc = 0.f;
+    float sum = 0.f;
 #pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) acc += red[w][tid];
-    a.tau_part[(S.colstrip0 + item.y) * kMaxBands + tid] = acc;
+    for (int w = 0; w < kThreads / 64; ++w) sum += red[w][tid];
+    a.tau_part[(S.colstrip0 + item.y) * kMaxBands + tid] = sum;
   }
   // ---- out of k-space
   if (out_plain) {
-    fft_lines<true, true, EPT>(V, a.ffts[S.fft_yl[0]], kColW, 1, kColW, tw_s + twoff[0]);
+    fft_cols16<true, EPT>(V, a.ffts[S.fft_yl[0]], tw_s + twoff[0]);
     for (int e = tid; e < n16; e += kThreads) a.X[S.off + (long long)(e >> 4) * nx + c0 + (e & 15)] = V[e];
     return;
   }
@@ -246,18 +277,18 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
   for (int l = 1; l <= s; ++l)
     for (int kind = 0; kind < 2; ++kind) {
       const int ng = ny >> l, nal = 1 << l;
-      const float2* F = ry + filt_index(l, kind, s) * ny;
+      const float2* F = Fy + filt_index(l, kind, s) * ny;
       for (int e = tid; e < ng * kColW; e += kThreads) {
         const int k = e >> 4, cc = e & 15;
-        float2 acc = make_float2(0.f, 0.f);
+        float2 sum = make_float2(0.f, 0.f);
         for (int j = 0; j < nal; ++j) {
           const int ky = k + j * ng;
-          acc = cadd(acc, conj_mul(F[ky], V[ky * kColW + cc]));
+          sum = cadd(sum, conj_mul(F[ky], V[ky * kColW + cc]));
         }
-        G[e] = acc;
+        G[e] = sum;
       }
       __syncthreads();
-      fft_lines<true, true, EPT>(G, a.ffts[S.fft_yl[l]], kColW, 1, kColW, tw_s + twoff[l]);
+      fft_cols16<true, EPT>(G, a.ffts[S.fft_yl[l]], tw_s + twoff[l]);
       for (int e = tid; e < ng * kColW; e += kThreads)
         a.Z[S.zoff + (long long)(goff + (e >> 4)) * nx + c0 + (e & 15)] = G[e];
       __syncthreads();  // G is read before the next group overwrites it
@@ -266,7 +297,8 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
 }
 
 // ------------------------------------------------------------------ analysis
-// Dynamic LDS: the item's group rows (rpi x nx) and its band rows (rpi x nseg x m).
+// Dynamic LDS: the item's group rows (rpi x nx), its band rows (rpi x nseg x m) and the
+// x responses of A_l and D_l.
 __global__ void __launch_bounds__(kThreads) k_oanal(KArgs a) {
   extern __shared__ float4 lds4[];
   float2* Zs = reinterpret_cast<float2*>(lds4);
@@ -291,15 +323,17 @@ __global__ void __launch_bounds__(kThreads) k_oanal(KArgs a) {
   const int rpi = rows_per_item(ng), i0 = item.y - goff;
   const int mx = nx >> l, nseg = (kind || l == s) ? 2 : 1, j0 = 2 - nseg, seglen = nseg * mx;
   const int row0 = (kind ? (ny >> l) : 0) + i0, nal = 1 << l;
-  float2* Ss = Zs + rpi * nx;
+  float2* Ss = Zs + 8 * nx;
+  float2* Fx = Ss + 8 * nx;  // x responses of A_l and D_l
   const FftPlanDev& P = a.ffts[S.fft_xl[l]];
   load_twiddles(tw_s, P, a.twiddles);
+  for (int i = tid; i < 2 * nx; i += kThreads)
+    Fx[i] = a.resp[S.xresp_off + filt_index(l, i >= nx, s) * nx + (i >= nx ? i - nx : i)];
   for (int e = tid; e < rpi * nx; e += kThreads) Zs[e] = a.Z[S.zoff + (long long)item.y * nx + e];
   __syncthreads();
-  const float2* rx = a.resp + S.xresp_off;
   for (int e = tid; e < rpi * seglen; e += kThreads) {
     const int rr = e / seglen, rem = e - rr * seglen, js = rem / mx, k = rem - js * mx;
-    const float2* F = rx + filt_index(l, j0 + js, s) * nx;
+    const float2* F = Fx + (j0 + js) * nx;
     float2 acc = make_float2(0.f, 0.f);
     for (int j = 0; j < nal; ++j) acc = cadd(acc, conj_mul(F[k + j * mx], Zs[rr * nx + k + j * mx]));
     Ss[e] = acc;
@@ -324,7 +358,7 @@ __global__ void __launch_bounds__(kThreads) k_oanal(KArgs a) {
 
 size_t ocols_lds_bytes(int maxny, int s) {
   return sizeof(float2) * (size_t)maxny * kColW + sizeof(float2) * (size_t)(maxny / 2) * kColW +
-         sizeof(float) * (size_t)2 * s * maxny;
+         sizeof(float2) * (size_t)2 * s * maxny;
 }
 
 hipError_t set_lds_limits_ortho(size_t synth, size_t cols, size_t anal) {
