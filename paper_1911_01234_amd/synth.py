@@ -250,3 +250,106 @@ def workload_c5(n: int, cfg_id: int = 5, first_slice: int = 0):
     """512x512 textured slices for the learned denoiser at scale (evaluation cfg_id 5,
     training 50): workload_batch512's recipe, R alternating 8 and 12."""
     return workload_batch512(n, cfg_id=cfg_id, first_slice=first_slice)
+
+
+# ---------------------------------------------------------------------------------
+# 3D volumes (Section 1: Phi may use a 3D DFT).  Random-ellipsoid phantoms with a
+# smooth phase, the polynomial variable density in the normalised 3D radius with a
+# fully sampled C x C x C centre, Bernoulli sampling and white complex noise, seeded as
+# for slices.  Arrays are [nz][ny][nx].
+
+@dataclass
+class Volume:
+    x0: np.ndarray       # complex128 [nz][ny][nx]
+    y: np.ndarray        # complex128 [nz][ny][nx] zero-filled measurements, natural order
+    mask: np.ndarray     # uint8
+    p: np.ndarray        # float64
+    sigma2: float
+    R: float
+    snr_db: float
+
+
+def phantom3d(cfg_id: int, vol_id: int, nz: int, ny: int, nx: int, n_ellipsoids: int) -> np.ndarray:
+    w = 2.0 * (np.arange(nz) + 0.5) / nz - 1.0
+    v = 2.0 * (np.arange(ny) + 0.5) / ny - 1.0
+    u = 2.0 * (np.arange(nx) + 0.5) / nx - 1.0
+    W, V, U = np.meshgrid(w, v, u, indexing="ij")
+    rng = rng_for(cfg_id, vol_id, STREAM_PHANTOM)
+    mag = np.zeros(U.shape)
+    for e in range(n_ellipsoids):
+        if e == 0:
+            c = rng.uniform(-0.1, 0.1, size=3)
+            ax = rng.uniform(0.6, 0.85, size=3)
+        else:
+            c = rng.uniform(-0.5, 0.5, size=3)
+            ax = rng.uniform(0.05, 0.4, size=3)
+        ang = rng.uniform(0.0, np.pi)   # rotation about the z axis
+        inten = rng.uniform(0.1, 1.0)
+        du, dv, dw = U - c[0], V - c[1], W - c[2]
+        ur = np.cos(ang) * du + np.sin(ang) * dv
+        vr = -np.sin(ang) * du + np.cos(ang) * dv
+        mag[(ur / ax[0]) ** 2 + (vr / ax[1]) ** 2 + (dw / ax[2]) ** 2 <= 1.0] = inten
+    prng = rng_for(cfg_id, vol_id, STREAM_PHASE)
+    q = prng.uniform(-1.0, 1.0, size=4)
+    phi = q[0] + q[1] * U + q[2] * V + q[3] * W
+    pm = np.abs(phi).max()
+    if pm > 0:
+        phi = phi * (np.pi / 4.0) / pm
+    return mag * np.exp(1j * phi)
+
+
+@functools.lru_cache(maxsize=16)
+def _density3d_centred(nz: int, ny: int, nx: int, R: float, d: float, C: int) -> np.ndarray:
+    kz = np.arange(-(nz // 2), nz - nz // 2)[:, None, None].astype(np.float64)
+    ky = np.arange(-(ny // 2), ny - ny // 2)[None, :, None].astype(np.float64)
+    kx = np.arange(-(nx // 2), nx - nx // 2)[None, None, :].astype(np.float64)
+    rad = np.sqrt(kz ** 2 + ky ** 2 + kx ** 2)
+    base = (1.0 - rad / rad.max()) ** d
+    centre = ((np.abs(kz + 0.5) <= C / 2) & (np.abs(ky + 0.5) <= C / 2) & (np.abs(kx + 0.5) <= C / 2))
+    target = nz * ny * nx / float(R)
+    if target < centre.sum():
+        raise ValueError("undersampling factor incompatible with the fully sampled centre")
+    lo, hi = -1.0, 1.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        p = np.clip(base + mid, 0.0, 1.0)
+        p[centre] = 1.0
+        if p.sum() < target:
+            lo = mid
+        else:
+            hi = mid
+    p = np.clip(base + hi, 0.0, 1.0)
+    p[centre] = 1.0
+    p.setflags(write=False)
+    return p
+
+
+def density3d(nz: int, ny: int, nx: int, R: float, d: float, C: int) -> np.ndarray:
+    """p = clip((1 - r)^d + c, 0, 1) in the normalised 3D radius, fully sampled centre
+    cube, sum(p) = N / R; natural FFT order."""
+    return np.fft.ifftshift(_density3d_centred(nz, ny, nx, float(R), float(d), int(C)))
+
+
+def make_volume(cfg_id: int, vol_id: int, nz: int, ny: int, nx: int, n_ellipsoids: int, R: float,
+                d: float, C: int, snr_db: float) -> Volume:
+    x0 = phantom3d(cfg_id, vol_id, nz, ny, nx, n_ellipsoids)
+    p = density3d(nz, ny, nx, R, d, C)
+    mask = (rng_for(cfg_id, vol_id, STREAM_MASK).random(p.shape) < p).astype(np.uint8)
+    N = x0.size
+    sigma2 = float(np.sum(np.abs(x0) ** 2) / (N * 10.0 ** (snr_db / 10.0)))
+    nrng = rng_for(cfg_id, vol_id, STREAM_NOISE)
+    eps = (nrng.standard_normal(p.shape) + 1j * nrng.standard_normal(p.shape)) * np.sqrt(sigma2 / 2.0)
+    y = mask * (np.fft.fftn(x0, norm="ortho") + eps)
+    return Volume(x0=x0, y=y, mask=mask, p=p, sigma2=sigma2, R=float(R), snr_db=float(snr_db))
+
+
+def workload_volume32(vol_id: int = 0):
+    """32^3 volume, 6 ellipsoids, p ~ (1-r)^4 + c, 4^3 centre, R = 4, 35 dB, 2 Haar levels,
+    20 iterations."""
+    return [make_volume(60, vol_id, 32, 32, 32, 6, 4.0, 4.0, 4, 35.0)], 2, 20
+
+
+def workload_volume64(n: int = 1, R: float = 6.0):
+    """64^3 volumes, 12 ellipsoids, p ~ (1-r)^6 + c, 8^3 centre, R = 6, 40 dB, 3 Haar
+    levels, 30 iterations (finest band 32^3 = 32768 coefficients)."""
+    return [make_volume(61, v, 64, 64, 64, 12, R, 6.0, 8, 40.0) for v in range(n)], 3, 30

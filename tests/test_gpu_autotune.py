@@ -30,12 +30,20 @@ def test_describe_default_plan():
 
 
 def test_autotuned_plan_matches_default_and_oracle():
+    """A tuned plan of the mixed batch (2 slices each of 128^2 .. 320^2): its x_hat after
+    two iterations within 1e-5 of the default plan's (different FFT algorithms and
+    threshold-search groupings, the same arithmetic up to FP32 rounding), and, for every
+    slice, one step from the oracle's FP32-rounded state at k = 0 and 1 at the parity gate
+    (r, tau, x_hat to 1e-5; theta and alpha to the tolerances the iterate's implies)."""
     from paper_1911_01234_amd import vdamp as V
+    from gpu_helpers import fp32_state, run_resume
+    from test_gpu_parity import TOL_ITER, one_step_check, oracle_run
     slices, s, _ = synth.workload_mixed(n_per_size=2)
     K = 2
     g0 = run_vdamp(slices, s, K)
     g1 = run_vdamp(slices, s, K, flags=V.VDAMP_FLAG_AUTOTUNE)
-    d = g1["plan"].describe()
+    plan = g1["plan"]
+    d = plan.describe()
     print(d)
     assert "autotune:" in d
     for n in (128, 192, 256, 320):
@@ -45,10 +53,12 @@ def test_autotuned_plan_matches_default_and_oracle():
     for i in range(len(slices)):
         e = rel_l2(g1["x_hat"][i], g0["x_hat"][i])
         worst = max(worst, e)
-        assert e <= 1e-4, (i, slices[i].y.shape, e)
+        assert e <= TOL_ITER, (i, slices[i].y.shape, e)
     print(f"tuned vs default x_hat: worst rel L2 {worst:.2e}")
-    for i in range(len(slices)):
-        sl = slices[i]
-        ref = o.vdamp(sl.y, sl.mask, sl.p, sl.sigma2, s, K)
-        et = np.max(np.abs(g1["trace"][:, i, :, 0] - ref["tau"]) / ref["tau"])
-        assert et <= 1e-4, (i, sl.y.shape, et)
+    trajs = [oracle_run(sl, s, 3) for sl in slices]
+    for k in (0, 1):
+        states = {b: fp32_state(tr["r"][k], tr["theta"][k], tr["alpha"][k]) for b, tr in enumerate(trajs)}
+        g = run_resume(plan, slices, states, 1)
+        for b, sl in enumerate(slices):
+            e, et, fl = one_step_check(sl, s, states[b], g, b, k, what=f"tuned slice {b}")
+            print(f"k={k} slice {b} {sl.y.shape}: r {e:.2e} tau {et:.2e} flips {fl}")
