@@ -141,6 +141,28 @@ vdamp_status vdamp_plan_ortho(vdamp_plan_h* plan, int32_t batch, const int32_t* 
                               int32_t levels, const double* lowpass, int32_t filter_len,
                               uint32_t flags, size_t* workspace_bytes);
 
+/*
+ * vdamp_plan_3d -- plan a batch of volumes: Phi = M_Omega F with F the unitary 3D DFT
+ * (Section 1 allows a 2D or 3D DFT) and Psi the s-level periodic orthonormal 3D Haar
+ * transform.
+ *   nz, ny, nx      host int32[B]: volume sizes ([nz][ny][nx] row-major, packed volume
+ *                   after volume); each divisible by 2^levels, in [2^levels, 512], of the
+ *                   form 2^a 3^b 5^c; nx a multiple of 16; the finest band (nz ny nx / 8
+ *                   coefficients) at most 65536
+ *   levels          s, 1..4; 1 + 7 s bands: b = 0 is LLL_s, then for l = s .. 1 the
+ *                   octants of kind k = 1 .. 7 (bit 0: high along x, bit 1: along y,
+ *                   bit 2: along z), each block at (k&4 ? nz>>l : 0, k&2 ? ny>>l : 0,
+ *                   k&1 ? nx>>l : 0) of size (nz>>l, ny>>l, nx>>l)
+ *   flags           as vdamp_plan (VDAMP_FLAG_AUTOTUNE is not accepted)
+ * The tau weights of line 1 are separable: S_b = Z_b(kz) Y_b(ky) X_b(kx).  The plan
+ * serves vdamp_solve, vdamp_solve_resume, vdamp_solve_noalloc, vdamp_state_export and
+ * vdamp_wavelet_ws, with y, mask, p, x_hat, r as packed volumes and theta, alpha, tau
+ * with 1 + 7 s entries per volume; fista_solve, vdamp_wavelet and the learned
+ * denoiser return VDAMP_ERR_UNSUPPORTED.
+ */
+vdamp_status vdamp_plan_3d(vdamp_plan_h* plan, int32_t batch, const int32_t* nz, const int32_t* ny,
+                           const int32_t* nx, int32_t levels, uint32_t flags, size_t* workspace_bytes);
+
 vdamp_status vdamp_plan_destroy(vdamp_plan_h plan);
 
 /*

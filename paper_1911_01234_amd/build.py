@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvdamp.so")
 SOURCES = ["vdamp_passes.hip", "vdamp_sure.hip", "vdamp_misc.hip", "vdamp_cnn.hip", "vdamp_api.cpp",
-           "vdamp_cnn_api.cpp", "vdamp_tune.cpp", "vdamp_noalloc.hip", "vdamp_ortho.hip"]
+           "vdamp_cnn_api.cpp", "vdamp_tune.cpp", "vdamp_noalloc.hip", "vdamp_ortho.hip", "vdamp_3d.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

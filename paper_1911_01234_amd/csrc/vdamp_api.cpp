@@ -127,6 +127,10 @@ void free_plan(vdamp_plan_t* P) {
   hipFree(P->d_resp);
   hipFree(P->d_work_orows);
   hipFree(P->d_work_img);
+  hipFree(P->d_work_bricks);
+  hipFree(P->d_work_rows3);
+  hipFree(P->d_work_ystrips);
+  hipFree(P->d_work_zstrips);
   delete P;
 }
 
@@ -157,8 +161,8 @@ std::vector<int2> sure_work_list(vdamp_plan_t* P) {
   std::vector<std::pair<long long, int2>> wsc[kSureClasses];
   for (int b = 0; b < P->B; ++b)
     for (int band = 0; band < P->nbands; ++band) {
-      const int l = band == 0 ? P->levels : P->levels - (band - 1) / 3;
-      const long long nb = (long long)(P->ny[b] >> l) * (P->nx[b] >> l);
+      const int l = band == 0 ? P->levels : P->levels - (band - 1) / (P->dim3 ? 7 : 3);
+      const long long nb = (long long)(P->ny[b] >> l) * (P->nx[b] >> l) * (P->dim3 ? (P->nz[b] >> l) : 1);
       auto it = P->sure_cls_of_size.find(nb);
       int cls = it != P->sure_cls_of_size.end() ? it->second : sure_default_class(nb);
       if (cls < 0 || cls >= kSureClasses || nb > sure_class_capacity(cls)) cls = sure_default_class(nb);
@@ -214,10 +218,79 @@ struct Resume {
   const float *theta = nullptr, *theta2 = nullptr, *alpha = nullptr;
 };
 
+// Algorithm 1 on volumes: per iteration the 3D Haar synthesis of line 8's r_tilde, the
+// forward DFTs along x, y and z, the k-space step of lines 3-5 between the z DFTs, the
+// inverse DFTs along y and x, the 3D Haar analysis with line 4's + r_tilde, and the
+// threshold search of lines 6-7.  Timing classes: Haar synthesis = rows_synth, the DFT
+// and k-space passes = cols, Haar analysis = rows_anal.
+vdamp_status enqueue_vdamp3d(vdamp_plan_t* P, hipStream_t st, void* ws, const float2* y,
+                             const uint8_t* mask, const float* p, const float* sigma2, int iters,
+                             float2* x_hat, float* trace, bool timing, const Resume& rs,
+                             float2* x_monitor) {
+  const Ws w = layout(P, ws);
+  Launcher L{P, st, timing};
+  const int check = (P->flags & VDAMP_FLAG_CHECK_FINITE) ? 1 : 0;
+  const bool resume = rs.r != nullptr;
+  LAUNCH(L, VDAMP_PASS_PREP, launch_prep(mask, p, y, w.wgt, P->ntot, check, w.bad, st));
+  if (resume) {
+    HIP_TRY(hipMemcpyAsync(w.r, rs.r, sizeof(float2) * (size_t)P->ntot, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(launch_import_state(rs.theta, rs.theta2, rs.alpha, P->B, P->nbands, w.theta, w.thr2,
+                                w.alpha, check, w.bad, st));
+  }
+  KArgs a = base_args(P, w);
+  a.y = y;
+  a.sigma2 = sigma2;
+  a.trace = trace;
+  // line 10 into out: F^H [ (1 - m) F Psi^H w + m y ] (w = eta(r; theta)), or F^H y
+  auto output = [&](float2* out, bool has_w) -> vdamp_status {
+    KArgs m = a;
+    m.out = out;
+    if (has_w) {
+      m.mode = RS_WHAT;
+      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, pass3_haar(P, m, true, st));
+      LAUNCH(L, VDAMP_PASS_COLS, pass3_rows(P, m, false, false, st));
+      m.mode = AX_Y_FWD;
+      LAUNCH(L, VDAMP_PASS_COLS, pass3_axis(P, m, st));
+    }
+    m.mode = has_w ? CM_OUTPUT : CM_ZEROFILL;
+    LAUNCH(L, VDAMP_PASS_COLS, pass3_axis(P, m, st));
+    m.mode = AX_Y_INV;
+    LAUNCH(L, VDAMP_PASS_COLS, pass3_axis(P, m, st));
+    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, pass3_rows(P, m, true, true, st));
+    return VDAMP_OK;
+  };
+  for (int k = 0; k < iters; ++k) {
+    a.iter = k;
+    const bool has_prev = k > 0 || resume;
+    if (has_prev) {
+      a.mode = RS_RTILDE;
+      LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, pass3_haar(P, a, true, st));
+      LAUNCH(L, VDAMP_PASS_COLS, pass3_rows(P, a, false, false, st));
+      a.mode = AX_Y_FWD;
+      LAUNCH(L, VDAMP_PASS_COLS, pass3_axis(P, a, st));
+    }
+    a.mode = has_prev ? CM_VDAMP : CM_VDAMP_FIRST;
+    LAUNCH(L, VDAMP_PASS_COLS, pass3_axis(P, a, st));
+    a.mode = AX_Y_INV;
+    LAUNCH(L, VDAMP_PASS_COLS, pass3_axis(P, a, st));
+    LAUNCH(L, VDAMP_PASS_COLS, pass3_rows(P, a, true, false, st));
+    a.mode = has_prev ? RA_VDAMP : RA_VDAMP_FIRST;
+    LAUNCH(L, VDAMP_PASS_ROWS_ANAL, pass3_haar(P, a, false, st));
+    LAUNCH(L, VDAMP_PASS_SURE, launch_sure_all(P, a, w.big, st));
+    if (x_monitor) {
+      const vdamp_status s = output(x_monitor + (long long)k * P->ntot, true);
+      if (s != VDAMP_OK) return s;
+    }
+  }
+  return output(x_hat, iters > 0 || resume);
+}
+
 vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const float2* y,
                            const uint8_t* mask, const float* p, const float* sigma2, int iters,
                            float2* x_hat, float* trace, bool timing, const Resume& rs,
                            float2* x_monitor) {
+  if (P->dim3)
+    return enqueue_vdamp3d(P, st, ws, y, mask, p, sigma2, iters, x_hat, trace, timing, rs, x_monitor);
   const Ws w = layout(P, ws);
   Launcher L{P, st, timing};
   const int check = (P->flags & VDAMP_FLAG_CHECK_FINITE) ? 1 : 0;
@@ -502,6 +575,8 @@ static vdamp_status make_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* 
     S.xtab_off = get_tab(nx[b]);
     S.colstrip0 = colstrip;
     S.rowstrip0 = rowstrip;
+    S.nd = 1;
+    S.ncs = nx[b] / kColW;
     if (ortho) {
       for (int l = 0; l <= levels; ++l) {
         S.fft_yl[l] = get_fft(ny[b] >> l);
@@ -677,6 +752,186 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
   return make_plan(plan, batch, ny, nx, levels, nullptr, 0, flags, workspace_bytes);
 }
 
+static vdamp_status make_plan3d(vdamp_plan_h* plan, int32_t batch, const int32_t* nz, const int32_t* ny,
+                                const int32_t* nx, int32_t levels, uint32_t flags, size_t* workspace_bytes) {
+  g_err.clear();
+  if (!plan || !nz || !ny || !nx || !workspace_bytes) return fail(VDAMP_ERR_ARG, "null pointer argument");
+  *plan = nullptr;
+  if (batch < 1) return fail(VDAMP_ERR_ARG, "batch must be >= 1");
+  if (levels < 1 || levels > 4) return fail(VDAMP_ERR_UNSUPPORTED, "levels must be in 1..4");
+  const uint32_t known = VDAMP_FLAG_DETERMINISTIC | VDAMP_FLAG_USE_GRAPH | VDAMP_FLAG_CHECK_FINITE |
+                         VDAMP_FLAG_TIMING | VDAMP_FLAG_AUTOTUNE | VDAMP_FLAG_SURE_CONTINUOUS;
+  if (flags & ~known) return fail(VDAMP_ERR_ARG, "unknown flag bits");
+  if (flags & VDAMP_FLAG_AUTOTUNE) return fail(VDAMP_ERR_UNSUPPORTED, "VDAMP_FLAG_AUTOTUNE tunes 2D plans only");
+  const int C = 1 << levels;
+  std::vector<int> rad;
+  for (int b = 0; b < batch; ++b) {
+    for (int n : {nz[b], ny[b], nx[b]}) {
+      if (n < C || n % C || n > kMaxN)
+        return fail(VDAMP_ERR_SHAPE, "volume " + std::to_string(b) + ": size " + std::to_string(n) +
+                                         " must be a multiple of 2^levels in [2^levels, 512]");
+      if (!radix_plan(n, rad))
+        return fail(VDAMP_ERR_UNSUPPORTED, "size " + std::to_string(n) + " is not 2^a 3^b 5^c");
+    }
+    if (nx[b] % kColW) return fail(VDAMP_ERR_UNSUPPORTED, "nx must be a multiple of 16 (strip width)");
+    const long long finest = (long long)(nz[b] >> 1) * (ny[b] >> 1) * (nx[b] >> 1);
+    if (finest > kSureBigMaxKeys)
+      return fail(VDAMP_ERR_UNSUPPORTED, "finest subband larger than the threshold search (" +
+                                             std::to_string(kSureBigMaxKeys) + " coefficients)");
+  }
+  vdamp_plan_t* P = new vdamp_plan_t();
+  P->dim3 = true;
+  P->B = batch;
+  P->levels = levels;
+  P->nbands = 1 + 7 * levels;
+  P->flags = flags;
+  P->nz.assign(nz, nz + batch);
+  P->ny.assign(ny, ny + batch);
+  P->nx.assign(nx, nx + batch);
+  P->off.resize(batch);
+  std::map<int, int> fft_index, tab_index;
+  std::vector<FftPlanDev> ffts;
+  std::vector<float2> tw;
+  std::vector<float> tables;
+  auto get_fft = [&](int n) {
+    auto it = fft_index.find(n);
+    if (it != fft_index.end()) return it->second;
+    FftPlanDev f;
+    std::memset(&f, 0, sizeof(f));
+    std::vector<int> rr;
+    radix_plan(n, rr);
+    f.n = n;
+    f.nst = (int)rr.size();
+    for (size_t i = 0; i < rr.size(); ++i) f.rad[i] = rr[i];
+    f.tw_off = (int)tw.size();
+    for (int k = 0; k < n; ++k) {
+      const double ang = -2.0 * M_PI * double(k) / double(n);
+      tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
+    }
+    ffts.push_back(f);
+    return fft_index[n] = (int)ffts.size() - 1;
+  };
+  auto get_tab = [&](int n) {  // line 1's 1D factors: L_1..L_s then H_1..H_s
+    auto it = tab_index.find(n);
+    if (it != tab_index.end()) return it->second;
+    const int o = (int)tables.size();
+    std::vector<double> pw;
+    for (int wv = 0; wv < 2; ++wv)
+      for (int l = 1; l <= levels; ++l) {
+        haar_power(n, l, wv == 1, pw);
+        for (int k = 0; k < n; ++k) tables.push_back((float)pw[k]);
+      }
+    return tab_index[n] = o;
+  };
+  std::vector<SliceDev> sl(batch);
+  std::vector<std::pair<long long, int2>> wb, wr, wy, wz;
+  long long off = 0;
+  int colstrip = 0, maxn = 0, maxnd = 0, maxnx = 0;
+  size_t haar_elems = 0;
+  for (int b = 0; b < batch; ++b) {
+    SliceDev& S = sl[b];
+    std::memset(&S, 0, sizeof(S));
+    S.off = off;
+    S.nd = nz[b];
+    S.ny = ny[b];
+    S.nx = nx[b];
+    S.fft_x = get_fft(nx[b]);
+    S.fft_y = get_fft(ny[b]);
+    S.fft_z = get_fft(nz[b]);
+    S.xtab_off = get_tab(nx[b]);
+    S.ytab_off = get_tab(ny[b]);
+    S.ztab_off = get_tab(nz[b]);
+    S.colstrip0 = colstrip;
+    S.ncs = ny[b] * (nx[b] / kColW);
+    // bricks of m whole 2^s cubes along x: the largest m dividing nx / 2^s with
+    // m 2^(3s) <= 4096 complex (32 KB of LDS)
+    int m = 1;
+    for (int q = 1; q <= nx[b] / C; ++q)
+      if ((nx[b] / C) % q == 0 && (long long)q * C * C * C <= 4096) m = q;
+    S.bw3 = m * C;
+    haar_elems = std::max(haar_elems, (size_t)C * C * S.bw3);
+    const long long cost = (long long)nz[b] * ny[b] * nx[b];
+    const int nbrick = (nz[b] / C) * (ny[b] / C) * (nx[b] / S.bw3);
+    for (int i = 0; i < nbrick; ++i) wb.push_back({cost, make_int2(b, i)});
+    const int rows = nz[b] * ny[b];
+    const int rpi = (rows % 8 == 0) ? 8 : (rows % 4 == 0) ? 4 : (rows % 2 == 0) ? 2 : 1;
+    for (int i = 0; i < rows; i += rpi) wr.push_back({cost, make_int2(b, i)});
+    for (int i = 0; i < nz[b] * (nx[b] / kColW); ++i) wy.push_back({cost, make_int2(b, i)});
+    for (int i = 0; i < S.ncs; ++i) wz.push_back({cost, make_int2(b, i)});
+    P->off[b] = off;
+    off += cost;
+    colstrip += S.ncs;
+    maxn = std::max(maxn, std::max(ny[b], nz[b]));
+    maxnd = std::max(maxnd, nz[b]);
+    maxnx = std::max(maxnx, nx[b]);
+  }
+  P->ntot = off;
+  P->ncolstrips = colstrip;
+  auto sort_items = [](std::vector<std::pair<long long, int2>>& v) {
+    std::stable_sort(v.begin(), v.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    std::vector<int2> out;
+    for (auto& e : v) out.push_back(e.second);
+    return out;
+  };
+  std::vector<int2> vb = sort_items(wb), vr = sort_items(wr), vy = sort_items(wy), vz = sort_items(wz);
+  std::vector<int2> vs = sure_work_list(P);
+  P->n_bricks = (int)vb.size();
+  P->n_rows3 = (int)vr.size();
+  P->n_ystrips = (int)vy.size();
+  P->n_zstrips = (int)vz.size();
+  P->lds_k3haar = sizeof(float2) * haar_elems;
+  P->lds_k3rows = sizeof(float2) * (size_t)8 * maxnx;
+  P->lds_k3axis = k3_axis_lds_bytes(maxn, maxnd, levels);
+  P->k3_ept = maxn * kColW <= 16 * kThreads ? 16 : 32;
+  // workspace layout
+  size_t o = 0;
+  const size_t N = (size_t)P->ntot;
+  P->o_wgt = o; o = align256(o + 4 * N);
+  P->o_r = o; o = align256(o + 8 * N);
+  P->o_X = o; o = align256(o + 8 * N);
+  P->o_r2 = P->o_X;  // (no FISTA or learned denoiser on volumes)
+  P->o_theta = o; o = align256(o + 4 * (size_t)batch * kMaxBands);
+  P->o_thr2 = o; o = align256(o + 4 * (size_t)batch * kMaxBands);
+  P->o_alpha = o; o = align256(o + 4 * (size_t)batch * kMaxBands);
+  P->o_tau = o; o = align256(o + 4 * (size_t)batch * kMaxBands);
+  P->o_taup = o; o = align256(o + 4 * (size_t)colstrip * kMaxBands);
+  P->o_rpart = o;
+  P->o_bad = o; o = align256(o + 4);
+  if (P->nsure_cls[kSureBigClass]) {
+    P->o_big = o;
+    o = align256(o + 4 * (size_t)P->nsure_cls[kSureBigClass] * kSureBigStride);
+  }
+  P->ws_bytes = o;
+  auto upload = [&](auto*& dst, const auto& vec) -> hipError_t {
+    using T = typename std::decay_t<decltype(vec)>::value_type;
+    hipError_t e = hipMalloc((void**)&dst, sizeof(T) * std::max<size_t>(vec.size(), 1));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(dst, vec.data(), sizeof(T) * vec.size(), hipMemcpyHostToDevice);
+  };
+  hipError_t e = upload(P->d_slices, sl);
+  if (e == hipSuccess) e = upload(P->d_ffts, ffts);
+  if (e == hipSuccess) e = upload(P->d_tw, tw);
+  if (e == hipSuccess) e = upload(P->d_tables, tables);
+  if (e == hipSuccess) e = upload(P->d_work_bricks, vb);
+  if (e == hipSuccess) e = upload(P->d_work_rows3, vr);
+  if (e == hipSuccess) e = upload(P->d_work_ystrips, vy);
+  if (e == hipSuccess) e = upload(P->d_work_zstrips, vz);
+  if (e == hipSuccess) e = upload(P->d_work_sure, vs);
+  if (e == hipSuccess) e = set_lds_limits_3d(P->lds_k3haar, P->lds_k3rows, P->lds_k3axis);
+  if (e != hipSuccess) {
+    free_plan(P);
+    return fail(VDAMP_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));
+  }
+  *plan = P;
+  *workspace_bytes = P->ws_bytes;
+  return VDAMP_OK;
+}
+
+vdamp_status vdamp_plan_3d(vdamp_plan_h* plan, int32_t batch, const int32_t* nz, const int32_t* ny,
+                           const int32_t* nx, int32_t levels, uint32_t flags, size_t* workspace_bytes) {
+  return make_plan3d(plan, batch, nz, ny, nx, levels, flags, workspace_bytes);
+}
+
 vdamp_status vdamp_plan_ortho(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, const int32_t* nx,
                               int32_t levels, const double* lowpass, int32_t filter_len,
                               uint32_t flags, size_t* workspace_bytes) {
@@ -692,9 +947,10 @@ vdamp_status vdamp_plan_describe(vdamp_plan_h plan, char* buf, size_t len, size_
   g_err.clear();
   if (!plan) return fail(VDAMP_ERR_ARG, "plan is null");
   const vdamp_plan_t* P = plan;
-  std::string s = std::string(P->ortho ? "wavelet: orthonormal filter of " + std::to_string(P->filt.size()) +
-                                            " taps (Fourier-domain passes); "
-                                      : "wavelet: Haar; ") +
+  std::string s = std::string(P->dim3 ? "volumes: 3D Haar, 3D DFT; "
+                              : P->ortho ? "wavelet: orthonormal filter of " + std::to_string(P->filt.size()) +
+                                               " taps (Fourier-domain passes); "
+                                         : "wavelet: Haar; ") +
                   "slices " + std::to_string(P->B) + ", levels " + std::to_string(P->levels) + ", pixels " +
                   std::to_string(P->ntot) + ", workspace " + std::to_string(P->ws_bytes) + " bytes;";
   auto group = [&](const char* what, const std::array<int, 4>& g) {
@@ -794,7 +1050,7 @@ vdamp_status fista_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
   vdamp_status s = check_common(plan, workspace, workspace_bytes, y, mask, iters, x_hat);
   if (s != VDAMP_OK) return s;
   if (!lambda) return fail(VDAMP_ERR_ARG, "lambda must be non-null");
-  if (plan->ortho) return fail(VDAMP_ERR_UNSUPPORTED, "fista_solve runs on Haar plans only");
+  if (plan->ortho || plan->dim3) return fail(VDAMP_ERR_UNSUPPORTED, "fista_solve runs on 2D Haar plans only");
   GraphKey key;
   key.kind = 1; key.ws = workspace; key.y = y; key.mask = mask; key.lam = lambda;
   key.x = x_hat; key.iters = iters; key.stream = stream; key.obj = objective;
@@ -832,7 +1088,7 @@ vdamp_status vdamp_wavelet_ws(vdamp_plan_h plan, hipStream_t stream, void* works
   g_err.clear();
   if (!plan || !in || !out) return fail(VDAMP_ERR_ARG, "null pointer argument");
   if (in == out) return fail(VDAMP_ERR_ARG, "in and out must not overlap");
-  if (!plan->ortho) return vdamp_wavelet(plan, stream, inverse, in, out);
+  if (!plan->ortho && !plan->dim3) return vdamp_wavelet(plan, stream, inverse, in, out);
   if (!workspace) return fail(VDAMP_ERR_WORKSPACE, "workspace is null");
   if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(VDAMP_ERR_WORKSPACE, "workspace not 256-byte aligned");
   if (workspace_bytes < plan->ws_bytes)
@@ -841,6 +1097,20 @@ vdamp_status vdamp_wavelet_ws(vdamp_plan_h plan, hipStream_t stream, void* works
   const Ws w = layout(plan, workspace);
   KArgs a = base_args(plan, w);
   if (plan->state_ws == workspace) plan->has_state = false;  // the workspace's state is overwritten
+  if (plan->dim3) {  // the 3D Haar bricks read in and write out directly
+    if (inverse) {
+      a.r = reinterpret_cast<float2*>(const_cast<float*>(in));
+      a.X = reinterpret_cast<float2*>(out);
+      a.mode = RS_PLAIN;
+      HIP_TRY(pass3_haar(plan, a, true, stream));
+    } else {
+      a.X = reinterpret_cast<float2*>(const_cast<float*>(in));
+      a.out = reinterpret_cast<float2*>(out);
+      a.mode = OA_COEF;
+      HIP_TRY(pass3_haar(plan, a, false, stream));
+    }
+    return VDAMP_OK;
+  }
   if (inverse) {  // Psi^H: coefficient rows -> group rows -> image rows of X -> image
     a.r = reinterpret_cast<float2*>(const_cast<float*>(in));
     a.mode = RS_PLAIN;

@@ -356,14 +356,14 @@ __global__ void __launch_bounds__(kThr) k_pack_input(const SliceDev* slices, int
   *reinterpret_cast<uint4*>(&out[p * 8]) = o;
 }
 
-// Per-slice first-layer bias: b1 + Wt log(tau / s0^2).
+// Per-slice first-layer bias: b1 + Wt log(tau / s0^2); tau[slice * tau_stride + band].
 __global__ void k_slice_bias(const float* __restrict__ b1, const float* __restrict__ wt,
                              const float* __restrict__ tau, const float* __restrict__ s0,
-                             int nb, int batch, float* __restrict__ sb) {
+                             int nb, int batch, int tau_stride, float* __restrict__ sb) {
   const int sl = blockIdx.x, co = threadIdx.x;
   if (sl >= batch || co >= kCh) return;
   float z = b1[co];
-  for (int b = 0; b < nb; ++b) z += wt[co * nb + b] * tau_feature(tau[sl * kMaxBands + b], s0[sl]);
+  for (int b = 0; b < nb; ++b) z += wt[co * nb + b] * tau_feature(tau[sl * tau_stride + b], s0[sl]);
   sb[sl * kCh + co] = z;
 }
 
@@ -423,7 +423,7 @@ __global__ void __launch_bounds__(256) k_wt_grad(const float* __restrict__ tile_
                                                  const int* __restrict__ tile_off,
                                                  const float* __restrict__ tau,
                                                  const float* __restrict__ s0, int nb, int batch,
-                                                 float* __restrict__ dwt) {
+                                                 int tau_stride, float* __restrict__ dwt) {
   // one workgroup per output channel; wave w takes slices w, w + 4, ...: its lanes sum
   // the slice's tile partials, and lane b < nb accumulates the band-b term
   __shared__ float red[4][kMaxBands];
@@ -435,7 +435,7 @@ __global__ void __launch_bounds__(256) k_wt_grad(const float* __restrict__ tile_
     for (int ti = tile_off[sl] + lane; ti < tile_off[sl + 1]; ti += 64) ssum += tile_sums[(long long)ti * kCh + co];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) ssum += __shfl_xor(ssum, o, 64);
-    if (lane < nb) acc += ssum * tau_feature(tau[sl * kMaxBands + lane], s0[sl]);
+    if (lane < nb) acc += ssum * tau_feature(tau[sl * tau_stride + lane], s0[sl]);
   }
   if (lane < kMaxBands) red[wid][lane] = acc;
   __syncthreads();
@@ -525,8 +525,8 @@ hipError_t launch_pack_input(const SliceDev* slices, int batch, const float2* x,
   return hipGetLastError();
 }
 hipError_t launch_slice_bias(const float* b1, const float* wt, const float* tau, const float* s0,
-                             int nb, int batch, float* sb, hipStream_t st) {
-  hipLaunchKernelGGL(k_slice_bias, dim3(batch), dim3(64), 0, st, b1, wt, tau, s0, nb, batch, sb);
+                             int nb, int batch, int tau_stride, float* sb, hipStream_t st) {
+  hipLaunchKernelGGL(k_slice_bias, dim3(batch), dim3(64), 0, st, b1, wt, tau, s0, nb, batch, tau_stride, sb);
   return hipGetLastError();
 }
 hipError_t launch_loss_grad(const SliceDev* slices, int batch, const float2* xo, const float2* x0,
@@ -539,9 +539,9 @@ hipError_t launch_loss_grad(const SliceDev* slices, int batch, const float2* xo,
   return hipGetLastError();
 }
 hipError_t launch_wt_grad(const float* tile_sums, const int* tile_off, const float* tau,
-                          const float* s0, int nb, int batch, float* dwt, hipStream_t st) {
+                          const float* s0, int nb, int batch, int tau_stride, float* dwt, hipStream_t st) {
   hipLaunchKernelGGL(k_wt_grad, dim3(kCh), dim3(256), 0, st, tile_sums, tile_off, tau, s0, nb,
-                     batch, dwt);
+                     batch, tau_stride, dwt);
   return hipGetLastError();
 }
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float c1,

@@ -24,12 +24,12 @@ hipError_t launch_reduce_wgrad(const float* part, const float* part_bias, int nw
 hipError_t launch_pack_input(const SliceDev* slices, int batch, const float2* x, const float* s0,
                              long long npx, u16* out, hipStream_t st);
 hipError_t launch_slice_bias(const float* b1, const float* wt, const float* tau, const float* s0,
-                             int nb, int batch, float* sb, hipStream_t st);
+                             int nb, int batch, int tau_stride, float* sb, hipStream_t st);
 hipError_t launch_loss_grad(const SliceDev* slices, int batch, const float2* xo, const float2* x0,
                             const float* s0, long long npx, u16* go, float* part, float* loss,
                             hipStream_t st);
 hipError_t launch_wt_grad(const float* tile_sums, const int* tile_off, const float* tau,
-                          const float* s0, int nb, int batch, float* dwt, hipStream_t st);
+                          const float* s0, int nb, int batch, int tau_stride, float* dwt, hipStream_t st);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float c1,
                        float c2, hipStream_t st);
 hipError_t launch_pack_w(const float* W, int cout, int cin, int cinp, int coutp, int kpad, u16* wf,
@@ -142,7 +142,7 @@ T* at(void* ws, size_t off) {
 }
 
 vdamp_status check_cnn_ws(const vdamp_plan_t* P, int kind, void* ws, size_t wsb) {
-  if (P->ortho) return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser runs on Haar plans only");
+  if (P->ortho || P->dim3) return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser runs on 2D Haar plans only");
   if (!P->tiles_ok) return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser needs ny and nx multiples of 16");
   if (!ws) return fail(VDAMP_ERR_WORKSPACE, "denoiser workspace is null");
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(VDAMP_ERR_WORKSPACE, "denoiser workspace not 256-byte aligned");
@@ -176,14 +176,15 @@ int conv_grid(const vdamp_plan_t* P) { return std::max(1, std::min(P->ntiles, kC
 // Forward pass (and, with tangent, the JVP interleaved layer by layer: the tangent of
 // layer l needs only the ReLU pattern of the same layer).
 vdamp_status enqueue_forward(const vdamp_cnn_t* C, const vdamp_plan_t* P, const CnnWs& L, void* ws,
-                             const float2* x, const float* tau, const float* s0, float2* x_out,
-                             const float2* tangent, float2* jvp_out, hipStream_t st) {
+                             const float2* x, const float* tau, int tau_stride, const float* s0,
+                             float2* x_out, const float2* tangent, float2* jvp_out, hipStream_t st) {
   const long long N = P->ntot;
   u16* a0 = at<u16>(ws, L.a0);
   u16* t0 = at<u16>(ws, L.t0);
   float* sbias = at<float>(ws, L.sbias);
   HIP_TRY(cnn::launch_pack_input(P->d_slices, P->B, x, s0, N, a0, st));
-  HIP_TRY(cnn::launch_slice_bias(C->d_p + C->ob[1], C->d_p + C->oWt, tau, s0, C->nb, P->B, sbias, st));
+  HIP_TRY(cnn::launch_slice_bias(C->d_p + C->ob[1], C->d_p + C->oWt, tau, s0, C->nb, P->B, tau_stride,
+                                 sbias, st));
   if (tangent) HIP_TRY(cnn::launch_pack_input(P->d_slices, P->B, tangent, nullptr, N, t0, st));
   u16* act[2] = {at<u16>(ws, L.act[1]), at<u16>(ws, L.act[2])};
   u16* tan[2] = {at<u16>(ws, L.ta), at<u16>(ws, L.tb)};
@@ -244,7 +245,8 @@ vdamp_status enqueue_train(vdamp_cnn_t* C, const vdamp_plan_t* P, const CnnWs& L
   float* sbias = at<float>(ws, L.sbias);
   float2* xo = at<float2>(ws, L.xo);
   HIP_TRY(cnn::launch_pack_input(P->d_slices, P->B, x, s0, N, A[0], st));
-  HIP_TRY(cnn::launch_slice_bias(C->d_p + C->ob[1], C->d_p + C->oWt, tau, s0, C->nb, P->B, sbias, st));
+  HIP_TRY(cnn::launch_slice_bias(C->d_p + C->ob[1], C->d_p + C->oWt, tau, s0, C->nb, P->B, kCnnTauStride,
+                                 sbias, st));
   const int grid = conv_grid(P);
   for (int l = 1; l <= kLayers; ++l) {
     cnn::ConvArgs a = conv_args(P);
@@ -290,7 +292,8 @@ vdamp_status enqueue_train(vdamp_cnn_t* C, const vdamp_plan_t* P, const CnnWs& L
     HIP_TRY(cnn::launch_reduce_wgrad(part, pbias, wgrid, rows, cols, g.cinp, g.cout, g.cin,
                                      C->d_g + C->oW[l], C->d_g + C->ob[l], st));
     if (l == 1) {
-      HIP_TRY(cnn::launch_wt_grad(tsums, P->d_tile_off, tau, s0, C->nb, P->B, C->d_g + C->oWt, st));
+      HIP_TRY(cnn::launch_wt_grad(tsums, P->d_tile_off, tau, s0, C->nb, P->B, kCnnTauStride, C->d_g + C->oWt,
+                                  st));
       break;
     }
     // input gradient of layer l, masked by the ReLU pattern of layer l-1
@@ -356,7 +359,7 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
     s.mode = RS_PROBE; s.out = ti;
     LAUNCH(Lr, VDAMP_PASS_DENOISER, launch_rows_synth(s, P->ept, 0, P->lds_rows, st));
     HIP_TRY(Lr.begin(VDAMP_PASS_CNN));
-    vdamp_status e = enqueue_forward(C, P, L, cws, xi, w.tau, s0, xo, ti, to, st);
+    vdamp_status e = enqueue_forward(C, P, L, cws, xi, w.tau, kMaxBands, s0, xo, ti, to, st);
     if (e != VDAMP_OK) return e;
     HIP_TRY(Lr.end());
     // coefficients of f(x) into r2 with the judge's partial sums, then the judge
@@ -379,7 +382,7 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
 
 vdamp_status check_cnn(vdamp_cnn_h cnn, vdamp_plan_h plan) {
   if (!cnn || !plan) return fail(VDAMP_ERR_ARG, "denoiser and plan must be non-null");
-  if (plan->ortho) return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser runs on Haar plans only");
+  if (plan->ortho || plan->dim3) return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser runs on 2D Haar plans only");
   if (cnn->nb != plan->nbands)
     return fail(VDAMP_ERR_ARG, "denoiser built for " + std::to_string(cnn->nb) + " bands, plan has " +
                                    std::to_string(plan->nbands));
@@ -487,7 +490,7 @@ vdamp_status vdamp_cnn_forward(vdamp_cnn_h cnn, vdamp_plan_h plan, hipStream_t s
   s = check_cnn_ws(plan, VDAMP_CNN_WS_FORWARD, workspace, workspace_bytes);
   if (s != VDAMP_OK) return s;
   return enqueue_forward(cnn, plan, cnn_layout(plan, VDAMP_CNN_WS_FORWARD), workspace,
-                         reinterpret_cast<const float2*>(x), tau, s0, reinterpret_cast<float2*>(x_out),
+                         reinterpret_cast<const float2*>(x), tau, kCnnTauStride, s0, reinterpret_cast<float2*>(x_out),
                          reinterpret_cast<const float2*>(tangent), reinterpret_cast<float2*>(jvp_out), stream);
 }
 
@@ -591,7 +594,8 @@ vdamp_status vdamp_wavelet(vdamp_plan_h plan, hipStream_t stream, int32_t invers
   g_err.clear();
   if (!plan || !in || !out) return fail(VDAMP_ERR_ARG, "null pointer argument");
   if (in == out) return fail(VDAMP_ERR_ARG, "in and out must not overlap");
-  if (plan->ortho) return fail(VDAMP_ERR_UNSUPPORTED, "general-wavelet plans need a workspace: vdamp_wavelet_ws");
+  if (plan->ortho || plan->dim3)
+    return fail(VDAMP_ERR_UNSUPPORTED, "general-wavelet and volume plans need a workspace: vdamp_wavelet_ws");
   KArgs a;
   std::memset(&a, 0, sizeof(a));
   a.slices = plan->d_slices;

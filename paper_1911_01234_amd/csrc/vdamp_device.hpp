@@ -158,6 +158,23 @@ __device__ void fft_lines(float2* buf, const FftPlanDev& P, int nlines, int ls, 
   }
 }
 
+// In-LDS FFTs of the 16 columns of a strip block (element (i, c) at buf[16 i + c]): the
+// Stockham stages of fft_lines with the line count fixed at compile time.
+template <bool INV, int EPT>
+__device__ __forceinline__ void fft_cols16(float2* buf, const FftPlanDev& P, const float2* tw) {
+  int Ns = 1;
+  for (int st = 0; st < P.nst; ++st) {
+    const int R = P.rad[st];
+    switch (R) {
+      case 4: fft_stage<4, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
+      case 2: fft_stage<2, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
+      case 3: fft_stage<3, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
+      default: fft_stage<5, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
+    }
+    Ns *= R;
+  }
+}
+
 // ------------------------------------------------------------------ register FFT
 // M-point DFT of v[0..M) held in registers (natural order in and out), decimation in
 // time over the radices 4, 2, 3, 5; M = R * M2: the R interleaved sub-sequences
@@ -437,6 +454,53 @@ __device__ __forceinline__ void band_geom(int b, int s, int ny, int nx, int& r0,
   bh = ny >> l; bw = nx >> l;
   r0 = (kind == 0) ? 0 : bh;
   c0 = (kind == 1) ? 0 : bw;
+}
+
+// Band b of a slice (nd == 1: the 2D layout above, 1 + 3 s bands) or of a volume (nd > 1:
+// 3D Mallat layout, 1 + 7 s bands: b = 0 is LLL_s, then for l = s .. 1 the octants of
+// kind k = 1 .. 7, bit 0 of k high along x, bit 1 along y, bit 2 along z): origin
+// (d0, r0, c0) and extent (bd, bh, bw) of its block.
+__device__ __forceinline__ void band_geom3(int b, int s, int nd, int ny, int nx, int& d0, int& r0,
+                                           int& c0, int& bd, int& bh, int& bw) {
+  if (nd <= 1) {
+    d0 = 0;
+    bd = 1;
+    band_geom(b, s, ny, nx, r0, c0, bh, bw);
+    return;
+  }
+  if (b == 0) { d0 = 0; r0 = 0; c0 = 0; bd = nd >> s; bh = ny >> s; bw = nx >> s; return; }
+  const int l = s - (b - 1) / 7, k = (b - 1) % 7 + 1;
+  bd = nd >> l; bh = ny >> l; bw = nx >> l;
+  d0 = (k & 4) ? bd : 0;
+  r0 = (k & 2) ? bh : 0;
+  c0 = (k & 1) ? bw : 0;
+}
+
+// Offset of element i (row-major within the block) of a band block from the block's
+// first element, in a slice or volume of ny x nx planes.
+struct BandWalk {
+  int bd, bh, bw, lbw, plane;
+  bool pow2;
+  long long zs, nx;
+  __device__ __forceinline__ long long at(int i) const {
+    if (bd == 1) {
+      const int rr = pow2 ? (i >> lbw) : i / bw;
+      return (long long)rr * nx + (i - rr * bw);
+    }
+    const int dd = i / plane, rem = i - dd * plane;
+    const int rr = pow2 ? (rem >> lbw) : rem / bw;
+    return (long long)dd * zs + (long long)rr * nx + (rem - rr * bw);
+  }
+};
+__device__ __forceinline__ BandWalk band_walk(int bd, int bh, int bw, int ny, int nx) {
+  BandWalk w;
+  w.bd = bd; w.bh = bh; w.bw = bw;
+  w.lbw = 31 - __clz(bw);
+  w.pow2 = (bw & (bw - 1)) == 0;
+  w.plane = bh * bw;
+  w.zs = (long long)ny * nx;
+  w.nx = nx;
+  return w;
 }
 
 __device__ __forceinline__ float wave_sum(float v) {

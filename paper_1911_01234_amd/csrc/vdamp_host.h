@@ -110,6 +110,15 @@ struct vdamp_plan_t {
   size_t lds_osynth = 0, lds_ocols = 0, lds_oanal = 0;
   int ocols_ept = 16;
   size_t o_Z = 0;
+  // volumes (plans made by vdamp_plan_3d): depths, Haar bricks, x-row items, y and z
+  // strips, LDS sizes and elements a thread of the strip kernel
+  bool dim3 = false;
+  std::vector<int> nz;
+  int2 *d_work_bricks = nullptr, *d_work_rows3 = nullptr, *d_work_ystrips = nullptr,
+       *d_work_zstrips = nullptr;
+  int n_bricks = 0, n_rows3 = 0, n_ystrips = 0, n_zstrips = 0;
+  size_t lds_k3haar = 0, lds_k3rows = 0, lds_k3axis = 0;
+  int k3_ept = 16;
   // workspace layout (byte offsets)
   size_t o_wgt = 0, o_r = 0, o_X = 0, o_r2 = 0, o_theta = 0, o_thr2 = 0, o_alpha = 0, o_tau = 0,
          o_taup = 0, o_rpart = 0, o_bad = 0, o_big = 0, ws_bytes = 0;
@@ -177,6 +186,12 @@ hipError_t set_lds_limits_ortho(size_t synth, size_t cols, size_t anal);
 hipError_t launch_osynth(const KArgs& a, size_t lds, hipStream_t st);
 hipError_t launch_ocols(const KArgs& a, int ept, size_t lds, hipStream_t st);
 hipError_t launch_oanal(const KArgs& a, size_t lds, hipStream_t st);
+// volumes
+size_t k3_axis_lds_bytes(int maxn, int maxnd, int s);
+hipError_t set_lds_limits_3d(size_t haar, size_t rows, size_t axis);
+hipError_t launch_k3_haar(const KArgs& a, bool synth, size_t lds, hipStream_t st);
+hipError_t launch_k3_rows(const KArgs& a, bool inv, bool to_out, size_t lds, hipStream_t st);
+hipError_t launch_k3_axis(const KArgs& a, int ept, size_t lds, hipStream_t st);
 
 // Launch helper that records timing events around each kernel when asked.
 struct Launcher {
@@ -326,6 +341,24 @@ inline hipError_t pass_cols(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
   a.nwork = P->ncols;
   return launch_ocols(a, P->ocols_ept, P->lds_ocols, st);
 }
+// Volumes: Haar bricks (Psi^H into X, or Psi from X), x-row DFTs, y or z strip DFTs.
+inline hipError_t pass3_haar(const vdamp_plan_t* P, KArgs a, bool synth, hipStream_t st) {
+  a.work = P->d_work_bricks;
+  a.nwork = P->n_bricks;
+  return launch_k3_haar(a, synth, P->lds_k3haar, st);
+}
+inline hipError_t pass3_rows(const vdamp_plan_t* P, KArgs a, bool inv, bool to_out, hipStream_t st) {
+  a.work = P->d_work_rows3;
+  a.nwork = P->n_rows3;
+  return launch_k3_rows(a, inv, to_out, P->lds_k3rows, st);
+}
+inline hipError_t pass3_axis(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
+  const bool y = a.mode == AX_Y_FWD || a.mode == AX_Y_INV;
+  a.work = y ? P->d_work_ystrips : P->d_work_zstrips;
+  a.nwork = y ? P->n_ystrips : P->n_zstrips;
+  return launch_k3_axis(a, P->k3_ept, P->lds_k3axis, st);
+}
+
 inline hipError_t pass_anal(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
   if (!P->ortho) return launch_rows_anal_all(P, a, st);
   const bool img = a.mode == RA_IMAGE;

@@ -9,7 +9,8 @@ namespace vdamp {
 constexpr int kThreads = 256;      // threads per workgroup for every pass
 constexpr int kEpt = 32;           // max complex elements per thread held by an LDS pass
 constexpr int kMaxElems = kThreads * kEpt;  // complex elements an LDS tile may hold
-constexpr int kMaxBands = 16;      // per-slice band slots (1 + 3 s, s <= 4 uses 13)
+constexpr int kMaxBands = 32;      // per-slice band slots (2D: 1 + 3 s <= 13; 3D: 1 + 7 s <= 29)
+constexpr int kCnnTauStride = 16;  // row stride of the tau arrays the denoiser's entry points take
 constexpr int kColW = 16;          // columns per column strip (16 complex = 128 B per row)
 constexpr int kMaxRadices = 8;
 constexpr int kMaxN = 512;         // largest ny / nx
@@ -44,6 +45,14 @@ struct SliceDev {
   int zrows;             // group rows: sum over l = 1..s of 2 (ny >> l)
   int yresp_off;         // 2 s tables of ny complex: F_{A_1..A_s}, F_{D_1..D_s} (y axis)
   int xresp_off;         // the same for nx (x axis)
+  // volumes (3D plans): depth nd (1 for a 2D slice), the z-axis FFT plan and tau tables,
+  // the width of the Haar bricks (2^s x 2^s x bw3); ncs = the slice's tau partial strips
+  // (nx / 16 for a slice, ny nx / 16 for a volume)
+  int nd;
+  int fft_z;
+  int ztab_off;
+  int bw3;
+  int ncs;
 };
 
 // Modes of the row-synthesis pass (Psi^H on row strips, then row FFT).
@@ -82,7 +91,9 @@ enum OrthoMode : int {
   OS_IMAGE = 10,   // synthesis pass: row DFTs of image rows (a.r) into X
   OC_SYNTH = 11,   // column pass: from the group rows to the image rows of X (no k-space step)
   OC_ANAL = 12,    // column pass: from the row DFTs in X to the group rows (no k-space step)
-  OA_COEF = 13     // analysis pass: the coefficients themselves, into a.out
+  OA_COEF = 13,    // analysis pass: the coefficients themselves, into a.out
+  AX_Y_FWD = 14,   // volumes: DFTs along y of a strip
+  AX_Y_INV = 15    // volumes: inverse DFTs along y
 };
 
 struct KArgs {

@@ -204,7 +204,7 @@ __global__ void k_fista_obj(KArgs a, float* __restrict__ obj) {
   if (sl >= a.batch) return;
   const SliceDev S = a.slices[sl];
   double res = 0.0, l1 = 0.0;
-  for (int i = 0; i < S.nx / kColW; ++i) res += (double)a.tau_part[(long long)(S.colstrip0 + i) * kMaxBands];
+  for (int i = 0; i < S.ncs; ++i) res += (double)a.tau_part[(long long)(S.colstrip0 + i) * kMaxBands];
   for (int i = 0; i < (S.ny >> a.levels); ++i) l1 += (double)a.jpart[S.rowstrip0 + i];
   obj[(long long)a.iter * a.batch + sl] = (float)(0.5 * res + (double)a.lambda[sl] * l1);
 }

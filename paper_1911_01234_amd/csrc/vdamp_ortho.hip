@@ -62,22 +62,6 @@ __device__ __forceinline__ float2 conj_mul(float2 f, float2 v) {  // conj(f) v
   return make_float2(f.x * v.x + f.y * v.y, f.x * v.y - f.y * v.x);
 }
 
-// In-LDS FFTs of the 16 columns of a strip block (element (i, c) at buf[16 i + c]): the
-// Stockham stages of fft_lines with the line count fixed at compile time.
-template <bool INV, int EPT>
-__device__ __forceinline__ void fft_cols16(float2* buf, const FftPlanDev& P, const float2* tw) {
-  int Ns = 1;
-  for (int st = 0; st < P.nst; ++st) {
-    const int R = P.rad[st];
-    switch (R) {
-      case 4: fft_stage<4, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
-      case 2: fft_stage<2, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
-      case 3: fft_stage<3, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
-      default: fft_stage<5, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
-    }
-    Ns *= R;
-  }
-}
 
 // ------------------------------------------------------------------ synthesis
 __global__ void __launch_bounds__(kThreads) k_osynth(KArgs a) {

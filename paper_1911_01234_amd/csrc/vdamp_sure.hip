@@ -308,15 +308,15 @@ k_sure(KArgs a) {
   const int sl = item.x, b = item.y, s = a.levels;
   const SliceDev S = a.slices[sl];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  int r0, c0, bh, bw;
-  band_geom(b, s, S.ny, S.nx, r0, c0, bh, bw);
-  const int Nb = bh * bw;
+  int d0, r0, c0, bd, bh, bw;
+  band_geom3(b, s, S.nd, S.ny, S.nx, d0, r0, c0, bd, bh, bw);
+  const int Nb = bd * bh * bw;
   int npad = 1;
   while (npad < Nb) npad <<= 1;
 
   for (int i = tid; i <= NB; i += NT) off[i] = 0;
   if (wid == 0) {
-    const int ncs = S.nx / kColW;
+    const int ncs = S.ncs;
     double acc = 0.0;
     for (int i = lane; i < ncs; i += 64) acc += (double)a.tau_part[(S.colstrip0 + i) * kMaxBands + b];
 #pragma unroll
@@ -324,19 +324,14 @@ k_sure(KArgs a) {
     if (lane == 0) tau_sh = (float)acc;
   }
   // load the band (coalesced along rows) while the counters are cleared
-  const float2* r = a.r + S.off + (long long)r0 * S.nx + c0;
-  const int lbw = 31 - __clz(bw);  // band widths are powers of two times 1, 3 or 5
-  const bool pow2 = (bw & (bw - 1)) == 0;
+  const float2* r = a.r + S.off + ((long long)d0 * S.ny + r0) * S.nx + c0;
+  const BandWalk bwk = band_walk(bd, bh, bw, S.ny, S.nx);  // band widths: 2^a times 1, 3 or 5
   float kk[KPT];
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
     const int i = tid + j * NT;
     kk[j] = 0.f;
-    if (i < Nb) {
-      const int rr = pow2 ? (i >> lbw) : i / bw;
-      const int cc = i - rr * bw;
-      kk[j] = key_rn(r[(long long)rr * S.nx + cc]);
-    }
+    if (i < Nb) kk[j] = key_rn(r[bwk.at(i)]);
   }
   __syncthreads();
   const float inv_tau = 1.0f / tau_sh;
@@ -575,14 +570,12 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
   const int sl = item.x, b = item.y, s = a.levels;
   const SliceDev S = a.slices[sl];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  int r0, c0, bh, bw;
-  band_geom(b, s, S.ny, S.nx, r0, c0, bh, bw);
-  const int Nb = bh * bw;
-  const float2* r = a.r + S.off + (long long)r0 * S.nx + c0;
-  const int lbw = 31 - __clz(bw);
-  const bool pow2 = (bw & (bw - 1)) == 0;
-#define KEY_AT(i) key_rn(r[(long long)(pow2 ? ((i) >> lbw) : (i) / bw) * S.nx + \
-                           ((i) - (pow2 ? ((i) >> lbw) : (i) / bw) * bw)])
+  int d0, r0, c0, bd, bh, bw;
+  band_geom3(b, s, S.nd, S.ny, S.nx, d0, r0, c0, bd, bh, bw);
+  const int Nb = bd * bh * bw;
+  const float2* r = a.r + S.off + ((long long)d0 * S.ny + r0) * S.nx + c0;
+  const BandWalk bwk = band_walk(bd, bh, bw, S.ny, S.nx);
+#define KEY_AT(i) key_rn(r[bwk.at(i)])
   for (int i = tid; i < NB; i += NT) {
     cnt[i] = 0;
     kmn[i] = 0x7f800000;
@@ -591,7 +584,7 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
     sRq[i] = 0ull;
   }
   if (wid == 0) {
-    const int ncs = S.nx / kColW;
+    const int ncs = S.ncs;
     double acc = 0.0;
     for (int i = lane; i < ncs; i += 64) acc += (double)a.tau_part[(S.colstrip0 + i) * kMaxBands + b];
 #pragma unroll

@@ -44,7 +44,7 @@ EXPORTED = ("vdamp_plan", "vdamp_plan_destroy", "vdamp_solve", "vdamp_solve_resu
             "vdamp_cnn_create", "vdamp_cnn_destroy", "vdamp_cnn_param_count", "vdamp_cnn_set_params",
             "vdamp_cnn_get_params", "vdamp_cnn_workspace", "vdamp_cnn_forward", "vdamp_cnn_train_step",
             "vdamp_solve_learned", "vdamp_learned_export", "vdamp_wavelet", "vdamp_plan_describe",
-            "vdamp_plan_ortho", "vdamp_wavelet_ws")
+            "vdamp_plan_ortho", "vdamp_wavelet_ws", "vdamp_plan_3d")
 
 
 class VdampError(RuntimeError):
@@ -79,6 +79,9 @@ def load_library() -> ctypes.CDLL:
     lib.vdamp_plan_ortho.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                      i32, ctypes.POINTER(ctypes.c_double), i32, u32, ctypes.POINTER(sz)]
     lib.vdamp_plan_ortho.restype = ctypes.c_int
+    lib.vdamp_plan_3d.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32), i32, u32, ctypes.POINTER(sz)]
+    lib.vdamp_plan_3d.restype = ctypes.c_int
     lib.vdamp_plan_destroy.argtypes = [vp]
     lib.vdamp_plan_destroy.restype = ctypes.c_int
     lib.vdamp_solve.argtypes = [vp, vp, vp, sz, vp, vp, vp, vp, i32, vp, vp]
@@ -150,7 +153,7 @@ class Plan:
     Haar (``vdamp_plan_ortho``)."""
 
     def __init__(self, ny: Sequence[int], nx: Sequence[int], levels: int, flags: int = 0,
-                 lowpass=None):
+                 lowpass=None, nz: Optional[Sequence[int]] = None):
         lib = load_library()
         self.ny = [int(v) for v in ny]
         self.nx = [int(v) for v in nx]
@@ -158,15 +161,23 @@ class Plan:
             raise ValueError("ny and nx must have the same length")
         self.batch = len(self.ny)
         self.levels = int(levels)
-        self.nbands = 1 + 3 * self.levels
+        self.nz = None if nz is None else [int(v) for v in nz]
+        self.nbands = 1 + (7 if self.nz is not None else 3) * self.levels
         self.flags = int(flags)
-        self.offsets = np.concatenate([[0], np.cumsum([a * b for a, b in zip(self.ny, self.nx)])])
+        depth = self.nz if self.nz is not None else [1] * self.batch
+        self.offsets = np.concatenate([[0], np.cumsum([c * a * b for c, a, b in zip(depth, self.ny, self.nx)])])
         self.ntot = int(self.offsets[-1])
         a_ny = (ctypes.c_int32 * self.batch)(*self.ny)
         a_nx = (ctypes.c_int32 * self.batch)(*self.nx)
         h = ctypes.c_void_p()
         wsb = ctypes.c_size_t()
-        if lowpass is None:
+        if self.nz is not None:
+            if lowpass is not None:
+                raise ValueError("volumes use the 3D Haar transform")
+            a_nz = (ctypes.c_int32 * self.batch)(*self.nz)
+            _check(lib.vdamp_plan_3d(ctypes.byref(h), self.batch, a_nz, a_ny, a_nx, self.levels,
+                                     self.flags, ctypes.byref(wsb)))
+        elif lowpass is None:
             _check(lib.vdamp_plan(ctypes.byref(h), self.batch, a_ny, a_nx, self.levels,
                                   VDAMP_WAVELET_HAAR, self.flags, ctypes.byref(wsb)))
         else:
@@ -260,10 +271,11 @@ class Plan:
         return out
 
     def unpack(self, flat):
-        """Split a flat per-pixel array into per-slice 2D arrays."""
+        """Split a flat per-pixel array into per-slice 2D (or per-volume 3D) arrays."""
         flat = np.asarray(flat)
-        return [flat[self.offsets[b]:self.offsets[b + 1]].reshape(self.ny[b], self.nx[b])
-                for b in range(self.batch)]
+        shape = (lambda b: (self.ny[b], self.nx[b])) if self.nz is None else \
+            (lambda b: (self.nz[b], self.ny[b], self.nx[b]))
+        return [flat[self.offsets[b]:self.offsets[b + 1]].reshape(shape(b)) for b in range(self.batch)]
 
 
 def to_device(plan: Plan, slices, device="cuda"):

@@ -1,0 +1,250 @@
+"""GPU parity of VDAMP on volumes (vdamp_plan_3d: Phi with a 3D DFT, Section 1; the
+3D Haar transform) against the 3D oracle (oracle/vdamp3d_ref.py) on the same seeded
+volumes, at the gates of the 2D path: the transform to FP32 rounding, the first
+iterate r_0 and tau_0 (line 5 with the separable S) to 1e-5, one step from the oracle's
+FP32-rounded state at every iteration (r, tau, x_hat to 1e-5; theta and alpha to the
+tolerances the iterate's implies; near ties validated on the library's own data), the
+library's thresholds SURE-optimal on its own free-running iterates and its final NMSE
+within 0.05 dB of the oracle's (or of the envelope of oracle runs on inputs perturbed by
+3e-7), resumed solves, graph replays and the no-alloc entry point bitwise."""
+import numpy as np
+import pytest
+
+from oracle import vdamp3d_ref as o3
+from oracle import vdamp_ref as o
+from paper_1911_01234_amd import synth
+
+from gpu_helpers import gpu_available, rel_l2, snap_theta, theta_accepted
+from test_gpu_parity import TOL_ITER, TOL_NMSE_DB, TOL_TAU, theta_alpha_tols
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs an MI355X")]
+
+
+def fp32_vol(v):
+    y = np.asarray(v.y).astype(np.complex64).astype(np.complex128)
+    p = np.asarray(v.p).astype(np.float32).astype(np.float64)
+    return y, v.mask, p, float(np.float32(v.sigma2))
+
+
+def _plan(vols, s, flags=0):
+    from paper_1911_01234_amd import vdamp as V
+    return V.Plan([v.y.shape[1] for v in vols], [v.y.shape[2] for v in vols], s, flags,
+                  nz=[v.y.shape[0] for v in vols])
+
+
+def _solve(plan, vols, iters, state=None, monitor=False, stream=None):
+    """vdamp_solve (or vdamp_solve_resume from state = per-volume (r, theta, key,
+    alpha)); returns x_hat, trace and the exported state (r, theta, key, alpha, tau)."""
+    import torch
+    from paper_1911_01234_amd import vdamp as V
+    ws = plan.workspace()
+    y, mask, p, sigma2 = V.to_device(plan, vols)
+    x = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+    tr = torch.empty(max(iters, 1) * plan.batch * plan.nbands * 3, dtype=torch.float32, device="cuda")
+    mon = torch.empty(max(iters, 1) * plan.ntot, dtype=torch.complex64, device="cuda") if monitor else None
+    if state is None:
+        plan.vdamp_solve(ws, y, mask, p, sigma2, iters, x, tr, stream=stream)
+    else:
+        r = torch.from_numpy(plan.pack([st[0] for st in state], np.complex64)).cuda()
+        th = torch.from_numpy(np.concatenate([np.asarray(st[1], np.float32) for st in state])).cuda()
+        t2 = (None if state[0][2] is None else
+              torch.from_numpy(np.concatenate([np.asarray(st[2], np.float32) for st in state])).cuda())
+        al = torch.from_numpy(np.concatenate([np.asarray(st[3], np.float32) for st in state])).cuda()
+        plan.vdamp_solve_resume(ws, y, mask, p, sigma2, r, th, t2, al, iters, x, tr, mon, stream=stream)
+    out = {"x_hat": None}
+    if iters > 0 or state is not None:
+        r = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+        th = torch.empty(plan.batch * plan.nbands, dtype=torch.float32, device="cuda")
+        al, ta, t2 = torch.empty_like(th), torch.empty_like(th), torch.empty_like(th)
+        plan.vdamp_state_export(ws, r, th, al, ta, theta2=t2, stream=stream)
+        torch.cuda.synchronize()
+        nb = plan.nbands
+        out.update(r=plan.unpack(r.cpu().numpy()), theta=th.cpu().numpy().reshape(-1, nb),
+                   theta2=t2.cpu().numpy().reshape(-1, nb), alpha=al.cpu().numpy().reshape(-1, nb),
+                   tau=ta.cpu().numpy().reshape(-1, nb))
+    torch.cuda.synchronize()
+    out["x_hat"] = plan.unpack(x.cpu().numpy())
+    out["trace"] = tr.cpu().numpy()[: iters * plan.batch * plan.nbands * 3].reshape(iters, plan.batch, plan.nbands, 3)
+    if monitor:
+        m = mon.cpu().numpy()
+        out["monitor"] = [plan.unpack(m[k * plan.ntot:(k + 1) * plan.ntot]) for k in range(iters)]
+    return out
+
+
+def _band_view(r, blk):
+    zs, ys, xs, _, _ = blk
+    b = np.asarray(r)[zs, ys, xs]
+    return b.reshape(-1, b.shape[-1])
+
+
+def one_step3(v, s, st, g, b, k, what=""):
+    """The library's step (volume b of g) from the FP32-rounded oracle state st against
+    the oracle's step from the same state; returns (r error, tau error, flips)."""
+    y, mask, p, s2 = fp32_vol(v)
+    ref = o3.vdamp3_resume(y, mask, p, s2, s, st[0], st[1], st[3], 1, record=True)
+    r_ref = ref["r"][0]
+    rg = g["r"][b].astype(np.complex128)
+    e = rel_l2(rg, r_ref)
+    tr = g["trace"][0, b]
+    et = float(np.max(np.abs(tr[:, 0] - ref["tau"][0]) / ref["tau"][0]))
+    assert e <= TOL_ITER, (what, k, e)
+    assert et <= TOL_TAU, (what, k, et)
+    flips = 0
+    for bb, blk in enumerate(o3.bands3(*v.y.shape, s)):
+        th_g, al_g = float(tr[bb, 1]), float(tr[bb, 2])
+        band_ref = _band_view(r_ref, blk)
+        same = th_g > 0 and snap_theta(band_ref, th_g) == ref["theta"][0][bb]
+        if same:
+            th_tol, al_tol = theta_alpha_tols(band_ref, ref["theta"][0][bb], ref["alpha"][0][bb])
+            assert abs(th_g - ref["theta"][0][bb]) <= th_tol, (what, k, bb)
+            assert abs(al_g - ref["alpha"][0][bb]) <= al_tol, (what, k, bb)
+        else:
+            flips += 1
+            assert theta_accepted(_band_view(rg, blk), float(tr[bb, 0]), slice(None), slice(None), th_g,
+                                  alpha_gpu=al_g), (what, k, bb)
+    if flips == 0:
+        assert rel_l2(g["x_hat"][b], ref["x_hat"]) <= TOL_ITER, (what, k)
+    return e, et, flips
+
+
+def fp32_state3(r, th, al):
+    return (np.asarray(r).astype(np.complex64).astype(np.complex128),
+            np.asarray(th).astype(np.float32).astype(np.float64), None,
+            np.asarray(al).astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("shape,s", [((32, 32, 32), 2), ((16, 32, 48), 3), ((8, 16, 32), 1),
+                                     ((64, 64, 64), 3), ((64, 64, 128), 4)])
+def test_haar3_transform_matches_oracle(shape, s):
+    import torch
+    vols = [synth.Volume(x0=None, y=np.zeros(shape, complex), mask=None, p=None, sigma2=0.0, R=1.0, snr_db=0.0)]
+    plan = _plan(vols, s)
+    rng = np.random.default_rng(9)
+    x = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    ws = plan.workspace()
+    xt = torch.from_numpy(plan.pack([x], np.complex64)).cuda()
+    out = torch.empty_like(xt)
+    plan.vdamp_wavelet_ws(ws, xt, out, False)
+    torch.cuda.synchronize()
+    ef = rel_l2(plan.unpack(out.cpu().numpy())[0], o3.haar3_analysis(x.astype(np.complex128), s))
+    plan.vdamp_wavelet_ws(ws, xt, out, True)
+    torch.cuda.synchronize()
+    eb = rel_l2(plan.unpack(out.cpu().numpy())[0], o3.haar3_synthesis(x.astype(np.complex128), s))
+    print(f"{shape} s={s}: Psi {ef:.2e}, Psi^H {eb:.2e}")
+    assert ef <= 1e-6 and eb <= 1e-6
+    plan.close()
+
+
+@pytest.mark.parametrize("wl", ["volume32", "volume64"])
+def test_first_iteration_r0_tau0(wl):
+    vols, s, _ = getattr(synth, "workload_" + wl)()
+    v = vols[0]
+    plan = _plan([v], s)
+    g = _solve(plan, [v], 1)
+    y, mask, p, s2 = fp32_vol(v)
+    r0, tau0 = o3.vdamp3_step(np.zeros_like(y), y, mask, p, s2, s, o3.tau_weights3(*v.y.shape, s))
+    e = rel_l2(g["r"][0], r0)
+    et = float(np.max(np.abs(g["tau"][0] - tau0) / tau0))
+    print(f"{wl}: r_0 rel L2 {e:.2e}; tau_0 max rel {et:.2e}")
+    assert e <= TOL_ITER and et <= TOL_TAU
+    plan.close()
+
+
+@pytest.mark.parametrize("wl,ks", [("volume32", None), ("volume64", (0, 3, 10, 20, 28))])
+def test_one_step(wl, ks):
+    vols, s, K = getattr(synth, "workload_" + wl)()
+    v = vols[0]
+    traj = o3.vdamp3(*fp32_vol(v), s, K, record=True)
+    plan = _plan([v], s)
+    errs, terrs, nflip = [], [], 0
+    for k in (range(K - 1) if ks is None else ks):
+        st = fp32_state3(traj["r"][k], traj["theta"][k], traj["alpha"][k])
+        g = _solve(plan, [v], 1, state=[st])
+        e, et, f = one_step3(v, s, st, g, 0, k, wl)
+        errs.append(e)
+        terrs.append(et)
+        nflip += f
+    print(f"{wl} one step: max r {max(errs):.2e}, max tau {max(terrs):.2e}, flips {nflip}")
+    plan.close()
+
+
+def test_free_running_volume32():
+    """Thresholds SURE-optimal on the library's own iterates, final NMSE within 0.05 dB
+    of the oracle's (or the perturbation envelope when the runs part at a near tie)."""
+    vols, s, K = synth.workload_volume32()
+    v = vols[0]
+    plan = _plan([v], s)
+    g = _solve(plan, [v], K)
+    ref = o3.vdamp3(*fp32_vol(v), s, K)
+    for k in (1, K // 2, K):
+        gk = _solve(plan, [v], k)
+        for bb, blk in enumerate(o3.bands3(*v.y.shape, s)):
+            assert theta_accepted(_band_view(gk["r"][0], blk), float(gk["tau"][0][bb]), slice(None), slice(None),
+                                  float(gk["theta"][0][bb]), alpha_gpu=float(gk["alpha"][0][bb])), (k, bb)
+    n_gpu, n_ref = o.nmse_db(g["x_hat"][0], v.x0), o.nmse_db(ref["x_hat"], v.x0)
+    print(f"volume32 NMSE gpu {n_gpu:.3f} dB oracle {n_ref:.3f} dB")
+    if abs(n_gpu - n_ref) > TOL_NMSE_DB:
+        y, mask, p, s2 = fp32_vol(v)
+        rng = np.random.default_rng(2024)
+        vals = [n_ref]
+        for _ in range(16):
+            pert = (rng.standard_normal(y.shape) + 1j * rng.standard_normal(y.shape)) / np.sqrt(2)
+            vals.append(o.nmse_db(o3.vdamp3(y * (1 + 3e-7 * pert), mask, p, s2, s, K)["x_hat"], v.x0))
+        assert abs(n_gpu - np.mean(vals)) <= max(TOL_NMSE_DB, 4 * np.std(vals))
+    plan.close()
+
+
+def test_resume_monitor_graph_noalloc_and_ragged_batch_bitwise():
+    import torch
+    from paper_1911_01234_amd import vdamp as V
+    vols, s, K = synth.workload_volume32()
+    v = vols[0]
+    plan = _plan([v], s)
+    full = _solve(plan, [v], 10)
+    first = _solve(plan, [v], 4)
+    st = [(first["r"][0], first["theta"][0], first["theta2"][0], first["alpha"][0])]
+    rest = _solve(plan, [v], 6, state=st, monitor=True)
+    assert np.array_equal(rest["x_hat"][0], full["x_hat"][0])
+    assert np.array_equal(rest["r"][0], full["r"][0])
+    assert np.array_equal(rest["trace"], full["trace"][4:])
+    assert np.array_equal(rest["monitor"][-1][0], rest["x_hat"][0])
+    gplan = _plan([v], s, V.VDAMP_FLAG_USE_GRAPH)
+    stream = torch.cuda.Stream()
+    for _ in range(3):
+        gg = _solve(gplan, [v], 10, stream=stream)
+        assert np.array_equal(gg["x_hat"][0], full["x_hat"][0])
+    ws_free = plan.workspace()
+    y, mask, p, sigma2 = V.to_device(plan, [v])
+    xa = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+    plan.vdamp_solve_noalloc(y, mask, p, sigma2, 10, xa)
+    torch.cuda.synchronize()
+    assert np.array_equal(plan.unpack(xa.cpu().numpy())[0], full["x_hat"][0])
+    del ws_free
+    # a ragged batch: each volume equals its own single-volume solve
+    other = synth.make_volume(62, 0, 16, 32, 48, 5, 4.0, 4.0, 4, 30.0)
+    both = _plan([v, other], s)
+    gb = _solve(both, [v, other], 10)
+    assert np.array_equal(gb["x_hat"][0], full["x_hat"][0])
+    single = _plan([other], s)
+    assert np.array_equal(gb["x_hat"][1], _solve(single, [other], 10)["x_hat"][0])
+    for pl in (plan, gplan, both, single):
+        pl.close()
+
+
+def test_entry_points_without_a_volume_path_refuse():
+    import torch
+    from paper_1911_01234_amd import vdamp as V
+    vols, s, _ = synth.workload_volume32()
+    plan = _plan(vols, s)
+    ws = plan.workspace()
+    z = torch.zeros(plan.ntot, dtype=torch.complex64, device="cuda")
+    m = torch.zeros(plan.ntot, dtype=torch.uint8, device="cuda")
+    lam = torch.ones(1, dtype=torch.float32, device="cuda")
+    with pytest.raises(V.VdampError) as ei:
+        plan.fista_solve(ws, z, m, lam, 2, torch.empty_like(z))
+    assert ei.value.status == 3
+    with pytest.raises(V.VdampError) as ei:
+        plan.vdamp_wavelet(z, torch.empty_like(z), True)
+    assert ei.value.status == 3
+    plan.close()
