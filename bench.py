@@ -96,10 +96,23 @@ def algorithmic_bytes_per_solve(npx, iters, bytes_=None):
             "rows_anal": (ra, iters + 1), "sure": (su, iters)}
 
 
-def pass_rooflines(times, npx, iters, steps, bytes_=None):
+def algorithmic_bytes_per_solve_3d(npx, iters):
+    """Volumes (vdamp_plan_3d), per kernel class and voxel: rows_synth = the Haar
+    synthesis (read r, write X); cols = the DFT passes along x, y (X read and written)
+    and z (X, y, m/p read, X written; first iteration no X read; line 10: z pass and
+    inverse y, x into x_hat under rows_anal); rows_anal = the Haar analysis (read X and
+    r, write r; first: no r read) and line 10's inverse x DFTs (read X, write x_hat)."""
+    rs = 16.0 * iters
+    cols = (20 + 16 + 16) + (16 + 16 + 28 + 16 + 16) * (iters - 1) + (16 + 16 + 28 + 16)
+    ra = 16.0 + 24.0 * (iters - 1) + 16.0
+    return {"rows_synth": (rs * npx, iters), "cols": (cols * npx, None),
+            "rows_anal": (ra * npx, None), "sure": (8.0 * iters * npx, iters)}
+
+
+def pass_rooflines(times, npx, iters, steps, bytes_=None, alg=None):
     """Per kernel class: average launch time and algorithmic bytes / time against the
     HBM peak (times from the plan's per-kernel HIP events over `steps` solves)."""
-    alg = algorithmic_bytes_per_solve(npx, iters, bytes_)
+    alg = alg or algorithmic_bytes_per_solve(npx, iters, bytes_)
     out = {}
     for k, (b, _) in alg.items():
         ms, launches = times[k]
@@ -182,7 +195,64 @@ def other_workloads(stream, reps=3):
                      "autotune": desc[desc.index("autotune:") + 10:] if "autotune:" in desc else None}
         print(f"[bench] {name}: generated in {tg:.1f} s, {res[name]['slice_iterations_per_s']} slice-it/s",
               file=sys.stderr, flush=True)
+    res["volumes_32_of_64x64x64"] = volume_workload(stream, reps)
     return res
+
+
+def volume_workload(stream, reps=3, n=32):
+    """VDAMP on 3D k-space (vdamp_plan_3d): n volumes of 64^3 (12 ellipsoids, R = 6,
+    40 dB, 3 Haar levels: 22 bands, the finest of 32^3 = 32768 coefficients), 30
+    iterations; eager with per-kernel events, then the same solves from a hipGraph."""
+    import torch
+    from paper_1911_01234_amd import synth, vdamp as V
+    t = time.perf_counter()
+    vols, s, K = synth.workload_volume64(n)
+    tg = time.perf_counter() - t
+    nz = [v.y.shape[0] for v in vols]
+    ny = [v.y.shape[1] for v in vols]
+    nx = [v.y.shape[2] for v in vols]
+    npx = int(sum(a * b * c for a, b, c in zip(nz, ny, nx)))
+    with torch.cuda.stream(stream):
+        plan = V.Plan(ny, nx, s, V.VDAMP_FLAG_TIMING, nz=nz)
+        ws = plan.workspace()
+        y, mask, p, sigma2 = V.to_device(plan, vols)
+        xh = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
+        x0 = torch.from_numpy(plan.pack([v.x0 for v in vols], np.complex64)).cuda()
+        plan.vdamp_solve(ws, y, mask, p, sigma2, K, xh, stream=stream)
+        stream.synchronize()
+        plan.vdamp_pass_times()
+        t = time.perf_counter()
+        for _ in range(reps):
+            plan.vdamp_solve(ws, y, mask, p, sigma2, K, xh, stream=stream)
+        stream.synchronize()
+        dt = (time.perf_counter() - t) / reps
+        times = plan.vdamp_pass_times()
+        seg = torch.from_numpy(np.repeat(np.arange(n), npx // n)).cuda()
+        nm = float(nmse_db_batch(xh, x0, seg, n).mean())
+        plan.close()
+        gplan = V.Plan(ny, nx, s, V.VDAMP_FLAG_USE_GRAPH, nz=nz)
+        gws = gplan.workspace()
+        gx = torch.empty_like(xh)
+        gplan.vdamp_solve(gws, y, mask, p, sigma2, K, gx, stream=stream)
+        stream.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            gplan.vdamp_solve(gws, y, mask, p, sigma2, K, gx, stream=stream)
+        stream.synchronize()
+        dtg = (time.perf_counter() - t) / reps
+        gsame = bool(torch.equal(gx, xh))
+        gplan.close()
+    del ws, y, mask, p, sigma2, xh, x0, gws, gx
+    torch.cuda.empty_cache()
+    out = {"volumes": n, "voxels": npx, "levels": s, "iters": K, "seconds_per_solve": round(dt, 5),
+           "volume_iterations_per_s": round(n * K / dt, 1),
+           "mvoxel_iterations_per_s": round(npx * K / dt / 1e6, 1),
+           "hipgraph": {"volume_iterations_per_s": round(n * K / dtg, 1), "bitwise_equal_to_eager": gsame},
+           "nmse_db_mean": round(nm, 3),
+           "passes": pass_rooflines(times, npx, K, reps, alg=algorithmic_bytes_per_solve_3d(npx, K))}
+    print(f"[bench] volumes: generated in {tg:.1f} s, {out['volume_iterations_per_s']} volume-it/s",
+          file=sys.stderr, flush=True)
+    return out
 
 
 def make_batch(B):

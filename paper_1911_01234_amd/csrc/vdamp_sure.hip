@@ -325,13 +325,27 @@ k_sure(KArgs a) {
   }
   // load the band (coalesced along rows) while the counters are cleared
   const float2* r = a.r + S.off + ((long long)d0 * S.ny + r0) * S.nx + c0;
-  const BandWalk bwk = band_walk(bd, bh, bw, S.ny, S.nx);  // band widths: 2^a times 1, 3 or 5
+  const int lbw = 31 - __clz(bw);  // band widths are powers of two times 1, 3 or 5
+  const bool pow2 = (bw & (bw - 1)) == 0;
   float kk[KPT];
+  if (bd == 1) {  // a slice's band (the branch stays outside the unrolled loads)
 #pragma unroll
-  for (int j = 0; j < KPT; ++j) {
-    const int i = tid + j * NT;
-    kk[j] = 0.f;
-    if (i < Nb) kk[j] = key_rn(r[bwk.at(i)]);
+    for (int j = 0; j < KPT; ++j) {
+      const int i = tid + j * NT;
+      kk[j] = 0.f;
+      if (i < Nb) {
+        const int rr = pow2 ? (i >> lbw) : i / bw;
+        kk[j] = key_rn(r[(long long)rr * S.nx + (i - rr * bw)]);
+      }
+    }
+  } else {  // a volume's band
+    const BandWalk bwk = band_walk(bd, bh, bw, S.ny, S.nx);
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      const int i = tid + j * NT;
+      kk[j] = 0.f;
+      if (i < Nb) kk[j] = key_rn(r[bwk.at(i)]);
+    }
   }
   __syncthreads();
   const float inv_tau = 1.0f / tau_sh;
