@@ -26,6 +26,12 @@ Conventions (readings of the paper where it is silent; each is pinned by a test)
   each subband, so alpha has 1+3s entries.
 * Line 10's w is the last denoised estimate w_hat_{K-1}; with K = 0 the output is the
   zero-filled F^H y.
+* Structured sparsity (group=2; Section 4 names structured sparsity as a richer model
+  that SURE can tune): the two horizontally adjacent coefficients (x = 2j, 2j+1) of each
+  band row form a group, shrunk jointly by group soft thresholding
+  r_g max(0, 1 - theta/||r_g||), with theta minimising the group SURE (2d real
+  dimensions per group of d complex coefficients) and alpha the mean Wirtinger
+  derivative, i.e. half the real divergence per complex coefficient.
 """
 from __future__ import annotations
 
@@ -236,18 +242,23 @@ def soft(r, theta):
     return out
 
 
-def sure_value(a, theta, tau):
+def sure_value(a, theta, tau, d=1):
     """Complex colored SURE of soft thresholding one band at threshold theta, summed
     over the band: Stein's estimate with n ~ CN(0, tau) (2 real dimensions per
-    coefficient), written directly from its definition, O(N_b)."""
+    coefficient), written directly from its definition, O(N_b).
+
+    With d > 1, a holds the norms of groups of d coefficients thresholded jointly
+    (D = 2d real dimensions, noise variance tau/2 in each): a group at or below theta
+    contributes ||r_g||^2 - D tau/2, one above it D tau/2 + theta^2 - (D - 1) tau theta/||r_g||
+    (Stein: E||eta - mu||^2 = D sigma^2 + E||eta - r||^2 + 2 sigma^2 E div(eta - r))."""
     a = np.asarray(a, dtype=np.float64)
     below = a <= theta
     above = ~below
-    return (np.sum(a[below] ** 2 - tau)
-            + np.sum(theta ** 2 + tau - tau * theta / a[above]))
+    return (np.sum(a[below] ** 2 - d * tau)
+            + np.sum(theta ** 2 + d * tau - (2 * d - 1) * tau * theta / a[above]))
 
 
-def sure_threshold(a, tau):
+def sure_threshold(a, tau, d=1):
     """SURE-minimising threshold for one band.
 
     a: magnitudes |r_i| of the band (float64), tau: effective noise variance of the band.
@@ -259,31 +270,38 @@ def sure_threshold(a, tau):
     1 - theta/(2|r|) above the threshold and 0 below:
         alpha = ((N_b - m) - (theta/2) R_m) / N_b.
     Returns (theta, alpha, m, sure_min).  All-zero band: theta = 0, alpha = 0.
+
+    Groups (d > 1): a are the n group norms and, with tl = d tau and td = (2d - 1) tau
+    (sure_value),
+        SURE(m) = A_m - m tl + (n - m)(theta^2 + tl) - td theta R_m,
+        alpha = (d (n - m) - (td / tau)(theta/2) R_m) / (d n);
+    with d = 1 both reduce to the formulas above.
     """
     a = np.sort(np.asarray(a, dtype=np.float64).ravel())
     n = a.size
+    tl, td = d * tau, (2 * d - 1) * tau
     if n == 0:
         raise ValueError("empty band")
     if a[-1] == 0.0:
-        return 0.0, 0.0, n, float(n * (0.0 - tau))
+        return 0.0, 0.0, n, float(n * (0.0 - tl))
     A = np.cumsum(a ** 2)                                  # A[m-1] = A_m
     inv = np.zeros(n)
     pos = a > 0
     inv[pos] = 1.0 / a[pos]
     Rsuf = np.concatenate([np.cumsum(inv[::-1])[::-1][1:], [0.0]])  # Rsuf[m-1] = R_m
     m = np.arange(1, n + 1, dtype=np.float64)
-    sure = A - m * tau + (n - m) * (a ** 2 + tau) - tau * a * Rsuf
+    sure = A - m * tl + (n - m) * (a ** 2 + tl) - td * a * Rsuf
     last_of_run = np.concatenate([a[:-1] < a[1:], [True]])
     valid = last_of_run & (a > 0)
     sure_v = np.where(valid, sure, np.inf)
     i = int(np.argmin(sure_v))                             # first minimum = smallest theta
     theta = float(a[i])
     mm = i + 1
-    alpha = float(((n - mm) - 0.5 * theta * Rsuf[i]) / n)
+    alpha = float((d * (n - mm) - 0.5 * (2 * d - 1) * theta * Rsuf[i]) / (d * n))
     return theta, alpha, mm, float(sure_v[i])
 
 
-def sure_threshold_continuous(a, tau):
+def sure_threshold_continuous(a, tau, d=1):
     """SURE-minimising threshold over every theta > 0, not only the candidates |r_i|
     (the paper's SURE step is solved "approximately"; this is the exact minimiser).
 
@@ -293,10 +311,13 @@ def sure_threshold_continuous(a, tau):
     theta* counts where it lies strictly inside its interval (the interval below the
     smallest positive magnitude starts at 0).  The candidates a_(m) themselves are those
     of sure_threshold.  The smallest value wins, ties to the smaller theta.
-    Returns (theta, alpha, m, sure_min), alpha = ((N_b - m) - (theta/2) R_m) / N_b."""
+    Returns (theta, alpha, m, sure_min), alpha = ((N_b - m) - (theta/2) R_m) / N_b.
+    Groups (d > 1, a = group norms): tau becomes tl = d tau in the first two terms and
+    td = (2d - 1) tau in the last, so the vertex is td R_m / (2 (n - m)) (sure_threshold)."""
     a = np.sort(np.asarray(a, dtype=np.float64).ravel())
     n = a.size
-    th_d, al_d, m_d, v_d = sure_threshold(a, tau)
+    tl, td = d * tau, (2 * d - 1) * tau
+    th_d, al_d, m_d, v_d = sure_threshold(a, tau, d)
     if a[-1] == 0.0:
         return th_d, al_d, m_d, v_d
     best = (v_d, th_d, m_d)
@@ -311,33 +332,61 @@ def sure_threshold_continuous(a, tau):
         if hi == 0.0:
             continue
         R = Rs[m]
-        t = tau * R / (2.0 * (n - m))
+        t = td * R / (2.0 * (n - m))
         if lo < t < hi:
-            v = A[m] - m * tau + (n - m) * (t * t + tau) - tau * t * R
+            v = A[m] - m * tl + (n - m) * (t * t + tl) - td * t * R
             if v < best[0] or (v == best[0] and t < best[1]):
                 best = (v, t, m)
     v, t, m = best
     R = Rs[m]
-    return float(t), float(((n - m) - 0.5 * t * R) / n), int(m), float(v)
+    return float(t), float((d * (n - m) - 0.5 * (2 * d - 1) * t * R) / (d * n)), int(m), float(v)
 
 
-def sure_threshold_brute(a, tau):
+def sure_threshold_brute(a, tau, d=1):
     """O(N_b^2) reference for sure_threshold: evaluate sure_value at every candidate."""
     a = np.asarray(a, dtype=np.float64).ravel()
     cands = np.unique(a[a > 0])
     if cands.size == 0:
-        return 0.0, float(a.size * (0.0 - tau))
-    vals = np.array([sure_value(a, t, tau) for t in cands])
+        return 0.0, float(a.size * (0.0 - d * tau))
+    vals = np.array([sure_value(a, t, tau, d) for t in cands])
     i = int(np.argmin(vals))
     return float(cands[i]), float(vals[i])
 
 
-def wirtinger_mean_soft(r, theta):
+def wirtinger_mean_soft(r, theta, d=1):
     """alpha for one band straight from its definition: the mean over the band of
-    1 - theta/(2|r_i|) for |r_i| > theta, 0 otherwise."""
-    a = np.abs(r)
+    1 - theta/(2|r_i|) for |r_i| > theta, 0 otherwise.  With groups of d coefficients
+    (d > 1, r a band block): half the real divergence of group soft thresholding per
+    complex coefficient; the Jacobian of g (1 - theta/||g||) on R^D (D = 2d) has trace
+    D - (D - 1) theta/||g|| above the threshold and 0 below."""
+    if d == 1:
+        a = np.abs(r)
+        keep = a > theta
+        return float(np.sum(1.0 - theta / (2.0 * a[keep])) / a.size)
+    a, _ = group_norms(r, d)
     keep = a > theta
-    return float(np.sum(1.0 - theta / (2.0 * a[keep])) / a.size)
+    D = 2 * d
+    return float(np.sum(D - (D - 1) * theta / a[keep]) / (2.0 * r.size))
+
+
+def group_norms(rb, d):
+    """Norms of the groups of d horizontally adjacent coefficients (x = d j .. d j + d - 1)
+    of a band block rb, and the groups themselves ([rows][nx/d][d])."""
+    h, w = rb.shape
+    g = np.asarray(rb).reshape(h, w // d, d)
+    return np.sqrt(np.sum(np.abs(g) ** 2, axis=2)), g
+
+
+def soft_group(rb, theta, d):
+    """Group soft thresholding of a band block: each group g -> g max(0, 1 - theta/||g||);
+    d = 1 is soft()."""
+    if d == 1:
+        return soft(rb, theta)
+    a, g = group_norms(rb, d)
+    out = np.zeros_like(g)
+    keep = a > theta
+    out[keep] = g[keep] * (1.0 - theta / a[keep])[:, None]
+    return out.reshape(rb.shape)
 
 
 # ----------------------------------------------------------------------------------
@@ -364,12 +413,13 @@ def vdamp_step(rt, y, mask, p, sigma2, s, S, wavelet=None):
     return r, tau
 
 
-def denoise(r, tau, s, theta_override=None, alpha_override=None, continuous=False):
+def denoise(r, tau, s, theta_override=None, alpha_override=None, continuous=False, group=1):
     """Lines 6-8: per band SURE threshold, eta, alpha, and the corrected r_tilde_{k+1}.
     theta_override (optional, per band) replaces the SURE search; alpha then follows
     from its definition at that threshold unless alpha_override gives it too (a test
     that replays another implementation's decisions supplies both).  continuous=True
-    minimises SURE over every theta > 0 (sure_threshold_continuous)."""
+    minimises SURE over every theta > 0 (sure_threshold_continuous); group = 2
+    thresholds horizontal pairs jointly (structured sparsity, module docstring)."""
     ny, nx = r.shape
     w_hat = np.zeros_like(r)
     rt_next = np.zeros_like(r)
@@ -378,12 +428,15 @@ def denoise(r, tau, s, theta_override=None, alpha_override=None, continuous=Fals
         rb = r[rs, cs]
         if theta_override is None:
             search = sure_threshold_continuous if continuous else sure_threshold
-            th, al, _, _ = search(np.abs(rb), tau[b])
+            if group == 1:
+                th, al, _, _ = search(np.abs(rb), tau[b])
+            else:
+                th, al, _, _ = search(group_norms(rb, group)[0], tau[b], group)
         else:
             th = float(theta_override[b])
-            al = (wirtinger_mean_soft(rb, th) if alpha_override is None
+            al = (wirtinger_mean_soft(rb, th, group) if alpha_override is None
                   else float(alpha_override[b]))
-        wb = soft(rb, th)
+        wb = soft_group(rb, th, group)
         w_hat[rs, cs] = wb
         rt_next[rs, cs] = (wb - al * rb) / (1.0 - al)      # line 8
         thetas.append(th)
@@ -399,11 +452,12 @@ def output_step(w_hat, y, mask, s, wavelet=None):
     return x + ifft2u(resid)
 
 
-def vdamp(y, mask, p, sigma2, s, iters, record=False, continuous=False, wavelet=None):
+def vdamp(y, mask, p, sigma2, s, iters, record=False, continuous=False, wavelet=None, group=1):
     """Algorithm 1 in FP64.  y: zero-filled measurements (natural order), mask: 0/1,
     p: sampling probabilities (used on Omega), sigma2: E|eps_j|^2, s: wavelet levels.
     continuous=True takes each threshold as SURE's minimiser over every theta > 0;
-    wavelet: None for Haar, else an orthonormal lowpass filter (dwt2).
+    wavelet: None for Haar, else an orthonormal lowpass filter (dwt2); group = 2 for
+    joint thresholding of horizontal pairs (structured sparsity).
     Returns dict with x_hat and, per iteration, tau, theta, alpha (and r if record)."""
     y = np.asarray(y, dtype=np.complex128)
     p = np.asarray(p, dtype=np.float64)
@@ -415,7 +469,7 @@ def vdamp(y, mask, p, sigma2, s, iters, record=False, continuous=False, wavelet=
     taus, thetas, alphas, rs = [], [], [], []
     for _ in range(iters):
         r, tau = vdamp_step(rt, y, mask, p, sigma2, s, S, wavelet)
-        w_hat, rt, th, al = denoise(r, tau, s, continuous=continuous)
+        w_hat, rt, th, al = denoise(r, tau, s, continuous=continuous, group=group)
         taus.append(tau)
         thetas.append(th)
         alphas.append(al)
@@ -430,7 +484,7 @@ def vdamp(y, mask, p, sigma2, s, iters, record=False, continuous=False, wavelet=
 
 
 def vdamp_resume(y, mask, p, sigma2, s, r, theta, alpha, iters, record=False, continuous=False,
-                 wavelet=None):
+                 wavelet=None, group=1):
     """Algorithm 1 continued from the state (r_k, theta_k, alpha_k) of an earlier
     iteration: every further iteration starts with lines 6-8 applied to the previous
     state (eta with the given thresholds, line 8 with the given alpha), then lines 3-7.
@@ -442,11 +496,11 @@ def vdamp_resume(y, mask, p, sigma2, s, r, theta, alpha, iters, record=False, co
     ny, nx = y.shape
     check_shape(ny, nx, s)
     S = tau_weights(ny, nx, s, wavelet)
-    w_hat, rt, _, _ = denoise(r, None, s, theta_override=theta, alpha_override=alpha)
+    w_hat, rt, _, _ = denoise(r, None, s, theta_override=theta, alpha_override=alpha, group=group)
     taus, thetas, alphas, rs = [], [], [], []
     for _ in range(iters):
         r, tau = vdamp_step(rt, y, mask, p, sigma2, s, S, wavelet)
-        w_hat, rt, th, al = denoise(r, tau, s, continuous=continuous)
+        w_hat, rt, th, al = denoise(r, tau, s, continuous=continuous, group=group)
         taus.append(tau)
         thetas.append(th)
         alphas.append(al)
