@@ -85,7 +85,18 @@ enum {
      between consecutive distinct magnitudes SURE is a convex quadratic in theta, whose
      minimum tau R_m / (2 (N_b - m)) competes with the candidates when it lies inside its
      interval.  Line 7's alpha and line 6's eta use the threshold found. */
-  VDAMP_FLAG_SURE_CONTINUOUS = 1u << 7
+  VDAMP_FLAG_SURE_CONTINUOUS = 1u << 7,
+  /* Structured sparsity (Section 4 names it among the richer models SURE can tune):
+     the two horizontally adjacent coefficients x = 2j, 2j+1 of every subband row form a
+     group, shrunk jointly by group soft thresholding g max(0, 1 - theta/||g||).  theta
+     minimises the group's SURE (Stein's estimate over the 4 real dimensions of a pair
+     under CN(0, tau) noise per coefficient) over the candidates ||g|| (or over every
+     theta > 0 with VDAMP_FLAG_SURE_CONTINUOUS); line 7's alpha is half the real
+     divergence per coefficient.  theta's key is the FP32 squared norm of the pair
+     (|g_0|^2 + |g_1|^2, each term as for one coefficient, their sum rounded to nearest).
+     2D Haar plans of vdamp_plan only (VDAMP_ERR_UNSUPPORTED elsewhere); fista_solve and
+     the learned denoiser refuse such plans. */
+  VDAMP_FLAG_GROUP_PAIRS = 1u << 8
 };
 
 /* Kernel classes reported by vdamp_pass_times(). */

@@ -162,7 +162,7 @@ std::vector<int2> sure_work_list(vdamp_plan_t* P) {
   for (int b = 0; b < P->B; ++b)
     for (int band = 0; band < P->nbands; ++band) {
       const int l = band == 0 ? P->levels : P->levels - (band - 1) / (P->dim3 ? 7 : 3);
-      const long long nb = (long long)(P->ny[b] >> l) * (P->nx[b] >> l) * (P->dim3 ? (P->nz[b] >> l) : 1);
+      const long long nb = (long long)(P->ny[b] >> l) * (P->nx[b] >> l) * (P->dim3 ? (P->nz[b] >> l) : 1) / P->grp;
       auto it = P->sure_cls_of_size.find(nb);
       int cls = it != P->sure_cls_of_size.end() ? it->second : sure_default_class(nb);
       if (cls < 0 || cls >= kSureClasses || nb > sure_class_capacity(cls)) cls = sure_default_class(nb);
@@ -310,18 +310,18 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
     a.iter = k;
     const bool has_prev = k > 0 || resume;  // r_tilde_k from the previous r, theta, alpha
     if (has_prev) {
-      a.mode = RS_RTILDE;
+      a.mode = P->grp > 1 ? RS_RTILDE_G : RS_RTILDE;
       LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, pass_synth(P, a, st));
     }
     a.mode = has_prev ? CM_VDAMP : CM_VDAMP_FIRST;
     LAUNCH(L, VDAMP_PASS_COLS, pass_cols(P, a, st));
-    a.mode = has_prev ? RA_VDAMP : RA_VDAMP_FIRST;
+    a.mode = has_prev ? (P->grp > 1 ? RA_VDAMP_G : RA_VDAMP) : RA_VDAMP_FIRST;
     LAUNCH(L, VDAMP_PASS_ROWS_ANAL, pass_anal(P, a, st));
     LAUNCH(L, VDAMP_PASS_SURE, launch_sure_all(P, a, w.big, st));
     if (x_monitor) {  // line 10 at this iteration (X is free between iterations)
       KArgs m = a;
       m.out = x_monitor + (long long)k * P->ntot;
-      m.mode = RS_WHAT;
+      m.mode = P->grp > 1 ? RS_WHAT_G : RS_WHAT;
       LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, pass_synth(P, m, st));
       m.mode = CM_OUTPUT;
       LAUNCH(L, VDAMP_PASS_COLS, pass_cols(P, m, st));
@@ -332,7 +332,7 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
   // line 10: x_hat = F^H [ (1 - m) F Psi^H w + m y ]
   const bool has_w = iters > 0 || resume;
   if (has_w) {
-    a.mode = RS_WHAT;
+    a.mode = P->grp > 1 ? RS_WHAT_G : RS_WHAT;
     LAUNCH(L, VDAMP_PASS_ROWS_SYNTH, pass_synth(P, a, st));
   }
   a.mode = has_w ? CM_OUTPUT : CM_ZEROFILL;
@@ -457,8 +457,11 @@ static vdamp_status make_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* 
       return fail(VDAMP_ERR_UNSUPPORTED, "VDAMP_FLAG_AUTOTUNE tunes the Haar passes only");
   }
   const uint32_t known = VDAMP_FLAG_DETERMINISTIC | VDAMP_FLAG_USE_GRAPH | VDAMP_FLAG_CHECK_FINITE |
-                         VDAMP_FLAG_TIMING | VDAMP_FLAG_AUTOTUNE | VDAMP_FLAG_SURE_CONTINUOUS;
+                         VDAMP_FLAG_TIMING | VDAMP_FLAG_AUTOTUNE | VDAMP_FLAG_SURE_CONTINUOUS |
+                         VDAMP_FLAG_GROUP_PAIRS;
   if (flags & ~known) return fail(VDAMP_ERR_ARG, "unknown flag bits");
+  if (ortho && (flags & VDAMP_FLAG_GROUP_PAIRS))
+    return fail(VDAMP_ERR_UNSUPPORTED, "VDAMP_FLAG_GROUP_PAIRS runs on Haar plans only");
   const int H = 1 << levels;
   std::vector<int> rad;
   for (int b = 0; b < batch; ++b) {
@@ -492,6 +495,7 @@ static vdamp_status make_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* 
   P->off.resize(batch);
   P->ortho = ortho;
   if (ortho) P->filt.assign(filt, filt + flen);
+  P->grp = (flags & VDAMP_FLAG_GROUP_PAIRS) ? 2 : 1;
 
   // FFT plans and twiddles, one per distinct length
   std::map<int, int> fft_index;
@@ -760,9 +764,11 @@ static vdamp_status make_plan3d(vdamp_plan_h* plan, int32_t batch, const int32_t
   if (batch < 1) return fail(VDAMP_ERR_ARG, "batch must be >= 1");
   if (levels < 1 || levels > 4) return fail(VDAMP_ERR_UNSUPPORTED, "levels must be in 1..4");
   const uint32_t known = VDAMP_FLAG_DETERMINISTIC | VDAMP_FLAG_USE_GRAPH | VDAMP_FLAG_CHECK_FINITE |
-                         VDAMP_FLAG_TIMING | VDAMP_FLAG_AUTOTUNE | VDAMP_FLAG_SURE_CONTINUOUS;
+                         VDAMP_FLAG_TIMING | VDAMP_FLAG_AUTOTUNE | VDAMP_FLAG_SURE_CONTINUOUS |
+                         VDAMP_FLAG_GROUP_PAIRS;
   if (flags & ~known) return fail(VDAMP_ERR_ARG, "unknown flag bits");
   if (flags & VDAMP_FLAG_AUTOTUNE) return fail(VDAMP_ERR_UNSUPPORTED, "VDAMP_FLAG_AUTOTUNE tunes 2D plans only");
+  if (flags & VDAMP_FLAG_GROUP_PAIRS) return fail(VDAMP_ERR_UNSUPPORTED, "VDAMP_FLAG_GROUP_PAIRS runs on 2D plans only");
   const int C = 1 << levels;
   std::vector<int> rad;
   for (int b = 0; b < batch; ++b) {
@@ -1051,6 +1057,7 @@ vdamp_status fista_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
   if (s != VDAMP_OK) return s;
   if (!lambda) return fail(VDAMP_ERR_ARG, "lambda must be non-null");
   if (plan->ortho || plan->dim3) return fail(VDAMP_ERR_UNSUPPORTED, "fista_solve runs on 2D Haar plans only");
+  if (plan->grp > 1) return fail(VDAMP_ERR_UNSUPPORTED, "fista_solve thresholds single coefficients (no VDAMP_FLAG_GROUP_PAIRS)");
   GraphKey key;
   key.kind = 1; key.ws = workspace; key.y = y; key.mask = mask; key.lam = lambda;
   key.x = x_hat; key.iters = iters; key.stream = stream; key.obj = objective;

@@ -142,7 +142,8 @@ T* at(void* ws, size_t off) {
 }
 
 vdamp_status check_cnn_ws(const vdamp_plan_t* P, int kind, void* ws, size_t wsb) {
-  if (P->ortho || P->dim3) return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser runs on 2D Haar plans only");
+  if (P->ortho || P->dim3 || P->grp > 1)
+    return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser runs on 2D Haar plans without groups only");
   if (!P->tiles_ok) return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser needs ny and nx multiples of 16");
   if (!ws) return fail(VDAMP_ERR_WORKSPACE, "denoiser workspace is null");
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(VDAMP_ERR_WORKSPACE, "denoiser workspace not 256-byte aligned");
@@ -382,7 +383,8 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
 
 vdamp_status check_cnn(vdamp_cnn_h cnn, vdamp_plan_h plan) {
   if (!cnn || !plan) return fail(VDAMP_ERR_ARG, "denoiser and plan must be non-null");
-  if (plan->ortho || plan->dim3) return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser runs on 2D Haar plans only");
+  if (plan->ortho || plan->dim3 || plan->grp > 1)
+    return fail(VDAMP_ERR_UNSUPPORTED, "the learned denoiser runs on 2D Haar plans without groups only");
   if (cnn->nb != plan->nbands)
     return fail(VDAMP_ERR_ARG, "denoiser built for " + std::to_string(cnn->nb) + " bands, plan has " +
                                    std::to_string(plan->nbands));

@@ -420,6 +420,31 @@ __device__ __forceinline__ float2 rtilde_c(float2 v, float th, float th2, float 
   return make_float2((w.x - al * v.x) * inv, (w.y - al * v.y) * inv);
 }
 
+// Group soft thresholding of a horizontal pair g = (u, v) of one subband row (the
+// structured-sparsity denoiser): both shrink by max(0, 1 - theta/||g||), and the pair is
+// zeroed when its key |u|^2 + |v|^2 (key_rn of each, the sum rounded to nearest) is at
+// most th2, the threshold's own key.
+__device__ __forceinline__ float key_pair_rn(float2 u, float2 v) { return key_rn(u) + key_rn(v); }
+__device__ __forceinline__ void soft_pair(float2& u, float2& v, float th, float th2) {
+  const float key = key_pair_rn(u, v);
+  if (!(key > th2)) {
+    u = make_float2(0.f, 0.f);
+    v = make_float2(0.f, 0.f);
+    return;
+  }
+  const float g = 1.0f - th / sqrtf(key);
+  u = make_float2(u.x * g, u.y * g);
+  v = make_float2(v.x * g, v.y * g);
+}
+// line 8 for the pair: (eta(g) - alpha g) / (1 - alpha)
+__device__ __forceinline__ void rtilde_pair(float2& u, float2& v, float th, float th2, float al) {
+  float2 wu = u, wv = v;
+  soft_pair(wu, wv, th, th2);
+  const float inv = 1.0f / (1.0f - al);
+  u = make_float2((wu.x - al * u.x) * inv, (wu.y - al * u.y) * inv);
+  v = make_float2((wv.x - al * v.x) * inv, (wv.y - al * v.y) * inv);
+}
+
 // line 8 for a general denoiser output w: (w - alpha r) / (1 - alpha)
 __device__ __forceinline__ float2 rtilde_w(float2 w, float2 v, float al) {
   const float inv = 1.0f / (1.0f - al);

@@ -101,6 +101,7 @@ struct vdamp_plan_t {
   // general orthonormal wavelet (plans made with a filter): lowpass filter, complex filter
   // responses, group-row and image-row work lists, LDS sizes of its passes
   bool ortho = false;
+  int grp = 1;  // coefficients per thresholding group (VDAMP_FLAG_GROUP_PAIRS: 2)
   std::vector<double> filt;
   float2* d_resp = nullptr;
   int2* d_work_orows = nullptr;
@@ -319,6 +320,7 @@ inline KArgs base_args(const vdamp_plan_t* P, const Ws& w) {
   a.tau = w.tau;
   a.tau_part = w.taup;
   a.sure_cont = (P->flags & VDAMP_FLAG_SURE_CONTINUOUS) ? 1 : 0;
+  a.grp = P->grp;
   a.resp = P->d_resp;
   a.Z = w.Z;
   return a;

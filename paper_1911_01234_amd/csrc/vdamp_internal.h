@@ -62,7 +62,9 @@ enum RowSynthMode : int {
   RS_PLAIN = 2,    // r as is (FISTA momentum iterate; learned denoiser input)
   RS_RTILDE_L = 3, // line 8 with the learned denoiser where the judge chose it (sel = 1)
   RS_WHAT_L = 4,   // line 6 output with the learned denoiser where chosen
-  RS_PROBE = 5     // the Rademacher probe b of the divergence estimate (no input read)
+  RS_PROBE = 5,    // the Rademacher probe b of the divergence estimate (no input read)
+  RS_RTILDE_G = 6, // RS_RTILDE with group soft thresholding of horizontal pairs
+  RS_WHAT_G = 7    // RS_WHAT with group soft thresholding of horizontal pairs
 };
 
 // Modes of the column k-space pass.
@@ -83,7 +85,8 @@ enum RowAnalMode : int {
   RA_IMAGE = 2,        // no wavelet: write the image rows (line 10 output)
   RA_FISTA = 3,        // w = eta(v + g; lambda); v' = w + beta (w - w_prev)
   RA_FISTA_FIRST = 4,
-  RA_LEARNED = 5       // as RA_VDAMP with r_tilde from the judged denoiser (RS_RTILDE_L)
+  RA_LEARNED = 5,      // as RA_VDAMP with r_tilde from the judged denoiser (RS_RTILDE_L)
+  RA_VDAMP_G = 6       // as RA_VDAMP with r_tilde from group soft thresholding of pairs
 };
 
 // Extra modes of the general-wavelet passes (Psi and Psi^H on their own).
@@ -130,6 +133,7 @@ struct KArgs {
   float beta;                // FISTA momentum factor for this iteration
   int mode;
   int sure_cont;             // threshold search over every theta > 0, not only the keys
+  int grp;                   // coefficients per thresholding group: 1, or 2 (horizontal pairs)
   // general orthonormal wavelets
   const float2* resp;        // filter responses (SliceDev yresp_off / xresp_off)
   float2* Z;                 // group rows: every band's row DFT times its x filter response

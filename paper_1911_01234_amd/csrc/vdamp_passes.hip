@@ -88,6 +88,10 @@ __global__ void __launch_bounds__(NT) k_rows_synth(KArgs a, int do_fft) {
       } else if (mode == RS_PROBE) {
         x0 = probe_c(a.seed, a.iter, item.x, gi[u]);
         x1 = probe_c(a.seed, a.iter, item.x, gi[u] + 1);
+      } else if (mode == RS_RTILDE_G) {  // (x0, x1): a pair x = 2j, 2j + 1 of one band row
+        rtilde_pair(x0, x1, th_s[b], t2_s[b], al_s[b]);
+      } else if (mode == RS_WHAT_G) {
+        soft_pair(x0, x1, th_s[b], t2_s[b]);
       }
       lds4[p] = pack4(x0, x1);  // LDS index lr * nx + lc = 2 p
     }
@@ -578,7 +582,7 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
   float2* r2 = a.r2 ? a.r2 + S.off : nullptr;
   const float lam = a.lambda ? a.lambda[item.x] : 0.f;
   const float lam2 = __fmul_rn(lam, lam);
-  const bool need_r = (mode == RA_VDAMP || mode == RA_FISTA || mode == RA_LEARNED);
+  const bool need_r = (mode == RA_VDAMP || mode == RA_VDAMP_G || mode == RA_FISTA || mode == RA_LEARNED);
   int gi[U];  // offset in the slice
   int bnd[U];
   float4 ro[U], rw[U];
@@ -630,6 +634,12 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
     if (p < npairs) {
       const int b = bnd[u];
       const float4 gv = lds4[p];
+      if (mode == RA_VDAMP_G) {  // r_tilde of the pair x = 2j, 2j + 1 (line 8), + coefficients
+        float2 x0 = lo2(ro[u]), x1 = hi2(ro[u]);
+        rtilde_pair(x0, x1, th_s[b], t2_s[b], al_s[b]);
+        *reinterpret_cast<float4*>(r + gi[u]) = pack4(cadd(x0, lo2(gv)), cadd(x1, hi2(gv)));
+        continue;
+      }
       float2 o[2], w2[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {

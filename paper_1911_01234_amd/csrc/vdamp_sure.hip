@@ -110,17 +110,19 @@ __device__ __forceinline__ SureBest sure_none() {
 
 // Continuous search inside an open interval between keys klo < khi holding m keys at or
 // below it, with A = sum of those keys and R = sum of 1/a above: SURE is the convex
-// quadratic A - m tau + (N_b - m)(theta^2 + tau) - tau theta R, minimised at
-// theta* = tau R / (2 (N_b - m)); it counts when sqrt(klo) < theta* < sqrt(khi).  Its key
+// quadratic A - m tl + (N_b - m)(theta^2 + tl) - td theta R, minimised at
+// theta* = td R / (2 (N_b - m)); it counts when sqrt(klo) < theta* < sqrt(khi).  Its key
 // is fl(theta*)^2 kept inside [klo, khi) so that thresholding keeps exactly the keys
-// above the interval.
-__device__ __forceinline__ void sure_inner(float klo, float khi, double A, int m, double R, double tau,
-                                           double Nbd, SureBest& best) {
+// above the interval.  For single coefficients tl = td = tau; for groups of d
+// coefficients (keys = squared group norms, N_b = the number of groups) tl = d tau and
+// td = (2d - 1) tau: Stein's estimate over the group's 2d real dimensions.
+__device__ __forceinline__ void sure_inner(float klo, float khi, double A, int m, double R, double tl,
+                                           double td, double Nbd, SureBest& best) {
   const double nm = Nbd - (double)m;
   if (!(nm > 0.0) || !(R > 0.0)) return;
-  const double t = tau * R / (2.0 * nm);
+  const double t = td * R / (2.0 * nm);
   if (!(t > sqrt((double)klo)) || !(t < sqrt((double)khi))) return;
-  const double v = A - (double)m * tau + nm * (t * t + tau) - tau * t * R;
+  const double v = A - (double)m * tl + nm * (t * t + tl) - td * t * R;
   if (!sure_better(v, m, 1, best)) return;
   const float tf = (float)t;
   float key = __fmul_rn(tf, tf);
@@ -137,12 +139,13 @@ __device__ __forceinline__ void sure_inner(float klo, float khi, double A, int m
 // SURE at every candidate of the sorted keys: each thread walks a contiguous chunk with
 // a = sqrt(key), A_m = sum_{i<=m} a_i^2 and R_m = sum_{i>m} 1/a_i (FP64 accumulation of
 // FP32 terms, chunk offsets from FP64 prefix/suffix scans) and evaluates
-// SURE(m) = A_m - m tau + (N_b - m)(a_m^2 + tau) - tau a_m R_m at the last index of each
-// run of equal keys with a > 0; with cont, also the quadratic's minimum inside every
-// interval between distinct keys (sure_inner), from 0 up to the smallest positive key
-// onwards.  Per thread the best (SureBest).
+// SURE(m) = A_m - m tl + (N_b - m)(a_m^2 + tl) - td a_m R_m at the last index of each
+// run of equal keys with a > 0 (tl, td as in sure_inner); with cont, also the
+// quadratic's minimum inside every interval between distinct keys (sure_inner), from 0
+// up to the smallest positive key onwards.  Per thread the best (SureBest).
 template <int NT, bool CONT>
-__device__ void sure_walk_t(const float* sk, int Nb, double tau, double* wsA, double* wsR, SureBest& best) {
+__device__ void sure_walk_t(const float* sk, int Nb, double tl, double td, double* wsA, double* wsR,
+                            SureBest& best) {
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int E = (Nb + NT - 1) / NT;
@@ -171,14 +174,14 @@ __device__ void sure_walk_t(const float* sk, int Nb, double tau, double* wsA, do
     const float k2 = knext;
     knext = (i + 1 < Nb) ? sk[skx(i + 1)] : __builtin_huge_valf();
     if (CONT && k2 > 0.f && !(kprev > 0.f))  // the interval (0, a_i) below the first positive key
-      sure_inner(0.f, k2, A, i, Rrun, tau, Nbd, best);
+      sure_inner(0.f, k2, A, i, Rrun, tl, td, Nbd, best);
     A += (double)k2;
     if (k2 > 0.f) {
       Rrun -= (double)__frsqrt_rn(k2);  // now the sum over indices > i
       if (knext > k2) {                 // last index of a run of equal keys
         const double x = (double)__fsqrt_rn(k2);
         const double m = (double)(i + 1);
-        const double sv = A - m * tau + (Nbd - m) * ((double)k2 + tau) - tau * x * Rrun;
+        const double sv = A - m * tl + (Nbd - m) * ((double)k2 + tl) - td * x * Rrun;
         // a thread's candidates come in increasing m, so without inner thresholds a
         // strictly smaller value is the only way to win
         if (CONT ? sure_better(sv, i + 1, 0, best) : sv < best.v) {
@@ -188,26 +191,27 @@ __device__ void sure_walk_t(const float* sk, int Nb, double tau, double* wsA, do
           best.R = Rrun;
           best.key = k2;
         }
-        if (CONT && i + 1 < Nb) sure_inner(k2, knext, A, i + 1, Rrun, tau, Nbd, best);
+        if (CONT && i + 1 < Nb) sure_inner(k2, knext, A, i + 1, Rrun, tl, td, Nbd, best);
       }
     }
     if (CONT) kprev = k2;
   }
 }
 template <int NT>
-__device__ void sure_walk(const float* sk, int Nb, double tau, bool cont, double* wsA, double* wsR,
+__device__ void sure_walk(const float* sk, int Nb, double tl, double td, bool cont, double* wsA, double* wsR,
                           SureBest& best) {
   if (cont)
-    sure_walk_t<NT, true>(sk, Nb, tau, wsA, wsR, best);
+    sure_walk_t<NT, true>(sk, Nb, tl, td, wsA, wsR, best);
   else
-    sure_walk_t<NT, false>(sk, Nb, tau, wsA, wsR, best);
+    sure_walk_t<NT, false>(sk, Nb, tl, td, wsA, wsR, best);
 }
 
 // Workgroup argmin of the per-thread bests (sure_better), then theta (sqrt(key) for a
 // key, the continuous minimiser otherwise), its key and alpha = ((N_b - m) - theta R /
 // 2) / N_b (line 7) for the band, and the band's outputs.  No candidate (every key
-// zero): eta = 0, alpha = 0.
-template <int NT>
+// zero): eta = 0, alpha = 0.  With groups of GD coefficients (Nb groups) alpha is half
+// the real divergence per coefficient, (GD (N_b - m) - (2 GD - 1) theta R / 2) / (GD N_b).
+template <int NT, int GD = 1>
 __device__ void sure_finish(const KArgs& a, int sl, int b, int Nb, float tau_f, SureBest best,
                             SureBest* fin) {
   constexpr int NW = NT / 64;
@@ -229,7 +233,7 @@ __device__ void sure_finish(const KArgs& a, int sl, int b, int Nb, float tau_f, 
     SureBest f = fin[0];
     for (int w = 1; w < NW; ++w)
       if (sure_better(fin[w].v, fin[w].m, fin[w].inner, f)) f = fin[w];
-    const double Nbd = (double)Nb, tau = (double)tau_f;
+    const double Nbd = (double)Nb, tau = (double)tau_f, dd = (double)GD;
     const bool none = f.m == 0x7fffffff;
     float th, th2, al;
     if (none) {
@@ -240,10 +244,10 @@ __device__ void sure_finish(const KArgs& a, int sl, int b, int Nb, float tau_f, 
       th2 = f.key;
       th = f.inner ? (float)f.th : __fsqrt_rn(th2);
       const double m = (double)f.m;
-      al = (float)(((Nbd - m) - 0.5 * (double)th * f.R) / Nbd);
+      al = (float)(((Nbd - m) * dd - 0.5 * (2.0 * dd - 1.0) * (double)th * f.R) / (dd * Nbd));
     }
-    if (a.smin)  // every key zero: eta = 0 gives SURE = -N_b tau
-      a.smin[sl * kMaxBands + b] = none ? (float)(-Nbd * tau) : (float)f.v;
+    if (a.smin)  // every key zero: eta = 0 gives SURE = -N_b tau per coefficient
+      a.smin[sl * kMaxBands + b] = none ? (float)(-Nbd * (dd * tau)) : (float)f.v;
     a.theta[sl * kMaxBands + b] = th;
     a.thr2[sl * kMaxBands + b] = th2;
     a.alpha[sl * kMaxBands + b] = al;
@@ -289,7 +293,9 @@ constexpr int sure_smem_words(int NB, int MAXK, int KPT) {
                            : NB + 1 + MAXK + MAXK / 16 + 1;
 }
 
-template <int NT, int KPT, int NB, int MAXK>
+// GD = 2: keys are the squared norms of horizontal pairs (VDAMP_FLAG_GROUP_PAIRS, slices
+// only), N_b the number of pairs.
+template <int NT, int KPT, int NB, int MAXK, int GD>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sure_waves(NT, KPT))))
 k_sure(KArgs a) {
   static_assert(NT * KPT >= MAXK, "keys per thread");
@@ -310,7 +316,7 @@ k_sure(KArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   int d0, r0, c0, bd, bh, bw;
   band_geom3(b, s, S.nd, S.ny, S.nx, d0, r0, c0, bd, bh, bw);
-  const int Nb = bd * bh * bw;
+  const int Nb = bd * bh * bw / GD;
   int npad = 1;
   while (npad < Nb) npad <<= 1;
 
@@ -328,7 +334,19 @@ k_sure(KArgs a) {
   const int lbw = 31 - __clz(bw);  // band widths are powers of two times 1, 3 or 5
   const bool pow2 = (bw & (bw - 1)) == 0;
   float kk[KPT];
-  if (bd == 1) {  // a slice's band (the branch stays outside the unrolled loads)
+  if constexpr (GD == 2) {  // pairs x = 2j, 2j + 1 of a slice's band rows (bw is even)
+    const int lbp = lbw - 1, bwp = bw >> 1;
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      const int i = tid + j * NT;
+      kk[j] = 0.f;
+      if (i < Nb) {
+        const int rr = pow2 ? (i >> lbp) : i / bwp;
+        const float4 v = *reinterpret_cast<const float4*>(r + (long long)rr * S.nx + 2 * (i - rr * bwp));
+        kk[j] = key_pair_rn(lo2(v), hi2(v));
+      }
+    }
+  } else if (bd == 1) {  // a slice's band (the branch stays outside the unrolled loads)
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const int i = tid + j * NT;
@@ -499,8 +517,8 @@ k_sure(KArgs a) {
     }
   }
   SureBest best;
-  sure_walk<NT>(sk, Nb, (double)tau_sh, a.sure_cont != 0, wsA, wsR, best);
-  sure_finish<NT>(a, sl, b, Nb, tau_sh, best, fin);
+  sure_walk<NT>(sk, Nb, GD * (double)tau_sh, (2 * GD - 1) * (double)tau_sh, a.sure_cont != 0, wsA, wsR, best);
+  sure_finish<NT, GD>(a, sl, b, Nb, tau_sh, best, fin);
 }
 
 // In-place ascending sort of the keys sk[skx(0 .. Nb)) by a bitonic network whose
@@ -560,7 +578,7 @@ constexpr int kSureBigMaxSeg = 256;       // surviving buckets
 constexpr int kSureBigCap = 6144;         // surviving keys
 constexpr int kSureBigNB = 3072;
 
-template <int NT, int NB, int CAP>
+template <int NT, int NB, int CAP, int GD>
 __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ scratch, int stride) {
   constexpr int NW = NT / 64, BPT = NB / NT;
   static_assert(NB % NT == 0, "buckets per thread");
@@ -586,10 +604,10 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   int d0, r0, c0, bd, bh, bw;
   band_geom3(b, s, S.nd, S.ny, S.nx, d0, r0, c0, bd, bh, bw);
-  const int Nb = bd * bh * bw;
+  const int Nb = bd * bh * bw / GD;  // keys: coefficients, or pairs x = 2j, 2j + 1
   const float2* r = a.r + S.off + ((long long)d0 * S.ny + r0) * S.nx + c0;
   const BandWalk bwk = band_walk(bd, bh, bw, S.ny, S.nx);
-#define KEY_AT(i) key_rn(r[bwk.at(i)])
+#define KEY_AT(i) (GD == 2 ? key_pair_rn(r[bwk.at(2 * (i))], r[bwk.at(2 * (i)) + 1]) : key_rn(r[bwk.at(i)]))
   for (int i = tid; i < NB; i += NT) {
     cnt[i] = 0;
     kmn[i] = 0x7f800000;
@@ -608,6 +626,7 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
   __syncthreads();
   const float inv_tau = 1.0f / tau_sh;
   const double tau = (double)tau_sh;
+  const double tl = GD * tau, td = (2 * GD - 1) * tau;  // sure_inner
   for (int i = tid; i < Nb; i += NT) {
     const float k = KEY_AT(i);
     const int bk = sure_bucket<NB>(k, inv_tau);
@@ -690,7 +709,7 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
     if (c[q] && kx > 0.f) {
       const double m = (double)(Pq[q] + c[q]);
       const double x = (double)__fsqrt_rn(kx);
-      endv[q] = (Abq[q] + dA[q]) - m * tau + (Nbd - m) * ((double)kx + tau) - tau * x * Raq[q];
+      endv[q] = (Abq[q] + dA[q]) - m * tl + (Nbd - m) * ((double)kx + tl) - td * x * Raq[q];
       umin = fmin(umin, endv[q]);
     }
   }
@@ -706,7 +725,7 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
   }
   __syncthreads();
   const double ustar = ustar_sh;
-  const double margin = 1e-9 * (fabs(ustar) + Nbd * tau + mag_sh) + 1e-300;
+  const double margin = 1e-9 * (fabs(ustar) + Nbd * tl + mag_sh) + 1e-300;
   bool surv[BPT];
   int ssum = 0, nseg = 0, big = 0;
 #pragma unroll
@@ -725,8 +744,8 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
       for (int e2 = 0; e2 < 2; ++e2) {
         const int t = e2 ? c[q] - 1 : 1;
         const double m = (double)(Pq[q] + t);
-        lb = fmin(lb, Abq[q] + t * kminA - m * tau + (Nbd - m) * (kminA + tau) -
-                          tau * sx * (Raq[q] + (c[q] - t) * rmax));
+        lb = fmin(lb, Abq[q] + t * kminA - m * tl + (Nbd - m) * (kminA + tl) -
+                          td * sx * (Raq[q] + (c[q] - t) * rmax));
       }
       sv = sv || lb <= ustar + margin;
     }
@@ -833,7 +852,7 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
             const double Am = A + pa, Rm = R - pr;
             const double xx = (double)__fsqrt_rn(k2);
             const double m = (double)(P0 + l + 1);
-            const double sv = Am - m * tau + (Nbd - m) * ((double)k2 + tau) - tau * xx * Rm;
+            const double sv = Am - m * tl + (Nbd - m) * ((double)k2 + tl) - td * xx * Rm;
             if (sure_better(sv, P0 + l + 1, 0, best)) {
               best.v = sv;
               best.m = P0 + l + 1;
@@ -855,10 +874,10 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
     for (int i = tid; i < Nb; i += NT) sk[skx(i)] = KEY_AT(i);
     __syncthreads();
     sure_bitonic<NT>(sk, Nb, npad);
-    sure_walk<NT>(sk, Nb, tau, a.sure_cont != 0, wsA, wsR, best);
+    sure_walk<NT>(sk, Nb, tl, td, a.sure_cont != 0, wsA, wsR, best);
   }
 #undef KEY_AT
-  sure_finish<NT>(a, sl, b, Nb, tau_sh, best, fin);
+  sure_finish<NT, GD>(a, sl, b, Nb, tau_sh, best, fin);
 }
 
 // Size classes: up to 4096 keys (0: 256 threads x 16 keys, 2560 buckets; 1: 512 x 8,
@@ -868,18 +887,25 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
 // class 0 and bands of 2049-16384 keys class 2 (measured faster than classes 0 and 1 on
 // 4096-key bands of VDAMP iterates; class 1 is left to the plan-time tuner).  All LDS is static: the largest class uses about
 // 158 KB of the 160 KB a gfx950 workgroup may hold.
-hipError_t launch_sure(const KArgs& a, int cls, float* scratch, hipStream_t st) {
+template <int GD>
+static void launch_sure_t(const KArgs& a, int cls, float* scratch, hipStream_t st) {
   if (cls == kSureBigClass)
-    hipLaunchKernelGGL((k_sure_big<1024, kSureBigNB, kSureBigCap>), dim3(a.nwork), dim3(1024), 0, st, a,
+    hipLaunchKernelGGL((k_sure_big<1024, kSureBigNB, kSureBigCap, GD>), dim3(a.nwork), dim3(1024), 0, st, a,
                        scratch, kSureBigStride);
   else if (cls == 3)
-    hipLaunchKernelGGL((k_sure<1024, 32, 10240, kSureMaxKeys>), dim3(a.nwork), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL((k_sure<1024, 32, 10240, kSureMaxKeys, GD>), dim3(a.nwork), dim3(1024), 0, st, a);
   else if (cls == 2)
-    hipLaunchKernelGGL((k_sure<1024, 16, 19456, 4 * kSureSmall>), dim3(a.nwork), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL((k_sure<1024, 16, 19456, 4 * kSureSmall, GD>), dim3(a.nwork), dim3(1024), 0, st, a);
   else if (cls == 1)
-    hipLaunchKernelGGL((k_sure<512, 8, 5120, kSureSmall>), dim3(a.nwork), dim3(512), 0, st, a);
+    hipLaunchKernelGGL((k_sure<512, 8, 5120, kSureSmall, GD>), dim3(a.nwork), dim3(512), 0, st, a);
   else
-    hipLaunchKernelGGL((k_sure<256, 16, 2560, kSureSmall>), dim3(a.nwork), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_sure<256, 16, 2560, kSureSmall, GD>), dim3(a.nwork), dim3(256), 0, st, a);
+}
+hipError_t launch_sure(const KArgs& a, int cls, float* scratch, hipStream_t st) {
+  if (a.grp == 2)
+    launch_sure_t<2>(a, cls, scratch, st);
+  else
+    launch_sure_t<1>(a, cls, scratch, st);
   return hipGetLastError();
 }
 

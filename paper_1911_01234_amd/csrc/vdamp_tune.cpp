@@ -105,11 +105,11 @@ hipError_t autotune(vdamp_plan_t* P) {
       KArgs a = base;
       a.work = P->d_work_rows + g[0];
       a.nwork = g[1];
-      a.mode = RS_RTILDE;
+      a.mode = P->grp > 1 ? RS_RTILDE_G : RS_RTILDE;
       hipError_t r = m ? launch_rows_synth4(a, m, rows4_lds_bytes(m, H), T.st)
                        : launch_rows_synth(a, P->ept, 1, P->lds_rows, T.st);
       if (r != hipSuccess) return r;
-      a.mode = RA_VDAMP;
+      a.mode = P->grp > 1 ? RA_VDAMP_G : RA_VDAMP;
       return m ? launch_rows_anal4(a, m, rows4_lds_bytes(m, H), T.st) : launch_rows_anal(a, P->ept, P->lds_rows, T.st);
     };
     double t4 = 0, ts = 0;
@@ -146,7 +146,7 @@ hipError_t autotune(vdamp_plan_t* P) {
   for (int b = 0; b < P->B; ++b)
     for (int band = 0; band < P->nbands; ++band) {
       const int l = band == 0 ? P->levels : P->levels - (band - 1) / 3;
-      by_size[(long long)(P->ny[b] >> l) * (P->nx[b] >> l)].push_back(make_int2(b, band));
+      by_size[(long long)(P->ny[b] >> l) * (P->nx[b] >> l) / P->grp].push_back(make_int2(b, band));
     }
   size_t most = 0;
   for (auto& kv : by_size) most = std::max(most, kv.second.size());

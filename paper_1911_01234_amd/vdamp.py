@@ -25,6 +25,7 @@ VDAMP_FLAG_USE_GRAPH = 1 << 3
 VDAMP_FLAG_TIMING = 1 << 5
 VDAMP_FLAG_AUTOTUNE = 1 << 6
 VDAMP_FLAG_SURE_CONTINUOUS = 1 << 7
+VDAMP_FLAG_GROUP_PAIRS = 1 << 8
 VDAMP_NOALLOC_MAX_WORKSPACE = 64 << 20
 PASS_NAMES = ("prep", "rows_synth", "cols", "rows_anal", "sure", "denoiser", "cnn")
 VDAMP_CNN_WS_FORWARD = 0

@@ -148,23 +148,41 @@ def key32(r):
     return (x * x + y * y).astype(np.float32)
 
 
-def snap_theta(r_band, theta_gpu):
+def group_keys32(r_band, d=1):
+    """The kernels' keys of a band block: key32 per coefficient (d = 1), or per
+    horizontal pair x = 2j, 2j+1 (d = 2) the FP32 sum of the two coefficients' keys."""
+    k = key32(r_band)
+    if d == 1:
+        return k
+    return (k[:, 0::2] + k[:, 1::2]).astype(np.float32)
+
+
+def group_mags(r_band, d=1):
+    """FP64 magnitudes of a band block's thresholding units: |r| per coefficient, or the
+    norm of each horizontal pair."""
+    r = np.asarray(r_band, dtype=np.complex128)
+    if d == 1:
+        return np.abs(r)
+    return np.sqrt(np.abs(r[:, 0::2]) ** 2 + np.abs(r[:, 1::2]) ** 2)
+
+
+def snap_theta(r_band, theta_gpu, d=1):
     """The FP64 candidate magnitude nearest to a threshold the GPU took on its FP32
     keys (used only to tell whether two trajectories chose the same element)."""
-    a = np.unique(np.abs(np.asarray(r_band, dtype=np.complex128)).ravel())
+    a = np.unique(group_mags(r_band, d).ravel())
     if float(theta_gpu) == 0.0:
         return 0.0
     i = int(np.argmin(np.abs(a - float(theta_gpu))))
     return float(a[i])
 
 
-def theta_keys(r_band, theta_gpu):
+def theta_keys(r_band, theta_gpu, d=1):
     """Keys (FP32 squared magnitudes) the GPU's theta may stand for.  The kernel decides
     on keys and reports theta = sqrt(key) in FP32, which its sqrt can leave one ulp off
     the correctly rounded value, so the candidates are the keys whose FP32 square root
     is within one ulp of theta (two keys one ulp apart can both qualify); the nearest
     key if none does."""
-    k = np.unique(key32(r_band).ravel())
+    k = np.unique(group_keys32(r_band, d).ravel())
     if float(theta_gpu) == 0.0:
         return [0.0]
     t = np.float32(theta_gpu)
@@ -182,13 +200,16 @@ def theta_key(r_band, theta_gpu):
     return theta_keys(r_band, theta_gpu)[0]
 
 
-def sure_scan(a, tau):
+def sure_scan(a, tau, d=1):
     """SURE of complex soft thresholding at every candidate threshold, evaluated
     directly from its definition (Stein's estimate for noise CN(0, tau)):
         SURE(theta) = sum_{a_i <= theta} (a_i^2 - tau)
                       + sum_{a_i > theta} (theta^2 + tau - tau theta / a_i),
     for the candidates theta = the distinct positive magnitudes.  Written here for the
     validity check of a GPU result on the GPU's own data, independently of the oracle.
+    With groups of d coefficients (a = group norms, 2d real dimensions each, noise
+    variance tau/2 in each) Stein's estimate reads
+        sum_{a <= theta} (a^2 - d tau) + sum_{a > theta} (theta^2 + d tau - (2d - 1) tau theta / a).
     Returns (candidates, values)."""
     a = np.sort(np.asarray(a, dtype=np.float64).ravel())
     n = a.size
@@ -199,27 +220,28 @@ def sure_scan(a, tau):
     c2 = np.concatenate([[0.0], np.cumsum(a ** 2)])
     inv = np.where(a > 0, 1.0 / np.where(a > 0, a, 1.0), 0.0)
     cinv = np.concatenate([[0.0], np.cumsum(inv)])
-    s_below = c2[below] - below * tau
+    s_below = c2[below] - below * (d * tau)
     n_above = n - below
     r_above = cinv[n] - cinv[below]
-    vals = s_below + n_above * (cand ** 2 + tau) - tau * cand * r_above
+    vals = s_below + n_above * (cand ** 2 + d * tau) - (2 * d - 1) * tau * cand * r_above
     return cand, vals
 
 
-def theta_accepted(r, tau_b, rs, cs, theta_gpu, alpha_gpu=None, return_key=False):
+def theta_accepted(r, tau_b, rs, cs, theta_gpu, alpha_gpu=None, return_key=False, d=1):
     """Validity of the GPU's threshold on the GPU's own iterate: the SURE argmin is an
     index decided in floating point, so it is taken on the kernel's FP32 keys of that r
     (magnitudes sqrt(key32) in FP64).  The GPU's threshold is accepted when its SURE is
     the minimum over all candidates up to 1e-6 (|SURE_min| + N_b tau) (a near tie).
     Among keys theta may stand for, the one whose alpha (line 7) matches the GPU's
-    alpha is the GPU's choice."""
+    alpha is the GPU's choice.  d = 2: the keys are those of horizontal pairs (group
+    soft thresholding)."""
     band = np.asarray(r)[rs, cs]
-    a = np.sqrt(key32(band).astype(np.float64)).ravel()
-    cand, vals = sure_scan(a, float(tau_b))
+    a = np.sqrt(group_keys32(band, d).astype(np.float64)).ravel()
+    cand, vals = sure_scan(a, float(tau_b), d)
     s_min = float(vals.min())
-    cands = theta_keys(band, theta_gpu)
+    cands = theta_keys(band, theta_gpu, d)
     if alpha_gpu is not None and len(cands) > 1:
-        cands.sort(key=lambda kth: abs(alpha_at_key(band, kth) - float(alpha_gpu)))
+        cands.sort(key=lambda kth: abs(alpha_at_key(band, kth, d) - float(alpha_gpu)))
     ok_key = None
     for kth in cands:
         th = float(np.sqrt(kth))
@@ -227,32 +249,39 @@ def theta_accepted(r, tau_b, rs, cs, theta_gpu, alpha_gpu=None, return_key=False
             ok = cand.size == 1 and cand[0] == 0.0
         else:
             i = int(np.argmin(np.abs(cand - th)))
-            ok = cand[i] == th and vals[i] <= s_min + 1e-6 * (abs(s_min) + a.size * tau_b)
+            ok = cand[i] == th and vals[i] <= s_min + 1e-6 * (abs(s_min) + a.size * d * tau_b)
         if ok:
             ok_key = kth
             break
     return (ok_key is not None, ok_key) if return_key else ok_key is not None
 
 
-def alpha_at_key(r_band, kth):
-    """alpha (line 7) at the threshold with key kth, membership on the FP32 keys."""
-    k = key32(r_band).astype(np.float64).ravel()
+def alpha_at_key(r_band, kth, d=1):
+    """alpha (line 7) at the threshold with key kth, membership on the FP32 keys.  For
+    pairs (d = 2): half the real divergence of group soft thresholding per coefficient,
+    4 - 3 theta/||g|| per pair above the threshold, over 2 N_b."""
+    k = group_keys32(r_band, d).astype(np.float64).ravel()
     keep = k > kth
     th = np.sqrt(kth)
-    return float(np.sum(1.0 - th / (2.0 * np.sqrt(k[keep]))) / k.size)
+    if d == 1:
+        return float(np.sum(1.0 - th / (2.0 * np.sqrt(k[keep]))) / k.size)
+    return float(np.sum(2 * d - (2 * d - 1) * th / np.sqrt(k[keep])) / (2.0 * d * k.size))
 
 
-def sure_min_continuous(a, tau):
+def sure_min_continuous(a, tau, d=1):
     """The minimum over every theta > 0 of complex soft thresholding's SURE on magnitudes
     a (test code written from the definition, independently of the oracle): SURE is a
     quadratic in theta between consecutive distinct magnitudes, n_above (theta^2 + tau)
     - tau theta R_above + const, so its infimum on each interval is at the clipped vertex
-    or the interval's left end (a magnitude, counted below).  Returns the minimum."""
+    or the interval's left end (a magnitude, counted below).  Groups of d coefficients
+    (a = group norms): tau becomes d tau in the first two terms and (2d - 1) tau in the
+    last (sure_scan).  Returns the minimum."""
     a = np.sort(np.asarray(a, dtype=np.float64).ravel())
     n = a.size
+    tl, td = d * tau, (2 * d - 1) * tau
     u = np.unique(a[a > 0])
     if u.size == 0:
-        return -n * tau
+        return -n * tl
     ends = np.concatenate([[0.0], u])
     best = np.inf
     for j in range(u.size):
@@ -261,25 +290,26 @@ def sure_min_continuous(a, tau):
         nb = int(np.sum(~below))
         A = float(np.sum(a[below] ** 2))
         R = float(np.sum(1.0 / a[~below]))
-        c = A - (n - nb) * tau
+        c = A - (n - nb) * tl
         if lo > 0:   # theta = lo itself (a candidate)
-            best = min(best, c + nb * (lo * lo + tau) - tau * lo * R)
-        t = tau * R / (2.0 * nb)
+            best = min(best, c + nb * (lo * lo + tl) - td * lo * R)
+        t = td * R / (2.0 * nb)
         if lo < t < hi:
-            best = min(best, c + nb * (t * t + tau) - tau * t * R)
+            best = min(best, c + nb * (t * t + tl) - td * t * R)
     return best
 
 
-def theta_accepted_continuous(r, tau_b, rs, cs, theta_gpu, thr2_gpu):
+def theta_accepted_continuous(r, tau_b, rs, cs, theta_gpu, thr2_gpu, d=1):
     """The continuous search's threshold on the library's own iterate: the SURE of what
     the kernels apply (coefficients whose FP32 key is at most the threshold's key
     thr2_gpu are zeroed, the others shrunk by theta_gpu), from the definition on the FP32
     keys, is the continuous minimum up to the near-tie margin 1e-6 (|SURE_min| + N_b tau)."""
     band = np.asarray(r)[rs, cs]
-    k = key32(band).astype(np.float64).ravel()
+    k = group_keys32(band, d).astype(np.float64).ravel()
     a = np.sqrt(k)
     th = float(theta_gpu)
     below = k <= float(np.float32(thr2_gpu))
-    v = float(np.sum(a[below] ** 2 - tau_b) + np.sum(th * th + tau_b - tau_b * th / a[~below]))
-    m = sure_min_continuous(a, float(tau_b))
-    return v <= m + 1e-6 * (abs(m) + a.size * tau_b)
+    v = float(np.sum(a[below] ** 2 - d * tau_b)
+              + np.sum(th * th + d * tau_b - (2 * d - 1) * tau_b * th / a[~below]))
+    m = sure_min_continuous(a, float(tau_b), d)
+    return v <= m + 1e-6 * (abs(m) + a.size * d * tau_b)

@@ -108,7 +108,8 @@ def test_plan_accepts_every_documented_flag():
     """All VDAMP_FLAG_* bits pass the host checks together (the autotune flag included);
     an undocumented bit is rejected before anything touches the device."""
     flags = (V.VDAMP_FLAG_DETERMINISTIC | V.VDAMP_FLAG_USE_GRAPH | V.VDAMP_FLAG_CHECK_FINITE
-             | V.VDAMP_FLAG_TIMING | V.VDAMP_FLAG_AUTOTUNE | V.VDAMP_FLAG_SURE_CONTINUOUS)
+             | V.VDAMP_FLAG_TIMING | V.VDAMP_FLAG_AUTOTUNE | V.VDAMP_FLAG_SURE_CONTINUOUS
+             | V.VDAMP_FLAG_GROUP_PAIRS)
     lib = V.load_library()
     h = ctypes.c_void_p()
     wsb = ctypes.c_size_t()
@@ -119,7 +120,7 @@ def test_plan_accepts_every_documented_flag():
         assert lib.vdamp_plan_destroy(h) == 0
     else:
         assert st == 5 and "upload" in msg, msg
-    st, msg = _plan_status(1, [64], [64], 3, 0, 1 << 8)
+    st, msg = _plan_status(1, [64], [64], 3, 0, 1 << 9)
     assert st == 1 and "flag" in msg, msg
 
 
@@ -159,3 +160,21 @@ def test_plan_ortho_rejects_bad_filters_before_any_launch():
     assert _ortho_status(db2, ny=60)[0] == 2
     st, msg = _ortho_status(db2, levels=0)
     assert st == 3 and msg
+
+
+def test_group_pairs_refused_outside_2d_haar_plans():
+    """VDAMP_FLAG_GROUP_PAIRS (joint thresholding of horizontal pairs) is a 2D Haar
+    option: general-wavelet and volume plans refuse it on the host, before anything is
+    allocated; an unknown flag bit above it stays an argument error."""
+    from paper_1911_01234_amd import filters
+    st, msg = _ortho_status(list(filters.daubechies(2)), flags=V.VDAMP_FLAG_GROUP_PAIRS)
+    assert st == 3 and "GROUP_PAIRS" in msg
+    lib = V.load_library()
+    h = ctypes.c_void_p()
+    wsb = ctypes.c_size_t()
+    one = lambda v: (ctypes.c_int32 * 1)(v)
+    st = lib.vdamp_plan_3d(ctypes.byref(h), 1, one(32), one(32), one(32), 2, V.VDAMP_FLAG_GROUP_PAIRS,
+                           ctypes.byref(wsb))
+    assert st == 3 and "GROUP_PAIRS" in lib.vdamp_last_error().decode()
+    st = lib.vdamp_plan(ctypes.byref(h), 1, one(64), one(64), 3, 0, 1 << 9, ctypes.byref(wsb))
+    assert st == 1

@@ -34,8 +34,8 @@ import pytest
 from oracle import vdamp_ref as o
 from paper_1911_01234_amd import synth
 
-from gpu_helpers import (alpha_at_key, fp32_inputs, fp32_state, key32, rel_l2, run_fista, run_resume,
-                         run_vdamp, snap_theta, theta_accepted, theta_accepted_continuous)
+from gpu_helpers import (alpha_at_key, fp32_inputs, fp32_state, group_keys32, group_mags, rel_l2, run_fista,
+                         run_resume, run_vdamp, snap_theta, theta_accepted, theta_accepted_continuous)
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,7 @@ def theta_alpha_tols(r_band, theta, alpha):
     return th_tol, al_tol
 
 
-def fp32_horizon(sl, s, K, ref, realizations=4, step_noise=3e-7, wavelet=None):
+def fp32_horizon(sl, s, K, ref, realizations=4, step_noise=3e-7, wavelet=None, group=1):
     """How long an FP32 evaluation can follow the FP64 trajectory at all: the oracle's
     iteration with only its two FFTs evaluated in FP32 (scipy's complex64 FFT, whose
     one-step error, 3e-7 relative, is that of the library's kernels) against the FP64
@@ -84,7 +84,7 @@ def fp32_horizon(sl, s, K, ref, realizations=4, step_noise=3e-7, wavelet=None):
     S = o.tau_weights(y.shape[0], y.shape[1], s, wavelet)
     om = mask.astype(bool)
     band_list = _bands(sl, s)
-    ref_idx = [[int(np.argmin(np.abs(np.abs(ref["r"][k][rs, cs]).ravel() - ref["theta"][k][b])))
+    ref_idx = [[int(np.argmin(np.abs(group_mags(ref["r"][k][rs, cs], group).ravel() - ref["theta"][k][b])))
                 for b, (rs, cs, _, _) in enumerate(band_list)] for k in range(K)]
     horizon = K
     for real in range(realizations + 1):
@@ -100,11 +100,11 @@ def fp32_horizon(sl, s, K, ref, realizations=4, step_noise=3e-7, wavelet=None):
                 n = rng.standard_normal(r.shape) + 1j * rng.standard_normal(r.shape)
                 r = r + step_noise * np.linalg.norm(r) / np.linalg.norm(n) * n
             tau = o.tau_estimate(z, mask, p, s2, S)
-            _, rt, th, _ = o.denoise(r, tau, s)
+            _, rt, th, _ = o.denoise(r, tau, s, group=group)
             if rel_l2(r, ref["r"][k]) > TOL_ITER / 2:
                 horizon = k
                 break
-            if any(int(np.argmin(np.abs(np.abs(r[rs, cs]).ravel() - th[b]))) != ref_idx[k][b]
+            if any(int(np.argmin(np.abs(group_mags(r[rs, cs], group).ravel() - th[b]))) != ref_idx[k][b]
                    for b, (rs, cs, _, _) in enumerate(band_list)):
                 if not real:
                     horizon = k
@@ -112,8 +112,8 @@ def fp32_horizon(sl, s, K, ref, realizations=4, step_noise=3e-7, wavelet=None):
     return horizon
 
 
-def oracle_run(sl, s, K, record=True, cont=False, wavelet=None):
-    return o.vdamp(*fp32_inputs(sl), s, K, record=record, continuous=cont, wavelet=wavelet)
+def oracle_run(sl, s, K, record=True, cont=False, wavelet=None, group=1):
+    return o.vdamp(*fp32_inputs(sl), s, K, record=record, continuous=cont, wavelet=wavelet, group=group)
 
 
 def test_first_iteration_r0():
@@ -130,14 +130,16 @@ def test_first_iteration_r0():
     assert et <= TOL_TAU
 
 
-def one_step_check(sl, s, ref_k, g, b, k, what="", cont=False, wavelet=None):
+def one_step_check(sl, s, ref_k, g, b, k, what="", cont=False, wavelet=None, group=1):
     """Compare the library's one step (slice b of g) from the FP32-rounded oracle state
     ref_k = (r, theta, alpha) with the oracle's step from the same state.  Returns
     (r error, number of bands decided differently).  With cont (the continuous threshold
     search) theta is compared directly where both land in the same interval between
-    magnitudes (same count m at or below it), else validated on the library's own data."""
+    magnitudes (same count m at or below it), else validated on the library's own data.
+    group = 2: thresholds of horizontal pairs (VDAMP_FLAG_GROUP_PAIRS)."""
     y, mask, p, s2 = fp32_inputs(sl)
-    ref = o.vdamp_resume(y, mask, p, s2, s, *ref_k, 1, record=True, continuous=cont, wavelet=wavelet)
+    ref = o.vdamp_resume(y, mask, p, s2, s, *ref_k, 1, record=True, continuous=cont, wavelet=wavelet,
+                         group=group)
     r_ref = ref["r"][0]
     rg = g["r"][b].astype(np.complex128)
     e = rel_l2(rg, r_ref)
@@ -148,11 +150,11 @@ def one_step_check(sl, s, ref_k, g, b, k, what="", cont=False, wavelet=None):
     flips = 0
     for bb, (rs, cs, _, _) in enumerate(_bands(sl, s)):
         th_g, al_g = float(tr[bb, 1]), float(tr[bb, 2])
-        if cont:  # the same count of coefficients at or below the threshold
-            m_g = int(np.sum(key32(rg[rs, cs]) <= np.float32(g["theta2"][b, bb])))
-            same = m_g == int(np.sum(np.abs(r_ref[rs, cs]) <= ref["theta"][0][bb]))
+        if cont:  # the same count of coefficients (or pairs) at or below the threshold
+            m_g = int(np.sum(group_keys32(rg[rs, cs], group) <= np.float32(g["theta2"][b, bb])))
+            same = m_g == int(np.sum(group_mags(r_ref[rs, cs], group) <= ref["theta"][0][bb]))
         else:
-            same = snap_theta(r_ref[rs, cs], th_g) == ref["theta"][0][bb]
+            same = snap_theta(r_ref[rs, cs], th_g, group) == ref["theta"][0][bb]
         if same:
             th_tol, al_tol = theta_alpha_tols(r_ref[rs, cs], ref["theta"][0][bb], ref["alpha"][0][bb])
             assert abs(th_g - ref["theta"][0][bb]) <= th_tol, (what, k, bb)
@@ -160,29 +162,29 @@ def one_step_check(sl, s, ref_k, g, b, k, what="", cont=False, wavelet=None):
         else:
             flips += 1
             if cont:
-                assert theta_accepted_continuous(rg, float(tr[bb, 0]), rs, cs, th_g, g["theta2"][b, bb]), \
-                    (what, k, bb)
+                assert theta_accepted_continuous(rg, float(tr[bb, 0]), rs, cs, th_g, g["theta2"][b, bb],
+                                                 d=group), (what, k, bb)
             else:
-                assert theta_accepted(rg, float(tr[bb, 0]), rs, cs, th_g, alpha_gpu=al_g), (what, k, bb)
+                assert theta_accepted(rg, float(tr[bb, 0]), rs, cs, th_g, alpha_gpu=al_g, d=group), (what, k, bb)
     if flips == 0:
         ex = rel_l2(g["x_hat"][b], ref["x_hat"])
         assert ex <= TOL_ITER, (what, k, ex)
     return e, et, flips
 
 
-def one_step_every_iteration(sl, s, K, cont=False, wavelet=None):
+def one_step_every_iteration(sl, s, K, cont=False, wavelet=None, group=1):
     """At every k < K: the library's step from the oracle's FP32-rounded state against the
     oracle's step from the same state (wavelet: an orthonormal lowpass filter for a
     vdamp_plan_ortho plan, None for Haar)."""
     from paper_1911_01234_amd import vdamp as V
-    traj = oracle_run(sl, s, K, cont=cont, wavelet=wavelet)
-    plan = V.Plan([sl.y.shape[0]], [sl.y.shape[1]], s, V.VDAMP_FLAG_SURE_CONTINUOUS if cont else 0,
-                  lowpass=wavelet)
+    traj = oracle_run(sl, s, K, cont=cont, wavelet=wavelet, group=group)
+    flags = (V.VDAMP_FLAG_SURE_CONTINUOUS if cont else 0) | (V.VDAMP_FLAG_GROUP_PAIRS if group == 2 else 0)
+    plan = V.Plan([sl.y.shape[0]], [sl.y.shape[1]], s, flags, lowpass=wavelet)
     errs, terrs, nflip = [], [], 0
     for k in range(K - 1):
         st = fp32_state(traj["r"][k], traj["theta"][k], traj["alpha"][k])
         g = run_resume(plan, [sl], {0: st}, 1)
-        e, et, f = one_step_check(sl, s, st, g, 0, k, cont=cont, wavelet=wavelet)
+        e, et, f = one_step_check(sl, s, st, g, 0, k, cont=cont, wavelet=wavelet, group=group)
         errs.append(e)
         terrs.append(et)
         nflip += f
@@ -191,7 +193,7 @@ def one_step_every_iteration(sl, s, K, cont=False, wavelet=None):
     plan.close()
 
 
-def tau_tolerances(sl, s, K, ref, cont=False, wavelet=None):
+def tau_tolerances(sl, s, K, ref, cont=False, wavelet=None, group=1):
     """Per iteration, the relative tau error the 1e-5 iterate gate admits along a
     trajectory: tau (line 5) is quadratic in the residual z = y - Phi Psi^H r_tilde, the
     difference of the measurements and the prediction X = Phi Psi^H r_tilde, so an
@@ -201,14 +203,14 @@ def tau_tolerances(sl, s, K, ref, cont=False, wavelet=None):
     om = mask.astype(bool)
     out = [TOL_TAU_TRAJ]
     for k in range(1, K):
-        _, rt, _, _ = o.denoise(ref["r"][k - 1], ref["tau"][k - 1], s, continuous=cont)
+        _, rt, _, _ = o.denoise(ref["r"][k - 1], ref["tau"][k - 1], s, continuous=cont, group=group)
         X = o.fft2u(o.synthesis(rt, s, wavelet))[om]
         kappa = np.linalg.norm(X) / np.linalg.norm(y[om] - X)
         out.append(max(TOL_TAU_TRAJ, 2.0 * kappa * TOL_ITER))
     return out
 
 
-def free_running(sl, s, K, wavelet=None):
+def free_running(sl, s, K, wavelet=None, group=1):
     """Per iterate: the library's thresholds must be SURE-optimal (up to near ties) for
     its own r_k and tau_k, and its alpha line 7's value at that threshold on that
     iterate (to 1e-6; test code on the library's data).  Up to the first iteration where
@@ -219,23 +221,25 @@ def free_running(sl, s, K, wavelet=None):
     the errors are printed; the one-step gate covers those iterations.  The final NMSE
     must match to 0.05 dB when no flip occurred, else lie within the envelope of
     perturbed oracle runs."""
-    ref = oracle_run(sl, s, K, wavelet=wavelet)
-    hz = fp32_horizon(sl, s, K, ref, wavelet=wavelet)
-    ttol = tau_tolerances(sl, s, K, ref, wavelet=wavelet)
-    g = run_vdamp([sl], s, K, lowpass=wavelet)
+    from paper_1911_01234_amd import vdamp as V
+    flags = V.VDAMP_FLAG_GROUP_PAIRS if group == 2 else 0
+    ref = oracle_run(sl, s, K, wavelet=wavelet, group=group)
+    hz = fp32_horizon(sl, s, K, ref, wavelet=wavelet, group=group)
+    ttol = tau_tolerances(sl, s, K, ref, wavelet=wavelet, group=group)
+    g = run_vdamp([sl], s, K, flags=flags, lowpass=wavelet)
     tr = g["trace"][:, 0]
     errs = []
     first_flip = None
     for k in range(K):
-        gk = run_vdamp([sl], s, k + 1, want_state=True, lowpass=wavelet)
+        gk = run_vdamp([sl], s, k + 1, flags=flags, want_state=True, lowpass=wavelet)
         rg = gk["r"][0].astype(np.complex128)
         e = rel_l2(rg, ref["r"][k])
         errs.append(e)
         pre_flip = first_flip is None
         for b, (rs, cs, _, _) in enumerate(_bands(sl, s)):
             assert theta_accepted(rg, float(gk["tau"][0][b]), rs, cs, tr[k, b, 1],
-                                  alpha_gpu=tr[k, b, 2]), (k, b)
-            if first_flip is None and snap_theta(ref["r"][k][rs, cs], tr[k, b, 1]) != ref["theta"][k][b]:
+                                  alpha_gpu=tr[k, b, 2], d=group), (k, b)
+            if first_flip is None and snap_theta(ref["r"][k][rs, cs], tr[k, b, 1], group) != ref["theta"][k][b]:
                 first_flip = (k, b)
         if pre_flip and k < hz:
             assert e <= TOL_ITER, (k, e)
@@ -243,8 +247,8 @@ def free_running(sl, s, K, wavelet=None):
         for b, (rs, cs, _, _) in enumerate(_bands(sl, s)):
             # alpha of line 7 at the library's own threshold on its own iterate
             ok, kth = theta_accepted(rg, float(gk["tau"][0][b]), rs, cs, tr[k, b, 1],
-                                     alpha_gpu=tr[k, b, 2], return_key=True)
-            assert abs(tr[k, b, 2] - alpha_at_key(rg[rs, cs], kth)) <= 1e-6, (k, b)
+                                     alpha_gpu=tr[k, b, 2], return_key=True, d=group)
+            assert abs(tr[k, b, 2] - alpha_at_key(rg[rs, cs], kth, group)) <= 1e-6, (k, b)
     n_gpu = o.nmse_db(g["x_hat"][0], sl.x0)
     n_ref = o.nmse_db(ref["x_hat"], sl.x0)
     ex = rel_l2(g["x_hat"][0], ref["x_hat"])
@@ -258,19 +262,19 @@ def free_running(sl, s, K, wavelet=None):
         if hz == K:
             assert ex <= TOL_ITER
     elif abs(n_gpu - n_ref) > TOL_NMSE_DB:
-        mean, sd = oracle_nmse_envelope(sl, s, K, n_ref, wavelet=wavelet)
+        mean, sd = oracle_nmse_envelope(sl, s, K, n_ref, wavelet=wavelet, group=group)
         print(f"  oracle envelope under 3e-7 input perturbation: mean {mean:.3f} dB, sd {sd:.3f} dB")
         assert abs(n_gpu - mean) <= max(TOL_NMSE_DB, 4 * sd)
 
 
-def oracle_nmse_envelope(sl, s, K, n_ref, runs=16, eps=3e-7, cont=False, wavelet=None):
+def oracle_nmse_envelope(sl, s, K, n_ref, runs=16, eps=3e-7, cont=False, wavelet=None, group=1):
     y, mask, p, s2 = fp32_inputs(sl)
     rng = np.random.default_rng(2024)
     vals = [n_ref]
     for _ in range(runs):
         pert = (rng.standard_normal(y.shape) + 1j * rng.standard_normal(y.shape)) / np.sqrt(2)
         vals.append(o.nmse_db(o.vdamp(y * (1 + eps * pert), mask, p, s2, s, K, continuous=cont,
-                                      wavelet=wavelet)["x_hat"], sl.x0))
+                                      wavelet=wavelet, group=group)["x_hat"], sl.x0))
     return float(np.mean(vals)), float(np.std(vals))
 
 
