@@ -129,8 +129,10 @@ def other_workloads(stream, reps=3):
     256^2, the ragged batch of 512 slices (128 each of 128^2, 192^2, 256^2, 320^2) and 128
     slices of 512^2 (whose finest bands take the large-band threshold search), each
     planned with the plan-time tuner, and the benchmark's 256 slices of 256^2 with an
-    8-tap Daubechies wavelet instead of Haar (vdamp_plan_ortho, not tuned).  One warm-up
-    solve, then `reps` timed solves of 50 iterations each, eager with per-kernel events."""
+    8-tap Daubechies wavelet instead of Haar (vdamp_plan_ortho, not tuned) and with group
+    soft thresholding of horizontal pairs (VDAMP_FLAG_GROUP_PAIRS, not tuned).  One
+    warm-up solve, then `reps` timed solves of 50 iterations each, eager with per-kernel
+    events."""
     import torch
     from paper_1911_01234_amd import filters, synth, vdamp as V
     res = {}
@@ -139,7 +141,8 @@ def other_workloads(stream, reps=3):
                            ("mixed_512_slices_128_to_320", lambda: synth.workload_mixed(128), None),
                            ("batch_128_slices_512x512", lambda: synth.workload_batch512(128), None),
                            ("db4_wavelet_256_slices_256x256", lambda: synth.workload_batch256(256),
-                            filters.daubechies(4))):
+                            filters.daubechies(4)),
+                           ("pair_groups_256_slices_256x256", lambda: synth.workload_batch256(256), "pairs")):
         t = time.perf_counter()
         slices, s, K = gen()
         tg = time.perf_counter() - t
@@ -148,8 +151,11 @@ def other_workloads(stream, reps=3):
         npx = int(sum(u * v for u, v in zip(ny, nx)))
         with torch.cuda.stream(stream):
             t = time.perf_counter()
-            tune = V.VDAMP_FLAG_AUTOTUNE if low is None else 0
-            plan = V.Plan(ny, nx, s, V.VDAMP_FLAG_TIMING | tune, lowpass=low)
+            grp = V.VDAMP_FLAG_GROUP_PAIRS if isinstance(low, str) else 0
+            if grp:
+                low = None
+            tune = V.VDAMP_FLAG_AUTOTUNE if (low is None and not grp) else 0
+            plan = V.Plan(ny, nx, s, V.VDAMP_FLAG_TIMING | tune | grp, lowpass=low)
             t_plan = time.perf_counter() - t
             desc = plan.describe()
             ws = plan.workspace()
@@ -169,7 +175,7 @@ def other_workloads(stream, reps=3):
             nm = float(nmse_db_batch(xh, x0, seg, len(slices)).mean())
             plan.close()
             # the same solves captured once in a hipGraph (VDAMP_FLAG_USE_GRAPH) and replayed
-            gplan = V.Plan(ny, nx, s, V.VDAMP_FLAG_USE_GRAPH | tune, lowpass=low)
+            gplan = V.Plan(ny, nx, s, V.VDAMP_FLAG_USE_GRAPH | tune | grp, lowpass=low)
             gws = gplan.workspace()
             gx = torch.empty_like(xh)
             gplan.vdamp_solve(gws, y, mask, p, sigma2, K, gx, stream=stream)
@@ -191,6 +197,7 @@ def other_workloads(stream, reps=3):
                                   "bitwise_equal_to_eager": gsame},
                      "nmse_db_mean": round(nm, 3),
                      "passes": pass_rooflines(times, npx, K, reps, None if low is None else ortho_bytes(s)),
+                     "flags": "group_pairs" if grp else None,
                      "plan_seconds_with_autotune": round(t_plan, 3),
                      "autotune": desc[desc.index("autotune:") + 10:] if "autotune:" in desc else None}
         print(f"[bench] {name}: generated in {tg:.1f} s, {res[name]['slice_iterations_per_s']} slice-it/s",
