@@ -406,18 +406,23 @@ __device__ __forceinline__ float key_rn(float2 v) {
 
 // eta(r; theta) = r max(0, 1 - theta/|r|); zero when |r|^2 <= theta^2 (th2 is the
 // threshold's own key, so the element that defines theta is zeroed).
+// The shrink factor takes theta times the hardware reciprocal square root of the key
+// (within an ulp or two of 1/|r|), not an IEEE square root and division.
 __device__ __forceinline__ float2 soft_c(float2 v, float th, float th2) {
   const float key = key_rn(v);
   if (!(key > th2)) return make_float2(0.f, 0.f);
-  const float g = 1.0f - th / sqrtf(key);
+  const float g = 1.0f - th * rsqrtf(key);
   return make_float2(v.x * g, v.y * g);
 }
 
-// line 8: r_tilde = (eta(r) - alpha r) / (1 - alpha)
-__device__ __forceinline__ float2 rtilde_c(float2 v, float th, float th2, float al) {
+// line 8: r_tilde = (eta(r) - alpha r) / (1 - alpha), with inv = 1 / (1 - alpha) of the
+// band computed once (the same IEEE quotient rtilde_c forms per coefficient)
+__device__ __forceinline__ float2 rtilde_ci(float2 v, float th, float th2, float al, float inv) {
   const float2 w = soft_c(v, th, th2);
-  const float inv = 1.0f / (1.0f - al);
   return make_float2((w.x - al * v.x) * inv, (w.y - al * v.y) * inv);
+}
+__device__ __forceinline__ float2 rtilde_c(float2 v, float th, float th2, float al) {
+  return rtilde_ci(v, th, th2, al, 1.0f / (1.0f - al));
 }
 
 // Group soft thresholding of a horizontal pair g = (u, v) of one subband row (the
@@ -432,15 +437,14 @@ __device__ __forceinline__ void soft_pair(float2& u, float2& v, float th, float 
     v = make_float2(0.f, 0.f);
     return;
   }
-  const float g = 1.0f - th / sqrtf(key);
+  const float g = 1.0f - th * rsqrtf(key);
   u = make_float2(u.x * g, u.y * g);
   v = make_float2(v.x * g, v.y * g);
 }
-// line 8 for the pair: (eta(g) - alpha g) / (1 - alpha)
-__device__ __forceinline__ void rtilde_pair(float2& u, float2& v, float th, float th2, float al) {
+// line 8 for the pair: (eta(g) - alpha g) / (1 - alpha), inv = 1 / (1 - alpha)
+__device__ __forceinline__ void rtilde_pair(float2& u, float2& v, float th, float th2, float al, float inv) {
   float2 wu = u, wv = v;
   soft_pair(wu, wv, th, th2);
-  const float inv = 1.0f / (1.0f - al);
   u = make_float2((wu.x - al * u.x) * inv, (wu.y - al * u.y) * inv);
   v = make_float2((wv.x - al * v.x) * inv, (wv.y - al * v.y) * inv);
 }

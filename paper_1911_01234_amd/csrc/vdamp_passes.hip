@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(NT) k_rows_synth(KArgs a, int do_fft) {
   extern __shared__ float4 lds4[];
   float2* lds = reinterpret_cast<float2*>(lds4);
   __shared__ float2 tw_s[kMaxN];
-  __shared__ float th_s[kMaxBands], t2_s[kMaxBands], al_s[kMaxBands];
+  __shared__ float th_s[kMaxBands], t2_s[kMaxBands], al_s[kMaxBands], ia_s[kMaxBands];
   const int2 item = a.work[blockIdx.x];
   const SliceDev S = a.slices[item.x];
   const int strip = item.y, s = a.levels, H = 1 << s, nx = S.nx, ny = S.ny;
@@ -31,6 +31,7 @@ __global__ void __launch_bounds__(NT) k_rows_synth(KArgs a, int do_fft) {
     th_s[tid] = a.theta[item.x * kMaxBands + tid];
     t2_s[tid] = a.thr2[item.x * kMaxBands + tid];
     al_s[tid] = a.alpha[item.x * kMaxBands + tid];
+    ia_s[tid] = 1.0f / (1.0f - al_s[tid]);
   }
   const FftPlanDev& P = a.ffts[S.fft_x];
   if (do_fft) load_twiddles<NT>(tw_s, P, a.twiddles);
@@ -69,8 +70,8 @@ __global__ void __launch_bounds__(NT) k_rows_synth(KArgs a, int do_fft) {
       const int b = bnd[u];
       float2 x0 = lo2(v[u]), x1 = hi2(v[u]);
       if (mode == RS_RTILDE) {
-        x0 = rtilde_c(x0, th_s[b], t2_s[b], al_s[b]);
-        x1 = rtilde_c(x1, th_s[b], t2_s[b], al_s[b]);
+        x0 = rtilde_ci(x0, th_s[b], t2_s[b], al_s[b], ia_s[b]);
+        x1 = rtilde_ci(x1, th_s[b], t2_s[b], al_s[b], ia_s[b]);
       } else if (mode == RS_WHAT) {
         x0 = soft_c(x0, th_s[b], t2_s[b]);
         x1 = soft_c(x1, th_s[b], t2_s[b]);
@@ -79,8 +80,8 @@ __global__ void __launch_bounds__(NT) k_rows_synth(KArgs a, int do_fft) {
           x0 = rtilde_w(lo2(c4[u]), x0, al_s[b]);
           x1 = rtilde_w(hi2(c4[u]), x1, al_s[b]);
         } else {
-          x0 = rtilde_c(x0, th_s[b], t2_s[b], al_s[b]);
-          x1 = rtilde_c(x1, th_s[b], t2_s[b], al_s[b]);
+          x0 = rtilde_ci(x0, th_s[b], t2_s[b], al_s[b], ia_s[b]);
+          x1 = rtilde_ci(x1, th_s[b], t2_s[b], al_s[b], ia_s[b]);
         }
       } else if (mode == RS_WHAT_L) {
         x0 = sel_s[b] ? lo2(c4[u]) : soft_c(x0, th_s[b], t2_s[b]);
@@ -89,7 +90,7 @@ __global__ void __launch_bounds__(NT) k_rows_synth(KArgs a, int do_fft) {
         x0 = probe_c(a.seed, a.iter, item.x, gi[u]);
         x1 = probe_c(a.seed, a.iter, item.x, gi[u] + 1);
       } else if (mode == RS_RTILDE_G) {  // (x0, x1): a pair x = 2j, 2j + 1 of one band row
-        rtilde_pair(x0, x1, th_s[b], t2_s[b], al_s[b]);
+        rtilde_pair(x0, x1, th_s[b], t2_s[b], al_s[b], ia_s[b]);
       } else if (mode == RS_WHAT_G) {
         soft_pair(x0, x1, th_s[b], t2_s[b]);
       }
@@ -516,7 +517,7 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
   extern __shared__ float4 lds4[];
   float2* lds = reinterpret_cast<float2*>(lds4);
   __shared__ float2 tw_s[kMaxN];
-  __shared__ float th_s[kMaxBands], t2_s[kMaxBands], al_s[kMaxBands];
+  __shared__ float th_s[kMaxBands], t2_s[kMaxBands], al_s[kMaxBands], ia_s[kMaxBands];
   __shared__ int sel_s[kMaxBands];
   __shared__ float l1_s[NT / 64];
   const int2 item = a.work[blockIdx.x];
@@ -547,6 +548,7 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
     th_s[tid] = a.theta[item.x * kMaxBands + tid];
     t2_s[tid] = a.thr2[item.x * kMaxBands + tid];
     al_s[tid] = a.alpha[item.x * kMaxBands + tid];
+    ia_s[tid] = 1.0f / (1.0f - al_s[tid]);
     if (mode == RA_LEARNED) sel_s[tid] = a.sel[item.x * kMaxBands + tid];
   }
   const FftPlanDev& P = a.ffts[S.fft_x];
@@ -636,7 +638,7 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
       const float4 gv = lds4[p];
       if (mode == RA_VDAMP_G) {  // r_tilde of the pair x = 2j, 2j + 1 (line 8), + coefficients
         float2 x0 = lo2(ro[u]), x1 = hi2(ro[u]);
-        rtilde_pair(x0, x1, th_s[b], t2_s[b], al_s[b]);
+        rtilde_pair(x0, x1, th_s[b], t2_s[b], al_s[b], ia_s[b]);
         *reinterpret_cast<float4*>(r + gi[u]) = pack4(cadd(x0, lo2(gv)), cadd(x1, hi2(gv)));
         continue;
       }
@@ -648,12 +650,12 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
           case RA_VDAMP_FIRST: o[h] = g; break;
           case RA_VDAMP: {
             const float2 x = h ? hi2(ro[u]) : lo2(ro[u]);
-            o[h] = cadd(rtilde_c(x, th_s[b], t2_s[b], al_s[b]), g);
+            o[h] = cadd(rtilde_ci(x, th_s[b], t2_s[b], al_s[b], ia_s[b]), g);
           } break;
           case RA_LEARNED: {
             const float2 x = h ? hi2(ro[u]) : lo2(ro[u]);
             const float2 wv = h ? hi2(rw[u]) : lo2(rw[u]);
-            o[h] = cadd(sel_s[b] ? rtilde_w(wv, x, al_s[b]) : rtilde_c(x, th_s[b], t2_s[b], al_s[b]), g);
+            o[h] = cadd(sel_s[b] ? rtilde_w(wv, x, al_s[b]) : rtilde_ci(x, th_s[b], t2_s[b], al_s[b], ia_s[b]), g);
           } break;
           case RA_FISTA_FIRST: {
             w2[h] = soft_c(g, lam, lam2);

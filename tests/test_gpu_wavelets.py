@@ -14,8 +14,8 @@ from oracle import vdamp_ref as o
 from paper_1911_01234_amd import filters, synth
 
 from gpu_helpers import fp32_inputs, fp32_state, gpu_available, rel_l2, run_resume, run_vdamp
-from test_gpu_parity import (TOL_ITER, TOL_TAU, free_running, one_step_check,
-                             one_step_every_iteration, oracle_run)
+from test_gpu_parity import (TOL_ITER, TOL_NMSE_DB, TOL_TAU, free_running, one_step_check,
+                             one_step_every_iteration, oracle_nmse_envelope, oracle_run)
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs an MI355X")]
@@ -66,7 +66,11 @@ def test_transform_matches_oracle(ny, nx, s, name):
 def test_haar_filter_through_the_general_path_equals_the_haar_path():
     """The Haar filter given to vdamp_plan_ortho runs the Fourier-domain passes; its
     transform and its first iterate (r_0, tau_0) match the Haar plan's strip kernels to
-    FP32 rounding, and a 30-iteration solve ends at the same NMSE."""
+    FP32 rounding, and a 30-iteration solve of both ends within the final-NMSE gate of the
+    oracle: this recipe's thresholds hit near ties after about 12 iterations, from where
+    two FP32 evaluations follow different valid trajectories, so each final NMSE must
+    lie within max(0.05 dB, 4 sd) of the mean of oracle runs on inputs perturbed by 3e-7
+    (the gate every free-running test applies after a flip)."""
     from paper_1911_01234_amd import vdamp as V
     sl, s, K = synth.workload_single64()
     sl = sl[0]
@@ -86,8 +90,10 @@ def test_haar_filter_through_the_general_path_equals_the_haar_path():
     assert np.max(np.abs(go["tau"] - gh["tau"]) / gh["tau"]) <= 1e-6
     no = o.nmse_db(run_vdamp([sl], s, K, plan=po)["x_hat"][0], sl.x0)
     nh = o.nmse_db(run_vdamp([sl], s, K, plan=ph)["x_hat"][0], sl.x0)
-    print(f"NMSE general path {no:.3f} dB, Haar path {nh:.3f} dB")
-    assert abs(no - nh) <= 0.05
+    n_ref = o.nmse_db(oracle_run(sl, s, K, record=False)["x_hat"], sl.x0)
+    mean, sd = oracle_nmse_envelope(sl, s, K, n_ref)
+    print(f"NMSE general path {no:.3f} dB, Haar path {nh:.3f} dB, oracle envelope {mean:.3f} +- {sd:.3f} dB")
+    assert abs(no - mean) <= max(TOL_NMSE_DB, 4 * sd) and abs(nh - mean) <= max(TOL_NMSE_DB, 4 * sd)
     po.close()
     ph.close()
 
