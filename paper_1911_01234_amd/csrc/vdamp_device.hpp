@@ -296,9 +296,13 @@ struct RowFft4 {
 //   x00 = (a + b + c + d)/2, x01 = (a - b + c - d)/2,
 //   x10 = (a + b - c - d)/2, x11 = (a - b - c + d)/2,
 // with a = LL, b = LH (low y, high x), c = HL (high y, low x), d = HH.
-template <int EPT, int NT = kThreads>
-__device__ void haar_strip_synth(float2* buf, int H, int nx, int s) {
+// SL > 0 and NXC > 0 fix the level count and the strip width at compile time (the
+// level loop unrolls and every index divides by a constant); 0 reads them at run time.
+template <int EPT, int NT = kThreads, int SL = 0, int NXC = 0>
+__device__ void haar_strip_synth(float2* buf, int H, int nx_, int s_) {
   constexpr int MAXQ = EPT / 4;
+  const int s = SL ? SL : s_, nx = NXC ? NXC : nx_;
+#pragma unroll
   for (int l = s; l >= 1; --l) {
     const int hp = H >> l, w = nx >> l;
     const int nblk = hp * w;
@@ -333,9 +337,11 @@ __device__ void haar_strip_synth(float2* buf, int H, int nx, int s) {
   }
 }
 
-template <int EPT, int NT = kThreads>
-__device__ void haar_strip_anal(float2* buf, int H, int nx, int s) {
+template <int EPT, int NT = kThreads, int SL = 0, int NXC = 0>
+__device__ void haar_strip_anal(float2* buf, int H, int nx_, int s_) {
   constexpr int MAXQ = EPT / 4;
+  const int s = SL ? SL : s_, nx = NXC ? NXC : nx_;
+#pragma unroll
   for (int l = 1; l <= s; ++l) {
     const int hp = H >> l, w = nx >> l;
     const int nblk = hp * w;
@@ -389,6 +395,32 @@ __device__ __forceinline__ int strip_to_global(int lr, int lc, int strip, int s,
   }
   band = 0;
   return strip;
+}
+
+// strip_to_global with the level count SL and the width NXC known at compile time: the
+// level is the first l whose high half along y (lr >= 2^(SL-l)) or along x
+// (lc >= NXC >> l) holds the position, found without a loop.
+template <int SL, int NXC>
+__device__ __forceinline__ int strip_to_global_c(int lr, int lc, int strip, int ny, int& band) {
+  int l = SL + 1;
+#pragma unroll
+  for (int k = SL; k >= 1; --k)
+    if (lr >= (1 << (SL - k)) || lc >= (NXC >> k)) l = k;
+  if (l > SL) {
+    band = 0;
+    return strip;
+  }
+  const int hp = (1 << SL) >> l;
+  const bool hy = lr >= hp, hx = lc >= (NXC >> l);
+  band = 1 + 3 * (SL - l) + (hy ? (hx ? 2 : 1) : 0);
+  return (hy ? (ny >> l) : 0) + strip * hp + (lr - (hy ? hp : 0));
+}
+template <int SL, int NXC>
+__device__ __forceinline__ int strip_to_global_t(int lr, int lc, int strip, int s, int ny, int nx, int& band) {
+  if constexpr (SL > 0 && NXC > 0)
+    return strip_to_global_c<SL, NXC>(lr, lc, strip, ny, band);
+  else
+    return strip_to_global(lr, lc, strip, s, ny, nx, band);
 }
 
 // |r|^2 with each multiply and the add rounded to nearest (no contraction): the key on

@@ -17,7 +17,8 @@ namespace vdamp {
 
 // ------------------------------------------------------------------ rows_synth
 // do_fft = 0 writes the image rows Psi^H r (the FISTA output).
-template <int EPT, int M, int NT = kThreads>
+// SL > 0: the plan's level count, fixed at compile time (four-step kernels, nx = 16 M).
+template <int EPT, int M, int NT = kThreads, int SL = 0>
 __global__ void __launch_bounds__(NT) k_rows_synth(KArgs a, int do_fft) {
   extern __shared__ float4 lds4[];
   float2* lds = reinterpret_cast<float2*>(lds4);
@@ -25,7 +26,8 @@ __global__ void __launch_bounds__(NT) k_rows_synth(KArgs a, int do_fft) {
   __shared__ float th_s[kMaxBands], t2_s[kMaxBands], al_s[kMaxBands], ia_s[kMaxBands];
   const int2 item = a.work[blockIdx.x];
   const SliceDev S = a.slices[item.x];
-  const int strip = item.y, s = a.levels, H = 1 << s, nx = S.nx, ny = S.ny;
+  constexpr int NXC = M > 0 ? 16 * M : 0;
+  const int strip = item.y, s = SL ? SL : a.levels, H = 1 << s, nx = NXC ? NXC : S.nx, ny = S.ny;
   const int tid = threadIdx.x, mode = a.mode;
   if (tid < kMaxBands && a.theta) {  // null for the plain transform Psi^H
     th_s[tid] = a.theta[item.x * kMaxBands + tid];
@@ -53,7 +55,7 @@ __global__ void __launch_bounds__(NT) k_rows_synth(KArgs a, int do_fft) {
     if (p < npairs) {
       const int lr = p / half, lc = 2 * (p - lr * half);
       int b;
-      const int gr = strip_to_global(lr, lc, strip, s, ny, nx, b);
+      const int gr = strip_to_global_t<SL, NXC>(lr, lc, strip, s, ny, nx, b);
       bnd[u] = b;
       gi[u] = (long long)gr * nx + lc;
       if (mode != RS_PROBE) v[u] = *reinterpret_cast<const float4*>(r + gi[u]);
@@ -98,7 +100,7 @@ __global__ void __launch_bounds__(NT) k_rows_synth(KArgs a, int do_fft) {
     }
   }
   __syncthreads();
-  haar_strip_synth<EPT, NT>(lds, H, nx, s);
+  haar_strip_synth<EPT, NT, SL, NXC>(lds, H, nx, s);
   if constexpr (M > 0) {
     if (do_fft) {  // four-step row FFT, outputs straight to X
       using F = RowFft4<M, NT>;
@@ -512,7 +514,7 @@ __global__ void __launch_bounds__(cols4_threads(M)) k_cols4(KArgs a) {
 }
 
 // ------------------------------------------------------------------ rows_anal
-template <int EPT, int M, int NT = kThreads>
+template <int EPT, int M, int NT = kThreads, int SL = 0>
 __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
   extern __shared__ float4 lds4[];
   float2* lds = reinterpret_cast<float2*>(lds4);
@@ -522,7 +524,8 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
   __shared__ float l1_s[NT / 64];
   const int2 item = a.work[blockIdx.x];
   const SliceDev S = a.slices[item.x];
-  const int strip = item.y, s = a.levels, H = 1 << s, nx = S.nx, ny = S.ny;
+  constexpr int NXC = M > 0 ? 16 * M : 0;
+  const int strip = item.y, s = SL ? SL : a.levels, H = 1 << s, nx = NXC ? NXC : S.nx, ny = S.ny;
   const int tid = threadIdx.x, mode = a.mode;
   constexpr int U = EPT / 2;
   const int half = nx >> 1, npairs = H * half;
@@ -598,7 +601,7 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
     if (p < npairs) {                                                                        \
       const int lr = p / half, lc = 2 * (p - lr * half);                                     \
       int b;                                                                                 \
-      const int gr = strip_to_global(lr, lc, strip, s, ny, nx, b);                           \
+      const int gr = strip_to_global_t<SL, NXC>(lr, lc, strip, s, ny, nx, b);               \
       bnd[u] = b;                                                                            \
       gi[u] = gr * nx + lc;                                                                  \
       if (need_r) ro[u] = *reinterpret_cast<const float4*>(r + gi[u]);                       \
@@ -618,9 +621,9 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
   // cost more occupancy than the overlap gains.
   if constexpr (EPT <= 16) {
     RA_LOAD_R();
-    haar_strip_anal<EPT, NT>(lds, H, nx, s);
+    haar_strip_anal<EPT, NT, SL, NXC>(lds, H, nx, s);
   } else {
-    haar_strip_anal<EPT, NT>(lds, H, nx, s);
+    haar_strip_anal<EPT, NT, SL, NXC>(lds, H, nx, s);
     RA_LOAD_R();
   }
 #undef RA_LOAD_R
@@ -842,11 +845,50 @@ size_t rows4_lds_bytes(int m, int H) {
 #define NT_OF(MM) kThreads
 #define EPT_OF(MM) ((MM) <= 16 ? 16 : ((MM) <= 24 ? (MM) : 32))
 
+// Plans of 4 levels (the paper's s) on power-of-two widths run kernels with the level
+// count fixed at compile time (for the other widths the constant divisions it brings
+// cost registers: 320 wide, 137 VGPRs against 128).
+template <int MM> constexpr bool fixed_levels() { return (MM & (MM - 1)) == 0; }
+template <int MM>
+static void launch_rs4(const KArgs& a, size_t lds, hipStream_t st) {
+  if constexpr (fixed_levels<MM>()) {
+    if (a.levels == 4) {
+      hipLaunchKernelGGL((k_rows_synth<EPT_OF(MM), MM, NT_OF(MM), 4>), dim3(a.nwork), dim3(NT_OF(MM)), lds, st, a, 1);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_rows_synth<EPT_OF(MM), MM, NT_OF(MM)>), dim3(a.nwork), dim3(NT_OF(MM)), lds, st, a, 1);
+}
+template <int MM>
+static void launch_ra4(const KArgs& a, size_t lds, hipStream_t st) {
+  if constexpr (fixed_levels<MM>()) {
+    if (a.levels == 4) {
+      hipLaunchKernelGGL((k_rows_anal<EPT_OF(MM), MM, NT_OF(MM), 4>), dim3(a.nwork), dim3(NT_OF(MM)), lds, st, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_rows_anal<EPT_OF(MM), MM, NT_OF(MM)>), dim3(a.nwork), dim3(NT_OF(MM)), lds, st, a);
+}
+template <int MM>
+static hipError_t set_lds_rows4(int bytes) {
+  std::vector<const void*> fs = {(const void*)k_rows_synth<EPT_OF(MM), MM, NT_OF(MM)>,
+                                 (const void*)k_rows_anal<EPT_OF(MM), MM, NT_OF(MM)>};
+  if constexpr (fixed_levels<MM>()) {
+    fs.push_back((const void*)k_rows_synth<EPT_OF(MM), MM, NT_OF(MM), 4>);
+    fs.push_back((const void*)k_rows_anal<EPT_OF(MM), MM, NT_OF(MM), 4>);
+  }
+  for (const void* f : fs) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_rows_synth4(const KArgs& a, int m, size_t lds, hipStream_t st) {
   switch (m) {
 #define RS4(MM)                                                                                \
   case MM:                                                                                     \
-    hipLaunchKernelGGL((k_rows_synth<EPT_OF(MM), MM, NT_OF(MM)>), dim3(a.nwork), dim3(NT_OF(MM)), lds, st, a, 1); \
+    launch_rs4<MM>(a, lds, st);                                                                \
     break;
     ROWS4_CASES(RS4)
 #undef RS4
@@ -859,7 +901,7 @@ hipError_t launch_rows_anal4(const KArgs& a, int m, size_t lds, hipStream_t st) 
   switch (m) {
 #define RA4(MM)                                                                                \
   case MM:                                                                                     \
-    hipLaunchKernelGGL((k_rows_anal<EPT_OF(MM), MM, NT_OF(MM)>), dim3(a.nwork), dim3(NT_OF(MM)), lds, st, a); \
+    launch_ra4<MM>(a, lds, st);                                                                \
     break;
     ROWS4_CASES(RA4)
 #undef RA4
@@ -887,11 +929,7 @@ hipError_t set_lds_limits_passes(size_t rows, size_t cols) {
   const int r4 = (int)rows4_lds_bytes(32, 16);  // the largest four-step row tile
 #define LIM4(MM)                                                                                      \
   {                                                                                                   \
-    hipError_t e = hipFuncSetAttribute((const void*)k_rows_synth<EPT_OF(MM), MM, NT_OF(MM)>,                     \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, r4);               \
-    if (e == hipSuccess)                                                                              \
-      e = hipFuncSetAttribute((const void*)k_rows_anal<EPT_OF(MM), MM, NT_OF(MM)>,                               \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, r4);                        \
+    hipError_t e = set_lds_rows4<MM>(r4);                                                             \
     if (e != hipSuccess) return e;                                                                    \
   }
   ROWS4_CASES(LIM4)
