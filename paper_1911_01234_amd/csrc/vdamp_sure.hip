@@ -443,7 +443,8 @@ k_sure(KArgs a) {
     hi = off[bk_ + 1];                               \
     slot = SURE_SLOT(j);                             \
   }
-    // scatter into bucket slots
+    // scatter into bucket slots, unpadded (the rank loop then walks plain addresses; the
+    // padded sorted layout is written only after every rank read)
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       const int i = tid + j * NT;
@@ -451,7 +452,7 @@ k_sure(KArgs a) {
         int lo, hi, slot;
         SURE_BOUNDS(j, lo, hi, slot);
         (void)hi;
-        sk[skx(lo + slot)] = kk[j];
+        sk[lo + slot] = kk[j];
       }
     }
     __syncthreads();
@@ -463,10 +464,10 @@ k_sure(KArgs a) {
         int lo, hi, slot;
         SURE_BOUNDS(j, lo, hi, slot);
         const float v = kk[j];
-        const int me = lo + slot;
+        const float* me = sk + lo + slot;
         int rank = 0;
-        for (int x = lo; x < hi; ++x) {
-          const float u = sk[skx(x)];
+        for (const float* x = sk + lo; x < sk + hi; ++x) {
+          const float u = *x;
           rank += (u < v) || (u == v && x < me);
         }
         pos[j] = lo + rank;
