@@ -142,9 +142,11 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int n, int N
   __syncthreads();
 }
 
+// Always inlined: a call (the compiler declines to inline some instances) costs the
+// row kernels that use it a register save/restore and all constant propagation.
 template <bool INV, bool COLS, int EPT>
-__device__ void fft_lines(float2* buf, const FftPlanDev& P, int nlines, int ls, int es,
-                          const float2* __restrict__ tw) {
+__device__ __forceinline__ void fft_lines(float2* buf, const FftPlanDev& P, int nlines, int ls, int es,
+                                          const float2* __restrict__ tw) {
   int Ns = 1;
   for (int st = 0; st < P.nst; ++st) {
     const int R = P.rad[st];
@@ -299,7 +301,7 @@ struct RowFft4 {
 // SL > 0 and NXC > 0 fix the level count and the strip width at compile time (the
 // level loop unrolls and every index divides by a constant); 0 reads them at run time.
 template <int EPT, int NT = kThreads, int SL = 0, int NXC = 0>
-__device__ void haar_strip_synth(float2* buf, int H, int nx_, int s_) {
+__device__ __forceinline__ void haar_strip_synth(float2* buf, int H, int nx_, int s_) {
   constexpr int MAXQ = EPT / 4;
   const int s = SL ? SL : s_, nx = NXC ? NXC : nx_;
 #pragma unroll
@@ -338,7 +340,7 @@ __device__ void haar_strip_synth(float2* buf, int H, int nx_, int s_) {
 }
 
 template <int EPT, int NT = kThreads, int SL = 0, int NXC = 0>
-__device__ void haar_strip_anal(float2* buf, int H, int nx_, int s_) {
+__device__ __forceinline__ void haar_strip_anal(float2* buf, int H, int nx_, int s_) {
   constexpr int MAXQ = EPT / 4;
   const int s = SL ? SL : s_, nx = NXC ? NXC : nx_;
 #pragma unroll

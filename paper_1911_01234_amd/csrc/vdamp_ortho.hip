@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(kThreads) k_osynth(KArgs a) {
   const int rpi = rows_per_item(ng), i0 = item.y - goff;
   const int mx = nx >> l, nseg = (kind || l == s) ? 2 : 1, j0 = 2 - nseg, seglen = nseg * mx;
   const int row0 = (kind ? (ny >> l) : 0) + i0;  // coefficient row of group row i0
-  const FftPlanDev& P = a.ffts[S.fft_xl[l]];
+  const FftPlanDev& P = a.ffts[a.slices[sl].fft_xl[l]];  // (indexing the local copy would put it in scratch)
   load_twiddles(tw_s, P, a.twiddles);
   float2* Fx = buf + 8 * nx;  // x responses of A_l and D_l
   for (int i = tid; i < 2 * nx; i += kThreads)
@@ -140,16 +140,14 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
   const bool in_zero = (mode == CM_VDAMP_FIRST || mode == CM_ZEROFILL);
   const bool in_plain = (mode == OC_ANAL);
   const bool out_plain = (mode == CM_OUTPUT || mode == CM_ZEROFILL || mode == OC_SYNTH);
-  // twiddles of the lengths ny >> l, l = 0..s, one after another
-  int twoff[5];
-  {
-    int o = 0;
-    for (int l = 0; l <= s; ++l) {
-      const FftPlanDev& P = a.ffts[S.fft_yl[l]];
-      twoff[l] = o;
-      for (int i = tid; i < P.n; i += kThreads) tw_s[o + i] = a.twiddles[P.tw_off + i];
-      o += P.n;
-    }
+  // twiddles of the lengths ny >> l, l = 0..s, one after another: those of length
+  // ny >> l start at twoff(l) = sum_{j<l} ny >> j.  The plans are read from the slice
+  // descriptor in global memory (indexing the local copy by l would put it in scratch).
+  const int* fyl = a.slices[sl].fft_yl;
+  auto twoff = [ny](int l) { return l ? 2 * ny - (ny >> (l - 1)) : 0; };
+  for (int l = 0; l <= s; ++l) {
+    const FftPlanDev& P = a.ffts[fyl[l]];
+    for (int i = tid; i < P.n; i += kThreads) tw_s[twoff(l) + i] = a.twiddles[P.tw_off + i];
   }
   for (int i = tid; i < 2 * s * ny; i += kThreads) Fy[i] = a.resp[S.yresp_off + i];
   const int n16 = ny * kColW;
@@ -161,7 +159,7 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
   if (in_plain) {
     for (int e = tid; e < n16; e += kThreads) V[e] = a.X[S.off + (long long)(e >> 4) * nx + c0 + (e & 15)];
     __syncthreads();
-    fft_cols16<false, EPT>(V, a.ffts[S.fft_yl[0]], tw_s + twoff[0]);
+    fft_cols16<false, EPT>(V, a.ffts[fyl[0]], tw_s + twoff(0));
 #pragma unroll
     for (int j = 0; j < EPT; ++j)
       if (q + 16 * j < ny) acc[j] = V[(q + 16 * j) * kColW + c];
@@ -174,7 +172,7 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
         for (int e = tid; e < ng * kColW; e += kThreads)
           G[e] = a.Z[S.zoff + (long long)(goff + (e >> 4)) * nx + c0 + (e & 15)];
         __syncthreads();
-        fft_cols16<false, EPT>(G, a.ffts[S.fft_yl[l]], tw_s + twoff[l]);
+        fft_cols16<false, EPT>(G, a.ffts[fyl[l]], tw_s + twoff(l));
         const float2* F = Fy + filt_index(l, kind, s) * ny;
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
@@ -253,7 +251,7 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
   }
   // ---- out of k-space
   if (out_plain) {
-    fft_cols16<true, EPT>(V, a.ffts[S.fft_yl[0]], tw_s + twoff[0]);
+    fft_cols16<true, EPT>(V, a.ffts[fyl[0]], tw_s + twoff(0));
     for (int e = tid; e < n16; e += kThreads) a.X[S.off + (long long)(e >> 4) * nx + c0 + (e & 15)] = V[e];
     return;
   }
@@ -272,7 +270,7 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
         G[e] = sum;
       }
       __syncthreads();
-      fft_cols16<true, EPT>(G, a.ffts[S.fft_yl[l]], tw_s + twoff[l]);
+      fft_cols16<true, EPT>(G, a.ffts[fyl[l]], tw_s + twoff(l));
       for (int e = tid; e < ng * kColW; e += kThreads)
         a.Z[S.zoff + (long long)(goff + (e >> 4)) * nx + c0 + (e & 15)] = G[e];
       __syncthreads();  // G is read before the next group overwrites it
@@ -309,7 +307,7 @@ __global__ void __launch_bounds__(kThreads) k_oanal(KArgs a) {
   const int row0 = (kind ? (ny >> l) : 0) + i0, nal = 1 << l;
   float2* Ss = Zs + 8 * nx;
   float2* Fx = Ss + 8 * nx;  // x responses of A_l and D_l
-  const FftPlanDev& P = a.ffts[S.fft_xl[l]];
+  const FftPlanDev& P = a.ffts[a.slices[sl].fft_xl[l]];  // (indexing the local copy would put it in scratch)
   load_twiddles(tw_s, P, a.twiddles);
   for (int i = tid; i < 2 * nx; i += kThreads)
     Fx[i] = a.resp[S.xresp_off + filt_index(l, i >= nx, s) * nx + (i >= nx ? i - nx : i)];
