@@ -845,10 +845,11 @@ size_t rows4_lds_bytes(int m, int H) {
 #define NT_OF(MM) kThreads
 #define EPT_OF(MM) ((MM) <= 16 ? 16 : ((MM) <= 24 ? (MM) : 32))
 
-// Plans of 4 levels (the paper's s) on power-of-two widths run kernels with the level
-// count fixed at compile time (for the other widths the constant divisions it brings
-// cost registers: 320 wide, 137 VGPRs against 128).
-template <int MM> constexpr bool fixed_levels() { return (MM & (MM - 1)) == 0; }
+// Plans of 4 levels (the paper's s) on power-of-two widths, and 192 and 320 wide, run
+// kernels with the level count fixed at compile time (measured faster on the mixed
+// batch although the 320-wide synthesis then holds 137 VGPRs against 128; for 96, 160,
+// 240, 384 and 480 the runtime-level kernels are kept).
+template <int MM> constexpr bool fixed_levels() { return (MM & (MM - 1)) == 0 || MM == 12 || MM == 20; }
 template <int MM>
 static void launch_rs4(const KArgs& a, size_t lds, hipStream_t st) {
   if constexpr (fixed_levels<MM>()) {
