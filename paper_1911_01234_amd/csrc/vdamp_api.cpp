@@ -671,6 +671,7 @@ static vdamp_status make_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* 
     P->lds_oanal = sizeof(float2) * (size_t)18 * maxnx;   // 8 group rows + 8 band rows + 2 responses
     P->lds_ocols = ocols_lds_bytes(maxny, levels);
     P->ocols_ept = maxny * kColW <= 16 * kThreads ? 16 : 32;
+    P->ocols_ny = std::all_of(ny, ny + batch, [&](int v) { return v == ny[0]; }) ? ny[0] : 0;
   }
   P->lds_rows = sizeof(float2) * (size_t)H * maxnx;
   P->lds_cols = sizeof(float2) * (size_t)maxny * kColW;

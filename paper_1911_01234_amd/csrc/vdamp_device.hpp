@@ -3,6 +3,8 @@
 // mapping of a strip, and complex soft thresholding.
 #pragma once
 
+#include <type_traits>
+
 #include "vdamp_internal.h"
 
 namespace vdamp {
@@ -174,6 +176,27 @@ __device__ __forceinline__ void fft_cols16(float2* buf, const FftPlanDev& P, con
       default: fft_stage<5, INV, true, EPT>(buf, P.n, Ns, kColW, 1, kColW, tw); break;
     }
     Ns *= R;
+  }
+}
+
+// fft_cols16 for a power-of-two length N fixed at compile time: radix-4 stages, one
+// radix-2 stage last when log2 N is odd, every stage's constants folded.
+template <bool INV, int EPT, int N, int NS = 1>
+__device__ __forceinline__ void fft_cols16_n(float2* buf, const float2* tw) {
+  static_assert((N & (N - 1)) == 0, "power-of-two length");
+  if constexpr (NS < N) {
+    constexpr int R = ((N / NS) % 4 == 0) ? 4 : 2;
+    fft_stage<R, INV, true, EPT>(buf, N, NS, kColW, 1, kColW, tw);
+    fft_cols16_n<INV, EPT, N, NS * R>(buf, tw);
+  }
+}
+
+// f(std::integral_constant<int, I>) for I = 0 .. N-1, unrolled at compile time.
+template <int N, int I = 0, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<N, I + 1>(f);
   }
 }
 

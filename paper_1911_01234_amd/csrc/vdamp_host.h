@@ -110,6 +110,7 @@ struct vdamp_plan_t {
   int n_img = 0;
   size_t lds_osynth = 0, lds_ocols = 0, lds_oanal = 0;
   int ocols_ept = 16;
+  int ocols_ny = 0;  // the rows of every slice when they agree, else 0
   size_t o_Z = 0;
   // volumes (plans made by vdamp_plan_3d): depths, Haar bricks, x-row items, y and z
   // strips, LDS sizes and elements a thread of the strip kernel
@@ -185,7 +186,7 @@ hipError_t launch_judge(const KArgs& a, int nrowstrips, int always, int* sel, fl
 size_t ocols_lds_bytes(int maxny, int s);
 hipError_t set_lds_limits_ortho(size_t synth, size_t cols, size_t anal);
 hipError_t launch_osynth(const KArgs& a, size_t lds, hipStream_t st);
-hipError_t launch_ocols(const KArgs& a, int ept, size_t lds, hipStream_t st);
+hipError_t launch_ocols(const KArgs& a, int ept, int ny_all, size_t lds, hipStream_t st);
 hipError_t launch_oanal(const KArgs& a, size_t lds, hipStream_t st);
 // volumes
 size_t k3_axis_lds_bytes(int maxn, int maxnd, int s);
@@ -341,7 +342,7 @@ inline hipError_t pass_cols(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
   if (!P->ortho) return launch_cols_all(P, a, st);
   a.work = P->d_work_cols;
   a.nwork = P->ncols;
-  return launch_ocols(a, P->ocols_ept, P->lds_ocols, st);
+  return launch_ocols(a, P->ocols_ept, P->ocols_ny, P->lds_ocols, st);
 }
 // Volumes: Haar bricks (Psi^H into X, or Psi from X), x-row DFTs, y or z strip DFTs.
 inline hipError_t pass3_haar(const vdamp_plan_t* P, KArgs a, bool synth, hipStream_t st) {

@@ -122,7 +122,10 @@ __global__ void __launch_bounds__(kThreads) k_osynth(KArgs a) {
 // LDS once, after the k-space step, for the folds.  Dynamic LDS: the k-space strip V
 // (ny x 16), one group column block G (ny/2 x 16; during the k-space step it holds the
 // 2 s y-axis tau tables instead, ny floats each) and the y responses (2 s x ny complex).
-template <int EPT>
+// SL > 0, NYC > 0: every slice of the launch has NYC rows (a power of two) and the plan
+// SL levels, so the group loops unroll and every DFT runs with its length fixed at
+// compile time.
+template <int EPT, int SL = 0, int NYC = 0>
 __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
   extern __shared__ float4 lds4[];
   __shared__ float2 tw_s[2 * kMaxN];
@@ -130,7 +133,7 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
   const int2 item = a.work[xcd_item(blockIdx.x, gridDim.x)];
   const int sl = item.x;
   const SliceDev S = a.slices[sl];
-  const int ny = S.ny, nx = S.nx, c0 = item.y * kColW, s = a.levels;
+  const int ny = NYC ? NYC : S.ny, nx = S.nx, c0 = item.y * kColW, s = SL ? SL : a.levels;
   const int tid = threadIdx.x, mode = a.mode;
   float2* V = reinterpret_cast<float2*>(lds4);
   float2* G = V + ny * kColW;
@@ -149,6 +152,38 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
     const FftPlanDev& P = a.ffts[fyl[l]];
     for (int i = tid; i < P.n; i += kThreads) tw_s[twoff(l) + i] = a.twiddles[P.tw_off + i];
   }
+  // the column DFT of level l (length ny >> l) on buf: NG > 0 is that length at compile time
+  auto col_fft = [&](auto inv, auto ngc, float2* buf, int l) __attribute__((always_inline)) {
+    constexpr bool INV = decltype(inv)::value;
+    constexpr int NG = decltype(ngc)::value;
+    if constexpr (NG > 0)
+      fft_cols16_n<INV, EPT, NG>(buf, tw_s + twoff(l));
+    else
+      fft_cols16<INV, EPT>(buf, a.ffts[fyl[l]], tw_s + twoff(l));
+  };
+  // group loops: (l, kind) for l = 1 .. s, kind = 0, 1, in that order
+  auto for_groups = [&](auto&& body) __attribute__((always_inline)) {
+    if constexpr (SL > 0 && NYC > 0) {
+      // a loop over the levels (unrolled, it would keep all groups' values live), each
+      // level's body with its lengths fixed at compile time
+      static_assert(SL <= 4, "levels");
+#pragma unroll 1
+      for (int l = 1; l <= SL; ++l)
+#pragma unroll 1
+        for (int kind = 0; kind < 2; ++kind) {
+          if (l == 1) body(1, kind, std::integral_constant<int, (NYC >> 1)>{});
+          else if (l == 2) body(2, kind, std::integral_constant<int, (NYC >> 2)>{});
+          else if (l == 3) body(3, kind, std::integral_constant<int, (NYC >> 3)>{});
+          else body(4, kind, std::integral_constant<int, (NYC >> 4)>{});
+        }
+    } else {
+      for (int l = 1; l <= s; ++l)
+        for (int kind = 0; kind < 2; ++kind) body(l, kind, std::integral_constant<int, 0>{});
+    }
+  };
+  using FwdT = std::false_type;
+  using InvT = std::true_type;
+  using FullN = std::integral_constant<int, (SL > 0 && NYC > 0) ? NYC : 0>;
   for (int i = tid; i < 2 * s * ny; i += kThreads) Fy[i] = a.resp[S.yresp_off + i];
   const int n16 = ny * kColW;
   const int c = tid & (kColW - 1), q = tid >> 4;
@@ -159,28 +194,27 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
   if (in_plain) {
     for (int e = tid; e < n16; e += kThreads) V[e] = a.X[S.off + (long long)(e >> 4) * nx + c0 + (e & 15)];
     __syncthreads();
-    fft_cols16<false, EPT>(V, a.ffts[fyl[0]], tw_s + twoff(0));
+    col_fft(FwdT{}, FullN{}, V, 0);
 #pragma unroll
     for (int j = 0; j < EPT; ++j)
       if (q + 16 * j < ny) acc[j] = V[(q + 16 * j) * kColW + c];
   } else if (!in_zero) {
     int goff = 0;
-    for (int l = 1; l <= s; ++l)
-      for (int kind = 0; kind < 2; ++kind) {
-        const int ng = ny >> l;
-        __syncthreads();  // G is free (and the tables are in)
-        for (int e = tid; e < ng * kColW; e += kThreads)
-          G[e] = a.Z[S.zoff + (long long)(goff + (e >> 4)) * nx + c0 + (e & 15)];
-        __syncthreads();
-        fft_cols16<false, EPT>(G, a.ffts[fyl[l]], tw_s + twoff(l));
-        const float2* F = Fy + filt_index(l, kind, s) * ny;
+    for_groups([&](int l, int kind, auto ngc) __attribute__((always_inline)) {
+      const int ng = ny >> l;
+      __syncthreads();  // G is free (and the tables are in)
+      for (int e = tid; e < ng * kColW; e += kThreads)
+        G[e] = a.Z[S.zoff + (long long)(goff + (e >> 4)) * nx + c0 + (e & 15)];
+      __syncthreads();
+      col_fft(FwdT{}, ngc, G, l);
+      const float2* F = Fy + filt_index(l, kind, s) * ny;
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-          const int ky = q + 16 * j;
-          if (ky < ny) acc[j] = cadd(acc[j], cmul(F[ky], G[(ky % ng) * kColW + c]));
-        }
-        goff += ng;
+      for (int j = 0; j < EPT; ++j) {
+        const int ky = q + 16 * j;
+        if (ky < ny) acc[j] = cadd(acc[j], cmul(F[ky], G[(ky % ng) * kColW + c]));
       }
+      goff += ng;
+    });
   }
   __syncthreads();  // V and G free
   if (vd) {
@@ -251,31 +285,30 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
   }
   // ---- out of k-space
   if (out_plain) {
-    fft_cols16<true, EPT>(V, a.ffts[fyl[0]], tw_s + twoff(0));
+    col_fft(InvT{}, FullN{}, V, 0);
     for (int e = tid; e < n16; e += kThreads) a.X[S.off + (long long)(e >> 4) * nx + c0 + (e & 15)] = V[e];
     return;
   }
   int goff = 0;
-  for (int l = 1; l <= s; ++l)
-    for (int kind = 0; kind < 2; ++kind) {
-      const int ng = ny >> l, nal = 1 << l;
-      const float2* F = Fy + filt_index(l, kind, s) * ny;
-      for (int e = tid; e < ng * kColW; e += kThreads) {
-        const int k = e >> 4, cc = e & 15;
-        float2 sum = make_float2(0.f, 0.f);
-        for (int j = 0; j < nal; ++j) {
-          const int ky = k + j * ng;
-          sum = cadd(sum, conj_mul(F[ky], V[ky * kColW + cc]));
-        }
-        G[e] = sum;
+  for_groups([&](int l, int kind, auto ngc) __attribute__((always_inline)) {
+    const int ng = ny >> l, nal = 1 << l;
+    const float2* F = Fy + filt_index(l, kind, s) * ny;
+    for (int e = tid; e < ng * kColW; e += kThreads) {
+      const int k = e >> 4, cc = e & 15;
+      float2 sum = make_float2(0.f, 0.f);
+      for (int j = 0; j < nal; ++j) {
+        const int ky = k + j * ng;
+        sum = cadd(sum, conj_mul(F[ky], V[ky * kColW + cc]));
       }
-      __syncthreads();
-      fft_cols16<true, EPT>(G, a.ffts[fyl[l]], tw_s + twoff(l));
-      for (int e = tid; e < ng * kColW; e += kThreads)
-        a.Z[S.zoff + (long long)(goff + (e >> 4)) * nx + c0 + (e & 15)] = G[e];
-      __syncthreads();  // G is read before the next group overwrites it
-      goff += ng;
+      G[e] = sum;
     }
+    __syncthreads();
+    col_fft(InvT{}, ngc, G, l);
+    for (int e = tid; e < ng * kColW; e += kThreads)
+      a.Z[S.zoff + (long long)(goff + (e >> 4)) * nx + c0 + (e & 15)] = G[e];
+    __syncthreads();  // G is read before the next group overwrites it
+    goff += ng;
+  });
 }
 
 // ------------------------------------------------------------------ analysis
@@ -348,6 +381,8 @@ hipError_t set_lds_limits_ortho(size_t synth, size_t cols, size_t anal) {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_ocols<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cols);
   if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_ocols<16, 4, 256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cols);
+  if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_ocols<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cols);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_oanal, hipFuncAttributeMaxDynamicSharedMemorySize, (int)anal);
@@ -360,9 +395,11 @@ hipError_t launch_osynth(const KArgs& a, size_t lds, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_ocols(const KArgs& a, int ept, size_t lds, hipStream_t st) {
+hipError_t launch_ocols(const KArgs& a, int ept, int ny_all, size_t lds, hipStream_t st) {
   if (a.nwork <= 0) return hipSuccess;
-  if (ept == 16)
+  if (ept == 16 && ny_all == 256 && a.levels == 4)  // the 256-row slices of 4-level plans
+    hipLaunchKernelGGL((k_ocols<16, 4, 256>), dim3(a.nwork), dim3(kThreads), lds, st, a);
+  else if (ept == 16)
     hipLaunchKernelGGL((k_ocols<16>), dim3(a.nwork), dim3(kThreads), lds, st, a);
   else
     hipLaunchKernelGGL((k_ocols<32>), dim3(a.nwork), dim3(kThreads), lds, st, a);
