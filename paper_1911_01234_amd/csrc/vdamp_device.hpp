@@ -191,6 +191,18 @@ __device__ __forceinline__ void fft_cols16_n(float2* buf, const float2* tw) {
   }
 }
 
+// fft_lines (rows: consecutive threads take consecutive butterflies of one line) for a
+// power-of-two length N fixed at compile time, lines at buf[line * ls + i].
+template <bool INV, int EPT, int N, int NS = 1>
+__device__ __forceinline__ void fft_rows_n(float2* buf, int nlines, int ls, const float2* tw) {
+  static_assert((N & (N - 1)) == 0, "power-of-two length");
+  if constexpr (NS < N) {
+    constexpr int R = ((N / NS) % 4 == 0) ? 4 : 2;
+    fft_stage<R, INV, false, EPT>(buf, N, NS, nlines, ls, 1, tw);
+    fft_rows_n<INV, EPT, N, NS * R>(buf, nlines, ls, tw);
+  }
+}
+
 // f(std::integral_constant<int, I>) for I = 0 .. N-1, unrolled at compile time.
 template <int N, int I = 0, class F>
 __device__ __forceinline__ void static_for(F&& f) {

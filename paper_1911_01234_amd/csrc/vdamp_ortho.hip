@@ -64,6 +64,10 @@ __device__ __forceinline__ float2 conj_mul(float2 f, float2 v) {  // conj(f) v
 
 
 // ------------------------------------------------------------------ synthesis
+template <int NXC, int LC>
+__device__ __forceinline__ void osynth_group(const KArgs& a, const SliceDev& S, float2* buf, float2* tw_s, int sl,
+                                             int item_y, int l_, int kind, int ng, int goff);
+
 __global__ void __launch_bounds__(kThreads) k_osynth(KArgs a) {
   extern __shared__ float4 lds4[];
   float2* buf = reinterpret_cast<float2*>(lds4);
@@ -85,7 +89,26 @@ __global__ void __launch_bounds__(kThreads) k_osynth(KArgs a) {
   }
   int l, kind, ng, goff;
   group_of(item.y, ny, s, l, kind, ng, goff);
-  const int rpi = rows_per_item(ng), i0 = item.y - goff;
+  // 256-wide slices of 4-level plans: the level's lengths fixed at compile time
+  if (nx == 256 && s == 4) {
+    if (l == 1) osynth_group<256, 1>(a, S, buf, tw_s, sl, item.y, l, kind, ng, goff);
+    else if (l == 2) osynth_group<256, 2>(a, S, buf, tw_s, sl, item.y, l, kind, ng, goff);
+    else if (l == 3) osynth_group<256, 3>(a, S, buf, tw_s, sl, item.y, l, kind, ng, goff);
+    else osynth_group<256, 4>(a, S, buf, tw_s, sl, item.y, l, kind, ng, goff);
+  } else {
+    osynth_group<0, 0>(a, S, buf, tw_s, sl, item.y, l, kind, ng, goff);
+  }
+}
+
+// The group-row work of the synthesis pass: line 8 on the band rows of the group rows,
+// their DFTs, times the x responses, into Z.  NXC, LC > 0: the slice width and the level
+// at compile time.
+template <int NXC, int LC>
+__device__ __forceinline__ void osynth_group(const KArgs& a, const SliceDev& S, float2* buf, float2* tw_s, int sl,
+                                             int item_y, int l_, int kind, int ng, int goff) {
+  const int ny = S.ny, nx = NXC ? NXC : S.nx, s = LC ? 4 : a.levels, tid = threadIdx.x, mode = a.mode;
+  const int l = LC ? LC : l_;
+  const int rpi = rows_per_item(ng), i0 = item_y - goff;
   const int mx = nx >> l, nseg = (kind || l == s) ? 2 : 1, j0 = 2 - nseg, seglen = nseg * mx;
   const int row0 = (kind ? (ny >> l) : 0) + i0;  // coefficient row of group row i0
   const FftPlanDev& P = a.ffts[a.slices[sl].fft_xl[l]];  // (indexing the local copy would put it in scratch)
@@ -106,13 +129,16 @@ __global__ void __launch_bounds__(kThreads) k_osynth(KArgs a) {
     buf[e] = o;  // line rr * nseg + js, sample c
   }
   __syncthreads();
-  fft_lines<false, false, 16>(buf, P, rpi * nseg, mx, 1, tw_s);
+  if constexpr (NXC > 0 && LC > 0)
+    fft_rows_n<false, 16, (NXC >> LC)>(buf, rpi * nseg, mx, tw_s);
+  else
+    fft_lines<false, false, 16>(buf, P, rpi * nseg, mx, 1, tw_s);
   for (int e = tid; e < rpi * nx; e += kThreads) {
     const int rr = e / nx, kx = e - rr * nx, k = kx % mx;
     float2 acc = make_float2(0.f, 0.f);
     for (int js = 0; js < nseg; ++js)
       acc = cadd(acc, cmul(Fx[(j0 + js) * nx + kx], buf[(rr * nseg + js) * mx + k]));
-    a.Z[S.zoff + (long long)(item.y + rr) * nx + kx] = acc;
+    a.Z[S.zoff + (long long)(item_y + rr) * nx + kx] = acc;
   }
 }
 
@@ -314,6 +340,10 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
 // ------------------------------------------------------------------ analysis
 // Dynamic LDS: the item's group rows (rpi x nx), its band rows (rpi x nseg x m) and the
 // x responses of A_l and D_l.
+template <int NXC, int LC>
+__device__ __forceinline__ void oanal_group(const KArgs& a, const SliceDev& S, float2* Zs, float2* tw_s, int sl,
+                                            int item_y, int l_, int kind, int ng, int goff);
+
 __global__ void __launch_bounds__(kThreads) k_oanal(KArgs a) {
   extern __shared__ float4 lds4[];
   float2* Zs = reinterpret_cast<float2*>(lds4);
@@ -335,7 +365,26 @@ __global__ void __launch_bounds__(kThreads) k_oanal(KArgs a) {
   }
   int l, kind, ng, goff;
   group_of(item.y, ny, s, l, kind, ng, goff);
-  const int rpi = rows_per_item(ng), i0 = item.y - goff;
+  // 256-wide slices of 4-level plans: the level's lengths fixed at compile time
+  if (nx == 256 && s == 4) {
+    if (l == 1) oanal_group<256, 1>(a, S, Zs, tw_s, sl, item.y, l, kind, ng, goff);
+    else if (l == 2) oanal_group<256, 2>(a, S, Zs, tw_s, sl, item.y, l, kind, ng, goff);
+    else if (l == 3) oanal_group<256, 3>(a, S, Zs, tw_s, sl, item.y, l, kind, ng, goff);
+    else oanal_group<256, 4>(a, S, Zs, tw_s, sl, item.y, l, kind, ng, goff);
+  } else {
+    oanal_group<0, 0>(a, S, Zs, tw_s, sl, item.y, l, kind, ng, goff);
+  }
+}
+
+// The group-row work of the analysis pass: fold each group row into its bands, inverse
+// DFTs of the band rows, line 4.  NXC, LC > 0: the slice width and the level at compile
+// time (band rows of NXC >> LC samples).
+template <int NXC, int LC>
+__device__ __forceinline__ void oanal_group(const KArgs& a, const SliceDev& S, float2* Zs, float2* tw_s, int sl,
+                                            int item_y, int l_, int kind, int ng, int goff) {
+  const int ny = S.ny, nx = NXC ? NXC : S.nx, s = LC ? 4 : a.levels, tid = threadIdx.x, mode = a.mode;
+  const int l = LC ? LC : l_;
+  const int rpi = rows_per_item(ng), i0 = item_y - goff;
   const int mx = nx >> l, nseg = (kind || l == s) ? 2 : 1, j0 = 2 - nseg, seglen = nseg * mx;
   const int row0 = (kind ? (ny >> l) : 0) + i0, nal = 1 << l;
   float2* Ss = Zs + 8 * nx;
@@ -344,17 +393,22 @@ __global__ void __launch_bounds__(kThreads) k_oanal(KArgs a) {
   load_twiddles(tw_s, P, a.twiddles);
   for (int i = tid; i < 2 * nx; i += kThreads)
     Fx[i] = a.resp[S.xresp_off + filt_index(l, i >= nx, s) * nx + (i >= nx ? i - nx : i)];
-  for (int e = tid; e < rpi * nx; e += kThreads) Zs[e] = a.Z[S.zoff + (long long)item.y * nx + e];
+  for (int e = tid; e < rpi * nx; e += kThreads) Zs[e] = a.Z[S.zoff + (long long)item_y * nx + e];
   __syncthreads();
   for (int e = tid; e < rpi * seglen; e += kThreads) {
     const int rr = e / seglen, rem = e - rr * seglen, js = rem / mx, k = rem - js * mx;
     const float2* F = Fx + (j0 + js) * nx;
     float2 acc = make_float2(0.f, 0.f);
-    for (int j = 0; j < nal; ++j) acc = cadd(acc, conj_mul(F[k + j * mx], Zs[rr * nx + k + j * mx]));
+#pragma unroll
+    for (int j = 0; j < (LC ? (1 << LC) : nal); ++j)
+      acc = cadd(acc, conj_mul(F[k + j * mx], Zs[rr * nx + k + j * mx]));
     Ss[e] = acc;
   }
   __syncthreads();
-  fft_lines<true, false, 16>(Ss, P, rpi * nseg, mx, 1, tw_s);
+  if constexpr (NXC > 0 && LC > 0)
+    fft_rows_n<true, 16, (NXC >> LC)>(Ss, rpi * nseg, mx, tw_s);
+  else
+    fft_lines<true, false, 16>(Ss, P, rpi * nseg, mx, 1, tw_s);
   const float* th = a.theta + sl * kMaxBands;
   const float* t2 = a.thr2 + sl * kMaxBands;
   const float* al = a.alpha + sl * kMaxBands;
