@@ -53,8 +53,11 @@ __device__ __forceinline__ long long cube_to_global(int cz, int cy, int cx, int 
 // bit 1 = y, bit 2 = z.  The transform is its own inverse, so analysis (2x2x2 block ->
 // octants) and synthesis (octants -> block) differ only in where they read and write.
 // Every thread reads all its groups before the workgroup writes any.
-template <bool SYNTH>
-__device__ void haar3_level(float2* buf, int C, int W, int l) {
+// CC, WC > 0: the cube and brick widths at compile time (then l must be a constant too
+// for the index arithmetic to fold; the callers unroll the level loop).
+template <bool SYNTH, int CC = 0, int WC = 0>
+__device__ __forceinline__ void haar3_level(float2* buf, int C_, int W_, int l) {
+  const int C = CC ? CC : C_, W = WC ? WC : W_;
   const int h = C >> l, m = W / C, h3 = h * h * h, cnt = m * h3;
   constexpr int G = 2;  // groups a thread: m h^3 <= 512 for every brick the plan builds
   float2 v[G][8];
@@ -108,15 +111,30 @@ __device__ void haar3_level(float2* buf, int C, int W, int l) {
 // they are) -> image brick -> a.X.  Analysis: image a.X -> coefficients; RA_VDAMP:
 // r = r_tilde(r) + coefficients, RA_VDAMP_FIRST: r = coefficients, OA_COEF: a.out.
 // Dynamic LDS: the brick, 2^s x 2^s x W complex (at most 4096).
+template <bool SYNTH, int SL, int WC>
+__device__ __forceinline__ void k3_haar_body(const KArgs& a, float2* buf, float* th_s, float* t2_s, float* al_s);
+
 template <bool SYNTH>
 __global__ void __launch_bounds__(kThreads) k3_haar(KArgs a) {
   extern __shared__ float4 lds4[];
   float2* buf = reinterpret_cast<float2*>(lds4);
   __shared__ float th_s[kMaxBands], t2_s[kMaxBands], al_s[kMaxBands];
   const int2 item = a.work[blockIdx.x];
+  const int sl = item.x, s = a.levels, W = a.slices[sl].bw3;
+  // the bricks of 64^3 volumes at 3 levels and 32^3 volumes at 2 levels (64 and 32 wide):
+  // levels and widths at compile time
+  if (s == 3 && W == 64) k3_haar_body<SYNTH, 3, 64>(a, buf, th_s, t2_s, al_s);
+  else if (s == 2 && W == 32) k3_haar_body<SYNTH, 2, 32>(a, buf, th_s, t2_s, al_s);
+  else k3_haar_body<SYNTH, 0, 0>(a, buf, th_s, t2_s, al_s);
+}
+
+// The brick's work: SL, WC > 0 fix the level count and the brick width at compile time.
+template <bool SYNTH, int SL, int WC>
+__device__ __forceinline__ void k3_haar_body(const KArgs& a, float2* buf, float* th_s, float* t2_s, float* al_s) {
+  const int2 item = a.work[blockIdx.x];
   const int sl = item.x;
   const SliceDev S = a.slices[sl];
-  const int nd = S.nd, ny = S.ny, nx = S.nx, s = a.levels, C = 1 << s, W = S.bw3;
+  const int nd = S.nd, ny = S.ny, nx = S.nx, s = SL ? SL : a.levels, C = 1 << s, W = WC ? WC : S.bw3;
   const int nbx = nx / W, nby = ny / C, m = W / C;
   const int bx = item.y % nbx, by = (item.y / nbx) % nby, bz = item.y / (nbx * nby);
   const int tid = threadIdx.x, mode = a.mode;
@@ -142,10 +160,16 @@ __global__ void __launch_bounds__(kThreads) k3_haar(KArgs a) {
     }
   }
   __syncthreads();
-  if (SYNTH)
+  if constexpr (SL > 0 && WC > 0) {
+    static_for<SL>([&](auto li) __attribute__((always_inline)) {
+      constexpr int l = SYNTH ? SL - decltype(li)::value : decltype(li)::value + 1;
+      haar3_level<SYNTH, (1 << SL), WC>(buf, C, W, l);
+    });
+  } else if (SYNTH) {
     for (int l = s; l >= 1; --l) haar3_level<true>(buf, C, W, l);
-  else
+  } else {
     for (int l = 1; l <= s; ++l) haar3_level<false>(buf, C, W, l);
+  }
   for (int e = tid; e < n; e += kThreads) {
     const int lx = e % W, cy = (e / W) % C, cz = e / (W * C);
     if (SYNTH) {
