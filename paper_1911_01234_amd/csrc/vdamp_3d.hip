@@ -285,22 +285,29 @@ __global__ void __launch_bounds__(kThreads) k3_axis(KArgs a) {
     const float* ytab = a.tables + S.ytab_off;
     const float* xtab = a.tables + S.xtab_off;
     const int lane = tid & 63, wid = tid >> 6;
-    for (int b = 0; b < a.nbands; ++b) {
-      int tz, ty, tx;
-      if (b == 0) { tz = ty = tx = s - 1; }
-      else {
-        const int l = s - (b - 1) / 7, k = (b - 1) % 7 + 1;
-        tz = (k & 4) ? s + l - 1 : l - 1;
-        ty = (k & 2) ? s + l - 1 : l - 1;
-        tx = (k & 1) ? s + l - 1 : l - 1;
-      }
-      float qv = 0.f;
+    float vb[32];  // this lane's term of every band (1 + 7 s <= 29 bands)
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-        if (t == tz) qv = Q[t];
-      const float part = wave_sum(qv * ytab[ty * ny + ky] * xtab[tx * nx + kx]);
-      if (lane == 0) red[wid][b] = part;
+    for (int b = 0; b < 32; ++b) {
+      vb[b] = 0.f;
+      if (b < a.nbands) {
+        int tz, ty, tx;
+        if (b == 0) { tz = ty = tx = s - 1; }
+        else {
+          const int l = s - (b - 1) / 7, k = (b - 1) % 7 + 1;
+          tz = (k & 4) ? s + l - 1 : l - 1;
+          ty = (k & 2) ? s + l - 1 : l - 1;
+          tx = (k & 1) ? s + l - 1 : l - 1;
+        }
+        float qv = 0.f;
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (t == tz) qv = Q[t];
+        vb[b] = qv * ytab[ty * ny + ky] * xtab[tx * nx + kx];
+      }
     }
+    const float part = wave_sum_rs<32>(vb);  // band (lane >> 1) & 31
+    const int bl = (lane >> 1) & 31;
+    if ((lane & 1) == 0 && bl < a.nbands) red[wid][bl] = part;
   }
   __syncthreads();
   if (vd && tid < a.nbands) {

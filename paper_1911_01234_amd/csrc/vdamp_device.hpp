@@ -607,4 +607,26 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Sums over the wave of NV values a lane at once (reduce-scatter, NV = 2^k <= 64): at
+// each step xor 32, 16, ... a lane keeps the half of its values its lane bit selects
+// and adds the partner's copy of it; once one value is left, the remaining xor steps
+// finish its sum.  Lane l returns the sum of v[(l >> (6 - k)) & (NV - 1)] over the 64
+// lanes: NV + 6 - k shuffles where NV wave_sum calls take 6 NV.
+template <int NV, int O = 32>
+__device__ __forceinline__ float wave_sum_rs(const float (&v)[NV]) {
+  if constexpr (NV == 1) {
+    float w = v[0];
+#pragma unroll
+    for (int o = O; o >= 1; o >>= 1) w += __shfl_xor(w, o, 64);
+    return w;
+  } else {
+    const bool hi = threadIdx.x & O;
+    float h[NV / 2];
+#pragma unroll
+    for (int i = 0; i < NV / 2; ++i)
+      h[i] = (hi ? v[i + NV / 2] : v[i]) + __shfl_xor(hi ? v[i] : v[i + NV / 2], O, 64);
+    return wave_sum_rs<NV / 2, O / 2>(h);
+  }
+}
+
 }  // namespace vdamp

@@ -286,21 +286,28 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
     // tau_b partial = sum over this strip's columns of Xtab_b(kx) sum_ky Ytab_b(ky) c
     const float* xtab = a.tables + S.xtab_off;
     const int lane = tid & 63, wid = tid >> 6;
-    for (int b = 0; b < a.nbands; ++b) {
-      int ty, tx;
-      if (b == 0) { ty = s - 1; tx = s - 1; }
-      else {
-        const int l = s - (b - 1) / 3, k3 = (b - 1) % 3;
-        ty = (k3 == 0) ? l - 1 : s + l - 1;
-        tx = (k3 == 1) ? l - 1 : s + l - 1;
-      }
-      float qv = 0.f;
+    float vb[16];  // this lane's term of every band (1 + 3 s <= 13 bands)
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-        if (t == ty) qv = Q[t];
-      const float part = wave_sum(qv * xtab[tx * nx + kx]);
-      if (lane == 0) red[wid][b] = part;
+    for (int b = 0; b < 16; ++b) {
+      vb[b] = 0.f;
+      if (b < a.nbands) {
+        int ty, tx;
+        if (b == 0) { ty = s - 1; tx = s - 1; }
+        else {
+          const int l = s - (b - 1) / 3, k3 = (b - 1) % 3;
+          ty = (k3 == 0) ? l - 1 : s + l - 1;
+          tx = (k3 == 1) ? l - 1 : s + l - 1;
+        }
+        float qv = 0.f;
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (t == ty) qv = Q[t];
+        vb[b] = qv * xtab[tx * nx + kx];
+      }
     }
+    const float part = wave_sum_rs<16>(vb);  // band (lane >> 2) & 15
+    const int bl = (lane >> 2) & 15;
+    if ((lane & 3) == 0 && bl < a.nbands) red[wid][bl] = part;
   }
   __syncthreads();
   if (vd && tid < a.nbands) {

@@ -249,22 +249,29 @@ __global__ void __launch_bounds__(kThreads) k_cols(KArgs a) {
     const float* xtab = a.tables + S.xtab_off;
     const int kx = c0 + 2 * cp;
     const int lane = tid & 63, wid = tid >> 6;
-    for (int b = 0; b < a.nbands; ++b) {
-      int ty, tx;
-      if (b == 0) { ty = s - 1; tx = s - 1; }
-      else {
-        const int l = s - (b - 1) / 3, kind = (b - 1) % 3;
-        const int L = l - 1, Hh = s + l - 1;
-        ty = (kind == 0) ? L : Hh;
-        tx = (kind == 1) ? L : Hh;
-      }
-      float q0 = 0.f, q1 = 0.f;
+    float vb[16];  // this lane's term of every band (1 + 3 s <= 13 bands)
 #pragma unroll
-      for (int t = 0; t < 8; ++t)
-        if (t == ty) { q0 = Q0[t]; q1 = Q1[t]; }
-      const float part = wave_sum(q0 * xtab[tx * nx + kx] + q1 * xtab[tx * nx + kx + 1]);
-      if (lane == 0) red[wid][b] = part;
+    for (int b = 0; b < 16; ++b) {
+      vb[b] = 0.f;
+      if (b < a.nbands) {
+        int ty, tx;
+        if (b == 0) { ty = s - 1; tx = s - 1; }
+        else {
+          const int l = s - (b - 1) / 3, kind = (b - 1) % 3;
+          const int L = l - 1, Hh = s + l - 1;
+          ty = (kind == 0) ? L : Hh;
+          tx = (kind == 1) ? L : Hh;
+        }
+        float q0 = 0.f, q1 = 0.f;
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (t == ty) { q0 = Q0[t]; q1 = Q1[t]; }
+        vb[b] = q0 * xtab[tx * nx + kx] + q1 * xtab[tx * nx + kx + 1];
+      }
     }
+    const float part = wave_sum_rs<16>(vb);  // band (lane >> 2) & 15
+    const int bl = (lane >> 2) & 15;
+    if ((lane & 3) == 0 && bl < a.nbands) red[wid][bl] = part;
   }
   if (mode == CM_FISTA_OBJ) {  // the residual's partial sum is all this mode writes
     const float part = wave_sum(rsum);
@@ -446,25 +453,32 @@ __global__ void __launch_bounds__(cols4_threads(M)) k_cols4(KArgs a) {
     const float* xtab = a.tables + S.xtab_off;
     const int kx = c0 + c;
     const int lane = tid & 63, wid = tid >> 6;
-    for (int b = 0; b < a.nbands; ++b) {
-      int ty, tx;
-      if (b == 0) { ty = s - 1; tx = s - 1; }
-      else {
-        const int l = s - (b - 1) / 3, kind = (b - 1) % 3;
-        const int L = l - 1, Hh = s + l - 1;
-        ty = (kind == 0) ? L : Hh;
-        tx = (kind == 1) ? L : Hh;
-      }
-      const bool hb = ty >= s;
-      const int tt = hb ? ty - s : ty;
-      float q0 = 0.f;
+    float vb[16];  // this lane's term of every band (1 + 3 s <= 13 bands)
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (t == tt) q0 = hb ? QH[t] : QL[t];
-      q0 *= (float)(2 << tt) / (float)N;
-      const float part = wave_sum(q0 * xtab[tx * nx + kx]);
-      if (lane == 0) red[wid][b] = part;
+    for (int b = 0; b < 16; ++b) {
+      vb[b] = 0.f;
+      if (b < a.nbands) {
+        int ty, tx;
+        if (b == 0) { ty = s - 1; tx = s - 1; }
+        else {
+          const int l = s - (b - 1) / 3, kind = (b - 1) % 3;
+          const int L = l - 1, Hh = s + l - 1;
+          ty = (kind == 0) ? L : Hh;
+          tx = (kind == 1) ? L : Hh;
+        }
+        const bool hb = ty >= s;
+        const int tt = hb ? ty - s : ty;
+        float q0 = 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t == tt) q0 = hb ? QH[t] : QL[t];
+        q0 *= (float)(2 << tt) / (float)N;
+        vb[b] = q0 * xtab[tx * nx + kx];
+      }
     }
+    const float part = wave_sum_rs<16>(vb);  // band (lane >> 2) & 15
+    const int bl = (lane >> 2) & 15;
+    if ((lane & 3) == 0 && bl < a.nbands) red[wid][bl] = part;
   }
   if (mode == CM_FISTA_OBJ) {  // the residual's partial sum is all this mode writes
     const float part = wave_sum(rsum);
