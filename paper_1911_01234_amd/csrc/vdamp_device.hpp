@@ -484,11 +484,15 @@ __device__ __forceinline__ float2 soft_c(float2 v, float th, float th2) {
   return make_float2(v.x * g, v.y * g);
 }
 
-// line 8: r_tilde = (eta(r) - alpha r) / (1 - alpha), with inv = 1 / (1 - alpha) of the
-// band computed once (the same IEEE quotient rtilde_c forms per coefficient)
+// line 8: r_tilde = (eta(r) - alpha r) / (1 - alpha) = r (g - alpha) / (1 - alpha) with
+// g = max(0, 1 - theta/|r|) the shrink factor of eta (0 at or below the threshold's key),
+// inv = 1 / (1 - alpha) of the band computed once (the same IEEE quotient rtilde_c forms
+// per coefficient): one factor a coefficient, then two multiplies
 __device__ __forceinline__ float2 rtilde_ci(float2 v, float th, float th2, float al, float inv) {
-  const float2 w = soft_c(v, th, th2);
-  return make_float2((w.x - al * v.x) * inv, (w.y - al * v.y) * inv);
+  const float key = key_rn(v);
+  const float g = (key > th2) ? 1.0f - th * rsqrtf(key) : 0.f;
+  const float f = (g - al) * inv;
+  return make_float2(v.x * f, v.y * f);
 }
 __device__ __forceinline__ float2 rtilde_c(float2 v, float th, float th2, float al) {
   return rtilde_ci(v, th, th2, al, 1.0f / (1.0f - al));
@@ -510,12 +514,14 @@ __device__ __forceinline__ void soft_pair(float2& u, float2& v, float th, float 
   u = make_float2(u.x * g, u.y * g);
   v = make_float2(v.x * g, v.y * g);
 }
-// line 8 for the pair: (eta(g) - alpha g) / (1 - alpha), inv = 1 / (1 - alpha)
+// line 8 for the pair: (eta(g) - alpha g) / (1 - alpha) = g (s - alpha) / (1 - alpha)
+// with s the pair's shrink factor, inv = 1 / (1 - alpha)
 __device__ __forceinline__ void rtilde_pair(float2& u, float2& v, float th, float th2, float al, float inv) {
-  float2 wu = u, wv = v;
-  soft_pair(wu, wv, th, th2);
-  u = make_float2((wu.x - al * u.x) * inv, (wu.y - al * u.y) * inv);
-  v = make_float2((wv.x - al * v.x) * inv, (wv.y - al * v.y) * inv);
+  const float key = key_pair_rn(u, v);
+  const float g = (key > th2) ? 1.0f - th * rsqrtf(key) : 0.f;
+  const float f = (g - al) * inv;
+  u = make_float2(u.x * f, u.y * f);
+  v = make_float2(v.x * f, v.y * f);
 }
 
 // line 8 for a general denoiser output w: (w - alpha r) / (1 - alpha)
