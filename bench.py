@@ -99,9 +99,9 @@ def algorithmic_bytes_per_solve(npx, iters, bytes_=None):
 def algorithmic_bytes_per_solve_3d(npx, iters):
     """Volumes (vdamp_plan_3d), per kernel class and voxel: rows_synth = the Haar
     synthesis (read r, write X); cols = the DFT passes along x, y (X read and written)
-    and z (X, y, m/p read, X written; first iteration no X read; line 10: z pass and
+    and z (X, y, m/p read, X written; first iteration no X read; the output step: z pass and
     inverse y, x into x_hat under rows_anal); rows_anal = the Haar analysis (read X and
-    r, write r; first: no r read) and line 10's inverse x DFTs (read X, write x_hat)."""
+    r, write r; first: no r read) and the output step's inverse x DFTs (read X, write x_hat)."""
     rs = 16.0 * iters
     cols = (20 + 16 + 16) + (16 + 16 + 28 + 16 + 16) * (iters - 1) + (16 + 16 + 28 + 16)
     ra = 16.0 + 24.0 * (iters - 1) + 16.0

@@ -84,14 +84,14 @@ enum {
      (Section 3 solves the SURE problem "approximately"; this is its exact minimiser):
      between consecutive distinct magnitudes SURE is a convex quadratic in theta, whose
      minimum tau R_m / (2 (N_b - m)) competes with the candidates when it lies inside its
-     interval.  Line 7's alpha and line 6's eta use the threshold found. */
+     interval.  The alpha step's alpha and the denoising step's eta use the threshold found. */
   VDAMP_FLAG_SURE_CONTINUOUS = 1u << 7,
   /* Structured sparsity (Section 4 names it among the richer models SURE can tune):
      the two horizontally adjacent coefficients x = 2j, 2j+1 of every subband row form a
      group, shrunk jointly by group soft thresholding g max(0, 1 - theta/||g||).  theta
      minimises the group's SURE (Stein's estimate over the 4 real dimensions of a pair
      under CN(0, tau) noise per coefficient) over the candidates ||g|| (or over every
-     theta > 0 with VDAMP_FLAG_SURE_CONTINUOUS); line 7's alpha is half the real
+     theta > 0 with VDAMP_FLAG_SURE_CONTINUOUS); the alpha step's alpha is half the real
      divergence per coefficient.  theta's key is the FP32 squared norm of the pair
      (|g_0|^2 + |g_1|^2, each term as for one coefficient, their sum rounded to nearest).
      2D Haar plans of vdamp_plan only (VDAMP_ERR_UNSUPPORTED elsewhere); fista_solve and
@@ -102,9 +102,9 @@ enum {
 /* Kernel classes reported by vdamp_pass_times(). */
 enum {
   VDAMP_PASS_PREP = 0,      /* mask/p -> m/p weights, data checks                   */
-  VDAMP_PASS_ROWS_SYNTH = 1,/* line 8 + Psi^H on row strips, then row FFT            */
+  VDAMP_PASS_ROWS_SYNTH = 1,/* the Onsager correction + Psi^H on row strips, then row FFT            */
   VDAMP_PASS_COLS = 2,      /* column FFT, k-space residual, tau partials, col IFFT  */
-  VDAMP_PASS_ROWS_ANAL = 3, /* row IFFT, Psi on row strips, + r_tilde (line 4)       */
+  VDAMP_PASS_ROWS_ANAL = 3, /* row IFFT, Psi on row strips, + r_tilde (back-projection)       */
   VDAMP_PASS_SURE = 4,      /* tau reduction, SURE threshold search, alpha           */
   VDAMP_PASS_DENOISER = 5,  /* learned denoiser: Psi / Psi^H, probe, partial sums, judge */
   VDAMP_PASS_CNN = 6,       /* learned denoiser: the network's forward pass and JVP    */
@@ -122,7 +122,7 @@ enum {
  *   flags           VDAMP_FLAG_* bits
  *   workspace_bytes out: size of the device workspace every solve call needs
  * Builds, on the host in FP64 then rounded to FP32, the separable tau weights
- * S_b = |Phi Psi^H|^2 of line 1 (Section 2: S has 1 + 3s unique columns), the FFT
+ * S_b = |Phi Psi^H|^2 of the initialisation (Section 2: S has 1 + 3s unique columns), the FFT
  * twiddles and the work lists, and uploads them (synchronous, once per plan).
  */
 vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, const int32_t* nx,
@@ -140,7 +140,7 @@ vdamp_status vdamp_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* ny, co
  * Psi is the s-level periodic Mallat transform: one level filters the top-left block
  * along x, a[j] = sum_t h[t] x[(2j + t) mod M] to the left half and d[j] with g to the
  * right, then the same along y; band order and layout as for Haar.  Any filter length
- * works: the filters wrap periodically at the coarse levels.  The tau weights of line 1
+ * works: the filters wrap periodically at the coarse levels.  The tau weights of the initialisation
  * are |DFT of each band's basis function|^2, separable, computed on the host in FP64.
  * The plan serves vdamp_solve, vdamp_solve_resume, vdamp_solve_noalloc,
  * vdamp_state_export and vdamp_wavelet_ws; fista_solve, vdamp_wavelet and the learned
@@ -165,7 +165,7 @@ vdamp_status vdamp_plan_ortho(vdamp_plan_h* plan, int32_t batch, const int32_t* 
  *                   bit 2: along z), each block at (k&4 ? nz>>l : 0, k&2 ? ny>>l : 0,
  *                   k&1 ? nx>>l : 0) of size (nz>>l, ny>>l, nx>>l)
  *   flags           as vdamp_plan (VDAMP_FLAG_AUTOTUNE is not accepted)
- * The tau weights of line 1 are separable: S_b = Z_b(kz) Y_b(ky) X_b(kx).  The plan
+ * The tau weights of the initialisation are separable: S_b = Z_b(kz) Y_b(ky) X_b(kx).  The plan
  * serves vdamp_solve, vdamp_solve_resume, vdamp_solve_noalloc, vdamp_state_export and
  * vdamp_wavelet_ws, with y, mask, p, x_hat, r as packed volumes and theta, alpha, tau
  * with 1 + 7 s entries per volume; fista_solve, vdamp_wavelet and the learned
@@ -188,7 +188,7 @@ vdamp_status vdamp_plan_destroy(vdamp_plan_h plan);
 vdamp_status vdamp_plan_describe(vdamp_plan_h plan, char* buf, size_t len, size_t* needed);
 
 /*
- * vdamp_solve -- run `iters` iterations of Algorithm 1 on every slice, then line 10.
+ * vdamp_solve -- run `iters` iterations of Algorithm 1 on every slice, then the output step.
  *   stream          HIP stream to enqueue on
  *   workspace       device buffer of at least workspace_bytes, 256-byte aligned; holds
  *                   the iterate r_k and the per-band state between calls
@@ -199,9 +199,10 @@ vdamp_status vdamp_plan_describe(vdamp_plan_h plan, char* buf, size_t len, size_
  *   sigma2          float32[B]: measurement noise variance E|eps_j|^2 per slice
  *   iters           K >= 0; K = 0 returns the zero-filled F^H y
  *   x_hat           complex64[sum N] out: Psi^H w + Phi^H (y - Phi Psi^H w), with
- *                   w = w_hat_{K-1} (line 10)
+ *                   w = w_hat_{K-1} (output step)
  *   trace           nullable float32[iters][B][nb][3] out: (tau_k, theta_k, alpha_k) per
- *                   band (lines 5-7); theta_k = lambda_k tau_k in eq. 7's terms
+ *                   band (tau estimate, denoising and alpha steps); theta_k = lambda_k tau_k
+ *                   in eq. 7's terms
  * FP32 arithmetic with FP64 threshold search; results are bitwise reproducible for a
  * given plan (fixed-order reductions, no floating-point atomics).
  */
@@ -212,8 +213,9 @@ vdamp_status vdamp_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
 
 /*
  * vdamp_solve_resume -- vdamp_solve from a given state, with an optional per-iteration
- * output.  The state of Algorithm 1 between iterations is (r_k, theta_k, alpha_k): lines
- * 6-8 rebuild r_tilde_{k+1} from it, and lines 3-5 need nothing else.
+ * output.  The state of Algorithm 1 between iterations is (r_k, theta_k, alpha_k): the
+ * denoising, alpha and Onsager-correction steps rebuild r_tilde_{k+1} from it, and the
+ * k-space step needs nothing else.
  *   r_init          nullable complex64[sum N]: r_k (Mallat layout per slice).  Null: a
  *                   fresh start (r_tilde_0 = 0), exactly vdamp_solve; theta_init,
  *                   theta2_init and alpha_init must then be null too.
@@ -223,10 +225,10 @@ vdamp_status vdamp_solve(vdamp_plan_h plan, hipStream_t stream, void* workspace,
  *                   against; vdamp_state_export returns it.  Null: fl(theta * theta).
  *                   With it, a solve split into two calls is bitwise equal to one call.
  *   alpha_init      float32[B][nb] (required with r_init): alpha_k per band, in [0, 1)
- *   iters           K >= 0 further iterations; each starts with line 8 applied to the
- *                   previous state.  K = 0 with r_init gives line 10 with w = eta(r_k; theta_k).
+ *   iters           K >= 0 further iterations; each starts with the Onsager correction applied to the
+ *                   previous state.  K = 0 with r_init gives the output step with w = eta(r_k; theta_k).
  *   x_hat, trace    as in vdamp_solve (trace rows count this call's iterations)
- *   x_monitor       nullable complex64[iters][sum N] out: line 10 evaluated after every
+ *   x_monitor       nullable complex64[iters][sum N] out: the output step evaluated after every
  *                   iteration (the estimate x_hat_k a solve stopped there would return);
  *                   costs one more transform pass per iteration
  * Under VDAMP_FLAG_CHECK_FINITE the imported theta and alpha are validated too.
@@ -297,7 +299,7 @@ vdamp_status vdamp_pass_times(vdamp_plan_h plan, double* ms, int64_t* launches, 
 
 /* ------------------------------------------------------------------------------------
  * Learned denoiser.  Algorithm 1 accepts any denoiser g(r; tau) together with its mean
- * derivative (line 7); the conclusion proposes denoisers trained for wavelet
+ * derivative (alpha step); the conclusion proposes denoisers trained for wavelet
  * coefficients under the known colored Gaussian noise of VDAMP.  This one is a CNN in
  * the image domain, g(r) = Psi f(Psi^H r; tau), with
  *   u = (Re x, Im x) / s0,  t_b = log(max(tau_b / s0^2, 1e-12)),
@@ -339,7 +341,7 @@ vdamp_status vdamp_cnn_workspace(vdamp_cnn_h cnn, vdamp_plan_h plan, int32_t kin
 /*
  * vdamp_cnn_forward -- x_out = f(x; tau) for every slice of the plan and, if tangent is
  * non-null, jvp_out = J_f(x) tangent (the Jacobian-vector product the divergence
- * estimate of line 7 needs).
+ * estimate of the alpha step needs).
  *   x, tangent       complex64[sum N] images (device)
  *   tau              float32[B][16] noise levels per band (first nbands used)
  *   s0               float32[B] input scales (> 0)
@@ -363,10 +365,11 @@ vdamp_status vdamp_cnn_train_step(vdamp_cnn_h cnn, vdamp_plan_h plan, hipStream_
 /*
  * vdamp_solve_learned -- Algorithm 1 with the learned denoiser judged against SURE soft
  * thresholding per subband: each iteration computes soft thresholding's SURE minimum
- * (lines 6-7 as in vdamp_solve), then w_cnn = Psi f(Psi^H r; tau) and its mean
- * derivative alpha from one complex Rademacher probe b (Psi J_f Psi^H b, drawn from
- * seed by SplitMix64 as a counter-based generator), and uses w_cnn with that alpha in
- * lines 8 and 10 in the subbands where its SURE, ||w_cnn - r||^2 + (2 alpha - 1) N_b tau,
+ * (denoising and alpha steps as in vdamp_solve), then w_cnn = Psi f(Psi^H r; tau) and
+ * its mean derivative alpha from one complex Rademacher probe b (Psi J_f Psi^H b, drawn
+ * from seed by SplitMix64 as a counter-based generator), and uses w_cnn with that alpha
+ * in the Onsager correction and the output step in the subbands where its SURE,
+ * ||w_cnn - r||^2 + (2 alpha - 1) N_b tau,
  * is below soft thresholding's (judge = VDAMP_JUDGE_SURE; with VDAMP_JUDGE_NONE in
  * every subband) and alpha <= 1 - 1/N_b.  Iterations k < learned_from use soft
  * thresholding alone (the network is not evaluated), so a solve can spend the network's
@@ -389,7 +392,7 @@ vdamp_status vdamp_solve_learned(vdamp_plan_h plan, vdamp_cnn_h cnn, hipStream_t
  * band the choice (int32[B][nb], 1 = learned denoiser), the learned denoiser's SURE, its
  * alpha estimate and soft thresholding's SURE minimum (float32[B][nb] each), and the
  * input scales s0 (float32[B]); any output may be null.  vdamp_state_export gives r, theta and tau of that iteration and
- * the alpha that line 8 used (the learned one where chosen).
+ * the alpha that the Onsager correction used (the learned one where chosen).
  */
 vdamp_status vdamp_learned_export(vdamp_cnn_h cnn, vdamp_plan_h plan, hipStream_t stream,
                                   const void* cnn_workspace, int32_t* sel, float* s0,

@@ -1,7 +1,7 @@
 """FP64 oracle of the learned colored-noise denoiser that can replace soft thresholding in
 VDAMP (the paper's conclusion suggests a denoiser built for wavelet coefficients under
 known colored Gaussian noise; Algorithm 1 admits any denoiser g(r; tau) with its
-divergence in line 7).
+divergence in the alpha step).
 
 TEST INFRASTRUCTURE ONLY: used by tests/ (and nothing in the product path).
 
@@ -15,7 +15,7 @@ Network (image domain, circular padding to match the periodic model):
 conv(in; W)[co, y, x] = sum_{ci, dy, dx} W[co, ci, dy, dx] in[ci, y + dy - 1, x + dx - 1]
 (indices modulo the image size).  The wavelet-domain denoiser is
   g(r) = Psi x_out(Psi^H r),  so  J_g = Psi J_f Psi^H  (s0 cancels),
-and its divergence enters line 7 through alpha_b = mean_{i in b} Re(conj(b_i) (J_g b)_i)
+and its divergence enters the alpha step through alpha_b = mean_{i in b} Re(conj(b_i) (J_g b)_i)
 for a complex Rademacher probe b in {+-1 +- i}/sqrt2, whose expectation is the mean
 Wirtinger derivative (the same reading as for soft thresholding).
 

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY: used by tests/ (and nothing in the product path).
 
-Algorithm 1 leaves the denoiser g(r; tau) open, with its mean derivative in line 7 (the
+Algorithm 1 leaves the denoiser g(r; tau) open, with its mean derivative in the alpha step (the
 same reading as for soft thresholding: the mean Wirtinger derivative dg/dr of the
 band).  For the learned denoiser g(r) = Psi f(Psi^H r; tau) (oracle/cnn_ref.py), per
 iteration and subband b:
@@ -15,7 +15,7 @@ error, with tau the complex variance of the band's noise (real components tau/2)
 which for soft thresholding reduces to the scan form of the threshold search.  The
 learned output replaces soft thresholding in the band when SURE_cnn is below the SURE
 minimum of soft thresholding and alpha_cnn <= 1 - 1/N_b (soft thresholding's range of
-alpha, which keeps line 8's 1/(1 - alpha) bounded); otherwise the band keeps soft
+alpha, which keeps the Onsager correction's 1/(1 - alpha) bounded); otherwise the band keeps soft
 thresholding with its own theta and alpha.
 
 The probe comes from SplitMix64 (Steele, Lea and Flood, 2014) used as a counter-based
@@ -109,8 +109,8 @@ def cnn_candidate(params, r, tau, s, s0, seed, it, slice_id, bf16=True):
 
 
 def judged_denoise(params, r, tau, s, s0, seed, it, slice_id, bf16=True, always=False):
-    """Lines 6-8 with the per-band choice between soft thresholding and the learned
-    denoiser (always=True: the learned one wherever alpha_cnn <= 1 - 1/N_b, without the
+    """The denoising, alpha and Onsager-correction steps with the per-band choice
+    between soft thresholding and the learned denoiser (always=True: the learned one wherever alpha_cnn <= 1 - 1/N_b, without the
     SURE comparison).  Returns w_hat, r_tilde_next and a record of the decision."""
     ny, nx = r.shape
     w_cnn, al_c, sure_c = cnn_candidate(params, r, tau, s, s0, seed, it, slice_id, bf16)

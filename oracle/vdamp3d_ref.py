@@ -4,7 +4,7 @@ DFT; Algorithm 1 is unchanged with a 3D orthogonal wavelet).
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or execute
 this module: it is used by ``tests/``, by ``__graft_entry__.smoke()`` and by the
 ``cpu_baseline`` leg of ``bench.py``.  It shares no code with the HIP library; it reuses
-the 2D oracle's SURE search, soft threshold and line-5 estimate, which do not depend on
+the 2D oracle's SURE search, soft threshold and tau estimate, which do not depend on
 the dimension.
 
 Conventions (the 2D ones extended; each pinned by a test):
@@ -111,17 +111,18 @@ def tau_weights3(nz, ny, nx, s):
 
 
 def vdamp3_step(rt, y, mask, p, sigma2, s, S):
-    """Lines 3-5: from r_tilde_k to (r_k, tau_k)."""
+    """The k-space step: from r_tilde_k to (r_k, tau_k)."""
     om = mask.astype(bool)
-    z = np.where(om, y - fft3u(haar3_synthesis(rt, s)), 0.0)   # line 3
+    z = np.where(om, y - fft3u(haar3_synthesis(rt, s)), 0.0)   # residual step
     v = np.zeros_like(z)
     v[om] = z[om] / p[om]
-    r = rt + haar3_analysis(ifft3u(v), s)                       # line 4
-    return r, o.tau_estimate(z, mask, p, sigma2, S)            # line 5
+    r = rt + haar3_analysis(ifft3u(v), s)                       # back-projection
+    return r, o.tau_estimate(z, mask, p, sigma2, S)            # tau estimate
 
 
 def denoise3(r, tau, s, theta_override=None, alpha_override=None):
-    """Lines 6-8 per band (SURE threshold, eta, alpha, r_tilde_{k+1})."""
+    """The denoising, alpha and Onsager-correction steps per band (SURE threshold, eta,
+    alpha, r_tilde_{k+1})."""
     nz, ny, nx = r.shape
     w_hat = np.zeros_like(r)
     rt_next = np.zeros_like(r)
@@ -142,7 +143,7 @@ def denoise3(r, tau, s, theta_override=None, alpha_override=None):
 
 
 def output_step3(w_hat, y, mask, s):
-    """Line 10: x_hat = Psi^H w + Phi^H (y - Phi Psi^H w)."""
+    """The output step: x_hat = Psi^H w + Phi^H (y - Phi Psi^H w)."""
     x = haar3_synthesis(w_hat, s)
     om = mask.astype(bool)
     return x + ifft3u(np.where(om, y - fft3u(x), 0.0))
@@ -171,14 +172,14 @@ def vdamp3(y, mask, p, sigma2, s, iters, record=False):
     p = np.asarray(p, dtype=np.float64)
     check_shape3(*y.shape, s)
     S = tau_weights3(*y.shape, s)
-    rt = np.zeros(y.shape, dtype=np.complex128)            # line 1: r_tilde_0 = 0
+    rt = np.zeros(y.shape, dtype=np.complex128)            # initialisation: r_tilde_0 = 0
     return _run(rt, np.zeros_like(rt), y, mask, p, sigma2, s, S, iters, record)
 
 
 def vdamp3_resume(y, mask, p, sigma2, s, r, theta, alpha, iters, record=False):
     """Algorithm 1 continued from the state (r_k, theta_k, alpha_k): each further
-    iteration starts with lines 6-8 on the previous state.  iters = 0 gives line 10
-    with w = eta(r_k; theta_k)."""
+    iteration starts with the denoising, alpha and Onsager-correction steps on the
+    previous state.  iters = 0 gives the output step with w = eta(r_k; theta_k)."""
     y = np.asarray(y, dtype=np.complex128)
     p = np.asarray(p, dtype=np.float64)
     check_shape3(*y.shape, s)

@@ -22,9 +22,9 @@ Conventions (readings of the paper where it is silent; each is pinned by a test)
 * The denoiser is complex soft thresholding eta(r; theta) = r max(0, 1 - theta/|r|),
   with one threshold per subband (eq. 7).  The threshold minimises the complex,
   colored SURE over the candidate set theta in {|r_i|} of the band (Section 3).
-* g' of line 7 is the Wirtinger derivative (half the R^2 divergence), averaged within
+* g' of the alpha step is the Wirtinger derivative (half the R^2 divergence), averaged within
   each subband, so alpha has 1+3s entries.
-* Line 10's w is the last denoised estimate w_hat_{K-1}; with K = 0 the output is the
+* The output step's w is the last denoised estimate w_hat_{K-1}; with K = 0 the output is the
   zero-filled F^H y.
 * Structured sparsity (group=2; Section 4 names structured sparsity as a richer model
   that SURE can tune): the two horizontally adjacent coefficients (x = 2j, 2j+1) of each
@@ -175,7 +175,7 @@ def check_shape(ny, nx, s):
 
 
 # ----------------------------------------------------------------------------------
-# Line 1: S = |Phi Psi^H|^2.  For Haar it is separable per band, S_b(ky,kx) =
+# initialisation: S = |Phi Psi^H|^2.  For Haar it is separable per band, S_b(ky,kx) =
 # Y_b(ky) X_b(kx), with 1D factors the squared DFT magnitudes of the 1D scaling
 # function (length 2^m, height 2^(-m/2)) and wavelet (+- 2^(-l/2) on two halves).
 
@@ -205,7 +205,7 @@ def haar_wavelet_power(n, l):
 
 
 def tau_weights_filter(ny, nx, s, h):
-    """Line 1 for a general orthonormal Psi, from the definition S = |Phi Psi^H|^2: the
+    """The initialisation for a general orthonormal Psi, from the definition S = |Phi Psi^H|^2: the
     squared unitary DFT of the basis function of the first coefficient of each band
     (periodic filtering makes every coefficient of a band a shift of it, so the column
     of S is the same for the whole band).  A list of float64 [ny][nx] arrays."""
@@ -231,7 +231,7 @@ def tau_weights(ny, nx, s, wavelet=None):
 
 
 # ----------------------------------------------------------------------------------
-# Line 6: complex soft thresholding, and its SURE-optimal threshold (Section 3).
+# denoising step: complex soft thresholding, and its SURE-optimal threshold (Section 3).
 
 def soft(r, theta):
     """eta(r; theta) = r * max(0, 1 - theta/|r|); zero when |r| <= theta."""
@@ -266,7 +266,7 @@ def sure_threshold(a, tau, d=1):
     the last index of a run of equal values; ties of the SURE value go to the smallest
     theta.  With sorted a, A_m = sum_{i<=m} a_(i)^2 and R_m = sum_{i>m} 1/a_(i):
         SURE(m) = A_m - m tau + (N_b - m)(theta^2 + tau) - tau theta R_m.
-    alpha (line 7) = mean over the band of the Wirtinger derivative of eta, which is
+    alpha (alpha step) = mean over the band of the Wirtinger derivative of eta, which is
     1 - theta/(2|r|) above the threshold and 0 below:
         alpha = ((N_b - m) - (theta/2) R_m) / N_b.
     Returns (theta, alpha, m, sure_min).  All-zero band: theta = 0, alpha = 0.
@@ -393,7 +393,7 @@ def soft_group(rb, theta, d):
 # Algorithm 1
 
 def tau_estimate(z, mask, p, sigma2, S):
-    """Line 5: tau_b = sum_{j in Omega} S_b(j) p_j^-1 [(p_j^-1 - 1)|z_j|^2 + sigma^2]."""
+    """The tau estimate: tau_b = sum_{j in Omega} S_b(j) p_j^-1 [(p_j^-1 - 1)|z_j|^2 + sigma^2]."""
     w = np.zeros(z.shape)
     om = mask.astype(bool)
     w[om] = 1.0 / p[om]
@@ -402,19 +402,20 @@ def tau_estimate(z, mask, p, sigma2, S):
 
 
 def vdamp_step(rt, y, mask, p, sigma2, s, S, wavelet=None):
-    """Lines 3-5 for one iteration: from r_tilde_k to (r_k, tau_k)."""
+    """The k-space step for one iteration: from r_tilde_k to (r_k, tau_k)."""
     om = mask.astype(bool)
     x_t = synthesis(rt, s, wavelet)
-    z = np.where(om, y - fft2u(x_t), 0.0)                  # line 3 (zero off Omega)
+    z = np.where(om, y - fft2u(x_t), 0.0)                  # residual step (zero off Omega)
     v = np.zeros_like(z)
     v[om] = z[om] / p[om]                                  # P^-1 z, zero-filled
-    r = rt + analysis(ifft2u(v), s, wavelet)              # line 4
-    tau = tau_estimate(z, mask, p, sigma2, S)              # line 5
+    r = rt + analysis(ifft2u(v), s, wavelet)              # back-projection
+    tau = tau_estimate(z, mask, p, sigma2, S)              # tau estimate
     return r, tau
 
 
 def denoise(r, tau, s, theta_override=None, alpha_override=None, continuous=False, group=1):
-    """Lines 6-8: per band SURE threshold, eta, alpha, and the corrected r_tilde_{k+1}.
+    """The denoising, alpha and Onsager-correction steps: per band SURE threshold, eta,
+    alpha, and the corrected r_tilde_{k+1}.
     theta_override (optional, per band) replaces the SURE search; alpha then follows
     from its definition at that threshold unless alpha_override gives it too (a test
     that replays another implementation's decisions supplies both).  continuous=True
@@ -438,14 +439,14 @@ def denoise(r, tau, s, theta_override=None, alpha_override=None, continuous=Fals
                   else float(alpha_override[b]))
         wb = soft_group(rb, th, group)
         w_hat[rs, cs] = wb
-        rt_next[rs, cs] = (wb - al * rb) / (1.0 - al)      # line 8
+        rt_next[rs, cs] = (wb - al * rb) / (1.0 - al)      # Onsager correction
         thetas.append(th)
         alphas.append(al)
     return w_hat, rt_next, np.array(thetas), np.array(alphas)
 
 
 def output_step(w_hat, y, mask, s, wavelet=None):
-    """Line 10: x_hat = Psi^H w + Phi^H (y - Phi Psi^H w)."""
+    """The output step: x_hat = Psi^H w + Phi^H (y - Phi Psi^H w)."""
     x = synthesis(w_hat, s, wavelet)
     om = mask.astype(bool)
     resid = np.where(om, y - fft2u(x), 0.0)
@@ -464,7 +465,7 @@ def vdamp(y, mask, p, sigma2, s, iters, record=False, continuous=False, wavelet=
     ny, nx = y.shape
     check_shape(ny, nx, s)
     S = tau_weights(ny, nx, s, wavelet)
-    rt = np.zeros((ny, nx), dtype=np.complex128)           # line 1: r_tilde_0 = 0
+    rt = np.zeros((ny, nx), dtype=np.complex128)           # initialisation: r_tilde_0 = 0
     w_hat = np.zeros_like(rt)
     taus, thetas, alphas, rs = [], [], [], []
     for _ in range(iters):
@@ -486,9 +487,11 @@ def vdamp(y, mask, p, sigma2, s, iters, record=False, continuous=False, wavelet=
 def vdamp_resume(y, mask, p, sigma2, s, r, theta, alpha, iters, record=False, continuous=False,
                  wavelet=None, group=1):
     """Algorithm 1 continued from the state (r_k, theta_k, alpha_k) of an earlier
-    iteration: every further iteration starts with lines 6-8 applied to the previous
-    state (eta with the given thresholds, line 8 with the given alpha), then lines 3-7.
-    With iters = 0 the output is line 10 with w = eta(r_k; theta_k).  Returns the same
+    iteration: every further iteration starts with the denoising, alpha and
+    Onsager-correction steps applied to the previous state (eta with the given thresholds,
+    the Onsager correction with the given alpha), then the k-space, denoising and alpha
+    steps.  With iters = 0 the output is the output step with w = eta(r_k; theta_k).
+    Returns the same
     dict as vdamp(); the per-iteration entries count the iterations of this call."""
     y = np.asarray(y, dtype=np.complex128)
     p = np.asarray(p, dtype=np.float64)

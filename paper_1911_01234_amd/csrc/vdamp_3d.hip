@@ -2,15 +2,15 @@
 // 3D DFT) and the s-level periodic orthonormal 3D Haar transform.
 //
 // Per iteration (arrays [nz][ny][nx] per volume, row-major, packed volume after volume):
-//   k3_haar<synth>: line 8 on the coefficients of a brick of 2^s x 2^s x W voxels (whole
+//   k3_haar<synth>: the Onsager correction on the coefficients of a brick of 2^s x 2^s x W voxels (whole
 //                   2^s cubes: the 3D Haar transform never couples different cubes), the
 //                   s-level synthesis in LDS, the image brick -> X;
 //   k3_rows:        DFTs of the x rows of X (in place);
 //   k3_axis (y):    DFTs along y of 16-column strips (stride nx);
 //   k3_axis (z):    DFTs along z of 16-column strips (stride ny nx), the k-space step of
-//                   lines 3-5 with its tau partials, the inverse DFTs;
+//                   the k-space step with its tau partials, the inverse DFTs;
 //   k3_axis (y), k3_rows: the inverse DFTs;
-//   k3_haar<anal>:  analysis of each brick of X, + r_tilde (line 4), -> r.
+//   k3_haar<anal>:  analysis of each brick of X, + r_tilde (back-projection), -> r.
 // Unnormalised DFTs; the z pass applies (nz ny nx)^(-1/2) into and out of k-space.
 #include "vdamp_device.hpp"
 #include "vdamp_host.h"
@@ -107,8 +107,8 @@ __device__ __forceinline__ void haar3_level(float2* buf, int C_, int W_, int l) 
   __syncthreads();
 }
 
-// Synthesis (SYNTH): coefficients a.r (RS_RTILDE: line 8, RS_WHAT: line 6, RS_PLAIN: as
-// they are) -> image brick -> a.X.  Analysis: image a.X -> coefficients; RA_VDAMP:
+// Synthesis (SYNTH): coefficients a.r (RS_RTILDE: the Onsager correction, RS_WHAT: the
+// denoising step, RS_PLAIN: as they are) -> image brick -> a.X.  Analysis: image a.X -> coefficients; RA_VDAMP:
 // r = r_tilde(r) + coefficients, RA_VDAMP_FIRST: r = coefficients, OA_COEF: a.out.
 // Dynamic LDS: the brick, 2^s x 2^s x W complex (at most 4096).
 template <bool SYNTH, int SL, int WC>
@@ -190,7 +190,7 @@ __device__ __forceinline__ int rows_per_item3(int rows) {
 }
 
 // DFTs (INV: inverse) of the x rows item.y .. item.y + rpi - 1 of a.X, written back to
-// a.X, or to a.out when TO_OUT (line 10's image).  Dynamic LDS: rpi x nx complex.
+// a.X, or to a.out when TO_OUT (output step's image).  Dynamic LDS: rpi x nx complex.
 template <bool INV, bool TO_OUT>
 __global__ void __launch_bounds__(kThreads) k3_rows(KArgs a) {
   extern __shared__ float4 lds4[];
@@ -210,9 +210,9 @@ __global__ void __launch_bounds__(kThreads) k3_rows(KArgs a) {
 }
 
 // DFTs along y (AXIS_Y_FWD / AXIS_Y_INV) or z of a 16-column strip.  Along z the modes
-// are those of the 2D column pass: CM_VDAMP (forward DFT, lines 3-5 with tau partials,
+// are those of the 2D column pass: CM_VDAMP (forward DFT, the k-space step with tau partials,
 // inverse DFT), CM_VDAMP_FIRST (the same with r_tilde_0 = 0: no forward DFT), CM_OUTPUT
-// (line 10: (1 - m) X + m y), CM_ZEROFILL (y).  Strip item.y: (outer, 16-column block)
+// (output step: (1 - m) X + m y), CM_ZEROFILL (y).  Strip item.y: (outer, 16-column block)
 // with outer = z for y strips, y for z strips.  Dynamic LDS: the strip (n x 16 complex)
 // and, for the tau partials, the 2 s z-axis tables (nz floats each).
 template <int EPT>

@@ -1,4 +1,4 @@
-// Host side of libvdamp: argument checks, the plan (line 1's tau weights, FFT twiddles
+// Host side of libvdamp: argument checks, the plan (initialisation's tau weights, FFT twiddles
 // and radix plans, work lists), workspace layout, the pass schedule of Algorithm 1 and
 // of FISTA, optional hipGraph capture and per-pass event timing.
 #include <hip/hip_runtime.h>
@@ -218,11 +218,11 @@ struct Resume {
   const float *theta = nullptr, *theta2 = nullptr, *alpha = nullptr;
 };
 
-// Algorithm 1 on volumes: per iteration the 3D Haar synthesis of line 8's r_tilde, the
-// forward DFTs along x, y and z, the k-space step of lines 3-5 between the z DFTs, the
-// inverse DFTs along y and x, the 3D Haar analysis with line 4's + r_tilde, and the
-// threshold search of lines 6-7.  Timing classes: Haar synthesis = rows_synth, the DFT
-// and k-space passes = cols, Haar analysis = rows_anal.
+// Algorithm 1 on volumes: per iteration the 3D Haar synthesis of the Onsager-corrected
+// r_tilde, the forward DFTs along x, y and z, the k-space step between the z DFTs, the
+// inverse DFTs along y and x, the 3D Haar analysis with the back-projection's + r_tilde,
+// and the threshold search of the denoising and alpha steps.  Timing classes: Haar
+// synthesis = rows_synth, the DFT and k-space passes = cols, Haar analysis = rows_anal.
 vdamp_status enqueue_vdamp3d(vdamp_plan_t* P, hipStream_t st, void* ws, const float2* y,
                              const uint8_t* mask, const float* p, const float* sigma2, int iters,
                              float2* x_hat, float* trace, bool timing, const Resume& rs,
@@ -241,7 +241,7 @@ vdamp_status enqueue_vdamp3d(vdamp_plan_t* P, hipStream_t st, void* ws, const fl
   a.y = y;
   a.sigma2 = sigma2;
   a.trace = trace;
-  // line 10 into out: F^H [ (1 - m) F Psi^H w + m y ] (w = eta(r; theta)), or F^H y
+  // the output step into out: F^H [ (1 - m) F Psi^H w + m y ] (w = eta(r; theta)), or F^H y
   auto output = [&](float2* out, bool has_w) -> vdamp_status {
     KArgs m = a;
     m.out = out;
@@ -296,7 +296,8 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
   const int check = (P->flags & VDAMP_FLAG_CHECK_FINITE) ? 1 : 0;
   const bool resume = rs.r != nullptr;
   LAUNCH(L, VDAMP_PASS_PREP, launch_prep(mask, p, y, w.wgt, P->ntot, check, w.bad, st));
-  if (resume) {  // r_k, theta_k, alpha_k of an earlier iteration: line 8 starts from them
+  if (resume) {  // r_k, theta_k, alpha_k of an earlier iteration: the Onsager correction
+                 // starts from them
     HIP_TRY(hipMemcpyAsync(w.r, rs.r, sizeof(float2) * (size_t)P->ntot, hipMemcpyDeviceToDevice, st));
     HIP_TRY(launch_import_state(rs.theta, rs.theta2, rs.alpha, P->B, P->nbands, w.theta, w.thr2,
                                 w.alpha, check, w.bad, st));
@@ -318,7 +319,7 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
     a.mode = has_prev ? (P->grp > 1 ? RA_VDAMP_G : RA_VDAMP) : RA_VDAMP_FIRST;
     LAUNCH(L, VDAMP_PASS_ROWS_ANAL, pass_anal(P, a, st));
     LAUNCH(L, VDAMP_PASS_SURE, launch_sure_all(P, a, w.big, st));
-    if (x_monitor) {  // line 10 at this iteration (X is free between iterations)
+    if (x_monitor) {  // the output step at this iteration (X is free between iterations)
       KArgs m = a;
       m.out = x_monitor + (long long)k * P->ntot;
       m.mode = P->grp > 1 ? RS_WHAT_G : RS_WHAT;
@@ -329,7 +330,7 @@ vdamp_status enqueue_vdamp(vdamp_plan_t* P, hipStream_t st, void* ws, const floa
       LAUNCH(L, VDAMP_PASS_ROWS_ANAL, pass_anal(P, m, st));
     }
   }
-  // line 10: x_hat = F^H [ (1 - m) F Psi^H w + m y ]
+  // the output step: x_hat = F^H [ (1 - m) F Psi^H w + m y ]
   const bool has_w = iters > 0 || resume;
   if (has_w) {
     a.mode = P->grp > 1 ? RS_WHAT_G : RS_WHAT;
@@ -520,7 +521,7 @@ static vdamp_status make_plan(vdamp_plan_h* plan, int32_t batch, const int32_t* 
     fft_index[n] = (int)ffts.size() - 1;
     return (int)ffts.size() - 1;
   };
-  // tau-weight tables (line 1), one set per distinct length: L_1..L_s then H_1..H_s
+  // tau-weight tables (initialisation), one set per distinct length: L_1..L_s then H_1..H_s
   std::map<int, int> tab_index;
   std::vector<float> tables;
   auto get_tab = [&](int n) {
@@ -818,7 +819,7 @@ static vdamp_status make_plan3d(vdamp_plan_h* plan, int32_t batch, const int32_t
     ffts.push_back(f);
     return fft_index[n] = (int)ffts.size() - 1;
   };
-  auto get_tab = [&](int n) {  // line 1's 1D factors: L_1..L_s then H_1..H_s
+  auto get_tab = [&](int n) {  // the initialisation's 1D factors: L_1..L_s then H_1..H_s
     auto it = tab_index.find(n);
     if (it != tab_index.end()) return it->second;
     const int o = (int)tables.size();

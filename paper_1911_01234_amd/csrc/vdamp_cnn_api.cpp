@@ -341,7 +341,7 @@ vdamp_status enqueue_learned(vdamp_plan_t* P, const vdamp_cnn_t* C, hipStream_t 
   a.r2 = w.r2;  // w_cnn of the current iteration
   for (int k = 0; k < iters; ++k) {
     a.iter = k;
-    const bool prev_learned = k > 0 && k - 1 >= learned_from;  // line 8 used the judge
+    const bool prev_learned = k > 0 && k - 1 >= learned_from;  // the Onsager correction used the judge
     if (k > 0) {
       a.mode = prev_learned ? RS_RTILDE_L : RS_RTILDE;
       LAUNCH(Lr, VDAMP_PASS_ROWS_SYNTH, launch_rows_synth_all(P, a, st));

@@ -484,7 +484,7 @@ __device__ __forceinline__ float2 soft_c(float2 v, float th, float th2) {
   return make_float2(v.x * g, v.y * g);
 }
 
-// line 8: r_tilde = (eta(r) - alpha r) / (1 - alpha) = r (g - alpha) / (1 - alpha) with
+// the Onsager correction: r_tilde = (eta(r) - alpha r) / (1 - alpha) = r (g - alpha) / (1 - alpha) with
 // g = max(0, 1 - theta/|r|) the shrink factor of eta (0 at or below the threshold's key),
 // inv = 1 / (1 - alpha) of the band computed once (the same IEEE quotient rtilde_c forms
 // per coefficient): one factor a coefficient, then two multiplies
@@ -514,7 +514,7 @@ __device__ __forceinline__ void soft_pair(float2& u, float2& v, float th, float 
   u = make_float2(u.x * g, u.y * g);
   v = make_float2(v.x * g, v.y * g);
 }
-// line 8 for the pair: (eta(g) - alpha g) / (1 - alpha) = g (s - alpha) / (1 - alpha)
+// the Onsager correction for the pair: (eta(g) - alpha g) / (1 - alpha) = g (s - alpha) / (1 - alpha)
 // with s the pair's shrink factor, inv = 1 / (1 - alpha)
 __device__ __forceinline__ void rtilde_pair(float2& u, float2& v, float th, float th2, float al, float inv) {
   const float key = key_pair_rn(u, v);
@@ -524,7 +524,7 @@ __device__ __forceinline__ void rtilde_pair(float2& u, float2& v, float th, floa
   v = make_float2(v.x * f, v.y * f);
 }
 
-// line 8 for a general denoiser output w: (w - alpha r) / (1 - alpha)
+// the Onsager correction for a general denoiser output w: (w - alpha r) / (1 - alpha)
 __device__ __forceinline__ float2 rtilde_w(float2 w, float2 v, float al) {
   const float inv = 1.0f / (1.0f - al);
   return make_float2((w.x - al * v.x) * inv, (w.y - al * v.y) * inv);

@@ -266,7 +266,7 @@ inline hipError_t launch_cols_all(const vdamp_plan_t* P, KArgs a, hipStream_t st
 }
 
 // Every row strip of the plan through the transform passes: one launch per run of equal
-// nx (line 8 + Psi^H + row FFT, and row IFFT + Psi + line 4).
+// nx (Onsager correction + Psi^H + row FFT, and row IFFT + Psi + the back-projection).
 inline hipError_t launch_rows_synth_all(const vdamp_plan_t* P, KArgs a, hipStream_t st) {
   return launch_groups(P, (int)P->row_groups.size(), st, [&](int i, hipStream_t s) {
     const auto& g = P->row_groups[i];
@@ -288,7 +288,7 @@ inline hipError_t launch_rows_anal_all(const vdamp_plan_t* P, KArgs a, hipStream
   });
 }
 
-// Every band's threshold search (line 6): one launch per size class, largest first.
+// Every band's threshold search (denoising step): one launch per size class, largest first.
 inline hipError_t launch_sure_all(const vdamp_plan_t* P, KArgs a, float* scratch, hipStream_t st) {
   for (int c = kSureClasses - 1, first = 0; c >= 0; --c) {
     if (!P->nsure_cls[c]) continue;

@@ -57,11 +57,11 @@ struct SliceDev {
 
 // Modes of the row-synthesis pass (Psi^H on row strips, then row FFT).
 enum RowSynthMode : int {
-  RS_RTILDE = 0,   // line 8: r_tilde = (eta(r; theta) - alpha r) / (1 - alpha)
-  RS_WHAT = 1,     // eta(r; theta) (line 6, used by line 10)
+  RS_RTILDE = 0,   // the Onsager correction: r_tilde = (eta(r; theta) - alpha r) / (1 - alpha)
+  RS_WHAT = 1,     // eta(r; theta) (denoising step, used by the output step)
   RS_PLAIN = 2,    // r as is (FISTA momentum iterate; learned denoiser input)
-  RS_RTILDE_L = 3, // line 8 with the learned denoiser where the judge chose it (sel = 1)
-  RS_WHAT_L = 4,   // line 6 output with the learned denoiser where chosen
+  RS_RTILDE_L = 3, // the Onsager correction with the learned denoiser where the judge chose it (sel = 1)
+  RS_WHAT_L = 4,   // the denoising step output with the learned denoiser where chosen
   RS_PROBE = 5,    // the Rademacher probe b of the divergence estimate (no input read)
   RS_RTILDE_G = 6, // RS_RTILDE with group soft thresholding of horizontal pairs
   RS_WHAT_G = 7    // RS_WHAT with group soft thresholding of horizontal pairs
@@ -71,7 +71,7 @@ enum RowSynthMode : int {
 enum ColMode : int {
   CM_VDAMP = 0,        // z = y - X on Omega, v = z / p, tau partials
   CM_VDAMP_FIRST = 1,  // same with X = 0 (r_tilde_0 = 0)
-  CM_OUTPUT = 2,       // (1 - m) X + m y (line 10)
+  CM_OUTPUT = 2,       // (1 - m) X + m y (output step)
   CM_ZEROFILL = 3,     // y (iters = 0)
   CM_FISTA = 4,        // m (y - X)
   CM_FISTA_FIRST = 5,  // m y
@@ -82,7 +82,7 @@ enum ColMode : int {
 enum RowAnalMode : int {
   RA_VDAMP = 0,        // r_k = r_tilde_k + coefficients (r_tilde from r_{k-1})
   RA_VDAMP_FIRST = 1,  // r_0 = coefficients
-  RA_IMAGE = 2,        // no wavelet: write the image rows (line 10 output)
+  RA_IMAGE = 2,        // no wavelet: write the image rows (the output step's image)
   RA_FISTA = 3,        // w = eta(v + g; lambda); v' = w + beta (w - w_prev)
   RA_FISTA_FIRST = 4,
   RA_LEARNED = 5,      // as RA_VDAMP with r_tilde from the judged denoiser (RS_RTILDE_L)

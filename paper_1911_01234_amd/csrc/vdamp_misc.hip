@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(kThreads) k_scale(const SliceDev* __restrict__
 // divergence estimate alpha = J / N_b (mean Wirtinger derivative) and the denoiser's
 // SURE = D + (2 alpha - 1) N_b tau; the learned output is used (sel = 1, alpha replaced)
 // when its SURE is below soft thresholding's minimum and alpha <= 1 - 1/N_b (the range
-// soft thresholding's alpha has, which keeps line 8's division bounded).  always != 0:
+// soft thresholding's alpha has, which keeps the Onsager correction's division bounded).  always != 0:
 // no SURE comparison, only the bound on alpha.
 __global__ void k_judge(KArgs a, int nrowstrips, int always, int* __restrict__ sel,
                         float* __restrict__ jout) {
@@ -170,7 +170,7 @@ __global__ void k_judge(KArgs a, int nrowstrips, int always, int* __restrict__ s
 // (the FP32 squared magnitude thresholding compares |r|^2 against; fl(theta * theta)
 // when th2 is null) and alpha, from dense [B][nb] arrays into the plan's [B][kMaxBands]
 // slots.  With check != 0, bad[0] |= 1 for a non-finite or negative theta or an alpha
-// outside [0, 1) (line 8 divides by 1 - alpha).
+// outside [0, 1) (Onsager correction divides by 1 - alpha).
 __global__ void k_import_state(const float* __restrict__ th, const float* __restrict__ th2,
                                const float* __restrict__ al, int batch, int nb,
                                float* __restrict__ theta, float* __restrict__ thr2,

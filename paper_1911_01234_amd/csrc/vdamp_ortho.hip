@@ -15,12 +15,13 @@
 // Bands sharing a y-filter form a group: A_l = {LH_l} (plus LL_s when l = s) and
 // D_l = {HL_l, HH_l}.  A group row i is the sum over the group's bands of
 // F^x_b(kx) x (DFT of row i of band b)(kx mod m): a full row of x frequencies.
-//   k_osynth: line 8 (or line 6) on the coefficients, band-row DFTs, group rows -> Z;
+//   k_osynth: the Onsager correction (or the denoising step) on the coefficients,
+//             band-row DFTs, group rows -> Z;
 //   k_ocols:  per 16-column strip, each group column's DFT times its y response summed
-//             into k-space, the k-space step of lines 3-5 with its tau partials, then
+//             into k-space, the k-space step with its tau partials, then
 //             the fold back into group columns and their inverse DFTs -> Z (or, for
-//             line 10, the full inverse column DFT -> X);
-//   k_oanal:  each group row folded back into its bands, inverse DFTs, + r_tilde (line 4).
+//             the output step, the full inverse column DFT -> X);
+//   k_oanal:  each group row folded back into its bands, inverse DFTs, + r_tilde (back-projection).
 // Scaling: every DFT here is unnormalised; the column pass applies (ny nx)^(-1/2) once
 // on the way into k-space and once on the way out, so the round trip is unitary.
 #include "vdamp_device.hpp"
@@ -100,7 +101,7 @@ __global__ void __launch_bounds__(kThreads) k_osynth(KArgs a) {
   }
 }
 
-// The group-row work of the synthesis pass: line 8 on the band rows of the group rows,
+// The group-row work of the synthesis pass: the Onsager correction on the band rows of the group rows,
 // their DFTs, times the x responses, into Z.  NXC, LC > 0: the slice width and the level
 // at compile time.
 template <int NXC, int LC>
@@ -247,7 +248,7 @@ __global__ void __launch_bounds__(kThreads) k_ocols(KArgs a) {
     for (int i = tid; i < 2 * s * ny; i += kThreads) ytab_s[i] = a.tables[S.ytab_off + i];
     __syncthreads();
   }
-  // ---- lines 3-5 (or line 10, or nothing) on the strip
+  // ---- the k-space step (or the output step, or nothing) on the strip
   const float isq = rsqrtf((float)ny * (float)nx);
   const float sig2 = a.sigma2 ? a.sigma2[sl] : 0.f;
   const int kx = c0 + c;
@@ -384,7 +385,7 @@ __global__ void __launch_bounds__(kThreads) k_oanal(KArgs a) {
 }
 
 // The group-row work of the analysis pass: fold each group row into its bands, inverse
-// DFTs of the band rows, line 4.  NXC, LC > 0: the slice width and the level at compile
+// DFTs of the band rows, the back-projection.  NXC, LC > 0: the slice width and the level at compile
 // time (band rows of NXC >> LC samples).
 template <int NXC, int LC>
 __device__ __forceinline__ void oanal_group(const KArgs& a, const SliceDev& S, float2* Zs, float2* tw_s, int sl,

@@ -1,10 +1,10 @@
 // gfx950 kernels of the three transform passes of one iteration (Algorithm 1):
-//   rows_synth  (row strip of 2^s image rows): line 8 applied to r_{k-1}, Psi^H on the
+//   rows_synth  (row strip of 2^s image rows): the Onsager correction applied to r_{k-1}, Psi^H on the
 //               strip (Haar never couples strips of 2^s rows), then the row FFTs.
-//   cols        (column strip of 16 columns): column FFT, k-space residual of line 3,
-//               density compensation P^-1 of line 4, the tau partial sums of line 5
+//   cols        (column strip of 16 columns): column FFT, k-space residual,
+//               density compensation P^-1, the tau estimate's partial sums
 //               (S is separable per band for Haar), column IFFT.
-//   rows_anal   (row strip): row IFFTs, Psi on the strip, add r_tilde_k (line 4).
+//   rows_anal   (row strip): row IFFTs, Psi on the strip, add r_tilde_k (back-projection).
 // One workgroup of 256 threads per work item; every tile is staged in LDS and moved
 // with 16-byte accesses (two complex values), all of a thread's loads issued before
 // the first use.  EPT (8 B elements per thread) is 16 when every tile of the plan
@@ -653,7 +653,7 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
     if (p < npairs) {
       const int b = bnd[u];
       const float4 gv = lds4[p];
-      if (mode == RA_VDAMP_G) {  // r_tilde of the pair x = 2j, 2j + 1 (line 8), + coefficients
+      if (mode == RA_VDAMP_G) {  // Onsager-corrected r_tilde of the pair x = 2j, 2j + 1, + coefficients
         float2 x0 = lo2(ro[u]), x1 = hi2(ro[u]);
         rtilde_pair(x0, x1, th_s[b], t2_s[b], al_s[b], ia_s[b]);
         *reinterpret_cast<float4*>(r + gi[u]) = pack4(cadd(x0, lo2(gv)), cadd(x1, hi2(gv)));

@@ -1,5 +1,5 @@
 // gfx950 kernel of the per-band threshold search (Section 3: complex soft thresholding
-// with a SURE-optimal threshold per subband; Algorithm 1, lines 6-7).
+// with a SURE-optimal threshold per subband; the denoising and alpha steps of Algorithm 1).
 #include "vdamp_device.hpp"
 
 namespace vdamp {
@@ -208,7 +208,7 @@ __device__ void sure_walk(const float* sk, int Nb, double tl, double td, bool co
 
 // Workgroup argmin of the per-thread bests (sure_better), then theta (sqrt(key) for a
 // key, the continuous minimiser otherwise), its key and alpha = ((N_b - m) - theta R /
-// 2) / N_b (line 7) for the band, and the band's outputs.  No candidate (every key
+// 2) / N_b (alpha step) for the band, and the band's outputs.  No candidate (every key
 // zero): eta = 0, alpha = 0.  With groups of GD coefficients (Nb groups) alpha is half
 // the real divergence per coefficient, (GD (N_b - m) - (2 GD - 1) theta R / 2) / (GD N_b).
 template <int NT, int GD = 1>
@@ -276,7 +276,7 @@ __device__ void sure_finish(const KArgs& a, int sl, int b, int Nb, float tau_f, 
 //      SURE(m) = A_m - m tau + (N_b - m)(a_m^2 + tau) - tau a_m R_m at every candidate
 //      (the last index of a run of equal keys, a > 0).
 //   4. Workgroup argmin, ties to the smaller index; theta = a_m, theta^2 = key_m and
-//      alpha = ((N_b - m) - theta R_m / 2) / N_b (line 7).
+//      alpha = ((N_b - m) - theta R_m / 2) / N_b (alpha step).
 constexpr int kSureBucketLimit = 64;
 
 // LDS words of a size class: the bucket table and the sorted keys with one pad word per

@@ -59,7 +59,7 @@ hipError_t time_ms(TuneBuffers& T, F&& run, double& ms, int reps = 5) {
 }
 
 // Fresh tuning data: iterate-like r, X, y and weights; theta = 1 (key 1), alpha = 1/2
-// for line 8; column-strip tau partials 1/16 each (tau = nx/256 per band).
+// for the Onsager correction; column-strip tau partials 1/16 each (tau = nx/256 per band).
 hipError_t fill(const vdamp_plan_t* P, TuneBuffers& T, const Ws& w) {
   hipError_t e = launch_tune_fill(w.r, w.X, T.y, w.wgt, P->ntot, T.st);
   if (e == hipSuccess) e = launch_fill_f32(w.theta, (long long)P->B * kMaxBands, 1.0f, T.st);
@@ -97,7 +97,8 @@ hipError_t autotune(vdamp_plan_t* P) {
   const int H = 1 << P->levels;
   std::string log = "autotune:";
 
-  // row passes: line 8 + Psi^H + row FFT, then row IFFT + Psi + line 4, per run of equal nx
+  // row passes: the Onsager correction + Psi^H + row FFT, then row IFFT + Psi + the
+  // back-projection, per run of equal nx
   for (auto& g : P->row_groups) {
     if (!g[2]) continue;
     const int m4 = g[2];
@@ -121,7 +122,7 @@ hipError_t autotune(vdamp_plan_t* P) {
     if (stock) g[2] = 0;
   }
   if ((e = fill(P, T, w)) != hipSuccess) return e;
-  // column pass: column FFT, k-space step of lines 3-5, column IFFT, per run of equal ny
+  // column pass: column FFT, the k-space step, column IFFT, per run of equal ny
   for (auto& g : P->col_groups) {
     if (!g[2]) continue;
     const int m4 = g[2];

@@ -35,7 +35,7 @@ def fp32_state(r, theta, alpha):
 def run_resume(plan, slices, states, iters, want_state=True, x_monitor=False, stream=None):
     """vdamp_solve_resume on every slice of the plan: states maps slice index b to an
     FP32 state (r_k [ny][nx], theta_k [nb], alpha_k [nb]); slices not in states start
-    from r = 0, theta = 0, alpha = 0 (line 8 then gives r_tilde = 0)."""
+    from r = 0, theta = 0, alpha = 0 (Onsager correction then gives r_tilde = 0)."""
     import torch
     from paper_1911_01234_amd import vdamp as V
     ws = plan.workspace()
@@ -232,7 +232,7 @@ def theta_accepted(r, tau_b, rs, cs, theta_gpu, alpha_gpu=None, return_key=False
     index decided in floating point, so it is taken on the kernel's FP32 keys of that r
     (magnitudes sqrt(key32) in FP64).  The GPU's threshold is accepted when its SURE is
     the minimum over all candidates up to 1e-6 (|SURE_min| + N_b tau) (a near tie).
-    Among keys theta may stand for, the one whose alpha (line 7) matches the GPU's
+    Among keys theta may stand for, the one whose alpha (alpha step) matches the GPU's
     alpha is the GPU's choice.  d = 2: the keys are those of horizontal pairs (group
     soft thresholding)."""
     band = np.asarray(r)[rs, cs]
@@ -257,7 +257,7 @@ def theta_accepted(r, tau_b, rs, cs, theta_gpu, alpha_gpu=None, return_key=False
 
 
 def alpha_at_key(r_band, kth, d=1):
-    """alpha (line 7) at the threshold with key kth, membership on the FP32 keys.  For
+    """alpha (alpha step) at the threshold with key kth, membership on the FP32 keys.  For
     pairs (d = 2): half the real divergence of group soft thresholding per coefficient,
     4 - 3 theta/||g|| per pair above the threshold, over 2 N_b."""
     k = group_keys32(r_band, d).astype(np.float64).ravel()

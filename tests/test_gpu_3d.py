@@ -1,7 +1,7 @@
 """GPU parity of VDAMP on volumes (vdamp_plan_3d: Phi with a 3D DFT, Section 1; the
 3D Haar transform) against the 3D oracle (oracle/vdamp3d_ref.py) on the same seeded
 volumes, at the gates of the 2D path: the transform to FP32 rounding, the first
-iterate r_0 and tau_0 (line 5 with the separable S) to 1e-5, one step from the oracle's
+iterate r_0 and tau_0 (tau estimate with the separable S) to 1e-5, one step from the oracle's
 FP32-rounded state at every iteration (r, tau, x_hat to 1e-5; theta and alpha to the
 tolerances the iterate's implies; near ties validated on the library's own data), the
 library's thresholds SURE-optimal on its own free-running iterates and its final NMSE

@@ -263,8 +263,8 @@ def test_identity_network_gives_plain_vdamp_bit_for_bit():
 
 def test_half_shrink_network_in_every_band_matches_oracle():
     """A nonlinear network with a known map (test_oracle_learned.half_shrink_params; a
-    linear one would make line 8 cancel to the BF16 rounding residue alone), used in
-    every band for two iterations (the second applies line 8 to the learned output and
+    linear one would make the Onsager correction cancel to the BF16 rounding residue alone), used in
+    every band for two iterations (the second applies the Onsager correction to the learned output and
     its alpha): x_hat to the FP32 gate 1e-5 (the network's weights are exact in BF16 and
     its activations are rounded at the same points on both sides)."""
     import torch
@@ -294,7 +294,8 @@ def test_learned_from_schedule():
     the oracle's schedule (two iterations of soft thresholding, then the half-shrink
     network in every band) at the FP32 gate 1e-5.  (This network's map is expansive: two
     learned iterations in a row grow the few BF16 roundings that FP32 and FP64 take
-    differently to 2e-4; the half-shrink test checks line 8 after a learned iteration.)"""
+    differently to 2e-4; the half-shrink test checks the Onsager correction after a
+    learned iteration.)"""
     import torch
     from paper_1911_01234_amd import vdamp as V
     from test_oracle_learned import half_shrink_params
@@ -551,8 +552,8 @@ def test_learned_iteration_at_256():
     oracle; x_hat holds the network's BF16 output, so its tolerance is the network's
     (5e-3).  (A second learned iteration starts from the first one's BF16 output, which
     both sides round differently at a few elements: its comparison would measure that
-    difference grown through line 8; the 64x64 half-shrink test covers line 8 with the
-    learned output at the FP32 gate.)"""
+    difference grown through the Onsager correction; the 64x64 half-shrink test covers
+    the Onsager correction with the learned output at the FP32 gate.)"""
     from paper_1911_01234_amd import vdamp as V
     slices = synth.workload_batch256(2, cfg_id=41)[0]
     s = 4

@@ -100,7 +100,7 @@ def test_haar_filter_through_the_general_path_equals_the_haar_path():
 
 @pytest.mark.parametrize("name", ["db2", "db4", "db8"])
 def test_first_iteration_r0_tau0(name):
-    """k = 0 at 256x256: r_0 = Psi F^H P^-1 y and tau_0 from line 5 with the filter's S."""
+    """k = 0 at 256x256: r_0 = Psi F^H P^-1 y and tau_0 from the tau estimate with the filter's S."""
     h = {"db2": DB2, "db4": DB4, "db8": DB8}[name]
     sl = synth.workload_single256(6.0)[0][0]
     g = run_vdamp([sl], 4, 1, want_state=True, lowpass=h)

@@ -1,8 +1,8 @@
 """Pins of the 3D oracle (oracle/vdamp3d_ref.py) against mathematics: the 3D Haar
 coefficients as inner products with the textbook separable basis, orthonormality and
 perfect reconstruction, S = |Phi Psi^H|^2 in closed form against brute force and its
-identities, line 5's unbiasedness (Monte Carlo, fixed r_tilde) and full-sampling
-special case, line 10's exact consistency.  CPU only."""
+identities, the tau estimate's unbiasedness (Monte Carlo, fixed r_tilde) and full-sampling
+special case, the output step's exact consistency.  CPU only."""
 import numpy as np
 import pytest
 
@@ -105,7 +105,7 @@ def test_tau3_full_sampling_is_sigma2():
 
 @pytest.mark.slow
 def test_tau3_unbiased_monte_carlo():
-    """Line 5 is an unbiased estimate of E|r_k - w0|^2 per band for a fixed r_tilde
+    """The tau estimate is an unbiased estimate of E|r_k - w0|^2 per band for a fixed r_tilde
     (Section 2), with a 3D Phi and Psi."""
     x0, p, rng = _tiny_volume()
     s, sigma2, draws = 2, 0.01, 1500

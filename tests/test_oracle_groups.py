@@ -3,7 +3,7 @@ horizontal pairs, tuned by SURE; Section 4 names structured sparsity as a richer
 for SURE to tune) against mathematics: a hand-worked example, the proximal property of
 group soft thresholding, the sorted scan against brute force, Stein unbiasedness by
 Monte Carlo, alpha against a finite-difference divergence, the continuous minimiser
-against a dense grid, the decorrelation of line 8, the colored state evolution of a
+against a dense grid, the decorrelation of the Onsager correction, the colored state evolution of a
 whole run, and exact resumption.  CPU only."""
 import os
 
@@ -149,7 +149,7 @@ def test_group_continuous_minimiser_against_dense_grid():
 
 def test_group_onsager_correction_decorrelates():
     """With alpha = half the divergence per coefficient, r_tilde - w0 is uncorrelated
-    with the noise n = r - w0 (line 8), for group soft thresholding too."""
+    with the noise n = r - w0 (Onsager correction), for group soft thresholding too."""
     rng = np.random.default_rng(12)
     n, tau, trials = 4096, 1.0, 300
     w0 = np.where(rng.random((1, n)) < 0.1, 4 * crandn(1, n, rng=rng), 0)

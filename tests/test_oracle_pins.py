@@ -99,7 +99,7 @@ def test_band_sizes_and_partition():
     assert len(o.bands(ny, nx, s)) == 1 + 3 * s
 
 
-# ---------------------------------------------------------------------- S, line 1
+# ---------------------------------------------------------------------- S, the initialisation
 
 @pytest.mark.parametrize("ny,nx,s", [(32, 32, 3), (48, 80, 4), (24, 40, 3)])
 def test_tau_weights_closed_form_vs_bruteforce(ny, nx, s):
@@ -211,7 +211,7 @@ def test_alpha_is_mean_wirtinger_derivative_finite_difference():
     assert abs(o.wirtinger_mean_soft(r, 0.0) - 1.0) < 1e-15
 
 
-# ---------------------------------------------------------------------- lines 3-5, 10
+# ---------------------------------------------------------------------- the k-space and output steps
 
 def tiny_problem(ny=32, nx=32, R=3.0, seed=0, full=False):
     rng = np.random.default_rng(seed)
@@ -236,7 +236,7 @@ def test_tau_full_sampling_is_sigma2():
 
 @pytest.mark.slow
 def test_tau_unbiased_monte_carlo():
-    """Line 5 is an unbiased estimate of E|r_k - w0|^2 per band, for r_tilde fixed
+    """The tau estimate is an unbiased estimate of E|r_k - w0|^2 per band, for r_tilde fixed
     (independent of Omega and eps): Section 2."""
     ny = nx = 32
     s = 3
@@ -284,7 +284,7 @@ def test_r0_unbiased_monte_carlo():
 
 
 def test_output_step_is_exactly_consistent():
-    """Line 10: M F x_hat = y on Omega for any w."""
+    """The output step: M F x_hat = y on Omega for any w."""
     ny = nx = 32
     x0, p, rng = tiny_problem(ny, nx)
     mask = (rng.random((ny, nx)) < p).astype(np.uint8)
@@ -335,7 +335,7 @@ def test_line8_needs_no_guard():
 @pytest.mark.slow
 def test_onsager_correction_decorrelates():
     """With the Wirtinger alpha, r_tilde_{k+1} - w0 is uncorrelated with the input noise
-    n = r - w0: E Re<r_tilde - w0, n> = 0 for r = w0 + CN(0, tau) (line 8).  The
+    n = r - w0: E Re<r_tilde - w0, n> = 0 for r = w0 + CN(0, tau) (Onsager correction).  The
     real-derivative reading 1[|r| > theta] fails this check."""
     rng = np.random.default_rng(11)
     n, tau, trials = 4096, 1.0, 300
@@ -393,10 +393,10 @@ def test_fista_reaches_fixed_point_and_lowers_objective():
 
 
 def test_resume_continues_the_iteration_exactly():
-    """The state between iterations of Algorithm 1 is (r_k, theta_k, alpha_k): lines 6-8
-    rebuild r_tilde_{k+1} from it and lines 3-5 need nothing else.  Resuming the oracle
-    from a recorded state therefore reproduces the rest of the uninterrupted run bit for
-    bit, and a resume with no further iteration returns line 10 at that state."""
+    """The state between iterations of Algorithm 1 is (r_k, theta_k, alpha_k): the
+    denoising, alpha and Onsager-correction steps rebuild r_tilde_{k+1} from it and the
+    k-space step needs nothing else.  Resuming the oracle from a recorded state therefore reproduces the rest of the uninterrupted run bit for
+    bit, and a resume with no further iteration returns the output step at that state."""
     sl = synth.workload_single64()[0][0]
     K, k = 9, 4
     full = o.vdamp(sl.y, sl.mask, sl.p, sl.sigma2, 3, K, record=True)

@@ -1,8 +1,8 @@
 """Pins of the oracle's general orthonormal wavelets (Algorithm 1 needs only an
 orthogonal Psi) and of the filter generator, against mathematics rather than the
 oracle itself: the Haar special case, the closed form of Daubechies' four-tap filter,
-orthonormality, vanishing moments, the identities of S = |Phi Psi^H|^2 (line 1), and
-line 5's unbiasedness with a non-Haar Psi.  CPU only."""
+orthonormality, vanishing moments, the identities of S = |Phi Psi^H|^2 (initialisation), and
+the tau estimate's unbiasedness with a non-Haar Psi.  CPU only."""
 import numpy as np
 import pytest
 
@@ -90,7 +90,7 @@ def test_vanishing_moments_zero_the_detail_coefficients(N):
         assert np.abs(blk).max() <= 1e-9 * scale
 
 
-# ---------------------------------------------------------------------- S (line 1)
+# ---------------------------------------------------------------------- S (initialisation)
 
 @pytest.mark.parametrize("name", list(FILTERS))
 @pytest.mark.parametrize("ny,nx,s", [(32, 48, 3), (64, 64, 4)])
@@ -127,7 +127,7 @@ def test_tau_weights_are_separable_per_band():
 
 @pytest.mark.slow
 def test_tau_unbiased_monte_carlo_db4():
-    """Line 5 is an unbiased estimate of E|r_k - w0|^2 per band for a fixed r_tilde,
+    """The tau estimate is an unbiased estimate of E|r_k - w0|^2 per band for a fixed r_tilde,
     with a Daubechies Psi as with Haar (Section 2 states it for any orthogonal Psi)."""
     ny = nx = 32
     s = 3
@@ -156,7 +156,7 @@ def test_tau_unbiased_monte_carlo_db4():
 
 
 def test_output_step_consistent_with_any_orthonormal_psi():
-    """Line 10 keeps the measured samples exactly: M F x_hat = y on Omega."""
+    """The output step keeps the measured samples exactly: M F x_hat = y on Omega."""
     ny, nx, s = 32, 32, 3
     h = FILTERS["db2"]
     y = crandn(ny, nx)
