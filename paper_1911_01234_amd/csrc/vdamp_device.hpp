@@ -497,6 +497,15 @@ __device__ __forceinline__ float2 rtilde_ci(float2 v, float th, float th2, float
 __device__ __forceinline__ float2 rtilde_c(float2 v, float th, float th2, float al) {
   return rtilde_ci(v, th, th2, al, 1.0f / (1.0f - al));
 }
+// r_tilde + c with the factor form and one rounding per component (an explicit fused
+// multiply-add, so that every pass that adds the back-projected coefficients c to the
+// corrected iterate rounds alike, whatever the compiler contracts elsewhere)
+__device__ __forceinline__ float2 rtilde_ci_add(float2 v, float th, float th2, float al, float inv, float2 c) {
+  const float key = key_rn(v);
+  const float g = (key > th2) ? 1.0f - th * rsqrtf(key) : 0.f;
+  const float f = (g - al) * inv;
+  return make_float2(__fmaf_rn(v.x, f, c.x), __fmaf_rn(v.y, f, c.y));
+}
 
 // Group soft thresholding of a horizontal pair g = (u, v) of one subband row (the
 // structured-sparsity denoiser): both shrink by max(0, 1 - theta/||g||), and the pair is

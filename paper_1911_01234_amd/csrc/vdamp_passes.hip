@@ -667,12 +667,15 @@ __global__ void __launch_bounds__(NT) k_rows_anal(KArgs a) {
           case RA_VDAMP_FIRST: o[h] = g; break;
           case RA_VDAMP: {
             const float2 x = h ? hi2(ro[u]) : lo2(ro[u]);
-            o[h] = cadd(rtilde_ci(x, th_s[b], t2_s[b], al_s[b], ia_s[b]), g);
+            o[h] = rtilde_ci_add(x, th_s[b], t2_s[b], al_s[b], ia_s[b], g);
           } break;
           case RA_LEARNED: {
             const float2 x = h ? hi2(ro[u]) : lo2(ro[u]);
             const float2 wv = h ? hi2(rw[u]) : lo2(rw[u]);
-            o[h] = cadd(sel_s[b] ? rtilde_w(wv, x, al_s[b]) : rtilde_ci(x, th_s[b], t2_s[b], al_s[b], ia_s[b]), g);
+            if (sel_s[b])
+              o[h] = cadd(rtilde_w(wv, x, al_s[b]), g);
+            else  // as RA_VDAMP, so that a band left to soft thresholding matches the plain solve
+              o[h] = rtilde_ci_add(x, th_s[b], t2_s[b], al_s[b], ia_s[b], g);
           } break;
           case RA_FISTA_FIRST: {
             w2[h] = soft_c(g, lam, lam2);
