@@ -52,7 +52,10 @@ typedef enum {
   VDAMP_ERR_WORKSPACE = 4,    /* workspace missing, too small or misaligned          */
   VDAMP_ERR_HIP = 5,          /* a HIP runtime call failed                           */
   VDAMP_ERR_NONFINITE = 6,    /* VDAMP_FLAG_CHECK_FINITE found bad data              */
-  VDAMP_ERR_STATE = 7         /* no solve has produced the requested state yet       */
+  VDAMP_ERR_STATE = 7,        /* no solve has produced the requested state yet       */
+  VDAMP_STATUS_MAX_ENUM = 0x7FFFFFFF  /* not a status: makes every int32 value a valid
+                                         vdamp_status, so vdamp_status_string may be
+                                         handed any code */
 } vdamp_status;
 
 enum { VDAMP_WAVELET_HAAR = 0 };

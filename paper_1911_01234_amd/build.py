@@ -1,19 +1,20 @@
 """Build libvdamp.so in-tree for gfx950 with hipcc (no JIT cache, no torch extension).
 
 Each source compiles to an object in its own hipcc process (in parallel), then one
-link step writes the library."""
+link step writes the library.  The objects stay in `_build/` beside this file (the host
+sanitizer test links its instrumented host sources against the device objects)."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
-import tempfile
 from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvdamp.so")
+OBJ_DIR = os.path.join(PKG, "_build")
 SOURCES = ["vdamp_passes.hip", "vdamp_sure.hip", "vdamp_misc.hip", "vdamp_cnn.hip", "vdamp_api.cpp",
            "vdamp_cnn_api.cpp", "vdamp_tune.cpp", "vdamp_noalloc.hip", "vdamp_ortho.hip", "vdamp_3d.hip"]
 
@@ -34,21 +35,23 @@ def _run(cmd, verbose):
 
 def build(verbose: bool = False) -> str:
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    with tempfile.TemporaryDirectory(prefix="vdamp_build_") as tmpdir:
-        objs = [os.path.join(tmpdir, s + ".o") for s in SOURCES]
-        cmds = [[HIPCC, *FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
-        jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
-        with ThreadPoolExecutor(jobs) as ex:
-            results = list(ex.map(lambda c: _run(c, verbose), cmds))
-        for s, res in zip(SOURCES, results):
-            if res.returncode != 0:
-                sys.stderr.write(res.stdout + res.stderr)
-                raise RuntimeError(f"hipcc failed compiling {s}")
-        tmp = LIB + ".tmp"
-        res = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    objs = [os.path.join(OBJ_DIR, s + ".o") for s in SOURCES]
+    cmds = [[HIPCC, *FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", o + ".tmp"] for s, o in zip(SOURCES, objs)]
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(lambda c: _run(c, verbose), cmds))
+    for s, res in zip(SOURCES, results):
         if res.returncode != 0:
             sys.stderr.write(res.stdout + res.stderr)
-            raise RuntimeError("hipcc failed linking libvdamp.so")
+            raise RuntimeError(f"hipcc failed compiling {s}")
+    for o in objs:
+        os.replace(o + ".tmp", o)
+    tmp = LIB + ".tmp"
+    res = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed linking libvdamp.so")
     os.replace(tmp, LIB)
     return LIB
 

@@ -431,6 +431,7 @@ const char* vdamp_status_string(vdamp_status s) {
     case VDAMP_ERR_HIP: return "HIP error";
     case VDAMP_ERR_NONFINITE: return "invalid data";
     case VDAMP_ERR_STATE: return "no state";
+    case VDAMP_STATUS_MAX_ENUM: break;
   }
   return "unknown status";
 }
