@@ -131,8 +131,9 @@ def other_workloads(stream, reps=3):
     planned with the plan-time tuner, and the benchmark's 256 slices of 256^2 with an
     8-tap Daubechies wavelet instead of Haar (vdamp_plan_ortho, not tuned) and with group
     soft thresholding of horizontal pairs (VDAMP_FLAG_GROUP_PAIRS, not tuned).  One
-    warm-up solve, then `reps` timed solves of 50 iterations each, eager with per-kernel
-    events."""
+    warm-up solve, then `reps` timed solves of 50 iterations each: eager with nothing
+    else on the stream (the rate), on a plan with an event pair around every pass (the
+    pass rooflines), and replayed from a hipGraph."""
     import torch
     from paper_1911_01234_amd import filters, synth, vdamp as V
     res = {}
@@ -155,44 +156,36 @@ def other_workloads(stream, reps=3):
             if grp:
                 low = None
             tune = V.VDAMP_FLAG_AUTOTUNE if (low is None and not grp) else 0
-            plan = V.Plan(ny, nx, s, V.VDAMP_FLAG_TIMING | tune | grp, lowpass=low)
+            base = tune | grp
+            plan = V.Plan(ny, nx, s, base, lowpass=low)
             t_plan = time.perf_counter() - t
             desc = plan.describe()
-            ws = plan.workspace()
-            y, mask, p, sigma2 = V.to_device(plan, slices)
+            inputs = V.to_device(plan, slices)
             xh = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
             x0 = torch.from_numpy(plan.pack([sl.x0 for sl in slices], np.complex64)).cuda()
             seg = torch.from_numpy(np.repeat(np.arange(len(slices)), [u * v for u, v in zip(ny, nx)])).cuda()
-            plan.vdamp_solve(ws, y, mask, p, sigma2, K, xh, stream=stream)
-            stream.synchronize()
-            plan.vdamp_pass_times()
-            t = time.perf_counter()
-            for _ in range(reps):
-                plan.vdamp_solve(ws, y, mask, p, sigma2, K, xh, stream=stream)
-            stream.synchronize()
-            dt = (time.perf_counter() - t) / reps
-            times = plan.vdamp_pass_times()
+            # eager solves with nothing else on the stream
+            dt, _ = time_solves(plan, inputs, K, reps, stream, xh)
             nm = float(nmse_db_batch(xh, x0, seg, len(slices)).mean())
             plan.close()
+            # per-pass times from the same solves on a plan with an event pair around every pass
+            tplan = V.Plan(ny, nx, s, V.VDAMP_FLAG_TIMING | base, lowpass=low)
+            tx = torch.empty_like(xh)
+            dte, times = time_solves(tplan, inputs, K, reps, stream, tx, pass_times=True)
+            tplan.close()
             # the same solves captured once in a hipGraph (VDAMP_FLAG_USE_GRAPH) and replayed
-            gplan = V.Plan(ny, nx, s, V.VDAMP_FLAG_USE_GRAPH | tune | grp, lowpass=low)
-            gws = gplan.workspace()
+            gplan = V.Plan(ny, nx, s, V.VDAMP_FLAG_USE_GRAPH | base, lowpass=low)
             gx = torch.empty_like(xh)
-            gplan.vdamp_solve(gws, y, mask, p, sigma2, K, gx, stream=stream)
-            stream.synchronize()
-            t = time.perf_counter()
-            for _ in range(reps):
-                gplan.vdamp_solve(gws, y, mask, p, sigma2, K, gx, stream=stream)
-            stream.synchronize()
-            dtg = (time.perf_counter() - t) / reps
-            gsame = bool(torch.equal(gx, xh))
+            dtg, _ = time_solves(gplan, inputs, K, reps, stream, gx)
+            gsame = bool(torch.equal(gx, xh)) and bool(torch.equal(tx, xh))
             gplan.close()
-        del ws, y, mask, p, sigma2, xh, x0, seg, gws, gx
+        del inputs, xh, x0, seg, tx, gx
         torch.cuda.empty_cache()
         res[name] = {"slices": len(slices), "pixels": npx, "iters": K,
                      "seconds_per_solve": round(dt, 5),
                      "slice_iterations_per_s": round(len(slices) * K / dt, 1),
                      "mpx_iterations_per_s": round(npx * K / dt / 1e6, 1),
+                     "with_pass_events": {"slice_iterations_per_s": round(len(slices) * K / dte, 1)},
                      "hipgraph": {"slice_iterations_per_s": round(len(slices) * K / dtg, 1),
                                   "bitwise_equal_to_eager": gsame},
                      "nmse_db_mean": round(nm, 3),
@@ -206,10 +199,29 @@ def other_workloads(stream, reps=3):
     return res
 
 
+def time_solves(plan, inputs, K, reps, stream, out, pass_times=False):
+    """A warm-up solve, then `reps` timed solves on `stream`: seconds per solve and, with
+    pass_times (a VDAMP_FLAG_TIMING plan), the plan's per-pass event times over the timed
+    solves."""
+    ws = plan.workspace()
+    y, mask, p, sigma2 = inputs
+    plan.vdamp_solve(ws, y, mask, p, sigma2, K, out, stream=stream)
+    stream.synchronize()
+    if pass_times:
+        plan.vdamp_pass_times()
+    t = time.perf_counter()
+    for _ in range(reps):
+        plan.vdamp_solve(ws, y, mask, p, sigma2, K, out, stream=stream)
+    stream.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    return dt, (plan.vdamp_pass_times() if pass_times else None)
+
+
 def volume_workload(stream, reps=3, n=32):
     """VDAMP on 3D k-space (vdamp_plan_3d): n volumes of 64^3 (12 ellipsoids, R = 6,
     40 dB, 3 Haar levels: 22 bands, the finest of 32^3 = 32768 coefficients), 30
-    iterations; eager with per-kernel events, then the same solves from a hipGraph."""
+    iterations; eager solves, the same solves with per-pass events (for the pass
+    rooflines), then from a hipGraph."""
     import torch
     from paper_1911_01234_amd import synth, vdamp as V
     t = time.perf_counter()
@@ -220,40 +232,29 @@ def volume_workload(stream, reps=3, n=32):
     nx = [v.y.shape[2] for v in vols]
     npx = int(sum(a * b * c for a, b, c in zip(nz, ny, nx)))
     with torch.cuda.stream(stream):
-        plan = V.Plan(ny, nx, s, V.VDAMP_FLAG_TIMING, nz=nz)
-        ws = plan.workspace()
-        y, mask, p, sigma2 = V.to_device(plan, vols)
+        plan = V.Plan(ny, nx, s, 0, nz=nz)
+        inputs = V.to_device(plan, vols)
         xh = torch.empty(plan.ntot, dtype=torch.complex64, device="cuda")
         x0 = torch.from_numpy(plan.pack([v.x0 for v in vols], np.complex64)).cuda()
-        plan.vdamp_solve(ws, y, mask, p, sigma2, K, xh, stream=stream)
-        stream.synchronize()
-        plan.vdamp_pass_times()
-        t = time.perf_counter()
-        for _ in range(reps):
-            plan.vdamp_solve(ws, y, mask, p, sigma2, K, xh, stream=stream)
-        stream.synchronize()
-        dt = (time.perf_counter() - t) / reps
-        times = plan.vdamp_pass_times()
+        dt, _ = time_solves(plan, inputs, K, reps, stream, xh)
         seg = torch.from_numpy(np.repeat(np.arange(n), npx // n)).cuda()
         nm = float(nmse_db_batch(xh, x0, seg, n).mean())
         plan.close()
+        tplan = V.Plan(ny, nx, s, V.VDAMP_FLAG_TIMING, nz=nz)
+        tx = torch.empty_like(xh)
+        dte, times = time_solves(tplan, inputs, K, reps, stream, tx, pass_times=True)
+        tplan.close()
         gplan = V.Plan(ny, nx, s, V.VDAMP_FLAG_USE_GRAPH, nz=nz)
-        gws = gplan.workspace()
         gx = torch.empty_like(xh)
-        gplan.vdamp_solve(gws, y, mask, p, sigma2, K, gx, stream=stream)
-        stream.synchronize()
-        t = time.perf_counter()
-        for _ in range(reps):
-            gplan.vdamp_solve(gws, y, mask, p, sigma2, K, gx, stream=stream)
-        stream.synchronize()
-        dtg = (time.perf_counter() - t) / reps
-        gsame = bool(torch.equal(gx, xh))
+        dtg, _ = time_solves(gplan, inputs, K, reps, stream, gx)
+        gsame = bool(torch.equal(gx, xh)) and bool(torch.equal(tx, xh))
         gplan.close()
-    del ws, y, mask, p, sigma2, xh, x0, gws, gx
+    del inputs, xh, x0, seg, tx, gx
     torch.cuda.empty_cache()
     out = {"volumes": n, "voxels": npx, "levels": s, "iters": K, "seconds_per_solve": round(dt, 5),
            "volume_iterations_per_s": round(n * K / dt, 1),
            "mvoxel_iterations_per_s": round(npx * K / dt / 1e6, 1),
+           "with_pass_events": {"volume_iterations_per_s": round(n * K / dte, 1)},
            "hipgraph": {"volume_iterations_per_s": round(n * K / dtg, 1), "bitwise_equal_to_eager": gsame},
            "nmse_db_mean": round(nm, 3),
            "passes": pass_rooflines(times, npx, K, reps, alg=algorithmic_bytes_per_solve_3d(npx, K))}
