@@ -604,7 +604,7 @@ def test_resume_continues_bitwise():
             assert np.array_equal(mj[b], stop["x_hat"][b]), (j, b)
 
 
-def test_resume_without_iterations_is_line10():
+def test_resume_without_iterations_is_the_output_step():
     """iters = 0 with a state: the output step with w = eta(r_k; theta_k), against the oracle's
     the output step on the same FP32-rounded state."""
     from paper_1911_01234_amd import vdamp as V

@@ -320,7 +320,7 @@ def test_zero_iterations_is_zero_filled():
     assert np.abs(out["x_hat"] - o.ifft2u(y)).max() < 1e-13
 
 
-def test_line8_needs_no_guard():
+def test_onsager_correction_needs_no_guard():
     """alpha in [0, 1 - 1/N_b] for every band and iteration."""
     ny = nx = 32
     x0, p, rng = tiny_problem(ny, nx)
