@@ -367,18 +367,30 @@ k_sure(KArgs a) {
   }
   __syncthreads();
   const float inv_tau = 1.0f / tau_sh;
-  // slot of each key in its bucket, one byte per key, four to a register (slots above
-  // 255 saturate: such a bucket exceeds kSureBucketLimit and takes the bitonic path)
-  constexpr int KP = (KPT + 3) / 4;
+  // slot of each key in its bucket (slots above 255 saturate: such a bucket exceeds
+  // kSureBucketLimit and takes the bitonic path).  Overlay classes on single keys keep
+  // the bucket and the slot of each key packed in one register, bucket | slot << 15, so
+  // the bounds step below needs no second bucket computation; the others (pair keys
+  // would spill with those registers live through the bucket scan) keep the slots one
+  // byte per key, four to a register, and recompute the bucket where they need it.
+  static_assert(NB < (1 << 15), "bucket index in 15 bits");
+  constexpr bool KEEPB = OV && GD == 1;
+  constexpr int KP = KEEPB ? 1 : (KPT + 3) / 4;
   unsigned pk[KP];
+  int pos[KPT];
 #pragma unroll
   for (int q = 0; q < KP; ++q) pk[q] = 0u;
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
     const int i = tid + j * NT;
+    pos[j] = 0;
     if (i < Nb) {
-      const unsigned sl = (unsigned)atomicAdd(&off[sure_bucket<NB>(kk[j], inv_tau)], 1);
-      pk[j >> 2] |= min(sl, 255u) << (8 * (j & 3));
+      const int bk = sure_bucket<NB>(kk[j], inv_tau);
+      const unsigned sl = min((unsigned)atomicAdd(&off[bk], 1), 255u);
+      if constexpr (KEEPB)
+        pos[j] = bk | (int)(sl << 15);
+      else
+        pk[j >> 2] |= sl << (8 * (j & 3));
     }
   }
   __syncthreads();
@@ -418,16 +430,21 @@ k_sure(KArgs a) {
     // they are taken into registers before the keys overwrite the table, later the
     // same registers hold the final positions
     static_assert(MAXK < (1 << 15) && kSureBucketLimit < (1 << 7), "packed bucket bounds");
-    int pos[KPT];
     if constexpr (OV) {
 #pragma unroll
       for (int j = 0; j < KPT; ++j) {
         const int i = tid + j * NT;
-        pos[j] = 0;
         if (i < Nb) {
-          const int bk = sure_bucket<NB>(kk[j], inv_tau);
+          int bk, slot;
+          if constexpr (KEEPB) {
+            bk = pos[j] & 0x7FFF;
+            slot = pos[j] >> 15;
+          } else {
+            bk = sure_bucket<NB>(kk[j], inv_tau);
+            slot = SURE_SLOT(j);
+          }
           const int lo = off[bk];
-          pos[j] = lo | ((off[bk + 1] - lo) << 15) | (SURE_SLOT(j) << 22);
+          pos[j] = lo | ((off[bk + 1] - lo) << 15) | (slot << 22);
         }
       }
       __syncthreads();
