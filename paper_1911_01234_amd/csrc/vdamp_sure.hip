@@ -30,25 +30,41 @@ __device__ __forceinline__ int wave_incl_prefix_int(int v, int lane) {
   return v;
 }
 
+// The wave index of a thread, as a scalar (it is the same for every lane of a wave;
+// held in a scalar register, the values derived from it need no vector registers).
+__device__ __forceinline__ int wave_id(int tid) { return __builtin_amdgcn_readfirstlane(tid >> 6); }
+
+// Value of lane src (the same for every lane of the wave, e.g. derived from the wave
+// index) broadcast to the wave: a scalar read of the lane, no LDS permute and no
+// per-lane address register.
+__device__ __forceinline__ int wave_bcast(int v, int src) {
+  return __builtin_amdgcn_readlane(v, __builtin_amdgcn_readfirstlane(src));
+}
+__device__ __forceinline__ double wave_bcast(double v, int src) {
+  const int s = __builtin_amdgcn_readfirstlane(src);
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), s),
+                          __builtin_amdgcn_readlane(__double2loint(v), s));
+}
+
 // Exclusive prefix (and suffix) over the NW per-wave totals tot[0..NW) at wave wid, for
 // every lane of the wave: lanes load one total each and scan with shuffles (no per-thread
 // loop over the waves, which would hold the totals in registers).
 template <int NW>
 __device__ __forceinline__ int wave_offset_int(const int* tot, int wid, int lane) {
   const int v = wave_incl_prefix_int(lane < NW ? tot[lane] : 0, lane);
-  const int o = __shfl(v, wid > 0 ? wid - 1 : 0, 64);
+  const int o = wave_bcast(v, wid > 0 ? wid - 1 : 0);
   return wid > 0 ? o : 0;
 }
 template <int NW>
 __device__ __forceinline__ double wave_offset_prefix(const double* tot, int wid, int lane) {
   const double v = wave_incl_prefix(lane < NW ? tot[lane] : 0.0, lane);
-  const double o = __shfl(v, wid > 0 ? wid - 1 : 0, 64);
+  const double o = wave_bcast(v, wid > 0 ? wid - 1 : 0);
   return wid > 0 ? o : 0.0;
 }
 template <int NW>
 __device__ __forceinline__ double wave_offset_suffix(const double* tot, int wid, int lane) {
   const double v = wave_incl_suffix(lane < NW ? tot[lane] : 0.0, lane);
-  const double o = __shfl(v, wid + 1 < NW ? wid + 1 : 0, 64);
+  const double o = wave_bcast(v, wid + 1 < NW ? wid + 1 : 0);
   return wid + 1 < NW ? o : 0.0;
 }
 
@@ -147,7 +163,7 @@ template <int NT, bool CONT>
 __device__ void sure_walk_t(const float* sk, int Nb, double tl, double td, double* wsA, double* wsR,
                             SureBest& best) {
   constexpr int NW = NT / 64;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wid = wave_id(tid);
   const int E = (Nb + NT - 1) / NT;
   const int i0 = tid * E;
   const int i1 = min(i0 + E, Nb);
@@ -215,7 +231,7 @@ template <int NT, int GD = 1>
 __device__ void sure_finish(const KArgs& a, int sl, int b, int Nb, float tau_f, SureBest best,
                             SureBest* fin) {
   constexpr int NW = NT / 64;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wid = wave_id(tid);
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     SureBest ob;
@@ -313,7 +329,7 @@ k_sure(KArgs a) {
   const int2 item = a.work[blockIdx.x];
   const int sl = item.x, b = item.y, s = a.levels;
   const SliceDev S = a.slices[sl];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wid = wave_id(tid);
   int d0, r0, c0, bd, bh, bw;
   band_geom3(b, s, S.nd, S.ny, S.nx, d0, r0, c0, bd, bh, bw);
   const int Nb = bd * bh * bw / GD;
@@ -619,7 +635,7 @@ __global__ void __launch_bounds__(NT) k_sure_big(KArgs a, float* __restrict__ sc
   const int2 item = a.work[blockIdx.x];
   const int sl = item.x, b = item.y, s = a.levels;
   const SliceDev S = a.slices[sl];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wid = wave_id(tid);
   int d0, r0, c0, bd, bh, bw;
   band_geom3(b, s, S.nd, S.ny, S.nx, d0, r0, c0, bd, bh, bw);
   const int Nb = bd * bh * bw / GD;  // keys: coefficients, or pairs x = 2j, 2j + 1
