@@ -159,19 +159,72 @@ __device__ __forceinline__ void sure_inner(float klo, float khi, double A, int m
 // run of equal keys with a > 0 (tl, td as in sure_inner); with cont, also the
 // quadratic's minimum inside every interval between distinct keys (sure_inner), from 0
 // up to the smallest positive key onwards.  Per thread the best (SureBest).
-template <int NT, bool CONT>
+// One key of the walk: key k2 at sorted index i, the next key knext (+inf after the
+// last), the previous key kprev (continuous mode); A (sum of a^2 below i) and Rrun (sum
+// of 1/a from i on) advance past the key.
+template <bool CONT>
+__device__ __forceinline__ void walk_step(float k2, float knext, float kprev, int i, int Nb, double& A,
+                                          double& Rrun, double tl, double td, double Nbd, SureBest& best) {
+  if (CONT && k2 > 0.f && !(kprev > 0.f))  // the interval (0, a_i) below the first positive key
+    sure_inner(0.f, k2, A, i, Rrun, tl, td, Nbd, best);
+  A += (double)k2;
+  if (k2 > 0.f) {
+    Rrun -= (double)__frsqrt_rn(k2);  // now the sum over indices > i
+    if (knext > k2) {                 // last index of a run of equal keys
+      const double x = (double)__fsqrt_rn(k2);
+      const double m = (double)(i + 1);
+      const double sv = A - m * tl + (Nbd - m) * ((double)k2 + tl) - td * x * Rrun;
+      // a thread's candidates come in increasing m, so without inner thresholds a
+      // strictly smaller value is the only way to win
+      if (CONT ? sure_better(sv, i + 1, 0, best) : sv < best.v) {
+        best.v = sv;
+        best.m = i + 1;
+        best.inner = 0;
+        best.R = Rrun;
+        best.key = k2;
+      }
+      if (CONT && i + 1 < Nb) sure_inner(k2, knext, A, i + 1, Rrun, tl, td, Nbd, best);
+    }
+  }
+}
+
+// SURE at every candidate of the sorted keys: each thread walks a contiguous chunk with
+// a = sqrt(key), A_m = sum_{i<=m} a_i^2 and R_m = sum_{i>m} 1/a_i (FP64 accumulation of
+// FP32 terms, chunk offsets from FP64 prefix/suffix scans) and evaluates
+// SURE(m) = A_m - m tl + (N_b - m)(a_m^2 + tl) - td a_m R_m at the last index of each
+// run of equal keys with a > 0 (tl, td as in sure_inner); with cont, also the
+// quadratic's minimum inside every interval between distinct keys (sure_inner), from 0
+// up to the smallest positive key onwards.  Per thread the best (SureBest).
+// CH = 16: a thread whose chunk holds exactly 16 keys starting at a multiple of 16 reads
+// them once into registers (contiguous in the padded layout) and walks them unrolled;
+// the sums and the order of every operation are those of the general loop.
+template <int NT, bool CONT, int CH>
 __device__ void sure_walk_t(const float* sk, int Nb, double tl, double td, double* wsA, double* wsR,
                             SureBest& best) {
+  static_assert(CH == 0 || CH == 16, "chunk of 16 keys or none");
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wid = wave_id(tid);
   const int E = (Nb + NT - 1) / NT;
   const int i0 = tid * E;
   const int i1 = min(i0 + E, Nb);
+  const bool full = CH > 0 && E == CH && i1 - i0 == CH;
   double cA = 0.0, cR = 0.0;
-  for (int i = i0; i < i1; ++i) {
-    const float k2 = sk[skx(i)];
-    cA += (double)k2;
-    if (k2 > 0.f) cR += (double)__frsqrt_rn(k2);
+  float kc[CH > 0 ? CH : 1];
+  if (full) {
+    const float* base = sk + skx(i0);
+#pragma unroll
+    for (int k = 0; k < CH; ++k) kc[k] = base[k];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      cA += (double)kc[k];
+      if (kc[k] > 0.f) cR += (double)__frsqrt_rn(kc[k]);
+    }
+  } else {
+    for (int i = i0; i < i1; ++i) {
+      const float k2 = sk[skx(i)];
+      cA += (double)k2;
+      if (k2 > 0.f) cR += (double)__frsqrt_rn(k2);
+    }
   }
   const double pA = wave_incl_prefix(cA, lane);
   const double sR = wave_incl_suffix(cR, lane);
@@ -184,42 +237,32 @@ __device__ void sure_walk_t(const float* sk, int Nb, double tl, double td, doubl
   double Rrun = offR + sR;            // sum of 1/a over indices >= i0
   best = sure_none();
   const double Nbd = (double)Nb;
+  if (full) {
+    const float after = (i1 < Nb) ? sk[skx(i1)] : __builtin_huge_valf();
+    float kprev = (CONT && i0 > 0) ? sk[skx(i0 - 1)] : 0.f;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      walk_step<CONT>(kc[k], k + 1 < CH ? kc[k + 1] : after, kprev, i0 + k, Nb, A, Rrun, tl, td, Nbd, best);
+      if (CONT) kprev = kc[k];
+    }
+    return;
+  }
   float knext = (i0 < i1) ? sk[skx(i0)] : 0.f;
   float kprev = (CONT && i0 > 0 && i0 < i1) ? sk[skx(i0 - 1)] : 0.f;
   for (int i = i0; i < i1; ++i) {
     const float k2 = knext;
     knext = (i + 1 < Nb) ? sk[skx(i + 1)] : __builtin_huge_valf();
-    if (CONT && k2 > 0.f && !(kprev > 0.f))  // the interval (0, a_i) below the first positive key
-      sure_inner(0.f, k2, A, i, Rrun, tl, td, Nbd, best);
-    A += (double)k2;
-    if (k2 > 0.f) {
-      Rrun -= (double)__frsqrt_rn(k2);  // now the sum over indices > i
-      if (knext > k2) {                 // last index of a run of equal keys
-        const double x = (double)__fsqrt_rn(k2);
-        const double m = (double)(i + 1);
-        const double sv = A - m * tl + (Nbd - m) * ((double)k2 + tl) - td * x * Rrun;
-        // a thread's candidates come in increasing m, so without inner thresholds a
-        // strictly smaller value is the only way to win
-        if (CONT ? sure_better(sv, i + 1, 0, best) : sv < best.v) {
-          best.v = sv;
-          best.m = i + 1;
-          best.inner = 0;
-          best.R = Rrun;
-          best.key = k2;
-        }
-        if (CONT && i + 1 < Nb) sure_inner(k2, knext, A, i + 1, Rrun, tl, td, Nbd, best);
-      }
-    }
+    walk_step<CONT>(k2, knext, kprev, i, Nb, A, Rrun, tl, td, Nbd, best);
     if (CONT) kprev = k2;
   }
 }
-template <int NT>
+template <int NT, int CH = 0>
 __device__ void sure_walk(const float* sk, int Nb, double tl, double td, bool cont, double* wsA, double* wsR,
                           SureBest& best) {
-  if (cont)
-    sure_walk_t<NT, true>(sk, Nb, tl, td, wsA, wsR, best);
+  if (cont)  // the continuous mode's inner-interval checks keep the general loop
+    sure_walk_t<NT, true, 0>(sk, Nb, tl, td, wsA, wsR, best);
   else
-    sure_walk_t<NT, false>(sk, Nb, tl, td, wsA, wsR, best);
+    sure_walk_t<NT, false, CH>(sk, Nb, tl, td, wsA, wsR, best);
 }
 
 // Workgroup argmin of the per-thread bests (sure_better), then theta (sqrt(key) for a
@@ -551,7 +594,9 @@ k_sure(KArgs a) {
     }
   }
   SureBest best;
-  sure_walk<NT>(sk, Nb, GD * (double)tau_sh, (2 * GD - 1) * (double)tau_sh, a.sure_cont != 0, wsA, wsR, best);
+  // (the unrolled walk of 16-key chunks on single keys: with pair keys it would spill)
+  sure_walk<NT, (KPT == 16 && GD == 1 ? 16 : 0)>(sk, Nb, GD * (double)tau_sh, (2 * GD - 1) * (double)tau_sh,
+                                                 a.sure_cont != 0, wsA, wsR, best);
   sure_finish<NT, GD>(a, sl, b, Nb, tau_sh, best, fin);
 }
 
