@@ -36,6 +36,7 @@ rate beside.
 from __future__ import annotations
 
 import argparse
+import collections
 import json
 import os
 import sys
@@ -330,6 +331,24 @@ def _oracle_slice(task):
     return b, float(10.0 * np.log10(np.sum(np.abs(xr - sl.x0) ** 2) / np.sum(np.abs(sl.x0) ** 2))), dt
 
 
+def _oracle_slice_perturbed(task):
+    """Worker of the NMSE check: the oracle on slice b of the benchmark's batch with y
+    multiplied by (1 + eps n), n a seeded standard complex Gaussian (run r): how far
+    FP32-sized input changes move the oracle's own 50-iteration NMSE on that slice."""
+    b, iters, r, eps = task
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+    from oracle import vdamp_ref as o
+    from paper_1911_01234_amd import synth
+    sl = synth.workload_batch256(1, first_slice=b)[0][0]
+    y = sl.y.astype(np.complex64).astype(np.complex128)
+    p = sl.p.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng((2024, b, r))
+    n = (rng.standard_normal(y.shape) + 1j * rng.standard_normal(y.shape)) / np.sqrt(2)
+    xr = o.vdamp(y * (1 + eps * n), sl.mask, p, float(np.float32(sl.sigma2)), LEVELS, iters)["x_hat"]
+    return b, float(10.0 * np.log10(np.sum(np.abs(xr - sl.x0) ** 2) / np.sum(np.abs(sl.x0) ** 2)))
+
+
 def make_cpu_pool():
     """Worker processes for the CPU baseline, one per core this process may use, forked
     before anything initialises the GPU (each worker runs NumPy with one thread)."""
@@ -352,7 +371,6 @@ def cpu_baseline(pool, cores, batch, iters, budget_s, gpu_nmse=None):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    pool.terminate()
     idx = sorted(done)
     nm = np.array([done[b] for b in idx])
     import platform
@@ -376,6 +394,25 @@ def cpu_baseline(pool, cores, batch, iters, budget_s, gpu_nmse=None):
                              "gpu_db_mean": round(float(g.mean()), 3),
                              "median_abs_diff_db": round(float(np.median(np.abs(d))), 4),
                              "max_abs_diff_db": round(float(np.max(np.abs(d))), 4)}
+        # the slices furthest from the oracle, each against the spread of 16 oracle runs
+        # on its inputs perturbed by 3e-7 relative (the final-NMSE bound of the parity
+        # tests: |gpu - mean| <= max(0.05 dB, 4 sd))
+        worst = [idx[i] for i in np.argsort(-np.abs(d))[:4]]
+        runs, eps = 16, 3e-7
+        pert = collections.defaultdict(list)
+        for b, v in pool.imap_unordered(_oracle_slice_perturbed,
+                                        [(b, iters, r, eps) for b in worst for r in range(runs)]):
+            pert[b].append(v)
+        rows = []
+        for b in worst:
+            vals = np.array([done[b]] + pert[b])
+            mean, sd = float(vals.mean()), float(vals.std())
+            gb = float(np.asarray(gpu_nmse, dtype=np.float64)[b])
+            rows.append({"slice": int(b), "gpu_db": round(gb, 3), "oracle_db": round(done[b], 3),
+                         "oracle_perturbed_mean_db": round(mean, 3), "oracle_perturbed_sd_db": round(sd, 3),
+                         "within_bound": bool(abs(gb - mean) <= max(0.05, 4 * sd))})
+        out["nmse_check"]["largest_gaps"] = {"runs": runs, "eps": eps, "slices": rows}
+    pool.terminate()
     return out
 
 
