@@ -225,38 +225,69 @@ __global__ void __launch_bounds__(kThr) k_wgrad(WgradArgs a) {
   f32x4 acc[NACC];
 #pragma unroll
   for (int j = 0; j < NACC; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  float bsum = 0.f;  // thread tid < MT*16: bias gradient of channel tid
+  float bsum = 0.f;  // thread 4 co (co < MT * 16): bias gradient of channel co
   for (int ti = blockIdx.x; ti < a.ntiles; ti += gridDim.x) {
     const int2 t = a.tiles[ti];
     const SliceDev S = a.slices[t.x];
     const int nx = S.nx, ny = S.ny, tpr = nx >> 4;
     const int ty0 = (t.y / tpr) * 16, tx0 = (t.y - (t.y / tpr) * tpr) * 16;
     __syncthreads();
-    // gradient tile, transposed: s_dz[co][p] (channels >= cout are zero)
+    // gradient tile, transposed: s_dz[co][p] (channels >= cout are zero); each pixel's
+    // channels arrive as 16-byte vectors of 8 (a pixel's dzc channels are 16-byte aligned)
     {
       const int p = tid;  // one pixel per thread
       const long long gp = S.off + (long long)(ty0 + (p >> 4)) * nx + tx0 + (p & 15);
-      for (int co = 0; co < MT * 16; ++co)
-        s_dz[co * DP + p] = (co < a.cout) ? a.dz[gp * a.dzc + co] : (u16)0;
+      const uint4* src = reinterpret_cast<const uint4*>(a.dz + gp * a.dzc);
+#pragma unroll
+      for (int q = 0; q < MT * 2; ++q) {
+        const uint4 v = (8 * q < a.dzc) ? src[q] : make_uint4(0u, 0u, 0u, 0u);
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int co = 8 * q + e;
+          s_dz[co * DP + p] = (co < a.cout) ? (u16)(w[e >> 1] >> (16 * (e & 1))) : (u16)0;
+        }
+      }
     }
-    // input halo, transposed: s_h[ci][hp]
-    for (int i = tid; i < 18 * 18; i += kThr) {
-      const int hy = i / 18, hx = i - hy * 18;
+    // input halo, transposed: s_h[ci][hp], read as 16-byte vectors of 8 channels
+    constexpr int CH8 = CIN / 8;
+    for (int i = tid; i < 18 * 18 * CH8; i += kThr) {
+      const int hp = i / CH8, c8 = i - hp * CH8;
+      const int hy = hp / 18, hx = hp - hy * 18;
       int gy = ty0 + hy - 1, gx = tx0 + hx - 1;
       gy += (gy < 0) ? ny : 0; gy -= (gy >= ny) ? ny : 0;
       gx += (gx < 0) ? nx : 0; gx -= (gx >= nx) ? nx : 0;
-      const u16* src = a.h + (S.off + (long long)gy * nx + gx) * CIN;
+      const uint4 v = *reinterpret_cast<const uint4*>(a.h + (S.off + (long long)gy * nx + gx) * CIN + 8 * c8);
+      const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int ci = 0; ci < CIN; ++ci) s_h[ci * HP + i] = src[ci];
+      for (int e = 0; e < 8; ++e) s_h[(8 * c8 + e) * HP + hp] = (u16)(w[e >> 1] >> (16 * (e & 1)));
     }
     __syncthreads();
-    if (tid < MT * 16) {
+    // bias gradient and the tile's channel sums: four threads a channel, 64 pixels each
+    // in order, the four partial sums combined in a fixed order ((q0 + q1) + (q2 + q3));
+    // the threads of a channel are neighbouring lanes of one wave and whole waves take
+    // part or not
+    if (tid < 4 * MT * 16) {
+      const int co = tid >> 2, qq = tid & 3;
+      const uint4* row = reinterpret_cast<const uint4*>(&s_dz[co * DP + qq * 64]);
       float sacc = 0.f;
-      for (int p = 0; p < 256; ++p) sacc += bf2f(s_dz[tid * DP + p]);
-      bsum += sacc;
-      if (a.tile_sums && tid < kCh) a.tile_sums[(long long)ti * kCh + tid] = sacc;
-    }
 #pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint4 v = row[q];
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sacc += bf2f((u16)(w[e >> 1] >> (16 * (e & 1))));
+      }
+      sacc += __shfl_xor(sacc, 1, 64);
+      sacc += __shfl_xor(sacc, 2, 64);
+      if (qq == 0) {
+        bsum += sacc;
+        if (a.tile_sums && co < kCh) a.tile_sums[(long long)ti * kCh + co] = sacc;
+      }
+    }
+    // the k-loop stays rolled: unrolled, the hoisted fragment reads of its eight steps hold
+    // about 370 registers (one wave a SIMD); rolled, about 200 (two workgroups a CU)
+#pragma unroll 1
     for (int ks = 0; ks < 8; ++ks) {  // 256 pixels = 8 steps of 32
       const int p0 = ks * 32 + g * 8;   // 8 consecutive pixels of one tile row
       const int py = p0 >> 4, px = p0 & 15;
@@ -294,7 +325,7 @@ __global__ void __launch_bounds__(kThr) k_wgrad(WgradArgs a) {
         P[(mt * 16 + 4 * g + i) * (NT * 16) + nt * 16 + c] = acc[j][i];
     }
   }
-  if (tid < MT * 16) a.part_bias[(long long)blockIdx.x * (MT * 16) + tid] = bsum;
+  if (tid < 4 * MT * 16 && (tid & 3) == 0) a.part_bias[(long long)blockIdx.x * (MT * 16) + (tid >> 2)] = bsum;
 }
 
 // Sum per-workgroup partials in a fixed order: out[i] = sum_w part[w][i].

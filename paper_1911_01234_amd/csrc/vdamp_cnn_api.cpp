@@ -45,7 +45,7 @@ namespace {
 constexpr int kC = 48;        // hidden channels
 constexpr int kLayers = 6;
 constexpr int kConvGrid = 512;   // persistent convolution workgroups (two per CU)
-constexpr int kWgradGrid = 256;  // weight-gradient workgroups (one per CU)
+constexpr int kWgradGrid = 512;  // weight-gradient workgroups (two per CU)
 
 // Geometry of layer l (1..6): channels, the padded channel stride of its input, the
 // rows of its forward weight matrix (16 per MFMA tile) and the padded K of the forward
