@@ -303,10 +303,19 @@ __global__ void __launch_bounds__(kThr) k_wgrad(WgradArgs a) {
           if (tap < 9) {
             const int dy = tap / 3, dx = tap - dy * 3;
             const u16* hrow = &s_h[ci * HP + (py + dy) * 18 + px + dx];
-            u16 tmp[8];
+            // with CIN a multiple of 16 the 16 columns of an n-tile share one tap, so dx
+            // is the same on every lane; HP, the row pitch and px are even, so for even dx
+            // the 8 values are 4-byte aligned and arrive as four 32-bit reads
+            if (CIN % 16 == 0 && (dx & 1) == 0) {
+              const unsigned* h32 = reinterpret_cast<const unsigned*>(hrow);
+              const uint4 q = make_uint4(h32[0], h32[1], h32[2], h32[3]);
+              B = *reinterpret_cast<const bf16x8*>(&q);
+            } else {
+              u16 tmp[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) tmp[e] = hrow[e];
-            B = *reinterpret_cast<const bf16x8*>(tmp);
+              for (int e = 0; e < 8; ++e) tmp[e] = hrow[e];
+              B = *reinterpret_cast<const bf16x8*>(tmp);
+            }
           }
           acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[j], 0, 0, 0);
         }
@@ -341,26 +350,50 @@ __global__ void __launch_bounds__(kThr) k_sum_partials(const float* __restrict__
 
 // Reduce the weight-gradient partials of one layer into the flat FP32 gradient in the
 // parameter layout W[co][ci][3][3], b[co]: gW[(co * cin + ci) * 9 + tap] = sum over
-// workgroups (in order) of part[w][co][tap * cinp + ci]; gb[co] = sum of part_bias.
-__global__ void __launch_bounds__(kThr) k_reduce_wgrad(const float* __restrict__ part,
-                                                       const float* __restrict__ part_bias,
-                                                       int nwg, int rows, int cols, int cinp,
-                                                       int cout, int cin, float* __restrict__ gW,
-                                                       float* __restrict__ gb) {
+// workgroups of part[w][co][tap * cinp + ci]; gb[co] = sum of part_bias.  Two stages in a
+// fixed order: up to kWgradReduceGroups contiguous groups of workgroups are summed in order,
+// then the group sums in group order.
+// Stage 1: column c of the partial matrices (or bias row c - rows * cols), summed over the
+// workgroups of group blockIdx.y (a contiguous range of them, in order).  Neighbouring
+// threads read neighbouring columns of one partial matrix.
+__global__ void __launch_bounds__(kThr) k_reduce_wgrad1(const float* __restrict__ part,
+                                                        const float* __restrict__ part_bias,
+                                                        int nwg, int rows, int cols,
+                                                        float* __restrict__ stage) {
+  const int c = blockIdx.x * kThr + threadIdx.x;
+  const int nm = rows * cols, n1 = nm + rows, G = gridDim.y, g = blockIdx.y;
+  const int w0 = (int)((long long)g * nwg / G), w1 = (int)((long long)(g + 1) * nwg / G);
+  if (c < nm) {
+    float s = 0.f;
+    for (int w = w0; w < w1; ++w) s += part[(long long)w * nm + c];
+    stage[(long long)g * n1 + c] = s;
+  } else if (c < n1) {
+    float s = 0.f;
+    for (int w = w0; w < w1; ++w) s += part_bias[(long long)w * rows + (c - nm)];
+    stage[(long long)g * n1 + c] = s;
+  }
+}
+// Stage 2: the group sums of each weight (co, ci, tap) and bias, in group order.
+__global__ void __launch_bounds__(kThr) k_reduce_wgrad2(const float* __restrict__ stage, int G,
+                                                        int rows, int cols, int cinp, int cout,
+                                                        int cin, float* __restrict__ gW,
+                                                        float* __restrict__ gb) {
   const int i = blockIdx.x * kThr + threadIdx.x;
-  const int nw = cout * cin * 9;
+  const int nw = cout * cin * 9, n1 = rows * cols + rows;
+  int col = -1;
   if (i < nw) {
     const int co = i / (cin * 9), rem = i - co * cin * 9, ci = rem / 9, tap = rem - ci * 9;
-    const long long col = (long long)co * cols + tap * cinp + ci;
-    float s = 0.f;
-    for (int w = 0; w < nwg; ++w) s += part[(long long)w * rows * cols + col];
-    gW[i] = s;
+    col = co * cols + tap * cinp + ci;
   } else if (i < nw + cout) {
-    const int co = i - nw;
-    float s = 0.f;
-    for (int w = 0; w < nwg; ++w) s += part_bias[(long long)w * rows + co];
-    gb[co] = s;
+    col = rows * cols + (i - nw);
   }
+  if (col < 0) return;
+  float s = 0.f;
+  for (int g = 0; g < G; ++g) s += stage[(long long)g * n1 + col];
+  if (i < nw)
+    gW[i] = s;
+  else
+    gb[i - nw] = s;
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -537,11 +570,14 @@ hipError_t launch_wgrad(const WgradArgs& a, int layer, int grid, hipStream_t st)
 }
 
 hipError_t launch_reduce_wgrad(const float* part, const float* part_bias, int nwg, int rows,
-                               int cols, int cinp, int cout, int cin, float* gW, float* gb,
-                               hipStream_t st) {
-  const int n = cout * cin * 9 + cout;
-  hipLaunchKernelGGL(k_reduce_wgrad, dim3((n + kThr - 1) / kThr), dim3(kThr), 0, st, part,
-                     part_bias, nwg, rows, cols, cinp, cout, cin, gW, gb);
+                               int cols, int cinp, int cout, int cin, float* stage, float* gW,
+                               float* gb, hipStream_t st) {
+  const int n1 = rows * cols + rows, n = cout * cin * 9 + cout;
+  const int G = nwg < kWgradReduceGroups ? nwg : kWgradReduceGroups;
+  hipLaunchKernelGGL(k_reduce_wgrad1, dim3((n1 + kThr - 1) / kThr, G), dim3(kThr), 0, st, part,
+                     part_bias, nwg, rows, cols, stage);
+  hipLaunchKernelGGL(k_reduce_wgrad2, dim3((n + kThr - 1) / kThr), dim3(kThr), 0, st, stage, G,
+                     rows, cols, cinp, cout, cin, gW, gb);
   return hipGetLastError();
 }
 hipError_t launch_sum_partials(const float* part, int nwg, long long n, float* out, hipStream_t st) {

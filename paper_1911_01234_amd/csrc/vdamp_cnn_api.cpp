@@ -19,8 +19,8 @@ namespace cnn {
 hipError_t launch_conv(const ConvArgs& a, int cin, int mt, int mode, int grid, hipStream_t st);
 hipError_t launch_wgrad(const WgradArgs& a, int layer, int grid, hipStream_t st);
 hipError_t launch_reduce_wgrad(const float* part, const float* part_bias, int nwg, int rows,
-                               int cols, int cinp, int cout, int cin, float* gW, float* gb,
-                               hipStream_t st);
+                               int cols, int cinp, int cout, int cin, float* stage, float* gW,
+                               float* gb, hipStream_t st);
 hipError_t launch_pack_input(const SliceDev* slices, int batch, const float2* x, const float* s0,
                              long long npx, u16* out, hipStream_t st);
 hipError_t launch_slice_bias(const float* b1, const float* wt, const float* tau, const float* s0,
@@ -90,7 +90,7 @@ void free_cnn(vdamp_cnn_t* C) {
 // Workspace layout of the denoiser on a plan (byte offsets; 0 = absent).
 struct CnnWs {
   size_t a0 = 0, t0 = 0, act[kLayers] = {}, ta = 0, tb = 0, g6 = 0, ga = 0, gb = 0;
-  size_t sbias = 0, lpart = 0, part = 0, pbias = 0, tsums = 0, xo = 0;
+  size_t sbias = 0, lpart = 0, part = 0, pbias = 0, rstage = 0, tsums = 0, xo = 0;
   size_t xi = 0, ti = 0, xo2 = 0, to = 0, jpart = 0, sel = 0, smin = 0, s0 = 0, jout = 0;
   size_t bits = 0;  // ReLU pattern of the current layer (forward and solve kinds)
   size_t bytes = 0;
@@ -112,6 +112,7 @@ CnnWs cnn_layout(const vdamp_plan_t* P, int kind) {
     take(L.lpart, 4 * ((N + 255) / 256));
     take(L.part, 4 * (size_t)kWgradGrid * kC * 432);
     take(L.pbias, 4 * (size_t)kWgradGrid * kC);
+    take(L.rstage, 4 * (size_t)cnn::kWgradReduceGroups * (kC * 432 + kC));  // first-stage group sums
     take(L.tsums, 4 * (size_t)std::max(P->ntiles, 1) * kC);
   } else {
     take(L.t0, 2 * 8 * N);
@@ -291,7 +292,7 @@ vdamp_status enqueue_train(vdamp_cnn_t* C, const vdamp_plan_t* P, const CnnWs& L
     const int rows = l == kLayers ? 16 : kC;
     const int cols = l == 1 ? 80 : 432;
     HIP_TRY(cnn::launch_reduce_wgrad(part, pbias, wgrid, rows, cols, g.cinp, g.cout, g.cin,
-                                     C->d_g + C->oW[l], C->d_g + C->ob[l], st));
+                                     at<float>(ws, L.rstage), C->d_g + C->oW[l], C->d_g + C->ob[l], st));
     if (l == 1) {
       HIP_TRY(cnn::launch_wt_grad(tsums, P->d_tile_off, tau, s0, C->nb, P->B, kCnnTauStride, C->d_g + C->oWt,
                                   st));

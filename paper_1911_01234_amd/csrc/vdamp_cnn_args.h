@@ -35,6 +35,9 @@ struct ConvArgs {
   float2* img_out;      // complex image (last layer)
 };
 
+// First-stage groups of the weight-gradient reduction (the workspace holds their sums).
+constexpr int kWgradReduceGroups = 16;
+
 struct WgradArgs {
   const SliceDev* slices;
   const int2* tiles;
