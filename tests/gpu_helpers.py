@@ -32,6 +32,18 @@ def fp32_state(r, theta, alpha):
             np.asarray(alpha).astype(np.float32).astype(np.float64))
 
 
+def oracle_states_batch256(task):
+    """Worker (no GPU): slice b of the 256x256 benchmark batch regenerated from its seeds,
+    the oracle run on its FP32-rounded inputs, and its state at each iteration k of ks
+    rounded to FP32: (b, {k: (r_k, theta_k, alpha_k)})."""
+    b, ks = task
+    from paper_1911_01234_amd import synth
+    sl = synth.workload_batch256(1, first_slice=b)[0][0]
+    traj = o.vdamp(*fp32_inputs(sl), 4, max(ks) + 1, record=True)
+    return b, {k: (traj["r"][k].astype(np.complex64), traj["theta"][k].astype(np.float32),
+                   traj["alpha"][k].astype(np.float32)) for k in ks}
+
+
 def run_resume(plan, slices, states, iters, want_state=True, x_monitor=False, stream=None):
     """vdamp_solve_resume on every slice of the plan: states maps slice index b to an
     FP32 state (r_k [ny][nx], theta_k [nb], alpha_k [nb]); slices not in states start

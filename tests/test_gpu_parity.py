@@ -532,6 +532,38 @@ def test_full_batch_256_sampled():
     sampled_one_step(g["plan"], slices, s, refs, (0, 7, 24, 48))
 
 
+def test_full_batch_256_one_step_every_slice():
+    """Every slice of the benchmark's batch inside the benchmark's plan (256 slices of
+    256x256, 4 levels, eager launches): at k = 6, 24 and 48 each slice resumes from the
+    oracle's FP32-rounded state at k in one call, and every slice's step is held to the
+    one-step gate (r_{k+1} and tau to 1e-5, theta and alpha to their tolerances or, at a
+    near tie, validated on the library's own iterate).  The oracle trajectories run in
+    worker processes."""
+    import multiprocessing as mp
+    import os
+    from paper_1911_01234_amd import vdamp as V
+    from gpu_helpers import oracle_states_batch256
+    slices, s, K = synth.workload_batch256(256)
+    ks = (6, 24, 48)
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        got = dict(pool.map(oracle_states_batch256, [(b, ks) for b in range(len(slices))]))
+    print(f"oracle states at k={ks} for {len(got)} slices", flush=True)
+    plan = V.Plan([256] * len(slices), [256] * len(slices), s)
+    for k in ks:
+        states = {b: fp32_state(*got[b][k]) for b in range(len(slices))}
+        g = run_resume(plan, slices, states, 1)
+        errs, terrs, flips = [], [], 0
+        for b in range(len(slices)):
+            e, et, f = one_step_check(slices[b], s, states[b], g, b, k, what=f"slice {b}")
+            errs.append(e)
+            terrs.append(et)
+            flips += f
+        print(f"one step at k={k} on all {len(slices)} slices: max r rel L2 {max(errs):.2e} (median "
+              f"{np.median(errs):.2e}), max tau rel {max(terrs):.2e}, bands decided differently {flips} of "
+              f"{len(slices) * (1 + 3 * s)}", flush=True)
+    plan.close()
+
+
 def test_mixed_size_batch_sampled():
     """The ragged batch of 512 slices (128, 192, 256 and 320 square, R 4-10, 25-45 dB)
     as one plan: one sampled slice of each size against the oracle."""
