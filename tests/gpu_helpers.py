@@ -44,6 +44,16 @@ def oracle_states_batch256(task):
                    traj["alpha"][k].astype(np.float32)) for k in ks}
 
 
+def oracle_states_of(task):
+    """Worker (no GPU): the oracle on one slice's FP32 inputs (y complex64, mask, p and
+    sigma^2 float32, upcast here), its state at each iteration k of ks rounded to FP32:
+    (b, {k: (r_k, theta_k, alpha_k)})."""
+    b, y, mask, p, s2, s, ks = task
+    traj = o.vdamp(y.astype(np.complex128), mask, p.astype(np.float64), float(s2), s, max(ks) + 1, record=True)
+    return b, {k: (traj["r"][k].astype(np.complex64), traj["theta"][k].astype(np.float32),
+                   traj["alpha"][k].astype(np.float32)) for k in ks}
+
+
 def run_resume(plan, slices, states, iters, want_state=True, x_monitor=False, stream=None):
     """vdamp_solve_resume on every slice of the plan: states maps slice index b to an
     FP32 state (r_k [ny][nx], theta_k [nb], alpha_k [nb]); slices not in states start

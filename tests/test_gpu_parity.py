@@ -564,6 +564,54 @@ def test_full_batch_256_one_step_every_slice():
     plan.close()
 
 
+def one_step_every_slice(slices, s, ks, what):
+    """Every slice of a batch in one plan: at each k of ks all slices resume from the
+    oracle's FP32-rounded states at k in one call and every slice's step is held to the
+    one-step gate.  The oracle trajectories run in worker processes."""
+    import multiprocessing as mp
+    import os
+    from paper_1911_01234_amd import vdamp as V
+    from gpu_helpers import oracle_states_of
+
+    def tasks():
+        for b, sl in enumerate(slices):
+            y, mask, p, s2 = fp32_inputs(sl)
+            yield (b, y.astype(np.complex64), mask, p.astype(np.float32), np.float32(s2), s, ks)
+
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        got = dict(pool.imap_unordered(oracle_states_of, tasks(), chunksize=4))
+    print(f"oracle states at k={ks} for {len(got)} slices", flush=True)
+    plan = V.Plan([sl.y.shape[0] for sl in slices], [sl.y.shape[1] for sl in slices], s)
+    for k in ks:
+        states = {b: fp32_state(*got[b][k]) for b in range(len(slices))}
+        g = run_resume(plan, slices, states, 1)
+        errs, terrs, flips = [], [], 0
+        for b in range(len(slices)):
+            e, et, f = one_step_check(slices[b], s, states[b], g, b, k, what=f"{what} slice {b}")
+            errs.append(e)
+            terrs.append(et)
+            flips += f
+        print(f"{what}: one step at k={k} on all {len(slices)} slices: max r rel L2 {max(errs):.2e} "
+              f"(median {np.median(errs):.2e}), max tau rel {max(terrs):.2e}, bands decided differently "
+              f"{flips} of {len(slices) * (1 + 3 * s)}", flush=True)
+        del g
+    plan.close()
+
+
+def test_mixed_size_batch_one_step_every_slice():
+    """The ragged batch of 512 slices (128 to 320 square) as one plan (size groups on
+    forked streams): every slice's step from the oracle's state at k = 24."""
+    slices, s, K = synth.workload_mixed()
+    one_step_every_slice(slices, s, (24,), "mixed batch")
+
+
+def test_batch_512_one_step_every_slice():
+    """128 textured slices of 512x512 (finest bands of 65536 keys: the large-band search)
+    as one plan: every slice's step from the oracle's state at k = 24."""
+    slices, s, K = synth.workload_batch512(128)
+    one_step_every_slice(slices, s, (24,), "512x512 batch")
+
+
 def test_mixed_size_batch_sampled():
     """The ragged batch of 512 slices (128, 192, 256 and 320 square, R 4-10, 25-45 dB)
     as one plan: one sampled slice of each size against the oracle."""
