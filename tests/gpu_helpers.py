@@ -46,10 +46,12 @@ def oracle_states_batch256(task):
 
 def oracle_states_of(task):
     """Worker (no GPU): the oracle on one slice's FP32 inputs (y complex64, mask, p and
-    sigma^2 float32, upcast here), its state at each iteration k of ks rounded to FP32:
+    sigma^2 float32, upcast here; wavelet: None for Haar or a lowpass filter; group 1 or
+    2), its state at each iteration k of ks rounded to FP32:
     (b, {k: (r_k, theta_k, alpha_k)})."""
-    b, y, mask, p, s2, s, ks = task
-    traj = o.vdamp(y.astype(np.complex128), mask, p.astype(np.float64), float(s2), s, max(ks) + 1, record=True)
+    b, y, mask, p, s2, s, ks, wavelet, group = task
+    traj = o.vdamp(y.astype(np.complex128), mask, p.astype(np.float64), float(s2), s, max(ks) + 1, record=True,
+                   wavelet=wavelet, group=group)
     return b, {k: (traj["r"][k].astype(np.complex64), traj["theta"][k].astype(np.float32),
                    traj["alpha"][k].astype(np.float32)) for k in ks}
 

@@ -564,10 +564,11 @@ def test_full_batch_256_one_step_every_slice():
     plan.close()
 
 
-def one_step_every_slice(slices, s, ks, what):
-    """Every slice of a batch in one plan: at each k of ks all slices resume from the
-    oracle's FP32-rounded states at k in one call and every slice's step is held to the
-    one-step gate.  The oracle trajectories run in worker processes."""
+def one_step_every_slice(slices, s, ks, what, flags=0, wavelet=None, group=1):
+    """Every slice of a batch in one plan (flags, wavelet and group as the plan's): at each
+    k of ks all slices resume from the oracle's FP32-rounded states at k in one call and
+    every slice's step is held to the one-step gate.  The oracle trajectories run in
+    worker processes."""
     import multiprocessing as mp
     import os
     from paper_1911_01234_amd import vdamp as V
@@ -576,18 +577,21 @@ def one_step_every_slice(slices, s, ks, what):
     def tasks():
         for b, sl in enumerate(slices):
             y, mask, p, s2 = fp32_inputs(sl)
-            yield (b, y.astype(np.complex64), mask, p.astype(np.float32), np.float32(s2), s, ks)
+            yield (b, y.astype(np.complex64), mask, p.astype(np.float32), np.float32(s2), s, ks, wavelet, group)
 
     with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
         got = dict(pool.imap_unordered(oracle_states_of, tasks(), chunksize=4))
     print(f"oracle states at k={ks} for {len(got)} slices", flush=True)
-    plan = V.Plan([sl.y.shape[0] for sl in slices], [sl.y.shape[1] for sl in slices], s)
+    if group == 2:
+        flags |= V.VDAMP_FLAG_GROUP_PAIRS
+    plan = V.Plan([sl.y.shape[0] for sl in slices], [sl.y.shape[1] for sl in slices], s, flags, lowpass=wavelet)
     for k in ks:
         states = {b: fp32_state(*got[b][k]) for b in range(len(slices))}
         g = run_resume(plan, slices, states, 1)
         errs, terrs, flips = [], [], 0
         for b in range(len(slices)):
-            e, et, f = one_step_check(slices[b], s, states[b], g, b, k, what=f"{what} slice {b}")
+            e, et, f = one_step_check(slices[b], s, states[b], g, b, k, what=f"{what} slice {b}", wavelet=wavelet,
+                                      group=group)
             errs.append(e)
             terrs.append(et)
             flips += f
@@ -599,17 +603,36 @@ def one_step_every_slice(slices, s, ks, what):
 
 
 def test_mixed_size_batch_one_step_every_slice():
-    """The ragged batch of 512 slices (128 to 320 square) as one plan (size groups on
-    forked streams): every slice's step from the oracle's state at k = 24."""
+    """The ragged batch of 512 slices (128 to 320 square) as one autotuned plan, as the
+    benchmark plans it (size groups on forked streams): every slice's step from the
+    oracle's state at k = 24."""
+    from paper_1911_01234_amd import vdamp as V
     slices, s, K = synth.workload_mixed()
-    one_step_every_slice(slices, s, (24,), "mixed batch")
+    one_step_every_slice(slices, s, (24,), "mixed batch", flags=V.VDAMP_FLAG_AUTOTUNE)
 
 
 def test_batch_512_one_step_every_slice():
     """128 textured slices of 512x512 (finest bands of 65536 keys: the large-band search)
-    as one plan: every slice's step from the oracle's state at k = 24."""
+    as one autotuned plan, as the benchmark plans it: every slice's step from the oracle's
+    state at k = 24."""
+    from paper_1911_01234_amd import vdamp as V
     slices, s, K = synth.workload_batch512(128)
-    one_step_every_slice(slices, s, (24,), "512x512 batch")
+    one_step_every_slice(slices, s, (24,), "512x512 batch", flags=V.VDAMP_FLAG_AUTOTUNE)
+
+
+def test_db4_batch_one_step_every_slice():
+    """The benchmark's db4 batch (256 slices of 256x256, vdamp_plan_ortho with the 8-tap
+    Daubechies filter): every slice's step from the oracle's state at k = 24."""
+    from paper_1911_01234_amd import filters
+    slices, s, K = synth.workload_batch256(256)
+    one_step_every_slice(slices, s, (24,), "db4 batch", wavelet=filters.daubechies(4))
+
+
+def test_pair_groups_batch_one_step_every_slice():
+    """The benchmark's pair-group batch (256 slices of 256x256, VDAMP_FLAG_GROUP_PAIRS):
+    every slice's step from the oracle's state at k = 24."""
+    slices, s, K = synth.workload_batch256(256)
+    one_step_every_slice(slices, s, (24,), "pair-group batch", group=2)
 
 
 def test_mixed_size_batch_sampled():
