@@ -56,6 +56,16 @@ def oracle_states_of(task):
                    traj["alpha"][k].astype(np.float32)) for k in ks}
 
 
+def oracle3_states_of(task):
+    """Worker (no GPU): the 3D oracle on one volume's FP32 inputs (upcast here), its state
+    at each iteration k of ks rounded to FP32: (b, {k: (r_k, theta_k, alpha_k)})."""
+    b, y, mask, p, s2, s, ks = task
+    from oracle import vdamp3d_ref as o3
+    traj = o3.vdamp3(y.astype(np.complex128), mask, p.astype(np.float64), float(s2), s, max(ks) + 1, record=True)
+    return b, {k: (traj["r"][k].astype(np.complex64), np.asarray(traj["theta"][k], np.float32),
+                   np.asarray(traj["alpha"][k], np.float32)) for k in ks}
+
+
 def run_resume(plan, slices, states, iters, want_state=True, x_monitor=False, stream=None):
     """vdamp_solve_resume on every slice of the plan: states maps slice index b to an
     FP32 state (r_k [ny][nx], theta_k [nb], alpha_k [nb]); slices not in states start

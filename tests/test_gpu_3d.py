@@ -169,6 +169,37 @@ def test_one_step(wl, ks):
     plan.close()
 
 
+def test_volume_batch_one_step_every_volume():
+    """The benchmark's volume batch (32 volumes of 64^3, 3 levels) as one plan: every
+    volume resumes from the oracle's FP32-rounded state at k = 15 in one call, and every
+    volume's step is held to the one-step gate.  The oracle trajectories run in worker
+    processes."""
+    import multiprocessing as mp
+    import os
+    from gpu_helpers import oracle3_states_of
+    vols, s, K = synth.workload_volume64(32)
+    k = 15
+    tasks = []
+    for b, v in enumerate(vols):
+        y, mask, p, s2 = fp32_vol(v)
+        tasks.append((b, y.astype(np.complex64), mask, p.astype(np.float32), np.float32(s2), s, (k,)))
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        got = dict(pool.map(oracle3_states_of, tasks))
+    states = [fp32_state3(*got[b][k]) for b in range(len(vols))]
+    plan = _plan(vols, s)
+    g = _solve(plan, vols, 1, state=states)
+    errs, terrs, nflip = [], [], 0
+    for b, v in enumerate(vols):
+        e, et, f = one_step3(v, s, states[b], g, b, k, f"volume {b}")
+        errs.append(e)
+        terrs.append(et)
+        nflip += f
+    print(f"one step at k={k} on all {len(vols)} volumes: max r rel L2 {max(errs):.2e} (median "
+          f"{np.median(errs):.2e}), max tau rel {max(terrs):.2e}, bands decided differently {nflip} of "
+          f"{len(vols) * (1 + 7 * s)}", flush=True)
+    plan.close()
+
+
 def test_free_running_volume32():
     """Thresholds SURE-optimal on the library's own iterates, final NMSE within 0.05 dB
     of the oracle's (or the perturbation envelope when the runs part at a near tie)."""
